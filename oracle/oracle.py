@@ -1,0 +1,233 @@
+"""Python side of the CPU oracle (TEST INFRASTRUCTURE).
+
+Loads ``liboracle.so`` (plain C, FP64, built from ``pf_oracle.c``) and adds
+the steps that are library primitives: summing Jacobian triplets into CSR
+(Section III: triplets assembled into a sparse matrix), the explicit
+transposed-Jacobian product, and a Newton loop whose linear solve is
+scipy's sparse LU (tasks 1-4 of Section I).
+
+Only tests, the package smoke check and the benchmark's CPU baseline may use
+this module.  It shares no code with the HIP library: it reads networks as
+the plain arrays of :class:`paper_2011_11880_amd.synth.Network`.
+"""
+
+from __future__ import annotations
+
+import ctypes
+import os
+import subprocess
+
+import numpy as np
+import scipy.sparse as sp
+import scipy.sparse.linalg as spla
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_SRC = os.path.join(_HERE, "pf_oracle.c")
+_LIB = os.path.join(_HERE, "liboracle.so")
+
+_i = ctypes.c_int
+_pi = ctypes.POINTER(ctypes.c_int)
+_pd = ctypes.POINTER(ctypes.c_double)
+
+
+class _Topo(ctypes.Structure):
+    _fields_ = [("n_bus", _i), ("n_branch", _i), ("n_load", _i), ("n_pv", _i),
+                ("n_slack", _i), ("n_shunt", _i),
+                ("br_from", _pi), ("br_to", _pi), ("br_status", _pi),
+                ("load_bus", _pi), ("pv_bus", _pi), ("slack_bus", _pi),
+                ("shunt_bus", _pi)]
+
+
+class _Data(ctypes.Structure):
+    _fields_ = [(k, _pd) for k in (
+        "br_r", "br_x", "br_b", "br_tap", "br_shift_deg", "load_p", "load_q",
+        "pv_p", "pv_v", "slack_v", "slack_theta", "shunt_g", "shunt_b")]
+
+
+PARAM_FIELDS = ("br_r", "br_x", "br_b", "br_tap", "br_shift_deg", "load_p",
+                "load_q", "pv_p", "pv_v", "slack_v", "slack_theta",
+                "shunt_g", "shunt_b")
+
+
+def build(force: bool = False) -> str:
+    """Compile liboracle.so with gcc (no contraction of a*b+c into FMA)."""
+    if force or not os.path.exists(_LIB) or \
+            os.path.getmtime(_LIB) < max(os.path.getmtime(_SRC),
+                                         os.path.getmtime(os.path.join(_HERE, "ora_core.inc"))):
+        tmp = _LIB + ".tmp%d" % os.getpid()
+        subprocess.check_call(["gcc", "-O2", "-ffp-contract=off", "-std=c99",
+                               "-fPIC", "-shared", _SRC, "-o", tmp, "-lm"])
+        os.replace(tmp, _LIB)
+    return _LIB
+
+
+_lib = None
+
+
+def _load(path):
+    L = ctypes.CDLL(path)
+    L.ora_residual.argtypes = [ctypes.POINTER(_Topo), ctypes.POINTER(_Data),
+                               _pd, _pd, _pd]
+    L.ora_residual_cs.argtypes = [ctypes.POINTER(_Topo)] + [_pd] * 15
+    L.ora_branch_flows.argtypes = [ctypes.c_double] * 9 + [_pd]
+    L.ora_jacobian_size.argtypes = [ctypes.POINTER(_Topo)]
+    L.ora_jacobian_size.restype = ctypes.c_long
+    L.ora_jacobian.argtypes = [ctypes.POINTER(_Topo), ctypes.POINTER(_Data),
+                               _pd, _pi, _pi, _pd]
+    L.ora_jacobian.restype = ctypes.c_long
+    L.ora_vjp_params.argtypes = [ctypes.POINTER(_Topo), ctypes.POINTER(_Data),
+                                 _pd, _pd] + [_pd] * 7
+    return L
+
+
+def lib():
+    global _lib
+    if _lib is None:
+        build()
+        _lib = _load(_LIB)
+    return _lib
+
+
+def use_library(path):
+    """Point this module at another build of the oracle (mutation tests load
+    deliberately broken copies); ``None`` restores the real one.  Returns the
+    previous handle."""
+    global _lib
+    prev = _lib
+    _lib = None if path is None else _load(path)
+    return prev
+
+
+def _ip(a):
+    return a.ctypes.data_as(_pi)
+
+
+def _dp(a):
+    return a.ctypes.data_as(_pd)
+
+
+class _Bound:
+    """Keeps the numpy arrays behind the ctypes structures alive."""
+
+    def __init__(self, net, data=None):
+        self.arrs = {}
+        keep = self.arrs
+
+        def I(name):
+            a = np.ascontiguousarray(getattr(net, name), dtype=np.int32)
+            keep[name] = a
+            return _ip(a)
+
+        def D(name, src):
+            a = np.ascontiguousarray(src, dtype=np.float64)
+            keep[name] = a
+            return _dp(a)
+
+        self.topo = _Topo(net.n_bus, net.n_branch, net.n_load, net.n_pv,
+                          net.n_slack, net.n_shunt, I("br_from"), I("br_to"),
+                          I("br_status"), I("load_bus"), I("pv_bus"),
+                          I("slack_bus"), I("shunt_bus"))
+        data = data or {}
+        self.data = _Data(*[D(k, data.get(k, getattr(net, k))) for k in PARAM_FIELDS])
+
+
+def n_var(net) -> int:
+    return 2 * net.n_bus + net.n_pv + 2 * net.n_slack
+
+
+def residual(net, y, data=None):
+    """F(y) and the per-row sum of |terms| S (eq. 2)."""
+    b = _Bound(net, data)
+    y = np.ascontiguousarray(y, dtype=np.float64)
+    n = n_var(net)
+    assert y.shape == (n,)
+    F = np.empty(n)
+    S = np.empty(n)
+    lib().ora_residual(ctypes.byref(b.topo), ctypes.byref(b.data), _dp(y), _dp(F), _dp(S))
+    return F, S
+
+
+def residual_complex(net, y, data=None):
+    """F in complex arithmetic: ``y`` and any entry of ``data`` may be complex."""
+    b = _Bound(net)
+    data = data or {}
+    keep = []
+
+    def Z(a):
+        z = np.ascontiguousarray(np.asarray(a, dtype=np.complex128))
+        keep.append(z)
+        return z.view(np.float64).ctypes.data_as(_pd)
+
+    args = [Z(data.get(k, getattr(net, k))) for k in PARAM_FIELDS]
+    yz = Z(y)
+    F = np.zeros(n_var(net), dtype=np.complex128)
+    lib().ora_residual_cs(ctypes.byref(b.topo), *args, yz,
+                          F.view(np.float64).ctypes.data_as(_pd))
+    return F
+
+
+def branch_flows(r, x, bc, tap, shift_deg, vf, vt, thf, tht):
+    out = np.empty(4)
+    lib().ora_branch_flows(r, x, bc, tap, shift_deg, vf, vt, thf, tht, _dp(out))
+    return out
+
+
+def jacobian_coo(net, y, data=None):
+    b = _Bound(net, data)
+    y = np.ascontiguousarray(y, dtype=np.float64)
+    m = lib().ora_jacobian_size(ctypes.byref(b.topo))
+    rows = np.empty(m, np.int32)
+    cols = np.empty(m, np.int32)
+    vals = np.empty(m)
+    k = lib().ora_jacobian(ctypes.byref(b.topo), ctypes.byref(b.data), _dp(y),
+                           _ip(rows), _ip(cols), _dp(vals))
+    return rows[:k], cols[:k], vals[:k]
+
+
+def jacobian(net, y, data=None):
+    """(J, |J|-scale) as scipy CSR: triplets summed into a sparse matrix; the
+    second matrix sums the absolute triplet values (used for tolerances)."""
+    n = n_var(net)
+    r, c, v = jacobian_coo(net, y, data)
+    J = sp.csr_matrix((v, (r, c)), shape=(n, n))
+    A = sp.csr_matrix((np.abs(v), (r, c)), shape=(n, n))
+    J.sort_indices()
+    A.sort_indices()
+    return J, A
+
+
+def vjp(net, y, w, data=None):
+    """(g_state, g_params) for the loss w.F: g_state = J^T w with the explicit
+    Jacobian; g_params is a dict keyed by parameter name."""
+    b = _Bound(net, data)
+    y = np.ascontiguousarray(y, dtype=np.float64)
+    w = np.ascontiguousarray(w, dtype=np.float64)
+    J, _ = jacobian(net, y, data)
+    gx = J.T @ w
+    B, L = net.n_branch, net.n_load
+    out = {k: np.empty(B) for k in ("br_r", "br_x", "br_b", "br_tap", "br_shift_deg")}
+    out["load_p"] = np.empty(L)
+    out["load_q"] = np.empty(L)
+    lib().ora_vjp_params(ctypes.byref(b.topo), ctypes.byref(b.data), _dp(y), _dp(w),
+                         _dp(out["br_r"]), _dp(out["br_x"]), _dp(out["br_b"]),
+                         _dp(out["br_tap"]), _dp(out["br_shift_deg"]),
+                         _dp(out["load_p"]), _dp(out["load_q"]))
+    return gx, out
+
+
+def newton(net, y0, tol=1e-10, max_iter=10, data=None):
+    """Full-step Newton (tasks 1-4): returns (y, list of ||F||_inf per
+    iteration, list of iterates).  The list of norms starts at y0."""
+    y = np.array(y0, dtype=np.float64)
+    norms, iters = [], [y.copy()]
+    for it in range(max_iter + 1):
+        F, _ = residual(net, y, data)
+        nf = float(np.max(np.abs(F))) if F.size else 0.0
+        norms.append(nf)
+        if nf < tol or it == max_iter:
+            break
+        J, _ = jacobian(net, y, data)
+        dx = spla.spsolve(J.tocsc(), F)
+        y = y - dx
+        iters.append(y.copy())
+    return y, norms, iters
