@@ -1,0 +1,307 @@
+/*
+ * pf.h - C ABI of the MI355X power-flow evaluation library (libpf.so).
+ *
+ * The library evaluates, in FP64 on a gfx950 GPU, the hot path of Newton
+ * power flow as formulated in Section II-A of Cui, Li & Fang, "Effective
+ * Parallelism for Equation and Jacobian Evaluation in Large-Scale Power Flow
+ * Calculation":
+ *
+ *   g(y) = 0                                   (eq. 1)
+ *   g = [g_p, g_q, g_V, g_theta]               (eq. 2: P and Q mismatch per
+ *                                               bus, voltage-control error per
+ *                                               generator, angle-control error
+ *                                               per slack)
+ *   y = [theta, V, Q_g, P_s]                   (eq. 3: bus angles, bus voltage
+ *                                               magnitudes, reactive output of
+ *                                               every generator (PV units first,
+ *                                               then slacks), slack active output)
+ *
+ * Models (Section II-A): bus, constant-power PQ load, PV generator, slack
+ * generator, line (pi-model) and two-winding transformer (ideal tap ratio t
+ * and phase shift phi on the from side), shunt admittance.  Line injections
+ * are computed per line and summed at the two buses (eq. 4 is the t = 1,
+ * phi = 0 case of the from/to active power).
+ *
+ * Sign convention: a bus row is the power leaving the bus into branches,
+ * shunts and loads minus the power produced there; g_V = V - V_set and
+ * g_theta = theta - theta_set.  Units are per unit; angles in y are radians;
+ * transformer phase shifts are given in degrees.
+ *
+ * Sizes: n = 2N + N_g + N_s variables and equations; the Jacobian has the
+ * fixed CSR pattern of nnz = 4N + 8B_u + 2N_g + 2N_s entries, where B_u is the
+ * number of distinct connected bus pairs (parallel branches share entries).
+ * Row P_i holds [theta cols of sorted({i} U adj(i))][V cols, same order]
+ * [P_s col if a slack sits at i]; row Q_i the same with the Q_g col of the
+ * generator at i; every control row has a single +1 entry.  Columns are
+ * sorted within each row.
+ *
+ * Conventions for every entry point:
+ *  - Return value: PF_OK (0) or a negative PF_E* status; pf_last_error()
+ *    then returns a thread-local message (valid until the next call on the
+ *    same thread).
+ *  - Pointers named "host" are read (or written) only during the call; the
+ *    caller keeps ownership.  Device pointers (x, F, Jval, X, W, gx, gparam,
+ *    params) are caller-owned GPU buffers on the plan's device; the library
+ *    never frees or retains them.
+ *  - Evaluation calls are asynchronous on the given HIP stream (NULL = the
+ *    default stream), allocate nothing, and check their arguments
+ *    synchronously; faults inside a kernel surface at the caller's next
+ *    synchronisation.  A plan serves one stream at a time.
+ *  - All floating-point data are IEEE FP64, all indices int32, 0-based.
+ *  - Results are deterministic: every bus sum is a fixed-order left fold, no
+ *    floating-point atomics are used, and every schedule gives bit-identical
+ *    outputs.
+ */
+#ifndef PF_H
+#define PF_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define PF_OK 0
+#define PF_EINVAL (-1)   /* bad argument or malformed network data */
+#define PF_ETOPO (-2)    /* self-loop, two voltage controllers on one bus, isolated bus */
+#define PF_EDEVICE (-3)  /* HIP runtime error, or no usable GPU */
+#define PF_ENOMEM (-4)   /* device or host allocation failed */
+#define PF_ESOLVE (-5)   /* linear-solve callback failed (e.g. singular Jacobian) */
+#define PF_ENOCONV (-6)  /* Newton reached max_iter without convergence */
+
+/*
+ * One network, host structure of arrays (Section II-A models).
+ *   br_from/br_to      branch terminal buses; the transformer is on br_from
+ *   br_r, br_x         series resistance and reactance (not both zero)
+ *   br_b               total line charging susceptance, split b/2 per end
+ *   br_tap             off-nominal ratio (> 0; 1 for a line)
+ *   br_shift_deg       phase shift in degrees (0 for a line)
+ *   br_status          1 in service / 0 out of service; NULL = all in service
+ *   load_*             constant-power loads; several may share a bus
+ *   pv_*               PV units: bus, active setpoint P, voltage setpoint V
+ *   slack_*            slack units: bus, voltage setpoint, angle setpoint (rad)
+ *   shunt_*            shunt admittance g + jb to ground; several may share a bus
+ * A bus carries at most one generator (PV or slack).  Array pointers for
+ * zero-length groups may be NULL.
+ */
+typedef struct pf_network {
+    int32_t n_bus, n_branch, n_load, n_pv, n_slack, n_shunt;
+    const int32_t *br_from, *br_to;
+    const double *br_r, *br_x, *br_b, *br_tap, *br_shift_deg;
+    const int32_t *br_status;
+    const int32_t *load_bus;
+    const double *load_p, *load_q;
+    const int32_t *pv_bus;
+    const double *pv_p, *pv_v;
+    const int32_t *slack_bus;
+    const double *slack_v, *slack_theta;
+    const int32_t *shunt_bus;
+    const double *shunt_g, *shunt_b;
+} pf_network;
+
+/*
+ * Launch schedule.  A zero field means "library default".  Any schedule
+ * yields bit-identical results; only speed differs.
+ *   tile_entries    single-instance kernel: admittance entries per wavefront
+ *                   tile (multiple of 64; rows are never split)
+ *   waves_per_block wavefronts per workgroup, 1..8
+ *   grid_blocks     persistent grid size in workgroups (0 = one tile range
+ *                   per wavefront, sized to the work)
+ *   batch_buses     batched kernel: buses per work item
+ *   batch_order     batched kernel bus order: 1 natural, 2 breadth-first
+ *                   from the lowest-numbered bus
+ *   xcd_remap       1: give each of the 8 XCDs a contiguous range of work
+ *                   items (L2 locality), 2: round-robin (hardware order)
+ */
+typedef struct pf_schedule {
+    int32_t tile_entries;
+    int32_t waves_per_block;
+    int32_t grid_blocks;
+    int32_t batch_buses;
+    int32_t batch_order;
+    int32_t xcd_remap;
+} pf_schedule;
+
+/*
+ * Setup options (NULL = defaults).
+ *   host_only  1: build and validate host structures only (pattern, sizes,
+ *              schedule) without touching a GPU; evaluation calls then fail
+ *              with PF_EINVAL.  Used for CPU-side checks.
+ *   device     HIP device ordinal; -1 = the calling thread's current device
+ *   sched      initial schedule
+ */
+typedef struct pf_setup_opts {
+    int32_t host_only;
+    int32_t device;
+    pf_schedule sched;
+} pf_setup_opts;
+
+typedef struct pf_plan pf_plan;
+
+/*
+ * Build a single-instance plan: validate the network, build the fixed
+ * Jacobian pattern, the per-bus admittance rows and every setup-time
+ * coefficient, and upload them (Section III: evaluation calls allocate
+ * nothing; the paper's per-call triplet assembly is replaced by the fixed
+ * pattern).  On success *out owns all device memory of the plan.
+ * Errors: PF_EINVAL (NULL pointers, sizes < 0, n_bus < 1, index out of
+ * range, r = x = 0, tap <= 0, non-finite data), PF_ETOPO (self-loop, two
+ * generators on one bus, a bus without in-service branches when n_bus > 1),
+ * PF_EDEVICE, PF_ENOMEM.
+ */
+int pf_setup(const pf_network *net, const pf_setup_opts *opt, pf_plan **out);
+
+/*
+ * Batch specification over one base network (scenarios and N-1 cases; the
+ * paper runs such jobs as separate processes, Section II-C / IV-C).
+ *   n_inst       number of instances (>= 1)
+ *   load_scale   host [n_inst][n_load]; instance k's load l draws
+ *                scale * (P_l, Q_l); NULL = all 1
+ *   pv_scale     host [n_inst][n_pv]; scales PV active setpoints; NULL = all 1
+ *   outage       host [n_inst]; branch taken out of service in instance k,
+ *                or -1; the branch must be in service in the base network.
+ *                Its Jacobian slots keep their place in the shared pattern
+ *                and receive 0 when nothing else connects the bus pair.
+ */
+typedef struct pf_batch_spec {
+    int32_t n_inst;
+    const double *load_scale;
+    const double *pv_scale;
+    const int32_t *outage;
+} pf_batch_spec;
+
+/*
+ * Build a batched plan: n_inst instances that share the base network's
+ * pattern and data, each with its own state and overlay.  All batched
+ * arrays are instance-fastest: X[n][n_inst], F[n][n_inst],
+ * Jval[nnz][n_inst] (instance k of variable i at i * n_inst + k).
+ * Errors as pf_setup, plus PF_EINVAL for a bad spec.
+ */
+int pf_setup_batch(const pf_network *net, const pf_batch_spec *spec,
+                   const pf_setup_opts *opt, pf_plan **out);
+
+/*
+ * Build a multi-grid plan over n_grids independent networks evaluated in
+ * one launch.  Their state, residual and Jacobian vectors are concatenated
+ * in grid order (block-diagonal system); pf_info_multi gives the offsets.
+ * Errors as pf_setup (for any grid), PF_EINVAL for n_grids < 1.
+ */
+int pf_setup_multi(const pf_network *nets, int32_t n_grids,
+                   const pf_setup_opts *opt, pf_plan **out);
+
+/* Sizes: n (state length of one instance, or of the concatenation) and nnz. */
+int pf_info(const pf_plan *plan, int64_t *n, int64_t *nnz);
+
+/* Extended sizes of a plan. */
+typedef struct pf_info_t {
+    int64_t n, nnz;        /* per instance (batch) or total (multi) */
+    int64_t n_params;      /* length of the parameter vector (pf_set_params) */
+    int64_t n_entries;     /* admittance-row entries (N + 2 B_u) */
+    int32_t n_bus, n_branch, n_load, n_pv, n_slack, n_shunt;
+    int32_t n_inst;        /* 1 unless batched */
+    int32_t n_grids;       /* 1 unless multi-grid */
+    int32_t n_tiles;       /* wavefront tiles of the single-instance kernel */
+    int32_t kind;          /* 0 single, 1 batched, 2 multi-grid */
+} pf_info_t;
+int pf_info_ex(const pf_plan *plan, pf_info_t *info);
+
+/* Host copies of per-grid offsets into the concatenated vectors of a
+ * multi-grid plan: x_off and j_off each receive n_grids + 1 entries. */
+int pf_info_multi(const pf_plan *plan, int64_t *x_off, int64_t *j_off);
+
+/* Host copy of the fixed CSR pattern: rowptr[n + 1], colidx[nnz]. */
+int pf_pattern(const pf_plan *plan, int32_t *rowptr, int32_t *colidx);
+
+/*
+ * Residual F(x) (task 1 of the Newton loop, Section I).  x, F: device [n].
+ * Errors: PF_EINVAL (NULL buffer, batched plan, host-only plan), PF_EDEVICE.
+ */
+int pf_eval_residual(pf_plan *plan, const double *x, double *F, void *stream);
+
+/* Jacobian values (task 2): writes all nnz values of Jval (device [nnz]) in
+ * pf_pattern order, constants and explicit zeros included. */
+int pf_eval_jacobian(pf_plan *plan, const double *x, double *Jval, void *stream);
+
+/* Fused residual + Jacobian in one launch; F or Jval may be NULL (not both). */
+int pf_eval(pf_plan *plan, const double *x, double *F, double *Jval, void *stream);
+
+/* Batched fused evaluation: X [n][n_inst], F [n][n_inst] (nullable),
+ * Jval [nnz][n_inst] (nullable, not both NULL).  Batched plans only. */
+int pf_eval_batch(pf_plan *plan, const double *X, double *F, double *Jval,
+                  void *stream);
+
+/*
+ * Replace the differentiable network data from a device vector laid out as
+ * [r(B), x(B), b(B), tap(B), shift_deg(B), load_p(N_L), load_q(N_L)]
+ * (n_params doubles; concatenated in grid order for multi-grid plans) and
+ * rebuild every derived coefficient on the device.  The pattern is fixed:
+ * r = x = 0 or tap <= 0 are not checked here and yield non-finite values.
+ */
+int pf_set_params(pf_plan *plan, const double *params, void *stream);
+
+/*
+ * Adjoint: for k cotangents W (device [n][k], cotangent-fastest) computes
+ *   gx     = J(x)^T W                              device [n][k]
+ *   gparam = (dF/dp)^T W  for p as in pf_set_params device [n_params][k]
+ * (shift gradient per degree, the unit the data is given in).  Either
+ * output may be NULL.  Single-instance plans only; 1 <= k <= 1024.
+ */
+int pf_vjp(pf_plan *plan, const double *x, const double *W, int32_t k,
+           double *gx, double *gparam, void *stream);
+
+/* Current and new launch schedule (setting may reallocate the plan's
+ * schedule tables; not an evaluation call). */
+int pf_get_schedule(const pf_plan *plan, pf_schedule *sched);
+int pf_set_schedule(pf_plan *plan, const pf_schedule *sched);
+
+/*
+ * Autotuner: times every candidate schedule of the plan's kernel on the
+ * given buffers (single: x, F, Jval as pf_eval; batched: as pf_eval_batch),
+ * keeps the fastest and returns it in *best (nullable).  reps >= 1 timed
+ * launches per candidate (median).  Synchronises the stream.
+ */
+int pf_autotune(pf_plan *plan, const double *x, double *F, double *Jval,
+                int32_t reps, void *stream, pf_schedule *best);
+
+/*
+ * Newton power flow (tasks 1-4, Section I): full steps
+ *   x <- x - J(x)^{-1} F(x)   until ||F||_inf < tol or max_iter steps.
+ * The sparse solve (task 3) is the caller's: the library copies J values and
+ * F to host and calls solve(user, n, rowptr, colidx, Jval_host, rhs_host,
+ * dx_host), which must fill dx and return 0 (non-zero -> PF_ESOLVE).
+ * x: device [n], updated in place.  Runs on the default stream and
+ * synchronises.  report (nullable) receives iteration counts, per-iteration
+ * norms (up to 64) and times.  Returns PF_ENOCONV if max_iter is reached.
+ */
+typedef int (*pf_linsolve_fn)(void *user, int64_t n, const int32_t *rowptr,
+                              const int32_t *colidx, const double *Jval_host,
+                              const double *rhs_host, double *dx_host);
+
+typedef struct pf_newton_opts {
+    double tol;        /* <= 0: 1e-10 */
+    int32_t max_iter;  /* <= 0: 10 */
+} pf_newton_opts;
+
+typedef struct pf_newton_report {
+    int32_t iterations;   /* solves performed */
+    int32_t converged;
+    double norm[65];      /* ||F||_inf at x_0 .. x_iterations */
+    double t_eval_s;      /* device evaluation time (residual + Jacobian) */
+    double t_solve_s;     /* host solve callback time */
+    double t_total_s;
+} pf_newton_report;
+
+int pf_newton(pf_plan *plan, double *x, const pf_newton_opts *opts,
+              pf_linsolve_fn solve, void *user, pf_newton_report *report);
+
+/* Release the plan and all its device memory.  NULL is ignored. */
+void pf_destroy(pf_plan *plan);
+
+/* Message describing the last failure on this thread ("" if none). */
+const char *pf_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* PF_H */

@@ -1,0 +1,331 @@
+"""Torch-facing wrapper of libpf: plans, evaluation, Newton, adjoint.
+
+PyTorch only provides device memory and streams here; every evaluation is a
+libpf HIP kernel launched on the caller's current stream.  Tensors passed in
+must be contiguous float64 CUDA tensors of the documented shapes.
+"""
+
+from __future__ import annotations
+
+import ctypes
+
+import numpy as np
+
+from . import capi
+from .capi import check
+
+_KIND = {0: "single", 1: "batch", 2: "multi"}
+
+
+def _i32(a):
+    return np.ascontiguousarray(np.asarray(a, dtype=np.int32))
+
+
+def _f64(a):
+    return np.ascontiguousarray(np.asarray(a, dtype=np.float64))
+
+
+class _NetStruct:
+    """pf_network over the arrays of a network object (keeps them alive)."""
+
+    INT = ("br_from", "br_to", "br_status", "load_bus", "pv_bus", "slack_bus", "shunt_bus")
+    DBL = ("br_r", "br_x", "br_b", "br_tap", "br_shift_deg", "load_p", "load_q", "pv_p",
+           "pv_v", "slack_v", "slack_theta", "shunt_g", "shunt_b")
+
+    def __init__(self, net):
+        self.keep = {}
+        kw = {}
+        for k in self.INT:
+            a = getattr(net, k, None)
+            if a is None:
+                kw[k] = None
+                continue
+            a = _i32(a)
+            self.keep[k] = a
+            kw[k] = a.ctypes.data_as(capi._pi32)
+        for k in self.DBL:
+            a = _f64(getattr(net, k))
+            self.keep[k] = a
+            kw[k] = a.ctypes.data_as(capi._pd)
+        self.s = capi.pf_network(
+            n_bus=int(net.n_bus), n_branch=len(self.keep["br_from"]),
+            n_load=len(self.keep["load_bus"]), n_pv=len(self.keep["pv_bus"]),
+            n_slack=len(self.keep["slack_bus"]), n_shunt=len(self.keep["shunt_bus"]), **kw)
+
+
+def _opts(host_only=False, device=None, schedule=None):
+    o = capi.pf_setup_opts()
+    o.host_only = 1 if host_only else 0
+    o.device = -1 if device is None else int(device)
+    if schedule:
+        for k, v in schedule.items():
+            setattr(o.sched, k, int(v))
+    return o
+
+
+def _ptr(t, numel, name):
+    """Device pointer of a contiguous float64 CUDA tensor with ``numel`` elements."""
+    import torch
+    if t is None:
+        return None
+    if not isinstance(t, torch.Tensor):
+        raise TypeError(f"{name} must be a torch tensor")
+    if t.dtype != torch.float64:
+        raise TypeError(f"{name} must be float64")
+    if not t.is_cuda:
+        raise ValueError(f"{name} must live on the GPU")
+    if not t.is_contiguous():
+        raise ValueError(f"{name} must be contiguous")
+    if t.numel() != numel:
+        raise ValueError(f"{name} has {t.numel()} elements, expected {numel}")
+    return ctypes.c_void_p(t.data_ptr())
+
+
+def _stream(device):
+    import torch
+    return ctypes.c_void_p(torch.cuda.current_stream(device).cuda_stream)
+
+
+class Plan:
+    """A setup-time plan over one network, a batch, or several grids.
+
+    ``Plan(net)``                         single instance
+    ``Plan(net, batch=dict(n_inst=..., load_scale=..., pv_scale=..., outage=...))``
+    ``Plan.multi([net0, net1, ...])``     block-diagonal multi-grid plan
+    """
+
+    def __init__(self, net=None, *, batch=None, host_only=False, device=None, schedule=None,
+                 _handle=None):
+        self._h = None
+        L = capi.lib()
+        if _handle is not None:
+            self._h = _handle
+        else:
+            ns = _NetStruct(net)
+            opts = _opts(host_only, device, schedule)
+            h = capi._P()
+            if batch is None:
+                check(L.pf_setup(ctypes.byref(ns.s), ctypes.byref(opts), ctypes.byref(h)))
+            else:
+                n_inst = int(batch["n_inst"])
+                spec = capi.pf_batch_spec(n_inst=n_inst)
+                keep = []
+                if batch.get("load_scale") is not None:
+                    a = _f64(batch["load_scale"])
+                    if a.shape != (n_inst, ns.s.n_load):
+                        raise ValueError("load_scale must be (n_inst, n_load)")
+                    keep.append(a)
+                    spec.load_scale = a.ctypes.data_as(capi._pd)
+                if batch.get("pv_scale") is not None:
+                    a = _f64(batch["pv_scale"])
+                    if a.shape != (n_inst, ns.s.n_pv):
+                        raise ValueError("pv_scale must be (n_inst, n_pv)")
+                    keep.append(a)
+                    spec.pv_scale = a.ctypes.data_as(capi._pd)
+                if batch.get("outage") is not None:
+                    a = _i32(batch["outage"])
+                    if a.shape != (n_inst,):
+                        raise ValueError("outage must be (n_inst,)")
+                    keep.append(a)
+                    spec.outage = a.ctypes.data_as(capi._pi32)
+                check(L.pf_setup_batch(ctypes.byref(ns.s), ctypes.byref(spec),
+                                       ctypes.byref(opts), ctypes.byref(h)))
+            self._h = h
+        self._load_info()
+        self.device = device
+
+    @classmethod
+    def multi(cls, nets, *, host_only=False, device=None, schedule=None):
+        structs = [_NetStruct(n) for n in nets]
+        arr = (capi.pf_network * len(structs))(*[s.s for s in structs])
+        opts = _opts(host_only, device, schedule)
+        h = capi._P()
+        check(capi.lib().pf_setup_multi(arr, len(structs), ctypes.byref(opts), ctypes.byref(h)))
+        p = cls(_handle=h, device=device)
+        xo = np.empty(len(structs) + 1, np.int64)
+        jo = np.empty(len(structs) + 1, np.int64)
+        check(capi.lib().pf_info_multi(h, xo.ctypes.data_as(capi._pi64),
+                                       jo.ctypes.data_as(capi._pi64)))
+        p.x_off, p.j_off = xo, jo
+        return p
+
+    def _load_info(self):
+        inf = capi.pf_info_t()
+        check(capi.lib().pf_info_ex(self._h, ctypes.byref(inf)))
+        self.info = {k: int(getattr(inf, k)) for k, _ in inf._fields_}
+        self.info["kind"] = _KIND[self.info["kind"]]
+        self.n = self.info["n"]
+        self.nnz = self.info["nnz"]
+        self.n_inst = self.info["n_inst"]
+        self.n_params = self.info["n_params"]
+
+    # lifetime ---------------------------------------------------------------
+    def close(self):
+        if self._h is not None and self._h.value:
+            capi.lib().pf_destroy(self._h)
+        self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *a):
+        self.close()
+
+    # structure --------------------------------------------------------------
+    def pattern(self):
+        rp = np.empty(self.n + 1, np.int32)
+        ci = np.empty(self.nnz, np.int32)
+        check(capi.lib().pf_pattern(self._h, rp.ctypes.data_as(capi._pi32),
+                                    ci.ctypes.data_as(capi._pi32)))
+        return rp, ci
+
+    @property
+    def schedule(self):
+        s = capi.pf_schedule()
+        check(capi.lib().pf_get_schedule(self._h, ctypes.byref(s)))
+        return s.as_dict()
+
+    @schedule.setter
+    def schedule(self, d):
+        s = capi.pf_schedule(**{k: int(v) for k, v in d.items()})
+        check(capi.lib().pf_set_schedule(self._h, ctypes.byref(s)))
+        self._load_info()
+
+    # evaluation -------------------------------------------------------------
+    def _dev(self, t):
+        import torch
+        return t.device if t is not None else torch.device("cuda", self.device or 0)
+
+    def eval(self, x, F=None, J=None, want_F=True, want_J=True):
+        """Fused residual + Jacobian values for one state (pf_eval)."""
+        import torch
+        dev = self._dev(x)
+        if want_F and F is None:
+            F = torch.empty(self.n, dtype=torch.float64, device=dev)
+        if want_J and J is None:
+            J = torch.empty(self.nnz, dtype=torch.float64, device=dev)
+        check(capi.lib().pf_eval(self._h, _ptr(x, self.n, "x"), _ptr(F, self.n, "F"),
+                                 _ptr(J, self.nnz, "J"), _stream(dev)))
+        return F, J
+
+    def eval_residual(self, x, F=None):
+        import torch
+        dev = self._dev(x)
+        F = torch.empty(self.n, dtype=torch.float64, device=dev) if F is None else F
+        check(capi.lib().pf_eval_residual(self._h, _ptr(x, self.n, "x"), _ptr(F, self.n, "F"),
+                                          _stream(dev)))
+        return F
+
+    def eval_jacobian(self, x, J=None):
+        import torch
+        dev = self._dev(x)
+        J = torch.empty(self.nnz, dtype=torch.float64, device=dev) if J is None else J
+        check(capi.lib().pf_eval_jacobian(self._h, _ptr(x, self.n, "x"),
+                                          _ptr(J, self.nnz, "J"), _stream(dev)))
+        return J
+
+    def eval_batch(self, X, F=None, J=None, want_F=True, want_J=True):
+        """Batched evaluation; X, F are (n, n_inst) and J is (nnz, n_inst),
+        instance-fastest (row-major contiguous)."""
+        import torch
+        dev = self._dev(X)
+        I = self.n_inst
+        if want_F and F is None:
+            F = torch.empty((self.n, I), dtype=torch.float64, device=dev)
+        if want_J and J is None:
+            J = torch.empty((self.nnz, I), dtype=torch.float64, device=dev)
+        check(capi.lib().pf_eval_batch(self._h, _ptr(X, self.n * I, "X"),
+                                       _ptr(F, self.n * I, "F"), _ptr(J, self.nnz * I, "J"),
+                                       _stream(dev)))
+        return F, J
+
+    def set_params(self, params):
+        """Replace [r, x, b, tap, shift_deg, load_p, load_q] (device vector)."""
+        dev = self._dev(params)
+        check(capi.lib().pf_set_params(self._h, _ptr(params, self.n_params, "params"),
+                                       _stream(dev)))
+
+    def vjp(self, x, W, gx=None, gparam=None, want_gx=True, want_gparam=True):
+        """J^T W and (dF/dparams)^T W for W of shape (n, k), cotangent-fastest."""
+        import torch
+        dev = self._dev(x)
+        if W.dim() != 2 or W.shape[0] != self.n:
+            raise ValueError("W must be (n, k)")
+        k = int(W.shape[1])
+        if want_gx and gx is None:
+            gx = torch.empty((self.n, k), dtype=torch.float64, device=dev)
+        if want_gparam and gparam is None:
+            gparam = torch.empty((self.n_params, k), dtype=torch.float64, device=dev)
+        check(capi.lib().pf_vjp(self._h, _ptr(x, self.n, "x"), _ptr(W, self.n * k, "W"), k,
+                                _ptr(gx, self.n * k, "gx"),
+                                _ptr(gparam, self.n_params * k, "gparam"), _stream(dev)))
+        return gx, gparam
+
+    def autotune(self, x, F=None, J=None, reps=5):
+        """Time every candidate schedule on these buffers and keep the fastest."""
+        dev = self._dev(x)
+        best = capi.pf_schedule()
+        if self.info["kind"] == "batch":
+            I = self.n_inst
+            xs = _ptr(x, self.n * I, "X")
+            Fs = _ptr(F, self.n * I, "F")
+            Js = _ptr(J, self.nnz * I, "J")
+        else:
+            xs, Fs, Js = _ptr(x, self.n, "x"), _ptr(F, self.n, "F"), _ptr(J, self.nnz, "J")
+        check(capi.lib().pf_autotune(self._h, xs, Fs, Js, int(reps), _stream(dev),
+                                     ctypes.byref(best)))
+        self._load_info()
+        return best.as_dict()
+
+    def newton(self, x, solve=None, tol=1e-10, max_iter=10):
+        """Newton power flow with a host sparse solve (scipy SuperLU by default).
+        ``x`` (device) is updated in place.  Returns a dict report; raises
+        PFError on failure except non-convergence (report['converged'] False)."""
+        import scipy.sparse as sp
+        import scipy.sparse.linalg as spla
+
+        n = self.n
+        errors = []
+
+        def default_solve(rp, ci, jv, rhs):
+            A = sp.csr_matrix((jv, ci, rp), shape=(n, n))
+            return spla.spsolve(A.tocsc(), rhs)
+
+        user_solve = solve or default_solve
+
+        @capi.pf_linsolve_fn
+        def cb(user, nn, rowptr, colidx, jv, rhs, dx):
+            try:
+                m = int(nn)
+                rp = np.ctypeslib.as_array(rowptr, shape=(m + 1,))
+                nz = int(rp[-1])
+                ci = np.ctypeslib.as_array(colidx, shape=(nz,))
+                J = np.ctypeslib.as_array(jv, shape=(nz,))
+                b = np.ctypeslib.as_array(rhs, shape=(m,))
+                out = np.ctypeslib.as_array(dx, shape=(m,))
+                sol = np.asarray(user_solve(rp.copy(), ci.copy(), J.copy(), b.copy()))
+                if sol.shape != (m,) or not np.all(np.isfinite(sol)):
+                    return 1
+                out[:] = sol
+                return 0
+            except Exception as ex:  # reported through PF_ESOLVE
+                errors.append(ex)
+                return 2
+
+        opts = capi.pf_newton_opts(tol=float(tol), max_iter=int(max_iter))
+        rep = capi.pf_newton_report()
+        rc = capi.lib().pf_newton(self._h, _ptr(x, n, "x"), ctypes.byref(opts), cb, None,
+                                  ctypes.byref(rep))
+        if rc not in (capi.PF_OK, capi.PF_ENOCONV):
+            check(rc)
+        it = int(rep.iterations)
+        return {"iterations": it, "converged": bool(rep.converged),
+                "norms": [float(v) for v in rep.norm[:min(it + 1, 65)]],
+                "t_eval_s": rep.t_eval_s, "t_solve_s": rep.t_solve_s,
+                "t_total_s": rep.t_total_s, "solver_errors": errors}

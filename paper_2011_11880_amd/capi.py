@@ -1,0 +1,139 @@
+"""ctypes declarations of libpf's C ABI (include/pf.h).
+
+Argument marshalling only: every step of the evaluation runs in libpf's HIP
+kernels.  Loading fails loudly when the library has not been built; there is
+no fallback implementation.
+"""
+
+from __future__ import annotations
+
+import ctypes
+import os
+
+PKG = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(PKG, "libpf.so")
+
+PF_OK = 0
+PF_EINVAL = -1
+PF_ETOPO = -2
+PF_EDEVICE = -3
+PF_ENOMEM = -4
+PF_ESOLVE = -5
+PF_ENOCONV = -6
+
+_i32 = ctypes.c_int32
+_i64 = ctypes.c_int64
+_d = ctypes.c_double
+_pi32 = ctypes.POINTER(ctypes.c_int32)
+_pi64 = ctypes.POINTER(ctypes.c_int64)
+_pd = ctypes.POINTER(ctypes.c_double)
+_vp = ctypes.c_void_p
+
+
+class pf_network(ctypes.Structure):
+    _fields_ = [
+        ("n_bus", _i32), ("n_branch", _i32), ("n_load", _i32), ("n_pv", _i32),
+        ("n_slack", _i32), ("n_shunt", _i32),
+        ("br_from", _pi32), ("br_to", _pi32),
+        ("br_r", _pd), ("br_x", _pd), ("br_b", _pd), ("br_tap", _pd), ("br_shift_deg", _pd),
+        ("br_status", _pi32),
+        ("load_bus", _pi32), ("load_p", _pd), ("load_q", _pd),
+        ("pv_bus", _pi32), ("pv_p", _pd), ("pv_v", _pd),
+        ("slack_bus", _pi32), ("slack_v", _pd), ("slack_theta", _pd),
+        ("shunt_bus", _pi32), ("shunt_g", _pd), ("shunt_b", _pd),
+    ]
+
+
+class pf_schedule(ctypes.Structure):
+    _fields_ = [("tile_entries", _i32), ("waves_per_block", _i32), ("grid_blocks", _i32),
+                ("batch_buses", _i32), ("batch_order", _i32), ("xcd_remap", _i32)]
+
+    def as_dict(self):
+        return {k: int(getattr(self, k)) for k, _ in self._fields_}
+
+
+class pf_setup_opts(ctypes.Structure):
+    _fields_ = [("host_only", _i32), ("device", _i32), ("sched", pf_schedule)]
+
+
+class pf_batch_spec(ctypes.Structure):
+    _fields_ = [("n_inst", _i32), ("load_scale", _pd), ("pv_scale", _pd), ("outage", _pi32)]
+
+
+class pf_info_t(ctypes.Structure):
+    _fields_ = [("n", _i64), ("nnz", _i64), ("n_params", _i64), ("n_entries", _i64),
+                ("n_bus", _i32), ("n_branch", _i32), ("n_load", _i32), ("n_pv", _i32),
+                ("n_slack", _i32), ("n_shunt", _i32), ("n_inst", _i32), ("n_grids", _i32),
+                ("n_tiles", _i32), ("kind", _i32)]
+
+
+class pf_newton_opts(ctypes.Structure):
+    _fields_ = [("tol", _d), ("max_iter", _i32)]
+
+
+class pf_newton_report(ctypes.Structure):
+    _fields_ = [("iterations", _i32), ("converged", _i32), ("norm", _d * 65),
+                ("t_eval_s", _d), ("t_solve_s", _d), ("t_total_s", _d)]
+
+
+pf_linsolve_fn = ctypes.CFUNCTYPE(ctypes.c_int, _vp, _i64, _pi32, _pi32, _pd, _pd, _pd)
+
+_P = ctypes.c_void_p  # pf_plan*
+
+SIGNATURES = {
+    "pf_setup": (ctypes.c_int, [ctypes.POINTER(pf_network), ctypes.POINTER(pf_setup_opts),
+                                ctypes.POINTER(_P)]),
+    "pf_setup_batch": (ctypes.c_int, [ctypes.POINTER(pf_network), ctypes.POINTER(pf_batch_spec),
+                                      ctypes.POINTER(pf_setup_opts), ctypes.POINTER(_P)]),
+    "pf_setup_multi": (ctypes.c_int, [ctypes.POINTER(pf_network), _i32,
+                                      ctypes.POINTER(pf_setup_opts), ctypes.POINTER(_P)]),
+    "pf_info": (ctypes.c_int, [_P, _pi64, _pi64]),
+    "pf_info_ex": (ctypes.c_int, [_P, ctypes.POINTER(pf_info_t)]),
+    "pf_info_multi": (ctypes.c_int, [_P, _pi64, _pi64]),
+    "pf_pattern": (ctypes.c_int, [_P, _pi32, _pi32]),
+    "pf_eval_residual": (ctypes.c_int, [_P, _vp, _vp, _vp]),
+    "pf_eval_jacobian": (ctypes.c_int, [_P, _vp, _vp, _vp]),
+    "pf_eval": (ctypes.c_int, [_P, _vp, _vp, _vp, _vp]),
+    "pf_eval_batch": (ctypes.c_int, [_P, _vp, _vp, _vp, _vp]),
+    "pf_set_params": (ctypes.c_int, [_P, _vp, _vp]),
+    "pf_vjp": (ctypes.c_int, [_P, _vp, _vp, _i32, _vp, _vp, _vp]),
+    "pf_get_schedule": (ctypes.c_int, [_P, ctypes.POINTER(pf_schedule)]),
+    "pf_set_schedule": (ctypes.c_int, [_P, ctypes.POINTER(pf_schedule)]),
+    "pf_autotune": (ctypes.c_int, [_P, _vp, _vp, _vp, _i32, _vp, ctypes.POINTER(pf_schedule)]),
+    "pf_newton": (ctypes.c_int, [_P, _vp, ctypes.POINTER(pf_newton_opts), pf_linsolve_fn, _vp,
+                                 ctypes.POINTER(pf_newton_report)]),
+    "pf_destroy": (None, [_P]),
+    "pf_last_error": (ctypes.c_char_p, []),
+}
+
+_lib = None
+
+
+def lib():
+    """The loaded libpf (raises if it has not been built)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError(
+                "libpf.so is missing: build it with `python -m paper_2011_11880_amd.build` "
+                "(or __graft_entry__.build()); there is no fallback path")
+        L = ctypes.CDLL(LIB_PATH)
+        for name, (res, args) in SIGNATURES.items():
+            fn = getattr(L, name)
+            fn.restype = res
+            fn.argtypes = args
+        _lib = L
+    return _lib
+
+
+class PFError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__(f"[{code}] {msg}")
+        self.code = code
+
+
+def check(rc):
+    if rc != PF_OK:
+        msg = lib().pf_last_error()
+        raise PFError(rc, msg.decode() if msg else "")
+    return rc

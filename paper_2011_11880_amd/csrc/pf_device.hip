@@ -1,0 +1,845 @@
+// Device side of libpf for gfx950 (CDNA4): plan buffers, setup-time
+// coefficient kernels and the evaluation kernels of the power-flow hot path
+// (Section II-A equations, tasks 1 and 2 of the Newton loop).
+//
+// Layout and arithmetic (all FP64):
+//  * Every in-service branch's pi-model (series g + jb = 1/(r + jx), charging
+//    b/2 per end, ideal transformer t e^{j phi} on the from side) is folded at
+//    setup into bus-admittance rows: row i holds one entry per column of
+//    sorted({i} U adj(i)) with the summed admittance G_ij + jB_ij of every
+//    branch joining i and j (and the shunts on the diagonal).  An entry is
+//    4 B of column + 16 B of coefficients.
+//  * The injections of row i are the join of its entries (Section II-B):
+//      P_i = sum_j V_i V_j (G_ij cos th_ij + B_ij sin th_ij)
+//      Q_i = sum_j V_i V_j (G_ij sin th_ij - B_ij cos th_ij)
+//    (diagonal term V_i^2 G_ii and -V_i^2 B_ii), summed by a left fold over
+//    the row in column order -- the same order in every kernel and for every
+//    schedule, so all outputs are bit-reproducible.  No atomics.
+//  * Jacobian values go straight to slots fixed at setup: off-diagonal
+//    entries by the lane that owns the admittance entry, the four diagonal
+//    sums and the constant +-1 entries by the lane that finishes the row.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <vector>
+
+#include "pf_internal.hpp"
+
+namespace pf {
+
+#define HIP_TRY(expr)                                                              \
+    do {                                                                           \
+        hipError_t e_ = (expr);                                                    \
+        if (e_ != hipSuccess)                                                      \
+            return fail(PF_EDEVICE, "%s failed: %s", #expr, hipGetErrorString(e_)); \
+    } while (0)
+
+struct DevPlan {
+    int device = 0;
+    std::vector<void *> allocs;
+    // structure
+    int32_t *yptr = nullptr, *ycol = nullptr, *cptr = nullptr, *clist = nullptr;
+    int4 *bus4 = nullptr;
+    int2 *bus2 = nullptr;
+    int32_t *shptr = nullptr, *shlist = nullptr, *ldptr = nullptr, *ldlist = nullptr;
+    int4 *gen4 = nullptr;
+    double2 *gen2 = nullptr;
+    int32_t *genpv = nullptr;
+    int32_t *br_f = nullptr, *br_t = nullptr;
+    GridDev *grids = nullptr;
+    int4 *tiles = nullptr;
+    int32_t ntiles_alloc = 0;
+    // data
+    double *params = nullptr, *pv_p = nullptr, *shunt_g = nullptr, *shunt_b = nullptr;
+    // derived
+    double *yG = nullptr, *yB = nullptr;
+    double2 *spec = nullptr;
+    // batched overlay
+    double *lscale = nullptr, *pscale = nullptr;
+    int32_t *outage = nullptr;
+    double *otab = nullptr;
+    int32_t *order_nat = nullptr, *order_bfs = nullptr;
+    // Newton scratch (allocated at setup for single-instance plans)
+    double *nw_F = nullptr, *nw_J = nullptr, *nw_dx = nullptr;
+};
+
+template <typename T>
+static int dalloc(DevPlan *dp, T **p, size_t count) {
+    *p = nullptr;
+    if (count == 0) return PF_OK;
+    void *q = nullptr;
+    hipError_t e = hipMalloc(&q, count * sizeof(T));
+    if (e != hipSuccess) return fail(PF_ENOMEM, "hipMalloc(%zu bytes): %s", count * sizeof(T),
+                                     hipGetErrorString(e));
+    dp->allocs.push_back(q);
+    *p = static_cast<T *>(q);
+    return PF_OK;
+}
+
+template <typename T, typename S>
+static int dupload(DevPlan *dp, T **p, const std::vector<S> &v) {
+    static_assert(sizeof(S) <= sizeof(T), "element size");
+    const size_t bytes = v.size() * sizeof(S);
+    const size_t count = (bytes + sizeof(T) - 1) / sizeof(T);
+    int rc = dalloc(dp, p, count);
+    if (rc) return rc;
+    if (bytes) HIP_TRY(hipMemcpy(*p, v.data(), bytes, hipMemcpyHostToDevice));
+    return PF_OK;
+}
+
+// ---------------------------------------------------------------------------
+// setup-time coefficients
+// ---------------------------------------------------------------------------
+
+// Admittance contribution of one branch end pair to entry (i, j):
+//   FF: (y + j b/2) / t^2          TT: y + j b/2
+//   FT: -y e^{j phi} / t           TF: -y e^{-j phi} / t
+// with y = g + jb = 1/(r + jx).
+__device__ __forceinline__ void branch_term(const double *__restrict__ P, int64_t B, int br,
+                                            int kind, double &G, double &Bv) {
+    const double r = P[br], x = P[B + br], bc = P[2 * B + br];
+    const double tap = P[3 * B + br], sh = P[4 * B + br];
+    const double d = r * r + x * x;
+    const double g = r / d;
+    const double b = -x / d;
+    if (kind == K_FF) {
+        const double t2 = tap * tap;
+        G = g / t2;
+        Bv = (b + 0.5 * bc) / t2;
+    } else if (kind == K_TT) {
+        G = g;
+        Bv = b + 0.5 * bc;
+    } else {
+        double sp, cp;
+        sincos(sh * (M_PI / 180.0), &sp, &cp);
+        if (kind == K_FT) {
+            G = -(g * cp - b * sp) / tap;
+            Bv = -(g * sp + b * cp) / tap;
+        } else {
+            G = -(g * cp + b * sp) / tap;
+            Bv = -(b * cp - g * sp) / tap;
+        }
+    }
+}
+
+// One lane per bus: admittance entries of its row, then its specified
+// injection (loads minus PV setpoint).  Sums run in fixed list order.
+__global__ void __launch_bounds__(256)
+k_build_coeffs(int Nt, int64_t B, const int32_t *__restrict__ yptr, const int2 *__restrict__ bus2,
+               const int32_t *__restrict__ cptr, const int32_t *__restrict__ clist,
+               const int32_t *__restrict__ shptr, const int32_t *__restrict__ shlist,
+               const double *__restrict__ shg, const double *__restrict__ shb,
+               const int32_t *__restrict__ ldptr, const int32_t *__restrict__ ldlist,
+               const double *__restrict__ P, int64_t NL, const int32_t *__restrict__ genpv,
+               const double *__restrict__ pv_p, double *__restrict__ yG,
+               double *__restrict__ yB, double2 *__restrict__ spec) {
+    const int b = blockIdx.x * blockDim.x + threadIdx.x;
+    if (b >= Nt) return;
+    const int32_t ys = yptr[b], ye = yptr[b + 1];
+    const int2 b2 = bus2[b];
+    for (int32_t e = ys; e < ye; ++e) {
+        double G = 0.0, Bv = 0.0;
+        for (int32_t c = cptr[e]; c < cptr[e + 1]; ++c) {
+            const int32_t code = clist[c];
+            double g, bb;
+            branch_term(P, B, code >> 2, code & 3, g, bb);
+            G += g;
+            Bv += bb;
+        }
+        if (e - ys == b2.x) {
+            for (int32_t s = shptr[b]; s < shptr[b + 1]; ++s) {
+                G += shg[shlist[s]];
+                Bv += shb[shlist[s]];
+            }
+        }
+        yG[e] = G;
+        yB[e] = Bv;
+    }
+    const double *lp = P + 5 * B;
+    const double *lq = lp + NL;
+    double sp = 0.0, sq = 0.0;
+    for (int32_t l = ldptr[b]; l < ldptr[b + 1]; ++l) {
+        sp += lp[ldlist[l]];
+        sq += lq[ldlist[l]];
+    }
+    if (b2.y >= 0 && genpv[b2.y] >= 0) sp = sp - pv_p[genpv[b2.y]];
+    spec[b] = make_double2(sp, sq);
+}
+
+// One lane per branch: the four admittance terms it adds (FF, FT, TF, TT as
+// G, B pairs), used to take a branch out in N-1 instances.
+__global__ void __launch_bounds__(256)
+k_outage_table(int64_t B, const double *__restrict__ P, double *__restrict__ otab) {
+    const int e = blockIdx.x * blockDim.x + threadIdx.x;
+    if (e >= B) return;
+    for (int k = 0; k < 4; ++k) {
+        double G, Bv;
+        branch_term(P, B, e, k, G, Bv);
+        otab[8 * int64_t(e) + 2 * k] = G;
+        otab[8 * int64_t(e) + 2 * k + 1] = Bv;
+    }
+}
+
+// ---------------------------------------------------------------------------
+// evaluation
+// ---------------------------------------------------------------------------
+
+// Contribution of admittance entry (i, j) to row i.
+//   c[0..5]: P_i, Q_i, dP_i/dth_i, dP_i/dV_i, dQ_i/dth_i, dQ_i/dV_i
+//   o[0..3]: dP_i/dth_j, dP_i/dV_j, dQ_i/dth_j, dQ_i/dV_j   (j != i only)
+__device__ __forceinline__ void entry_eval(bool diag, double G, double B, double thi, double vi,
+                                           double thj, double vj, double c[6], double o[4]) {
+    if (diag) {
+        const double vi2 = vi * vi;
+        c[0] = vi2 * G;
+        c[1] = -(vi2 * B);
+        c[2] = 0.0;
+        c[3] = 2.0 * vi * G;
+        c[4] = 0.0;
+        c[5] = -(2.0 * vi * B);
+        o[0] = o[1] = o[2] = o[3] = 0.0;
+    } else {
+        double s, co;
+        sincos(thi - thj, &s, &co);
+        const double t1 = fma(G, co, B * s);     // G cos + B sin
+        const double t2 = fma(G, s, -(B * co));  // G sin - B cos
+        const double vv = vi * vj;
+        const double a = vv * t1;
+        const double q = vv * t2;
+        c[0] = a;
+        c[1] = q;
+        c[2] = -q;
+        c[3] = vj * t1;
+        c[4] = a;
+        c[5] = vj * t2;
+        o[0] = q;
+        o[1] = vi * t1;
+        o[2] = -a;
+        o[3] = vi * t2;
+    }
+}
+
+// Logical workgroup id that gives each XCD a contiguous range: the hardware
+// hands workgroup ids to the 8 XCDs round-robin.
+__device__ __forceinline__ int xcd_logical_block(int bid, int nb) {
+    const int q = nb >> 3, r = nb & 7, x = bid & 7;
+    return x * q + min(x, r) + (bid >> 3);
+}
+
+__device__ __forceinline__ void wave_sync() {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+// Single-instance fused residual + Jacobian.  Each wavefront walks a
+// contiguous range of tiles; a tile is a run of whole admittance rows,
+// processed 64 entries (one per lane) at a time.  The six per-entry row
+// contributions are staged in LDS and left-folded by the lane that holds the
+// first entry of each row (or lane 0 for a row continuing from the previous
+// chunk, which picks up the carried partial sums).
+template <bool WF, bool WJ>
+__global__ void __launch_bounds__(512)
+k_eval_single(const int4 *__restrict__ tiles, int ntiles, int tiles_per_wave, int remap,
+              const GridDev *__restrict__ grids, const int4 *__restrict__ bus4,
+              const int2 *__restrict__ bus2, const double2 *__restrict__ spec,
+              const int32_t *__restrict__ ycol, const double *__restrict__ yG,
+              const double *__restrict__ yB, const int4 *__restrict__ gen4,
+              const double2 *__restrict__ gen2, const double *__restrict__ x,
+              double *__restrict__ F, double *__restrict__ J) {
+    extern __shared__ double lds[];
+    const int lane = threadIdx.x & 63;
+    const int wv = threadIdx.x >> 6;
+    const int wpb = blockDim.x >> 6;
+    double *L = lds + wv * (6 * 64);
+    const int lb = remap ? xcd_logical_block(blockIdx.x, gridDim.x) : blockIdx.x;
+    const int lw = lb * wpb + wv;
+    const int t_begin = lw * tiles_per_wave;
+    const int t_end = min(ntiles, t_begin + tiles_per_wave);
+    const uint64_t le = (lane == 63) ? ~0ull : ((2ull << lane) - 1ull);
+    for (int t = t_begin; t < t_end; ++t) {
+        const int4 td = tiles[t];
+        const int e0 = td.x, e1 = td.y, b0 = td.z;
+        const GridDev gd = grids[td.w];
+        const double *xt = x + gd.xoff;
+        const double *xv = xt + gd.N;
+        double cy[6] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
+        int rows_seen = 0;
+        for (int c0 = e0; c0 < e1; c0 += 64) {
+            const int nvalid = min(64, e1 - c0);
+            const bool valid = lane < nvalid;
+            const int e = c0 + lane;
+            const int raw = valid ? ycol[e] : 0;
+            const bool start = raw < 0;
+            const int j = raw & kColMask;
+            const uint64_t smask = __ballot(start);
+            const int r = rows_seen + __popcll(smask & le) - 1;
+            const int b = b0 + r;
+            const int i = b - gd.bus_off;
+            double c[6] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
+            int4 bi = make_int4(0, 0, 0, 0);
+            double thi = 0.0, vi = 0.0;
+            if (valid) {
+                bi = bus4[b];
+                thi = xt[i];
+                vi = xv[i];
+                const double thj = xt[j], vj = xv[j];
+                double o[4];
+                const bool diag = (j == i);
+                entry_eval(diag, yG[e], yB[e], thi, vi, thj, vj, c, o);
+                if (WJ && !diag) {
+                    const int p = e - bi.x, Lr = bi.y - bi.x;
+                    J[bi.z + p] = o[0];
+                    J[bi.z + Lr + p] = o[1];
+                    J[bi.w + p] = o[2];
+                    J[bi.w + Lr + p] = o[3];
+                }
+            }
+#pragma unroll
+            for (int k = 0; k < 6; ++k) L[k * 64 + lane] = c[k];
+            wave_sync();
+            const bool carry_row = !(smask & 1ull);
+            const bool folder = start || (lane == 0 && carry_row);
+            const uint64_t after = smask & ~le;
+            const int next = after ? (__ffsll((unsigned long long)after) - 1) : nvalid;
+            const bool next_is_start = (c0 + nvalid >= e1) ? true : (ycol[c0 + nvalid] < 0);
+            const bool complete = (next < nvalid) || next_is_start;
+            double a[6];
+#pragma unroll
+            for (int k = 0; k < 6; ++k) a[k] = (lane == 0 && carry_row) ? cy[k] : 0.0;
+            if (folder) {
+                for (int q = lane; q < next; ++q) {
+#pragma unroll
+                    for (int k = 0; k < 6; ++k) a[k] += L[k * 64 + q];
+                }
+            }
+            if (!next_is_start) {
+                const int lastf = smask ? 63 - __clzll((long long)smask) : 0;
+#pragma unroll
+                for (int k = 0; k < 6; ++k) cy[k] = __shfl(a[k], lastf);
+            }
+            if (folder && complete) {
+                const int2 b2 = bus2[b];
+                const double2 sp = spec[b];
+                const int Lr = bi.y - bi.x;
+                double fp = a[0] + sp.x;
+                double fq = a[1] + sp.y;
+                const int g = b2.y;
+                if (g >= 0) {
+                    const int4 g4 = gen4[g];
+                    const double2 gs = gen2[g];
+                    fq = fq - x[g4.x];
+                    if (WF) F[g4.x] = vi - gs.x;
+                    if (WJ) {
+                        J[bi.w + 2 * Lr] = -1.0;
+                        J[g4.y] = 1.0;
+                    }
+                    if (g4.z >= 0) {
+                        fp = fp - x[g4.z];
+                        if (WF) F[g4.z] = thi - gs.y;
+                        if (WJ) {
+                            J[bi.z + 2 * Lr] = -1.0;
+                            J[g4.w] = 1.0;
+                        }
+                    }
+                }
+                if (WF) {
+                    F[gd.xoff + i] = fp;
+                    F[gd.xoff + gd.N + i] = fq;
+                }
+                if (WJ) {
+                    J[bi.z + b2.x] = a[2];
+                    J[bi.z + Lr + b2.x] = a[3];
+                    J[bi.w + b2.x] = a[4];
+                    J[bi.w + Lr + b2.x] = a[5];
+                }
+            }
+            rows_seen += __popcll(smask);
+            wave_sync();
+        }
+    }
+}
+
+// Batched fused residual + Jacobian, instance-fastest layout: lane = instance
+// (64 instances per wavefront), so every state gather and every output store
+// is a contiguous 512 B row segment, while the row structure and coefficients
+// are wave-uniform scalar loads.  A work item is (instance chunk, run of
+// buses in the chosen order); each wavefront walks a contiguous item range.
+// Per-instance overlays: load / PV scale factors (SCEN) and one branch taken
+// out (OUTG), whose admittance terms are subtracted from the entries it
+// joins -- exactly cancelling them when no parallel branch remains.
+template <bool WF, bool WJ, bool SCEN, bool OUTG>
+__global__ void __launch_bounds__(512)
+k_eval_batch(int N, int I, int n_btiles, int TB, int n_items, int items_per_wave, int remap,
+             const int32_t *__restrict__ order, const int4 *__restrict__ bus4,
+             const int2 *__restrict__ bus2, const double2 *__restrict__ spec,
+             const int32_t *__restrict__ ycol, const double *__restrict__ yG,
+             const double *__restrict__ yB, const int4 *__restrict__ gen4,
+             const double2 *__restrict__ gen2, const int32_t *__restrict__ genpv,
+             const int32_t *__restrict__ ldptr, const int32_t *__restrict__ ldlist,
+             const double *__restrict__ lp, const double *__restrict__ lq,
+             const double *__restrict__ pv_p, const double *__restrict__ lscale,
+             const double *__restrict__ pscale, const int32_t *__restrict__ outage,
+             const int32_t *__restrict__ br_f, const int32_t *__restrict__ br_t,
+             const double *__restrict__ otab, const double *__restrict__ X,
+             double *__restrict__ F, double *__restrict__ J) {
+    const int lane = threadIdx.x & 63;
+    const int wv = threadIdx.x >> 6;
+    const int wpb = blockDim.x >> 6;
+    const int lb = remap ? xcd_logical_block(blockIdx.x, gridDim.x) : blockIdx.x;
+    const int lw = lb * wpb + wv;
+    const int w_begin = lw * items_per_wave;
+    const int w_end = min(n_items, w_begin + items_per_wave);
+    const size_t SI = size_t(I);
+    int cur_chunk = -1;
+    int of = -1, ot = -1;
+    double oy[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+    for (int w = w_begin; w < w_end; ++w) {
+        const int ch = w / n_btiles;
+        const int bt = w - ch * n_btiles;
+        const int k = ch * 64 + lane;
+        const bool valid = k < I;
+        if (OUTG && ch != cur_chunk) {
+            cur_chunk = ch;
+            of = ot = -1;
+            const int o = valid ? outage[k] : -1;
+            if (o >= 0) {
+                of = br_f[o];
+                ot = br_t[o];
+#pragma unroll
+                for (int q = 0; q < 8; ++q) oy[q] = otab[8 * size_t(o) + q];
+            }
+        }
+        const int q0 = bt * TB;
+        const int q1 = min(N, q0 + TB);
+        for (int qq = q0; qq < q1; ++qq) {
+            const int b = order[qq];
+            const int4 bi = bus4[b];
+            const int Lr = bi.y - bi.x;
+            double thi = 0.0, vi = 0.0;
+            if (valid) {
+                thi = X[size_t(b) * SI + k];
+                vi = X[size_t(N + b) * SI + k];
+            }
+            double a[6] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
+            for (int e = bi.x; e < bi.y; ++e) {
+                const int j = ycol[e] & kColMask;
+                double G = yG[e], Bv = yB[e];
+                const bool diag = (j == b);
+                if (OUTG) {
+                    if (of == b) {
+                        if (diag) {
+                            G -= oy[0];
+                            Bv -= oy[1];
+                        } else if (j == ot) {
+                            G -= oy[2];
+                            Bv -= oy[3];
+                        }
+                    } else if (ot == b) {
+                        if (diag) {
+                            G -= oy[6];
+                            Bv -= oy[7];
+                        } else if (j == of) {
+                            G -= oy[4];
+                            Bv -= oy[5];
+                        }
+                    }
+                }
+                if (valid) {
+                    const double thj = X[size_t(j) * SI + k];
+                    const double vj = X[size_t(N + j) * SI + k];
+                    double c[6], o[4];
+                    entry_eval(diag, G, Bv, thi, vi, thj, vj, c, o);
+                    if (WJ && !diag) {
+                        const int p = e - bi.x;
+                        J[size_t(bi.z + p) * SI + k] = o[0];
+                        J[size_t(bi.z + Lr + p) * SI + k] = o[1];
+                        J[size_t(bi.w + p) * SI + k] = o[2];
+                        J[size_t(bi.w + Lr + p) * SI + k] = o[3];
+                    }
+#pragma unroll
+                    for (int q = 0; q < 6; ++q) a[q] += c[q];
+                }
+            }
+            if (!valid) continue;
+            const int2 b2 = bus2[b];
+            double spx, spy;
+            if (SCEN) {
+                spx = 0.0;
+                spy = 0.0;
+                for (int l = ldptr[b]; l < ldptr[b + 1]; ++l) {
+                    const int ld = ldlist[l];
+                    const double s = lscale ? lscale[size_t(ld) * SI + k] : 1.0;
+                    spx += lp[ld] * s;
+                    spy += lq[ld] * s;
+                }
+                if (b2.y >= 0) {
+                    const int pv = genpv[b2.y];
+                    if (pv >= 0) {
+                        const double s = pscale ? pscale[size_t(pv) * SI + k] : 1.0;
+                        spx = spx - pv_p[pv] * s;
+                    }
+                }
+            } else {
+                const double2 sp = spec[b];
+                spx = sp.x;
+                spy = sp.y;
+            }
+            double fp = a[0] + spx;
+            double fq = a[1] + spy;
+            const int g = b2.y;
+            if (g >= 0) {
+                const int4 g4 = gen4[g];
+                const double2 gs = gen2[g];
+                fq = fq - X[size_t(g4.x) * SI + k];
+                if (WF) F[size_t(g4.x) * SI + k] = vi - gs.x;
+                if (WJ) {
+                    J[size_t(bi.w + 2 * Lr) * SI + k] = -1.0;
+                    J[size_t(g4.y) * SI + k] = 1.0;
+                }
+                if (g4.z >= 0) {
+                    fp = fp - X[size_t(g4.z) * SI + k];
+                    if (WF) F[size_t(g4.z) * SI + k] = thi - gs.y;
+                    if (WJ) {
+                        J[size_t(bi.z + 2 * Lr) * SI + k] = -1.0;
+                        J[size_t(g4.w) * SI + k] = 1.0;
+                    }
+                }
+            }
+            if (WF) {
+                F[size_t(b) * SI + k] = fp;
+                F[size_t(N + b) * SI + k] = fq;
+            }
+            if (WJ) {
+                J[size_t(bi.z + b2.x) * SI + k] = a[2];
+                J[size_t(bi.z + Lr + b2.x) * SI + k] = a[3];
+                J[size_t(bi.w + b2.x) * SI + k] = a[4];
+                J[size_t(bi.w + Lr + b2.x) * SI + k] = a[5];
+            }
+        }
+    }
+}
+
+// x <- x - dx (Newton update, task 4).
+__global__ void __launch_bounds__(256) k_newton_update(int64_t n, double *__restrict__ x,
+                                                       const double *__restrict__ dx) {
+    const int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (i < n) x[i] = x[i] - dx[i];
+}
+
+// ---------------------------------------------------------------------------
+// host side
+// ---------------------------------------------------------------------------
+
+void dev_destroy(DevPlan *dp) {
+    if (!dp) return;
+    int prev = 0;
+    bool switched = hipGetDevice(&prev) == hipSuccess && prev != dp->device &&
+                    hipSetDevice(dp->device) == hipSuccess;
+    for (void *p : dp->allocs) (void)hipFree(p);
+    if (switched) (void)hipSetDevice(prev);
+    delete dp;
+}
+
+struct DeviceGuard {
+    int prev = -1;
+    bool ok = true;
+    explicit DeviceGuard(int dev) {
+        if (hipGetDevice(&prev) != hipSuccess) {
+            ok = false;
+            return;
+        }
+        if (prev != dev && hipSetDevice(dev) != hipSuccess) ok = false;
+    }
+    ~DeviceGuard() {
+        int cur = -1;
+        if (prev >= 0 && hipGetDevice(&cur) == hipSuccess && cur != prev) (void)hipSetDevice(prev);
+    }
+};
+
+static int build_coeffs(HostPlan &hp, DevPlan *dp, hipStream_t st) {
+    if (hp.Nt > 0) {
+        hipLaunchKernelGGL(k_build_coeffs, dim3((hp.Nt + 255) / 256), dim3(256), 0, st, hp.Nt,
+                           int64_t(hp.Bt), dp->yptr, dp->bus2, dp->cptr, dp->clist, dp->shptr,
+                           dp->shlist, dp->shunt_g, dp->shunt_b, dp->ldptr, dp->ldlist,
+                           dp->params, int64_t(hp.NLt), dp->genpv, dp->pv_p, dp->yG, dp->yB,
+                           dp->spec);
+        HIP_TRY(hipGetLastError());
+    }
+    if (dp->otab && hp.Bt > 0) {
+        hipLaunchKernelGGL(k_outage_table, dim3((hp.Bt + 255) / 256), dim3(256), 0, st,
+                           int64_t(hp.Bt), dp->params, dp->otab);
+        HIP_TRY(hipGetLastError());
+    }
+    return PF_OK;
+}
+
+int dev_upload_tiles(HostPlan &hp, DevPlan *dp) {
+    DeviceGuard g(dp->device);
+    if (!g.ok) return fail(PF_EDEVICE, "cannot select device %d", dp->device);
+    const int32_t nt = hp.n_tiles();
+    if (nt > dp->ntiles_alloc) {
+        int4 *p = nullptr;
+        int rc = dalloc(dp, &p, size_t(nt));
+        if (rc) return rc;
+        dp->tiles = p;
+        dp->ntiles_alloc = nt;
+    }
+    if (nt) HIP_TRY(hipMemcpy(dp->tiles, hp.tiles.data(), size_t(nt) * sizeof(int4),
+                              hipMemcpyHostToDevice));
+    return PF_OK;
+}
+
+int dev_create(HostPlan &hp, DevPlan **out) {
+    *out = nullptr;
+    int ndev = 0;
+    if (hipGetDeviceCount(&ndev) != hipSuccess || ndev < 1)
+        return fail(PF_EDEVICE, "no HIP device available");
+    if (hp.device < 0) HIP_TRY(hipGetDevice(&hp.device));
+    if (hp.device >= ndev) return fail(PF_EINVAL, "device %d does not exist", hp.device);
+    DeviceGuard guard(hp.device);
+    if (!guard.ok) return fail(PF_EDEVICE, "cannot select device %d", hp.device);
+    DevPlan *dp = new DevPlan();
+    dp->device = hp.device;
+    int rc = PF_OK;
+#define UP(field, vec) \
+    if (!rc) rc = dupload(dp, &dp->field, hp.vec)
+    UP(yptr, yptr);
+    UP(ycol, ycol);
+    UP(cptr, cptr);
+    UP(clist, clist);
+    UP(bus4, bus4);
+    UP(bus2, bus2);
+    UP(shptr, shptr);
+    UP(shlist, shlist);
+    UP(ldptr, ldptr);
+    UP(ldlist, ldlist);
+    UP(gen4, gen4);
+    UP(gen2, gen2);
+    UP(genpv, genpv);
+    UP(br_f, br_f);
+    UP(br_t, br_t);
+    UP(params, params);
+    UP(pv_p, pv_p);
+    UP(shunt_g, shunt_g);
+    UP(shunt_b, shunt_b);
+#undef UP
+    std::vector<GridDev> gd(hp.grids.size());
+    for (size_t g = 0; g < hp.grids.size(); ++g)
+        gd[g] = GridDev{hp.grids[g].N, hp.grids[g].bus_off, hp.grids[g].xoff};
+    if (!rc) rc = dupload(dp, &dp->grids, gd);
+    if (!rc) rc = dalloc(dp, &dp->yG, size_t(hp.n_y));
+    if (!rc) rc = dalloc(dp, &dp->yB, size_t(hp.n_y));
+    if (!rc) rc = dalloc(dp, &dp->spec, size_t(hp.Nt));
+    if (hp.kind == KIND_BATCH) {
+        if (!rc) rc = dupload(dp, &dp->lscale, hp.load_scale_t);
+        if (!rc) rc = dupload(dp, &dp->pscale, hp.pv_scale_t);
+        if (!rc) rc = dupload(dp, &dp->outage, hp.outage);
+        if (!rc && !hp.outage.empty()) rc = dalloc(dp, &dp->otab, size_t(hp.Bt) * 8);
+        if (!rc) rc = dupload(dp, &dp->order_nat, hp.order_natural);
+        if (!rc) rc = dupload(dp, &dp->order_bfs, hp.order_bfs);
+    } else {
+        if (!rc) rc = dalloc(dp, &dp->nw_F, size_t(hp.n));
+        if (!rc) rc = dalloc(dp, &dp->nw_J, size_t(hp.nnz));
+        if (!rc) rc = dalloc(dp, &dp->nw_dx, size_t(hp.n));
+    }
+    if (!rc) rc = dev_upload_tiles(hp, dp);
+    if (!rc) rc = build_coeffs(hp, dp, nullptr);
+    if (!rc) {
+        hipError_t e = hipDeviceSynchronize();
+        if (e != hipSuccess) rc = fail(PF_EDEVICE, "setup kernels: %s", hipGetErrorString(e));
+    }
+    if (rc) {
+        dev_destroy(dp);
+        return rc;
+    }
+    *out = dp;
+    return PF_OK;
+}
+
+int dev_set_params(HostPlan &hp, DevPlan *dp, const double *params_dev, void *stream) {
+    DeviceGuard g(dp->device);
+    if (!g.ok) return fail(PF_EDEVICE, "cannot select device %d", dp->device);
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    const size_t np = size_t(hp.n_params());
+    if (np) HIP_TRY(hipMemcpyAsync(dp->params, params_dev, np * sizeof(double),
+                                   hipMemcpyDeviceToDevice, st));
+    return build_coeffs(hp, dp, st);
+}
+
+static void wave_grid(int64_t units, const pf_schedule &s, int &blocks, int &units_per_wave) {
+    const int wpb = s.waves_per_block;
+    if (units <= 0) {
+        blocks = 0;
+        units_per_wave = 0;
+        return;
+    }
+    if (s.grid_blocks > 0) {
+        const int64_t waves = int64_t(s.grid_blocks) * wpb;
+        units_per_wave = int((units + waves - 1) / waves);
+    } else {
+        units_per_wave = 1;
+    }
+    const int64_t waves_needed = (units + units_per_wave - 1) / units_per_wave;
+    blocks = int((waves_needed + wpb - 1) / wpb);
+}
+
+int dev_eval_single(HostPlan &hp, DevPlan *dp, const double *x, double *F, double *J,
+                    void *stream) {
+    DeviceGuard g(dp->device);
+    if (!g.ok) return fail(PF_EDEVICE, "cannot select device %d", dp->device);
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    const pf_schedule &s = hp.sched;
+    int blocks, tpw;
+    wave_grid(hp.n_tiles(), s, blocks, tpw);
+    if (blocks == 0) return PF_OK;
+    const int threads = 64 * s.waves_per_block;
+    const size_t shm = size_t(s.waves_per_block) * 6 * 64 * sizeof(double);
+    const int remap = s.xcd_remap == 1 ? 1 : 0;
+#define LAUNCH(WF, WJ)                                                                       \
+    hipLaunchKernelGGL((k_eval_single<WF, WJ>), dim3(blocks), dim3(threads), shm, st,       \
+                       dp->tiles, hp.n_tiles(), tpw, remap, dp->grids, dp->bus4, dp->bus2,  \
+                       dp->spec, dp->ycol, dp->yG, dp->yB, dp->gen4, dp->gen2, x, F, J)
+    if (F && J)
+        LAUNCH(true, true);
+    else if (F)
+        LAUNCH(true, false);
+    else
+        LAUNCH(false, true);
+#undef LAUNCH
+    HIP_TRY(hipGetLastError());
+    return PF_OK;
+}
+
+int dev_eval_batch(HostPlan &hp, DevPlan *dp, const double *X, double *F, double *J,
+                   void *stream) {
+    DeviceGuard g(dp->device);
+    if (!g.ok) return fail(PF_EDEVICE, "cannot select device %d", dp->device);
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    const pf_schedule &s = hp.sched;
+    const int N = hp.Nt;
+    const int I = hp.n_inst;
+    const int TB = s.batch_buses;
+    const int n_btiles = (N + TB - 1) / TB;
+    const int n_chunks = (I + 63) / 64;
+    const int64_t n_items = int64_t(n_btiles) * n_chunks;
+    if (n_items > (int64_t(1) << 31) - 1) return fail(PF_EINVAL, "batch work list too long");
+    int blocks, ipw;
+    wave_grid(n_items, s, blocks, ipw);
+    if (blocks == 0) return PF_OK;
+    const int threads = 64 * s.waves_per_block;
+    const int remap = s.xcd_remap == 1 ? 1 : 0;
+    const int32_t *order = s.batch_order == 2 ? dp->order_bfs : dp->order_nat;
+    const bool scen = dp->lscale || dp->pscale;
+    const bool outg = dp->outage != nullptr;
+    const double *lp = dp->params + 5LL * hp.Bt;
+    const double *lq = lp + hp.NLt;
+#define LAUNCH(WF, WJ, SC, OG)                                                                 \
+    hipLaunchKernelGGL((k_eval_batch<WF, WJ, SC, OG>), dim3(blocks), dim3(threads), 0, st, N, \
+                       I, n_btiles, TB, int(n_items), ipw, remap, order, dp->bus4, dp->bus2,  \
+                       dp->spec, dp->ycol, dp->yG, dp->yB, dp->gen4, dp->gen2, dp->genpv,     \
+                       dp->ldptr, dp->ldlist, lp, lq, dp->pv_p, dp->lscale, dp->pscale,       \
+                       dp->outage, dp->br_f, dp->br_t, dp->otab, X, F, J)
+#define LAUNCH_OV(WF, WJ)              \
+    if (scen && outg)                  \
+        LAUNCH(WF, WJ, true, true);    \
+    else if (scen)                     \
+        LAUNCH(WF, WJ, true, false);   \
+    else if (outg)                     \
+        LAUNCH(WF, WJ, false, true);   \
+    else                               \
+        LAUNCH(WF, WJ, false, false)
+    if (F && J) {
+        LAUNCH_OV(true, true);
+    } else if (F) {
+        LAUNCH_OV(true, false);
+    } else {
+        LAUNCH_OV(false, true);
+    }
+#undef LAUNCH_OV
+#undef LAUNCH
+    HIP_TRY(hipGetLastError());
+    return PF_OK;
+}
+
+int dev_newton(HostPlan &hp, DevPlan *dp, double *x, const pf_newton_opts *opts,
+               pf_linsolve_fn solve, void *user, pf_newton_report *rep) {
+    DeviceGuard g(dp->device);
+    if (!g.ok) return fail(PF_EDEVICE, "cannot select device %d", dp->device);
+    const double tol = (opts && opts->tol > 0) ? opts->tol : 1e-10;
+    const int max_iter = (opts && opts->max_iter > 0) ? opts->max_iter : 10;
+    const int64_t n = hp.n, nnz = hp.nnz;
+    std::vector<double> Fh(static_cast<size_t>(n)), Jh(static_cast<size_t>(nnz)),
+        dxh(static_cast<size_t>(n));
+    pf_newton_report r{};
+    hipEvent_t ev0, ev1;
+    HIP_TRY(hipEventCreate(&ev0));
+    HIP_TRY(hipEventCreate(&ev1));
+    auto t_start = std::chrono::steady_clock::now();
+    int rc = PF_ENOCONV;
+    for (int it = 0;; ++it) {
+        HIP_TRY(hipEventRecord(ev0, nullptr));
+        int e = dev_eval_single(hp, dp, x, dp->nw_F, dp->nw_J, nullptr);
+        if (e) {
+            rc = e;
+            break;
+        }
+        HIP_TRY(hipEventRecord(ev1, nullptr));
+        HIP_TRY(hipMemcpy(Fh.data(), dp->nw_F, size_t(n) * sizeof(double), hipMemcpyDeviceToHost));
+        float ms = 0.f;
+        HIP_TRY(hipEventElapsedTime(&ms, ev0, ev1));
+        r.t_eval_s += ms * 1e-3;
+        double nf = 0.0;
+        for (int64_t q = 0; q < n; ++q) {
+            const double v = std::fabs(Fh[q]);
+            if (!(v <= nf)) nf = v;  // NaN propagates
+        }
+        if (it < 65) r.norm[it] = nf;
+        if (nf < tol) {
+            r.converged = 1;
+            rc = PF_OK;
+            break;
+        }
+        if (it >= max_iter) {
+            rc = fail(PF_ENOCONV, "Newton did not converge in %d iterations (|F| = %g)",
+                      max_iter, nf);
+            break;
+        }
+        HIP_TRY(hipMemcpy(Jh.data(), dp->nw_J, size_t(nnz) * sizeof(double),
+                          hipMemcpyDeviceToHost));
+        auto ts = std::chrono::steady_clock::now();
+        const int sr = solve(user, n, hp.rowptr.data(), hp.colidx.data(), Jh.data(), Fh.data(),
+                             dxh.data());
+        r.t_solve_s += std::chrono::duration<double>(std::chrono::steady_clock::now() - ts).count();
+        if (sr != 0) {
+            rc = fail(PF_ESOLVE, "linear solve callback returned %d at iteration %d", sr, it);
+            break;
+        }
+        HIP_TRY(hipMemcpy(dp->nw_dx, dxh.data(), size_t(n) * sizeof(double),
+                          hipMemcpyHostToDevice));
+        hipLaunchKernelGGL(k_newton_update, dim3(unsigned((n + 255) / 256)), dim3(256), 0, nullptr,
+                           n, x, dp->nw_dx);
+        HIP_TRY(hipGetLastError());
+        r.iterations = it + 1;
+    }
+    HIP_TRY(hipDeviceSynchronize());
+    r.t_total_s = std::chrono::duration<double>(std::chrono::steady_clock::now() - t_start).count();
+    (void)hipEventDestroy(ev0);
+    (void)hipEventDestroy(ev1);
+    if (rep) *rep = r;
+    return rc;
+}
+
+int dev_vjp(HostPlan &, DevPlan *, const double *, const double *, int32_t, double *, double *,
+            void *) {
+    return fail(PF_EINVAL, "pf_vjp is not available in this build");
+}
+
+int dev_autotune(HostPlan &, DevPlan *, const double *, double *, double *, int32_t, void *,
+                 pf_schedule *) {
+    return fail(PF_EINVAL, "pf_autotune is not available in this build");
+}
+
+}  // namespace pf

@@ -1,0 +1,128 @@
+// Internal structures of libpf: the host-side plan built at setup, and the
+// device mirror that the kernels read.  Not part of the public ABI.
+#pragma once
+
+#include <cstdint>
+#include <string>
+#include <vector>
+
+#include "pf.h"
+
+namespace pf {
+
+// Status helpers ------------------------------------------------------------
+int fail(int code, const char *fmt, ...);
+void clear_error();
+
+// Contribution kinds of a branch to an admittance-row entry (from/to ends).
+enum ContribKind : int32_t { K_FF = 0, K_FT = 1, K_TF = 2, K_TT = 3 };
+
+// Row-start flag kept in bit 31 of an admittance column index.
+constexpr int32_t kRowStart = int32_t(0x80000000u);
+constexpr int32_t kColMask = 0x7fffffff;
+
+// One grid inside a plan (a plan has one grid unless it is multi-grid).
+struct GridInfo {
+    int32_t N, NPV, NS, NG;      // buses, PV units, slacks, generators
+    int32_t NB, NL, NSH;         // branches, loads, shunts
+    int64_t xoff;                // first variable / equation of the grid
+    int64_t joff;                // first Jacobian value of the grid
+    int64_t nnz;                 // Jacobian values of the grid
+    int32_t bus_off, br_off, load_off, pv_off, gen_off, shunt_off;
+    int32_t y_off, n_y;          // admittance entries
+};
+
+// Grid descriptor read by the single-instance kernel (one per grid).
+struct GridDev {
+    int32_t N;
+    int32_t bus_off;
+    int64_t xoff;
+};
+
+enum PlanKind : int32_t { KIND_SINGLE = 0, KIND_BATCH = 1, KIND_MULTI = 2 };
+
+struct HostPlan {
+    int32_t kind = KIND_SINGLE;
+    int32_t n_inst = 1;
+    bool host_only = false;
+    int device = 0;
+    std::vector<GridInfo> grids;
+
+    // totals over grids
+    int64_t n = 0, nnz = 0;
+    int32_t Nt = 0, Bt = 0, NLt = 0, NPVt = 0, NSt = 0, NGt = 0, NSHt = 0;
+    int64_t n_y = 0;
+
+    // fixed Jacobian pattern (concatenated, absolute indices)
+    std::vector<int32_t> rowptr, colidx;
+
+    // admittance rows over all buses (global bus numbering); columns are the
+    // local bus index inside the grid, with kRowStart on each row's first entry
+    std::vector<int32_t> yptr;      // Nt + 1 (global entry index)
+    std::vector<int32_t> ycol;      // n_y
+    std::vector<int32_t> cptr;      // n_y + 1: contributions per entry
+    std::vector<int32_t> clist;     // (global branch id << 2) | kind
+
+    // per bus
+    std::vector<int32_t> bus4;      // Nt * 4: ystart, yend, jP (row P start), jQ
+    std::vector<int32_t> bus2;      // Nt * 2: diagonal position, generator (global) or -1
+    std::vector<int32_t> shptr, shlist;  // shunts per bus (global shunt ids)
+    std::vector<int32_t> ldptr, ldlist;  // loads per bus (global load ids)
+
+    // per generator (global: grid by grid, PV units then slacks)
+    std::vector<int32_t> gen4;      // NGt * 4: Q_g var (= V row), V-row slot,
+                                    //          P_s var (= theta row) or -1, theta-row slot
+    std::vector<double> gen2;       // NGt * 2: V setpoint, theta setpoint
+    std::vector<int32_t> genpv;     // NGt: PV unit id (global) or -1 for a slack
+
+    // per branch / device (global ids)
+    std::vector<int32_t> br_f, br_t;   // global bus ids
+    std::vector<int32_t> br_on;        // 1 in service
+    std::vector<double> params;        // [r][x][b][tap][shift_deg][load_p][load_q]
+    std::vector<double> pv_p;          // NPVt
+    std::vector<double> shunt_g, shunt_b;
+    std::vector<int32_t> load_bus;     // global bus id
+
+    // single-instance schedule
+    pf_schedule sched{};
+    std::vector<int32_t> tiles;        // ntiles * 4: e0, e1, b0 (global bus), grid
+
+    // batched overlay
+    std::vector<double> load_scale_t;  // [NL][I] or empty
+    std::vector<double> pv_scale_t;    // [NPV][I] or empty
+    std::vector<int32_t> outage;       // [I] or empty
+    std::vector<int32_t> order_natural, order_bfs;   // bus processing orders
+
+    int64_t n_params() const { return 5LL * Bt + 2LL * NLt; }
+    int32_t n_tiles() const { return int32_t(tiles.size() / 4); }
+};
+
+// Host setup (pf_setup.cpp)
+int build_host_plan(const pf_network *nets, int32_t n_grids, HostPlan &hp);
+int attach_batch(const pf_batch_spec *spec, HostPlan &hp);
+int normalise_schedule(const HostPlan &hp, const pf_schedule *in, pf_schedule &out);
+void build_tiles(HostPlan &hp);
+
+// Device side (pf_device.hip)
+struct DevPlan;
+int dev_create(HostPlan &hp, DevPlan **out);
+void dev_destroy(DevPlan *dp);
+int dev_upload_tiles(HostPlan &hp, DevPlan *dp);
+int dev_set_params(HostPlan &hp, DevPlan *dp, const double *params_dev, void *stream);
+int dev_eval_single(HostPlan &hp, DevPlan *dp, const double *x, double *F,
+                    double *J, void *stream);
+int dev_eval_batch(HostPlan &hp, DevPlan *dp, const double *X, double *F,
+                   double *J, void *stream);
+int dev_vjp(HostPlan &hp, DevPlan *dp, const double *x, const double *W,
+            int32_t k, double *gx, double *gp, void *stream);
+int dev_newton(HostPlan &hp, DevPlan *dp, double *x, const pf_newton_opts *opts,
+               pf_linsolve_fn solve, void *user, pf_newton_report *rep);
+int dev_autotune(HostPlan &hp, DevPlan *dp, const double *x, double *F,
+                 double *J, int32_t reps, void *stream, pf_schedule *best);
+
+}  // namespace pf
+
+struct pf_plan {
+    pf::HostPlan host;
+    pf::DevPlan *dev = nullptr;
+};
