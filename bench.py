@@ -184,12 +184,34 @@ def run_c1(args, torch, dev):
     return out
 
 
+def run_copy(args, torch, dev):
+    """Calibration: a plain device-to-device copy of known size (torch's
+    copy kernel), the reference for HBM byte counters and achievable
+    bandwidth."""
+    nbytes = args.copy_mib << 20
+    a = torch.empty(nbytes // 8, dtype=torch.float64, device=dev).fill_(1.0)
+    b = torch.empty_like(a)
+    for _ in range(args.warmup):
+        b.copy_(a)
+    with Timer(torch) as t:
+        for _ in range(args.steps):
+            b.copy_(a)
+    ms = t.ms / args.steps
+    gbs = 2 * nbytes / (ms * 1e-3) / 1e9
+    return {"metric": "device copy bandwidth (read + write)", "value": gbs, "unit": "GB/s",
+            "n_gpus": 1, "steps": args.steps, "warmup": args.warmup, "ms_per_step": ms,
+            "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f64",
+            "data": "synthetic", "config": {"workload": f"copy of {args.copy_mib} MiB",
+                                            "bytes_read": nbytes, "bytes_written": nbytes}}
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--config", default="c1", choices=["c1"])
+    ap.add_argument("--config", default="c1", choices=["c1", "copy"])
+    ap.add_argument("--copy-mib", type=int, default=1024)
     ap.add_argument("--states", type=int, default=1000)
     ap.add_argument("--autotune", action="store_true")
     ap.add_argument("--no-plain", action="store_true")
@@ -206,7 +228,7 @@ def main():
         print("bench.py: no GPU available", file=sys.stderr)
         sys.exit(1)
     dev = torch.device("cuda", 0)
-    out = run_c1(args, torch, dev)
+    out = {"c1": run_c1, "copy": run_copy}[args.config](args, torch, dev)
     print(json.dumps(out), flush=True)
 
 

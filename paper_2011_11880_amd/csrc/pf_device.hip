@@ -36,6 +36,10 @@ namespace pf {
             return fail(PF_EDEVICE, "%s failed: %s", #expr, hipGetErrorString(e_)); \
     } while (0)
 
+// Trailing padding of the admittance-entry arrays (>= the batched kernel's
+// entry group size minus one).
+constexpr int kEntryPad = 8;
+
 struct DevPlan {
     int device = 0;
     std::vector<void *> allocs;
@@ -228,6 +232,11 @@ __device__ __forceinline__ int xcd_logical_block(int bid, int nb) {
     return x * q + min(x, r) + (bid >> 3);
 }
 
+// Output stores are streamed (non-temporal): the residual and Jacobian
+// values are written once and never re-read by the kernel, and keeping them
+// out of L2 leaves it to the state gathers, which neighbouring buses reuse.
+__device__ __forceinline__ void st(double *p, double v) { __builtin_nontemporal_store(v, p); }
+
 __device__ __forceinline__ void wave_sync() {
     __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
     __builtin_amdgcn_wave_barrier();
@@ -251,7 +260,9 @@ k_eval_single(const int4 *__restrict__ tiles, int ntiles, int tiles_per_wave, in
               double *__restrict__ F, double *__restrict__ J) {
     extern __shared__ double lds[];
     const int lane = threadIdx.x & 63;
-    const int wv = threadIdx.x >> 6;
+    // wave index is uniform across the wavefront; telling the compiler so
+    // keeps the tile walk and every row-structure load in scalar registers
+    const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     const int wpb = blockDim.x >> 6;
     double *L = lds + wv * (6 * 64);
     const int lb = remap ? xcd_logical_block(blockIdx.x, gridDim.x) : blockIdx.x;
@@ -291,10 +302,10 @@ k_eval_single(const int4 *__restrict__ tiles, int ntiles, int tiles_per_wave, in
                 entry_eval(diag, yG[e], yB[e], thi, vi, thj, vj, c, o);
                 if (WJ && !diag) {
                     const int p = e - bi.x, Lr = bi.y - bi.x;
-                    J[bi.z + p] = o[0];
-                    J[bi.z + Lr + p] = o[1];
-                    J[bi.w + p] = o[2];
-                    J[bi.w + Lr + p] = o[3];
+                    st(&J[bi.z + p], o[0]);
+                    st(&J[bi.z + Lr + p], o[1]);
+                    st(&J[bi.w + p], o[2]);
+                    st(&J[bi.w + Lr + p], o[3]);
                 }
             }
 #pragma unroll
@@ -331,29 +342,29 @@ k_eval_single(const int4 *__restrict__ tiles, int ntiles, int tiles_per_wave, in
                     const int4 g4 = gen4[g];
                     const double2 gs = gen2[g];
                     fq = fq - x[g4.x];
-                    if (WF) F[g4.x] = vi - gs.x;
+                    if (WF) st(&F[g4.x], vi - gs.x);
                     if (WJ) {
-                        J[bi.w + 2 * Lr] = -1.0;
-                        J[g4.y] = 1.0;
+                        st(&J[bi.w + 2 * Lr], -1.0);
+                        st(&J[g4.y], 1.0);
                     }
                     if (g4.z >= 0) {
                         fp = fp - x[g4.z];
-                        if (WF) F[g4.z] = thi - gs.y;
+                        if (WF) st(&F[g4.z], thi - gs.y);
                         if (WJ) {
-                            J[bi.z + 2 * Lr] = -1.0;
-                            J[g4.w] = 1.0;
+                            st(&J[bi.z + 2 * Lr], -1.0);
+                            st(&J[g4.w], 1.0);
                         }
                     }
                 }
                 if (WF) {
-                    F[gd.xoff + i] = fp;
-                    F[gd.xoff + gd.N + i] = fq;
+                    st(&F[gd.xoff + i], fp);
+                    st(&F[gd.xoff + gd.N + i], fq);
                 }
                 if (WJ) {
-                    J[bi.z + b2.x] = a[2];
-                    J[bi.z + Lr + b2.x] = a[3];
-                    J[bi.w + b2.x] = a[4];
-                    J[bi.w + Lr + b2.x] = a[5];
+                    st(&J[bi.z + b2.x], a[2]);
+                    st(&J[bi.z + Lr + b2.x], a[3]);
+                    st(&J[bi.w + b2.x], a[4]);
+                    st(&J[bi.w + Lr + b2.x], a[5]);
                 }
             }
             rows_seen += __popcll(smask);
@@ -386,7 +397,7 @@ k_eval_batch(int N, int I, int n_btiles, int TB, int n_items, int items_per_wave
              const double *__restrict__ otab, const double *__restrict__ X,
              double *__restrict__ F, double *__restrict__ J) {
     const int lane = threadIdx.x & 63;
-    const int wv = threadIdx.x >> 6;
+    const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     const int wpb = blockDim.x >> 6;
     const int lb = remap ? xcd_logical_block(blockIdx.x, gridDim.x) : blockIdx.x;
     const int lw = lb * wpb + wv;
@@ -414,50 +425,80 @@ k_eval_batch(int N, int I, int n_btiles, int TB, int n_items, int items_per_wave
         }
         const int q0 = bt * TB;
         const int q1 = min(N, q0 + TB);
+        // masked lanes read a valid duplicate address so loads need no masking
+        const size_t kk = size_t(valid ? k : I - 1);
+        // the next bus's row header and own state are fetched one bus ahead
+        int b_nx = order[q0];
+        int4 bi_nx = bus4[b_nx];
+        double thi_nx = X[size_t(b_nx) * SI + kk];
+        double vi_nx = X[size_t(N + b_nx) * SI + kk];
         for (int qq = q0; qq < q1; ++qq) {
-            const int b = order[qq];
-            const int4 bi = bus4[b];
-            const int Lr = bi.y - bi.x;
-            double thi = 0.0, vi = 0.0;
-            if (valid) {
-                thi = X[size_t(b) * SI + k];
-                vi = X[size_t(N + b) * SI + k];
+            const int b = b_nx;
+            const int4 bi = bi_nx;
+            const double thi = thi_nx, vi = vi_nx;
+            if (qq + 1 < q1) {
+                b_nx = order[qq + 1];
+                bi_nx = bus4[b_nx];
+                thi_nx = X[size_t(b_nx) * SI + kk];
+                vi_nx = X[size_t(N + b_nx) * SI + kk];
             }
+            const int Lr = bi.y - bi.x;
             double a[6] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
-            for (int e = bi.x; e < bi.y; ++e) {
-                const int j = ycol[e] & kColMask;
-                double G = yG[e], Bv = yB[e];
-                const bool diag = (j == b);
-                if (OUTG) {
-                    if (of == b) {
-                        if (diag) {
-                            G -= oy[0];
-                            Bv -= oy[1];
-                        } else if (j == ot) {
-                            G -= oy[2];
-                            Bv -= oy[3];
-                        }
-                    } else if (ot == b) {
-                        if (diag) {
-                            G -= oy[6];
-                            Bv -= oy[7];
-                        } else if (j == of) {
-                            G -= oy[4];
-                            Bv -= oy[5];
-                        }
+            // entries in groups of EU: all gathers of a group are issued
+            // before any of its arithmetic, so they are in flight together
+            constexpr int EU = 4;
+            for (int e0 = bi.x; e0 < bi.y; e0 += EU) {
+                int jj[EU];
+                double GG[EU], BB[EU], thj[EU], vj[EU];
+                // the entry arrays carry kEntryPad trailing entries (column 0,
+                // zero admittance), so a group may read past the last row
+#pragma unroll
+                for (int u = 0; u < EU; ++u) {
+                    jj[u] = ycol[e0 + u] & kColMask;
+                    GG[u] = yG[e0 + u];
+                    BB[u] = yB[e0 + u];
+                }
+#pragma unroll
+                for (int u = 0; u < EU; ++u) {
+                    if (e0 + u < bi.y) {
+                        thj[u] = X[size_t(jj[u]) * SI + kk];
+                        vj[u] = X[size_t(N + jj[u]) * SI + kk];
                     }
                 }
-                if (valid) {
-                    const double thj = X[size_t(j) * SI + k];
-                    const double vj = X[size_t(N + j) * SI + k];
+#pragma unroll
+                for (int u = 0; u < EU; ++u) {
+                    const int e = e0 + u;
+                    if (e >= bi.y) break;
+                    const int j = jj[u];
+                    double G = GG[u], Bv = BB[u];
+                    const bool diag = (j == b);
+                    if (OUTG) {
+                        if (of == b) {
+                            if (diag) {
+                                G -= oy[0];
+                                Bv -= oy[1];
+                            } else if (j == ot) {
+                                G -= oy[2];
+                                Bv -= oy[3];
+                            }
+                        } else if (ot == b) {
+                            if (diag) {
+                                G -= oy[6];
+                                Bv -= oy[7];
+                            } else if (j == of) {
+                                G -= oy[4];
+                                Bv -= oy[5];
+                            }
+                        }
+                    }
                     double c[6], o[4];
-                    entry_eval(diag, G, Bv, thi, vi, thj, vj, c, o);
-                    if (WJ && !diag) {
+                    entry_eval(diag, G, Bv, thi, vi, thj[u], vj[u], c, o);
+                    if (WJ && !diag && valid) {
                         const int p = e - bi.x;
-                        J[size_t(bi.z + p) * SI + k] = o[0];
-                        J[size_t(bi.z + Lr + p) * SI + k] = o[1];
-                        J[size_t(bi.w + p) * SI + k] = o[2];
-                        J[size_t(bi.w + Lr + p) * SI + k] = o[3];
+                        st(&J[size_t(bi.z + p) * SI + k], o[0]);
+                        st(&J[size_t(bi.z + Lr + p) * SI + k], o[1]);
+                        st(&J[size_t(bi.w + p) * SI + k], o[2]);
+                        st(&J[size_t(bi.w + Lr + p) * SI + k], o[3]);
                     }
 #pragma unroll
                     for (int q = 0; q < 6; ++q) a[q] += c[q];
@@ -494,29 +535,29 @@ k_eval_batch(int N, int I, int n_btiles, int TB, int n_items, int items_per_wave
                 const int4 g4 = gen4[g];
                 const double2 gs = gen2[g];
                 fq = fq - X[size_t(g4.x) * SI + k];
-                if (WF) F[size_t(g4.x) * SI + k] = vi - gs.x;
+                if (WF) st(&F[size_t(g4.x) * SI + k], vi - gs.x);
                 if (WJ) {
-                    J[size_t(bi.w + 2 * Lr) * SI + k] = -1.0;
-                    J[size_t(g4.y) * SI + k] = 1.0;
+                    st(&J[size_t(bi.w + 2 * Lr) * SI + k], -1.0);
+                    st(&J[size_t(g4.y) * SI + k], 1.0);
                 }
                 if (g4.z >= 0) {
                     fp = fp - X[size_t(g4.z) * SI + k];
-                    if (WF) F[size_t(g4.z) * SI + k] = thi - gs.y;
+                    if (WF) st(&F[size_t(g4.z) * SI + k], thi - gs.y);
                     if (WJ) {
-                        J[size_t(bi.z + 2 * Lr) * SI + k] = -1.0;
-                        J[size_t(g4.w) * SI + k] = 1.0;
+                        st(&J[size_t(bi.z + 2 * Lr) * SI + k], -1.0);
+                        st(&J[size_t(g4.w) * SI + k], 1.0);
                     }
                 }
             }
             if (WF) {
-                F[size_t(b) * SI + k] = fp;
-                F[size_t(N + b) * SI + k] = fq;
+                st(&F[size_t(b) * SI + k], fp);
+                st(&F[size_t(N + b) * SI + k], fq);
             }
             if (WJ) {
-                J[size_t(bi.z + b2.x) * SI + k] = a[2];
-                J[size_t(bi.z + Lr + b2.x) * SI + k] = a[3];
-                J[size_t(bi.w + b2.x) * SI + k] = a[4];
-                J[size_t(bi.w + Lr + b2.x) * SI + k] = a[5];
+                st(&J[size_t(bi.z + b2.x) * SI + k], a[2]);
+                st(&J[size_t(bi.z + Lr + b2.x) * SI + k], a[3]);
+                st(&J[size_t(bi.w + b2.x) * SI + k], a[4]);
+                st(&J[size_t(bi.w + Lr + b2.x) * SI + k], a[5]);
             }
         }
     }
@@ -607,7 +648,6 @@ int dev_create(HostPlan &hp, DevPlan **out) {
 #define UP(field, vec) \
     if (!rc) rc = dupload(dp, &dp->field, hp.vec)
     UP(yptr, yptr);
-    UP(ycol, ycol);
     UP(cptr, cptr);
     UP(clist, clist);
     UP(bus4, bus4);
@@ -630,8 +670,20 @@ int dev_create(HostPlan &hp, DevPlan **out) {
     for (size_t g = 0; g < hp.grids.size(); ++g)
         gd[g] = GridDev{hp.grids[g].N, hp.grids[g].bus_off, hp.grids[g].xoff};
     if (!rc) rc = dupload(dp, &dp->grids, gd);
-    if (!rc) rc = dalloc(dp, &dp->yG, size_t(hp.n_y));
-    if (!rc) rc = dalloc(dp, &dp->yB, size_t(hp.n_y));
+    // admittance entries with kEntryPad zeroed trailing entries
+    const size_t ny_pad = size_t(hp.n_y) + kEntryPad;
+    if (!rc) rc = dalloc(dp, &dp->ycol, ny_pad);
+    if (!rc) rc = dalloc(dp, &dp->yG, ny_pad);
+    if (!rc) rc = dalloc(dp, &dp->yB, ny_pad);
+    if (!rc) {
+        hipError_t e = hipMemset(dp->ycol, 0, ny_pad * sizeof(int32_t));
+        if (e == hipSuccess) e = hipMemset(dp->yG, 0, ny_pad * sizeof(double));
+        if (e == hipSuccess) e = hipMemset(dp->yB, 0, ny_pad * sizeof(double));
+        if (e == hipSuccess && hp.n_y)
+            e = hipMemcpy(dp->ycol, hp.ycol.data(), size_t(hp.n_y) * sizeof(int32_t),
+                          hipMemcpyHostToDevice);
+        if (e != hipSuccess) rc = fail(PF_EDEVICE, "entry upload: %s", hipGetErrorString(e));
+    }
     if (!rc) rc = dalloc(dp, &dp->spec, size_t(hp.Nt));
     if (hp.kind == KIND_BATCH) {
         if (!rc) rc = dupload(dp, &dp->lscale, hp.load_scale_t);
@@ -837,9 +889,94 @@ int dev_vjp(HostPlan &, DevPlan *, const double *, const double *, int32_t, doub
     return fail(PF_EINVAL, "pf_vjp is not available in this build");
 }
 
-int dev_autotune(HostPlan &, DevPlan *, const double *, double *, double *, int32_t, void *,
-                 pf_schedule *) {
-    return fail(PF_EINVAL, "pf_autotune is not available in this build");
+// Median time (ms) of `reps` launches of the plan's kernel under its
+// current schedule, each bracketed by its own pair of events.
+static int time_schedule(HostPlan &hp, DevPlan *dp, const double *x, double *F, double *J,
+                         int reps, hipStream_t st, float &ms_out) {
+    std::vector<hipEvent_t> ev(2 * size_t(reps));
+    for (auto &e : ev) HIP_TRY(hipEventCreate(&e));
+    int rc = PF_OK;
+    auto launch = [&]() {
+        return hp.kind == KIND_BATCH ? dev_eval_batch(hp, dp, x, F, J, st)
+                                     : dev_eval_single(hp, dp, x, F, J, st);
+    };
+    rc = launch();  // warm-up
+    for (int r = 0; r < reps && !rc; ++r) {
+        HIP_TRY(hipEventRecord(ev[2 * r], st));
+        rc = launch();
+        HIP_TRY(hipEventRecord(ev[2 * r + 1], st));
+    }
+    if (!rc) HIP_TRY(hipStreamSynchronize(st));
+    std::vector<float> t(reps, 0.f);
+    for (int r = 0; r < reps && !rc; ++r)
+        HIP_TRY(hipEventElapsedTime(&t[r], ev[2 * r], ev[2 * r + 1]));
+    for (auto &e : ev) (void)hipEventDestroy(e);
+    if (rc) return rc;
+    std::sort(t.begin(), t.end());
+    ms_out = t[reps / 2];
+    return PF_OK;
+}
+
+// Coordinate descent over the schedule space: starting from the current
+// schedule, each parameter in turn is set to the fastest of its candidate
+// values while the others stay fixed; two sweeps.  Every candidate gives
+// bit-identical results, so only time decides.
+int dev_autotune(HostPlan &hp, DevPlan *dp, const double *x, double *F, double *J, int32_t reps,
+                 void *stream, pf_schedule *best_out) {
+    DeviceGuard g(dp->device);
+    if (!g.ok) return fail(PF_EDEVICE, "cannot select device %d", dp->device);
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    const bool batch = hp.kind == KIND_BATCH;
+    struct Axis {
+        int32_t pf_schedule::*field;
+        std::vector<int32_t> values;
+    };
+    std::vector<Axis> axes;
+    if (batch) {
+        axes.push_back({&pf_schedule::batch_buses, {1, 2, 4, 8, 16, 32, 64}});
+        axes.push_back({&pf_schedule::batch_order, {1, 2}});
+    } else {
+        axes.push_back({&pf_schedule::tile_entries, {64, 128, 256, 512, 1024, 2048}});
+    }
+    axes.push_back({&pf_schedule::waves_per_block, {1, 2, 4, 8}});
+    axes.push_back({&pf_schedule::grid_blocks, {0, 256, 512, 1024, 2048, 4096}});
+    axes.push_back({&pf_schedule::xcd_remap, {1, 2}});
+
+    pf_schedule best = hp.sched;
+    auto apply = [&](const pf_schedule &s) -> int {
+        const bool retile = s.tile_entries != hp.sched.tile_entries;
+        hp.sched = s;
+        if (retile) {
+            build_tiles(hp);
+            return dev_upload_tiles(hp, dp);
+        }
+        return PF_OK;
+    };
+    float best_ms = 0.f;
+    int rc = apply(best);
+    if (!rc) rc = time_schedule(hp, dp, x, F, J, reps, st, best_ms);
+    for (int sweep = 0; sweep < 2 && !rc; ++sweep) {
+        for (const Axis &ax : axes) {
+            for (int32_t v : ax.values) {
+                if (best.*(ax.field) == v) continue;
+                pf_schedule cand = best;
+                cand.*(ax.field) = v;
+                float ms = 0.f;
+                rc = apply(cand);
+                if (!rc) rc = time_schedule(hp, dp, x, F, J, reps, st, ms);
+                if (rc) break;
+                if (ms < best_ms) {
+                    best_ms = ms;
+                    best = cand;
+                }
+            }
+            if (rc) break;
+        }
+    }
+    const int rc2 = apply(best);
+    if (!rc) rc = rc2;
+    if (!rc && best_out) *best_out = best;
+    return rc;
 }
 
 }  // namespace pf

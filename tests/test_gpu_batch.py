@@ -1,0 +1,183 @@
+"""GPU parity of the batched kernel (pf_eval_batch): random states as
+instances (bit-identical to the single-instance kernel), load/PV scenario
+overlays and N-1 outages (against the oracle on the modified network),
+ragged instance counts, schedule invariance, graph replay, and the
+10,000-bus x 1024-instance batch on sampled instances."""
+
+import numpy as np
+import pytest
+
+from paper_2011_11880_amd import synth
+from parity import check_close, check_jacobian
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+
+@pytest.fixture(scope="module")
+def cuda():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    return torch.device("cuda", 0)
+
+
+def _Plan():
+    from paper_2011_11880_amd.api import Plan
+    return Plan
+
+
+def _net():
+    net = synth.tiny_grid(4, n_bus=150, n_branch=210, n_pv=25, n_shunt=12)
+    return synth.with_parallel_branches(net, 8, 3)
+
+
+def _batch_eval(plan, Y, cuda):
+    X = torch.from_numpy(np.ascontiguousarray(Y.T)).to(cuda)
+    F, J = plan.eval_batch(X)
+    torch.cuda.synchronize()
+    return F.cpu().numpy(), J.cpu().numpy()
+
+
+def _instance_net(net, spec, k):
+    n = net.copy()
+    if spec.get("load_scale") is not None:
+        n.load_p = net.load_p * spec["load_scale"][k]
+        n.load_q = net.load_q * spec["load_scale"][k]
+    if spec.get("pv_scale") is not None:
+        n.pv_p = net.pv_p * spec["pv_scale"][k]
+    if spec.get("outage") is not None and spec["outage"][k] >= 0:
+        n = n.without_branch(int(spec["outage"][k]))
+    return n
+
+
+@pytest.mark.parametrize("n_inst", [1, 63, 64, 65, 130])
+def test_states_as_instances_bitwise_equal_single(cuda, n_inst):
+    Plan = _Plan()
+    net = _net()
+    Y = synth.random_states(net, n_inst, seed=n_inst)
+    bp = Plan(net, batch=dict(n_inst=n_inst))
+    Fb, Jb = _batch_eval(bp, Y, cuda)
+    sp = Plan(net)
+    for k in sorted({0, n_inst // 2, n_inst - 1}):
+        F, J = sp.eval(torch.from_numpy(Y[k]).to(cuda))
+        torch.cuda.synchronize()
+        assert np.array_equal(F.cpu().numpy(), Fb[:, k])
+        assert np.array_equal(J.cpu().numpy(), Jb[:, k])
+
+
+def test_scenarios_and_outages_vs_oracle(ora, cuda):
+    Plan = _Plan()
+    net = _net()
+    I = 48
+    ls, ps = synth.batch_scenarios(net, I, seed=5)
+    cand = synth.non_bridge_branches(net)
+    par = np.arange(net.n_branch - 8, net.n_branch)   # parallel branches
+    out = np.full(I, -1, np.int32)
+    out[16:] = np.concatenate([par[:4], cand[:I - 20]])[:I - 16]
+    ls[16:24] = 1.0
+    spec = dict(n_inst=I, load_scale=ls, pv_scale=ps, outage=out)
+    bp = Plan(net, batch=spec)
+    Y = synth.random_states(net, I, seed=6)
+    Fb, Jb = _batch_eval(bp, Y, cuda)
+    rp, ci = bp.pattern()
+    for k in range(I):
+        nk = _instance_net(net, spec, k)
+        Fo, So = ora.residual(nk, Y[k])
+        Jo, Ao = ora.jacobian(nk, Y[k])
+        check_close(Fb[:, k], Fo, So, f"inst {k} F")
+        check_jacobian(rp, ci, Jb[:, k], Jo, Ao, f"inst {k} J")
+
+
+def test_outage_slots_are_exact_zero(cuda):
+    """Taking out a branch with no parallel partner zeroes its eight
+    off-diagonal slots exactly."""
+    Plan = _Plan()
+    net = synth.tiny_grid(0)
+    e = int(synth.non_bridge_branches(net)[7])
+    f, t = int(net.br_from[e]), int(net.br_to[e])
+    bp = Plan(net, batch=dict(n_inst=2, outage=[-1, e]))
+    Y = synth.random_states(net, 2, seed=1)
+    Y[1] = Y[0]
+    _, Jb = _batch_eval(bp, Y, cuda)
+    rp, ci = bp.pattern()
+    N = net.n_bus
+    slots = []
+    for r, c in [(f, t), (f, N + t), (N + f, t), (N + f, N + t),
+                 (t, f), (t, N + f), (N + t, f), (N + t, N + f)]:
+        row = ci[rp[r]:rp[r + 1]]
+        slots.append(rp[r] + int(np.nonzero(row == c)[0][0]))
+    assert np.all(Jb[slots, 1] == 0.0)
+    assert np.all(Jb[slots, 0] != 0.0)
+
+
+def test_schedules_bitwise(cuda):
+    Plan = _Plan()
+    net = synth.grid_10k()
+    I = 100
+    ls, ps = synth.batch_scenarios(net, I, seed=2)
+    out = np.full(I, -1, np.int32)
+    out[::3] = synth.contingencies(net, len(out[::3]), seed=2)
+    bp = Plan(net, batch=dict(n_inst=I, load_scale=ls, pv_scale=ps, outage=out))
+    X = torch.from_numpy(np.ascontiguousarray(synth.random_states(net, I, seed=3).T)).to(cuda)
+    F0, J0 = bp.eval_batch(X)
+    for s in [dict(batch_buses=1, batch_order=1, waves_per_block=1, grid_blocks=0, xcd_remap=2),
+              dict(batch_buses=7, batch_order=2, waves_per_block=8, grid_blocks=5, xcd_remap=1),
+              dict(batch_buses=64, batch_order=1, waves_per_block=2, grid_blocks=1000, xcd_remap=1),
+              dict(batch_buses=3, batch_order=2, waves_per_block=4, grid_blocks=0, xcd_remap=1)]:
+        bp.schedule = dict(bp.schedule, **s)
+        F, J = bp.eval_batch(X)
+        torch.cuda.synchronize()
+        assert torch.equal(F, F0) and torch.equal(J, J0), s
+
+
+def test_graph_replay_matches_eager(cuda):
+    Plan = _Plan()
+    net = _net()
+    I = 70
+    bp = Plan(net, batch=dict(n_inst=I))
+    X = torch.from_numpy(np.ascontiguousarray(synth.random_states(net, I, seed=9).T)).to(cuda)
+    F0, J0 = bp.eval_batch(X)
+    F = torch.zeros_like(F0)
+    J = torch.zeros_like(J0)
+    torch.cuda.synchronize()
+    g = torch.cuda.CUDAGraph()
+    st = torch.cuda.Stream()
+    st.wait_stream(torch.cuda.current_stream())
+    with torch.cuda.stream(st):
+        with torch.cuda.graph(g, stream=st):
+            bp.eval_batch(X, F, J)
+    torch.cuda.synchronize()
+    for r in range(3):
+        F.zero_()
+        J.fill_(7.0)
+        torch.cuda.synchronize()
+        g.replay()
+        torch.cuda.synchronize()
+        assert torch.equal(F, F0) and torch.equal(J, J0), r
+        X.add_(0.0)   # eager work between replays
+
+
+def test_10k_1024_scenarios_and_contingencies(ora, cuda):
+    """512 load/renewable scenarios and 512 N-1 contingencies of the
+    10,000-bus grid in one launch; sampled instances against the oracle."""
+    Plan = _Plan()
+    net = synth.grid_10k()
+    I = 1024
+    ls = np.ones((I, net.n_load))
+    ps = np.ones((I, net.n_pv))
+    a, b = synth.batch_scenarios(net, 512, seed=2001)
+    ls[:512], ps[:512] = a, b
+    out = np.full(I, -1, np.int32)
+    out[512:] = synth.contingencies(net, 512, seed=2002)
+    spec = dict(n_inst=I, load_scale=ls, pv_scale=ps, outage=out)
+    bp = Plan(net, batch=spec)
+    Y = synth.random_states(net, I, seed=2003)
+    Fb, Jb = _batch_eval(bp, Y, cuda)
+    rp, ci = bp.pattern()
+    for k in [0, 1, 300, 511, 512, 513, 777, 1023]:
+        nk = _instance_net(net, spec, k)
+        Fo, So = ora.residual(nk, Y[k])
+        Jo, Ao = ora.jacobian(nk, Y[k])
+        check_close(Fb[:, k], Fo, So, f"inst {k} F")
+        check_jacobian(rp, ci, Jb[:, k], Jo, Ao, f"inst {k} J")
