@@ -112,6 +112,10 @@ typedef struct pf_network {
  *                   from the lowest-numbered bus
  *   xcd_remap       1: give each of the 8 XCDs a contiguous range of work
  *                   items (L2 locality), 2: round-robin (hardware order)
+ *   batch_layout    batched kernel work order: 1 instance-chunk major (all
+ *                   buses of a 64-instance chunk, then the next chunk),
+ *                   2 bus major (every chunk of a bus run back to back, so
+ *                   whole instance rows of the outputs are written together)
  */
 typedef struct pf_schedule {
     int32_t tile_entries;
@@ -120,6 +124,7 @@ typedef struct pf_schedule {
     int32_t batch_buses;
     int32_t batch_order;
     int32_t xcd_remap;
+    int32_t batch_layout;
 } pf_schedule;
 
 /*

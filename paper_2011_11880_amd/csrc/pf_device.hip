@@ -383,7 +383,8 @@ k_eval_single(const int4 *__restrict__ tiles, int ntiles, int tiles_per_wave, in
 // joins -- exactly cancelling them when no parallel branch remains.
 template <bool WF, bool WJ, bool SCEN, bool OUTG>
 __global__ void __launch_bounds__(512)
-k_eval_batch(int N, int I, int n_btiles, int TB, int n_items, int items_per_wave, int remap,
+k_eval_batch(int N, int I, int n_btiles, int n_chunks, int TB, int n_items, int items_per_wave,
+             int remap, int bus_major,
              const int32_t *__restrict__ order, const int4 *__restrict__ bus4,
              const int2 *__restrict__ bus2, const double2 *__restrict__ spec,
              const int32_t *__restrict__ ycol, const double *__restrict__ yG,
@@ -408,8 +409,14 @@ k_eval_batch(int N, int I, int n_btiles, int TB, int n_items, int items_per_wave
     int of = -1, ot = -1;
     double oy[8] = {0, 0, 0, 0, 0, 0, 0, 0};
     for (int w = w_begin; w < w_end; ++w) {
-        const int ch = w / n_btiles;
-        const int bt = w - ch * n_btiles;
+        int ch, bt;
+        if (bus_major) {
+            bt = w / n_chunks;
+            ch = w - bt * n_chunks;
+        } else {
+            ch = w / n_btiles;
+            bt = w - ch * n_btiles;
+        }
         const int k = ch * 64 + lane;
         const bool valid = k < I;
         if (OUTG && ch != cur_chunk) {
@@ -790,7 +797,8 @@ int dev_eval_batch(HostPlan &hp, DevPlan *dp, const double *X, double *F, double
     const double *lq = lp + hp.NLt;
 #define LAUNCH(WF, WJ, SC, OG)                                                                 \
     hipLaunchKernelGGL((k_eval_batch<WF, WJ, SC, OG>), dim3(blocks), dim3(threads), 0, st, N, \
-                       I, n_btiles, TB, int(n_items), ipw, remap, order, dp->bus4, dp->bus2,  \
+                       I, n_btiles, n_chunks, TB, int(n_items), ipw, remap,                   \
+                       s.batch_layout == 2 ? 1 : 0, order, dp->bus4, dp->bus2,                \
                        dp->spec, dp->ycol, dp->yG, dp->yB, dp->gen4, dp->gen2, dp->genpv,     \
                        dp->ldptr, dp->ldlist, lp, lq, dp->pv_p, dp->lscale, dp->pscale,       \
                        dp->outage, dp->br_f, dp->br_t, dp->otab, X, F, J)
@@ -935,6 +943,7 @@ int dev_autotune(HostPlan &hp, DevPlan *dp, const double *x, double *F, double *
     if (batch) {
         axes.push_back({&pf_schedule::batch_buses, {1, 2, 4, 8, 16, 32, 64}});
         axes.push_back({&pf_schedule::batch_order, {1, 2}});
+        axes.push_back({&pf_schedule::batch_layout, {1, 2}});
     } else {
         axes.push_back({&pf_schedule::tile_entries, {64, 128, 256, 512, 1024, 2048}});
     }
