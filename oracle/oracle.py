@@ -77,6 +77,8 @@ def _load(path):
     L.ora_jacobian.restype = ctypes.c_long
     L.ora_vjp_params.argtypes = [ctypes.POINTER(_Topo), ctypes.POINTER(_Data),
                                  _pd, _pd] + [_pd] * 7
+    L.ora_vjp_params_scale.argtypes = [ctypes.POINTER(_Topo), ctypes.POINTER(_Data),
+                                       _pd, _pd] + [_pd] * 5
     return L
 
 
@@ -213,6 +215,20 @@ def vjp(net, y, w, data=None):
                          _dp(out["br_tap"]), _dp(out["br_shift_deg"]),
                          _dp(out["load_p"]), _dp(out["load_q"]))
     return gx, out
+
+
+def vjp_params_scale(net, y, w, data=None):
+    """Per-parameter sum of |terms| behind vjp()'s parameter gradients (a
+    tolerance scale for comparisons under cancellation)."""
+    b = _Bound(net, data)
+    y = np.ascontiguousarray(y, dtype=np.float64)
+    w = np.ascontiguousarray(w, dtype=np.float64)
+    B = net.n_branch
+    out = {k: np.empty(B) for k in ("br_r", "br_x", "br_b", "br_tap", "br_shift_deg")}
+    lib().ora_vjp_params_scale(ctypes.byref(b.topo), ctypes.byref(b.data), _dp(y), _dp(w),
+                               _dp(out["br_r"]), _dp(out["br_x"]), _dp(out["br_b"]),
+                               _dp(out["br_tap"]), _dp(out["br_shift_deg"]))
+    return out
 
 
 def newton(net, y0, tol=1e-10, max_iter=10, data=None):

@@ -20,6 +20,7 @@
  *   ora_branch_flows  one branch's four terminal injections
  *   ora_jacobian      dF/dy as COO triplets, model by model
  *   ora_vjp_params    gradient of w.F with respect to branch and load data
+ *   ora_vjp_params_scale  sum of |terms| behind each of those gradients
  */
 #include <complex.h>
 #include <math.h>
@@ -298,5 +299,65 @@ void ora_vjp_params(const ora_topo *tp, const ora_data *dd, const double *y,
     for (e = 0; e < tp->n_load; ++e) {
         g_lp[e] = w[tp->load_bus[e]];
         g_lq[e] = w[N + tp->load_bus[e]];
+    }
+}
+
+/*
+ * Tolerance scale for ora_vjp_params: the same chain of products with every
+ * factor replaced by its absolute value, i.e. the sum of |terms| that the
+ * gradient of each parameter adds up.  Used only to judge rounding
+ * differences under cancellation; it is not part of the reference values.
+ */
+void ora_vjp_params_scale(const ora_topo *tp, const ora_data *dd, const double *y,
+                          const double *w, double *s_r, double *s_x, double *s_b,
+                          double *s_tap, double *s_shift)
+{
+    const int N = tp->n_bus;
+    const double *th = y, *V = y + N;
+    int e;
+    for (e = 0; e < tp->n_branch; ++e) {
+        int f, t;
+        double r, x, bc, tap, phi, D, D2, g, b, delta, C, S, u, t2, vf, vt;
+        double A1, B1, A2, B2, wpf, wqf, wpt, wqt, sg, sb;
+        s_r[e] = s_x[e] = s_b[e] = s_tap[e] = s_shift[e] = 0.0;
+        if (tp->br_status && !tp->br_status[e]) continue;
+        f = tp->br_from[e];
+        t = tp->br_to[e];
+        r = dd->br_r[e];
+        x = dd->br_x[e];
+        bc = dd->br_b[e];
+        tap = dd->br_tap[e];
+        phi = dd->br_shift_deg[e] * (ORA_PI / 180.0);
+        D = r * r + x * x;
+        D2 = D * D;
+        g = r / D;
+        b = -x / D;
+        vf = V[f];
+        vt = V[t];
+        delta = th[f] - th[t] - phi;
+        C = cos(delta);
+        S = sin(delta);
+        u = vf * vt / tap;
+        t2 = tap * tap;
+        A1 = fabs(u * (g * C + b * S));
+        B1 = fabs(u * (g * S - b * C));
+        A2 = fabs(u * (g * C - b * S));
+        B2 = fabs(u * (g * S + b * C));
+        wpf = fabs(w[f]);
+        wqf = fabs(w[N + f]);
+        wpt = fabs(w[t]);
+        wqt = fabs(w[N + t]);
+        sg = wpf * (vf * vf / t2 + fabs(u * C)) + wqf * fabs(u * S) +
+             wpt * (vt * vt + fabs(u * C)) + wqt * fabs(u * S);
+        sb = wpf * fabs(u * S) + wqf * (vf * vf / t2 + fabs(u * C)) +
+             wpt * fabs(u * S) + wqt * (vt * vt + fabs(u * C));
+        s_r[e] = sg * fabs(x * x - r * r) / D2 + sb * fabs(2.0 * r * x) / D2 +
+                 (sg + sb) * (x * x + r * r) / D2;
+        s_x[e] = s_r[e];
+        s_b[e] = wqf * vf * vf / (2.0 * t2) + wqt * vt * vt / 2.0;
+        s_tap[e] = wpf * (2.0 * vf * vf * fabs(g) / (t2 * tap) + A1 / tap) +
+                   wqf * (2.0 * vf * vf * fabs(b + bc / 2.0) / (t2 * tap) + B1 / tap) +
+                   wpt * (A2 / tap) + wqt * (B2 / tap);
+        s_shift[e] = (wpf * B1 + wqf * A1 + wpt * B2 + wqt * A2) * (ORA_PI / 180.0);
     }
 }

@@ -53,6 +53,16 @@ class _NetStruct:
             n_slack=len(self.keep["slack_bus"]), n_shunt=len(self.keep["shunt_bus"]), **kw)
 
 
+def params_vector(nets):
+    """Host vector [r, x, b, tap, shift_deg, load_p, load_q] of one network,
+    or of several concatenated in grid order (the layout of pf_set_params)."""
+    if not isinstance(nets, (list, tuple)):
+        nets = [nets]
+    cat = np.concatenate
+    return cat([cat([_f64(getattr(n, k)) for n in nets])
+                for k in ("br_r", "br_x", "br_b", "br_tap", "br_shift_deg", "load_p", "load_q")])
+
+
 def _opts(host_only=False, device=None, schedule=None):
     o = capi.pf_setup_opts()
     o.host_only = 1 if host_only else 0

@@ -51,7 +51,9 @@ struct DevPlan {
     int4 *gen4 = nullptr;
     double2 *gen2 = nullptr;
     int32_t *genpv = nullptr;
-    int32_t *br_f = nullptr, *br_t = nullptr;
+    int32_t *br_f = nullptr, *br_t = nullptr, *br_on = nullptr, *load_bus = nullptr;
+    int2 *busx = nullptr;
+    int32_t *ytr = nullptr;
     GridDev *grids = nullptr;
     int4 *tiles = nullptr;
     int32_t ntiles_alloc = 0;
@@ -578,6 +580,297 @@ __global__ void __launch_bounds__(256) k_newton_update(int64_t n, double *__rest
 }
 
 // ---------------------------------------------------------------------------
+// adjoint (vector-Jacobian products)
+// ---------------------------------------------------------------------------
+
+// Entries (or branches) per adjoint work tile and cotangent group of the
+// second phase (gathers of a group are issued together).
+constexpr int kVjpGroup = 8;
+
+// State part of the adjoint, gx = J(x)^T W, one wavefront per (tile of whole
+// admittance rows, 64-cotangent chunk).  Column a of J collects, for every
+// entry (a, c) of row a, the entry's share of the diagonal sums of rows P_a
+// and Q_a and the off-diagonal values J[P_c, .a], J[Q_c, .a] of the
+// transpose-partner entry (c, a).  Phase 1 (lane = entry) evaluates these
+// eight state-only coefficients once per entry into LDS; phase 2 (lane =
+// cotangent) walks the entries in row order, folding them against the W rows
+// of P_a, Q_a, P_c, Q_c, and writes column a when its row ends.
+__global__ void __launch_bounds__(256)
+k_vjp_state(const int4 *__restrict__ tiles, int ntiles, int n_kchunks,
+            const GridDev *__restrict__ grids, const int2 *__restrict__ bus2,
+            const int32_t *__restrict__ ycol, const int32_t *__restrict__ ytr,
+            const double *__restrict__ yG, const double *__restrict__ yB,
+            const int4 *__restrict__ gen4, const double *__restrict__ x,
+            const double *__restrict__ W, int K, double *__restrict__ gx) {
+    __shared__ double sc[4][8][64];
+    __shared__ int sp[4][64];
+    const int lane = threadIdx.x & 63;
+    const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    const int wid = blockIdx.x * 4 + wv;
+    if (wid >= ntiles * n_kchunks) return;
+    const int t = wid / n_kchunks;
+    const int kc = wid - t * n_kchunks;
+    const int k = kc * 64 + lane;
+    const bool kvalid = k < K;
+    const size_t kk = size_t(kvalid ? k : K - 1);
+    const size_t SK = size_t(K);
+    double(*C)[64] = sc[wv];
+    int *PC = sp[wv];
+    const int4 td = tiles[t];
+    const int e0 = td.x, e1 = td.y, b0 = td.z;
+    const GridDev gd = grids[td.w];
+    const double *xt = x + gd.xoff;
+    const double *xv = xt + gd.N;
+    const uint64_t le = (lane == 63) ? ~0ull : ((2ull << lane) - 1ull);
+    int rows_seen = 0;
+    // open row (phase 2 state, uniform except the per-lane accumulators)
+    int row_bus = -1;
+    double wPa = 0.0, wQa = 0.0, accT = 0.0, accV = 0.0;
+    auto flush = [&](int b) {
+        const int ia = b - gd.bus_off;
+        const int2 b2 = bus2[b];
+        double gt = accT, gv = accV;
+        if (b2.y >= 0) {
+            const int4 g4 = gen4[b2.y];
+            gv = gv + W[size_t(g4.x) * SK + kk];   // V-control row: +1 at (V row, V_a)
+            if (kvalid) st(&gx[size_t(g4.x) * SK + k], -wQa);   // Q_g column: -1 in row Q_a
+            if (g4.z >= 0) {
+                gt = gt + W[size_t(g4.z) * SK + kk];   // angle row: +1 at (theta row, theta_a)
+                if (kvalid) st(&gx[size_t(g4.z) * SK + k], -wPa);   // P_s column
+            }
+        }
+        if (kvalid) {
+            st(&gx[size_t(gd.xoff + ia) * SK + k], gt);
+            st(&gx[size_t(gd.xoff + gd.N + ia) * SK + k], gv);
+        }
+    };
+    for (int c0 = e0; c0 < e1; c0 += 64) {
+        const int nvalid = min(64, e1 - c0);
+        // ---- phase 1: one entry per lane
+        uint64_t smask;
+        {
+            const bool valid = lane < nvalid;
+            const int e = c0 + lane;
+            const int raw = valid ? ycol[e] : 0;
+            const bool start = raw < 0;
+            const int ic = raw & kColMask;
+            smask = __ballot(start);
+            const int r = rows_seen + __popcll(smask & le) - 1;
+            const int ia = b0 + r - gd.bus_off;
+            double cf[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+            int partner = -1;
+            if (valid) {
+                const double tha = xt[ia], va = xv[ia];
+                const double G = yG[e], B = yB[e];
+                if (ic == ia) {
+                    cf[2] = 2.0 * va * G;      // dP_a/dV_a (diagonal term)
+                    cf[3] = -(2.0 * va * B);   // dQ_a/dV_a
+                } else {
+                    const double thc = xt[ic], vc = xv[ic];
+                    const int et = ytr[e];
+                    const double Gp = yG[et], Bp = yB[et];
+                    double s, co;
+                    sincos(tha - thc, &s, &co);
+                    const double t1 = fma(G, co, B * s);
+                    const double t2 = fma(G, s, -(B * co));
+                    const double t1p = fma(Gp, co, -(Bp * s));
+                    const double t2p = -fma(Gp, s, Bp * co);
+                    const double vv = va * vc;
+                    cf[0] = -(vv * t2);   // dP_a/dth_a share   (x W[P_a])
+                    cf[1] = vv * t1;      // dQ_a/dth_a share   (x W[Q_a])
+                    cf[2] = vc * t1;      // dP_a/dV_a share
+                    cf[3] = vc * t2;      // dQ_a/dV_a share
+                    cf[4] = vv * t2p;     // dP_c/dth_a         (x W[P_c])
+                    cf[5] = -(vv * t1p);  // dQ_c/dth_a         (x W[Q_c])
+                    cf[6] = vc * t1p;     // dP_c/dV_a
+                    cf[7] = vc * t2p;     // dQ_c/dV_a
+                    partner = ic;
+                }
+            }
+#pragma unroll
+            for (int q = 0; q < 8; ++q) C[q][lane] = cf[q];
+            PC[lane] = partner;
+        }
+        wave_sync();
+        // ---- phase 2: one cotangent per lane, entries in order; the W rows
+        // of a group's partners are gathered together before the group's
+        // arithmetic
+        for (int q0 = 0; q0 < nvalid; q0 += kVjpGroup) {
+            double wPc[kVjpGroup], wQc[kVjpGroup];
+#pragma unroll
+            for (int u = 0; u < kVjpGroup; ++u) {
+                const int q = q0 + u;
+                wPc[u] = 0.0;
+                wQc[u] = 0.0;
+                if (q < nvalid) {
+                    const int icp = PC[q];
+                    if (icp >= 0) {
+                        wPc[u] = W[size_t(gd.xoff + icp) * SK + kk];
+                        wQc[u] = W[size_t(gd.xoff + gd.N + icp) * SK + kk];
+                    }
+                }
+            }
+#pragma unroll
+            for (int u = 0; u < kVjpGroup; ++u) {
+                const int q = q0 + u;
+                if (q >= nvalid) break;
+                if ((smask >> q) & 1ull) {   // a row starts here
+                    if (row_bus >= 0) flush(row_bus);
+                    row_bus = b0 + rows_seen;
+                    ++rows_seen;
+                    const int ia = row_bus - gd.bus_off;
+                    wPa = W[size_t(gd.xoff + ia) * SK + kk];
+                    wQa = W[size_t(gd.xoff + gd.N + ia) * SK + kk];
+                    accT = 0.0;
+                    accV = 0.0;
+                }
+                accT = accT + C[0][q] * wPa + C[1][q] * wQa + C[4][q] * wPc[u] + C[5][q] * wQc[u];
+                accV = accV + C[2][q] * wPa + C[3][q] * wQa + C[6][q] * wPc[u] + C[7][q] * wQc[u];
+            }
+        }
+        wave_sync();
+    }
+    if (row_bus >= 0) flush(row_bus);
+}
+
+// Parameter part of the adjoint.  Phase 1 (lane = branch): the partials of
+// the branch's four terminal injections P_f, Q_f, P_t, Q_t with respect to
+// r, x, line charging b, tap and phase shift (per degree), from the pi-model
+// with series g + jb = 1/(r + jx):
+//   dg/dr = db/dx = (x^2 - r^2)/D^2, dg/dx = -2rx/D^2, db/dr = 2rx/D^2
+//   (D = r^2 + x^2), chained through the flows' g and b partials; the charging
+//   enters Q only; the tap partials follow from the 1/t^2 and 1/t factors;
+//   a phase shift acts as -theta_f.  Phase 2 (lane = cotangent): each
+//   gradient row is the four partials dotted with the W rows of the branch's
+//   bus equations.  Out-of-service branches get zero rows.  Load rows are
+//   copies of the W rows of their bus (dF_p/dP_load = dF_q/dQ_load = 1).
+__global__ void __launch_bounds__(256)
+k_vjp_params(int B, int NL, int n_btiles, int n_ltiles, int n_kchunks,
+             const int32_t *__restrict__ br_f, const int32_t *__restrict__ br_t,
+             const int32_t *__restrict__ br_on, const int2 *__restrict__ busx,
+             const int32_t *__restrict__ load_bus, const double *__restrict__ P,
+             const double *__restrict__ x, const double *__restrict__ W, int K,
+             double *__restrict__ gp) {
+    __shared__ double sd[4][20][64];
+    __shared__ int4 sr[4][64];
+    const int lane = threadIdx.x & 63;
+    const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    const int wid = blockIdx.x * 4 + wv;
+    if (wid >= (n_btiles + n_ltiles) * n_kchunks) return;
+    const int t = wid / n_kchunks;
+    const int kc = wid - t * n_kchunks;
+    const int k = kc * 64 + lane;
+    const bool kvalid = k < K;
+    const size_t kk = size_t(kvalid ? k : K - 1);
+    const size_t SK = size_t(K);
+    const int64_t B64 = B;
+    if (t >= n_btiles) {   // loads
+        const int l0 = (t - n_btiles) * 64;
+        const int nl = min(64, NL - l0);
+        for (int q0 = 0; q0 < nl; q0 += kVjpGroup) {
+            double wp[kVjpGroup], wq[kVjpGroup];
+#pragma unroll
+            for (int u = 0; u < kVjpGroup; ++u) {
+                if (q0 + u < nl) {
+                    const int2 bx = busx[load_bus[l0 + q0 + u]];
+                    wp[u] = W[size_t(bx.x) * SK + kk];
+                    wq[u] = W[size_t(bx.y) * SK + kk];
+                }
+            }
+#pragma unroll
+            for (int u = 0; u < kVjpGroup; ++u) {
+                const int l = l0 + q0 + u;
+                if (q0 + u < nl && kvalid) {
+                    st(&gp[size_t(5 * B64 + l) * SK + k], wp[u]);
+                    st(&gp[size_t(5 * B64 + NL + l) * SK + k], wq[u]);
+                }
+            }
+        }
+        return;
+    }
+    double(*D)[64] = sd[wv];
+    int4 *R = sr[wv];
+    const int e0 = t * 64;
+    const int nb = min(64, B - e0);
+    {   // phase 1
+        const int e = e0 + lane;
+        double d[20];
+#pragma unroll
+        for (int q = 0; q < 20; ++q) d[q] = 0.0;
+        int4 rows = make_int4(0, 0, 0, 0);
+        if (lane < nb && br_on[e]) {
+            const int2 xf = busx[br_f[e]], xt = busx[br_t[e]];
+            rows = make_int4(xf.x, xf.y, xt.x, xt.y);
+            const double r = P[e], xx = P[B64 + e], bc = P[2 * B64 + e];
+            const double tap = P[3 * B64 + e], sh = P[4 * B64 + e];
+            const double thf = x[xf.x], vf = x[xf.y], tht = x[xt.x], vt = x[xt.y];
+            const double Dd = r * r + xx * xx;
+            const double D2 = Dd * Dd;
+            const double g = r / Dd;
+            const double b = -xx / Dd;
+            const double delta = thf - tht - sh * (M_PI / 180.0);
+            double S, Cc;
+            sincos(delta, &S, &Cc);
+            const double u = vf * vt / tap;
+            const double t2 = tap * tap;
+            const double A1 = u * (g * Cc + b * S), B1 = u * (g * S - b * Cc);
+            const double A2 = u * (g * Cc - b * S), B2 = u * (g * S + b * Cc);
+            const double vf2 = vf * vf, vt2 = vt * vt;
+            // flow partials w.r.t. series g and b: [Pf, Qf, Pt, Qt]
+            const double dg[4] = {vf2 / t2 - u * Cc, -(u * S), vt2 - u * Cc, u * S};
+            const double db[4] = {-(u * S), -(vf2 / t2) + u * Cc, u * S, -vt2 + u * Cc};
+            const double dg_dr = (xx * xx - r * r) / D2, dg_dx = -(2.0 * r * xx) / D2;
+            const double db_dr = (2.0 * r * xx) / D2, db_dx = (xx * xx - r * r) / D2;
+            const double deg = -(M_PI / 180.0);
+#pragma unroll
+            for (int f = 0; f < 4; ++f) {
+                d[f] = dg[f] * dg_dr + db[f] * db_dr;
+                d[4 + f] = dg[f] * dg_dx + db[f] * db_dx;
+            }
+            d[9] = -(vf2 / (2.0 * t2));
+            d[11] = -(vt2 / 2.0);
+            d[12] = -(2.0 * vf2 * g) / (t2 * tap) + A1 / tap;
+            d[13] = (2.0 * vf2 * (b + 0.5 * bc)) / (t2 * tap) + B1 / tap;
+            d[14] = A2 / tap;
+            d[15] = -(B2 / tap);
+            d[16] = deg * B1;
+            d[17] = deg * (-A1);
+            d[18] = deg * B2;
+            d[19] = deg * A2;
+        }
+#pragma unroll
+        for (int q = 0; q < 20; ++q) D[q][lane] = d[q];
+        R[lane] = rows;
+    }
+    wave_sync();
+    for (int q0 = 0; q0 < nb; q0 += kVjpGroup) {   // phase 2
+        double w[kVjpGroup][4];
+#pragma unroll
+        for (int u = 0; u < kVjpGroup; ++u) {
+            if (q0 + u < nb) {
+                const int4 rr = R[q0 + u];
+                w[u][0] = W[size_t(rr.x) * SK + kk];
+                w[u][1] = W[size_t(rr.y) * SK + kk];
+                w[u][2] = W[size_t(rr.z) * SK + kk];
+                w[u][3] = W[size_t(rr.w) * SK + kk];
+            }
+        }
+#pragma unroll
+        for (int u = 0; u < kVjpGroup; ++u) {
+            const int q = q0 + u;
+            if (q >= nb) break;
+            const int e = e0 + q;
+#pragma unroll
+            for (int pr = 0; pr < 5; ++pr) {
+                const double v = D[4 * pr][q] * w[u][0] + D[4 * pr + 1][q] * w[u][1] +
+                                 D[4 * pr + 2][q] * w[u][2] + D[4 * pr + 3][q] * w[u][3];
+                if (kvalid) st(&gp[size_t(pr * B64 + e) * SK + k], v);
+            }
+        }
+    }
+}
+
+// ---------------------------------------------------------------------------
 // host side
 // ---------------------------------------------------------------------------
 
@@ -668,6 +961,10 @@ int dev_create(HostPlan &hp, DevPlan **out) {
     UP(genpv, genpv);
     UP(br_f, br_f);
     UP(br_t, br_t);
+    UP(br_on, br_on);
+    UP(load_bus, load_bus);
+    UP(busx, busx);
+    UP(ytr, ytr);
     UP(params, params);
     UP(pv_p, pv_p);
     UP(shunt_g, shunt_g);
@@ -892,10 +1189,6 @@ int dev_newton(HostPlan &hp, DevPlan *dp, double *x, const pf_newton_opts *opts,
     return rc;
 }
 
-int dev_vjp(HostPlan &, DevPlan *, const double *, const double *, int32_t, double *, double *,
-            void *) {
-    return fail(PF_EINVAL, "pf_vjp is not available in this build");
-}
 
 // Median time (ms) of `reps` launches of the plan's kernel under its
 // current schedule, each bracketed by its own pair of events.
@@ -929,6 +1222,32 @@ static int time_schedule(HostPlan &hp, DevPlan *dp, const double *x, double *F, 
 // schedule, each parameter in turn is set to the fastest of its candidate
 // values while the others stay fixed; two sweeps.  Every candidate gives
 // bit-identical results, so only time decides.
+int dev_vjp(HostPlan &hp, DevPlan *dp, const double *x, const double *W, int32_t K, double *gx,
+            double *gp, void *stream) {
+    DeviceGuard g(dp->device);
+    if (!g.ok) return fail(PF_EDEVICE, "cannot select device %d", dp->device);
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    const int n_kchunks = (K + 63) / 64;
+    if (gx && hp.n_tiles() > 0) {
+        const int64_t waves = int64_t(hp.n_tiles()) * n_kchunks;
+        hipLaunchKernelGGL(k_vjp_state, dim3(unsigned((waves + 3) / 4)), dim3(256), 0, st,
+                           dp->tiles, hp.n_tiles(), n_kchunks, dp->grids, dp->bus2, dp->ycol,
+                           dp->ytr, dp->yG, dp->yB, dp->gen4, x, W, int(K), gx);
+        HIP_TRY(hipGetLastError());
+    }
+    if (gp) {
+        const int nbt = (hp.Bt + 63) / 64, nlt = (hp.NLt + 63) / 64;
+        const int64_t waves = int64_t(nbt + nlt) * n_kchunks;
+        if (waves > 0) {
+            hipLaunchKernelGGL(k_vjp_params, dim3(unsigned((waves + 3) / 4)), dim3(256), 0, st,
+                               hp.Bt, hp.NLt, nbt, nlt, n_kchunks, dp->br_f, dp->br_t, dp->br_on,
+                               dp->busx, dp->load_bus, dp->params, x, W, int(K), gp);
+            HIP_TRY(hipGetLastError());
+        }
+    }
+    return PF_OK;
+}
+
 int dev_autotune(HostPlan &hp, DevPlan *dp, const double *x, double *F, double *J, int32_t reps,
                  void *stream, pf_schedule *best_out) {
     DeviceGuard g(dp->device);

@@ -66,6 +66,8 @@ struct HostPlan {
     // per bus
     std::vector<int32_t> bus4;      // Nt * 4: ystart, yend, jP (row P start), jQ
     std::vector<int32_t> bus2;      // Nt * 2: diagonal position, generator (global) or -1
+    std::vector<int32_t> busx;      // Nt * 2: theta and V variable (= P and Q row) index
+    std::vector<int32_t> ytr;       // n_y: entry (j, i) of row j for entry (i, j), -1 on the diagonal
     std::vector<int32_t> shptr, shlist;  // shunts per bus (global shunt ids)
     std::vector<int32_t> ldptr, ldlist;  // loads per bus (global load ids)
 

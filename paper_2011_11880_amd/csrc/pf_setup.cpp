@@ -135,6 +135,8 @@ int build_host_plan(const pf_network *nets, int32_t n_grids, HostPlan &hp) {
     hp.rowptr.assign(1, 0);
     hp.bus4.clear();
     hp.bus2.clear();
+    hp.busx.clear();
+    hp.ytr.clear();
     hp.ycol.clear();
     hp.colidx.clear();
     hp.cptr.assign(1, 0);
@@ -271,6 +273,22 @@ int build_host_plan(const pf_network *nets, int32_t n_grids, HostPlan &hp) {
             hp.bus4.push_back(int32_t(joff + rp[N + i]));
             hp.bus2.push_back(pd);
             hp.bus2.push_back(gen_at[i] >= 0 ? gen_off + gen_at[i] : -1);
+            hp.busx.push_back(int32_t(xoff + i));
+            hp.busx.push_back(int32_t(xoff + N + i));
+        }
+        // transpose partner of every off-diagonal entry (the pattern is
+        // structurally symmetric)
+        for (int i = 0; i < N; ++i) {
+            for (int q = 0; q < rl[i]; ++q) {
+                const int32_t c = rowcols[rs[i] + q];
+                if (c == i) {
+                    hp.ytr.push_back(-1);
+                    continue;
+                }
+                auto b0 = rowcols.begin() + rs[c], b1 = b0 + rl[c];
+                const int32_t pos = int32_t(std::lower_bound(b0, b1, i) - rowcols.begin());
+                hp.ytr.push_back(y_off + pos);
+            }
         }
 
         // contributions of each in-service branch to the four entries it
