@@ -71,6 +71,44 @@ class Timer:
         self.ms = self.a.elapsed_time(self.b)
 
 
+def time_ms(torch, fn, reps=10, warmup=2):
+    """Median time of fn() over reps runs, each bracketed by events on the
+    current stream (libpf launches on torch's current stream)."""
+    for _ in range(warmup):
+        fn()
+    ts = []
+    for _ in range(reps):
+        a = torch.cuda.Event(enable_timing=True)
+        b = torch.cuda.Event(enable_timing=True)
+        a.record()
+        fn()
+        b.record()
+        torch.cuda.synchronize()
+        ts.append(a.elapsed_time(b))
+    ts.sort()
+    return ts[len(ts) // 2]
+
+
+def kernel_source_hash():
+    from paper_2011_11880_amd.build import kernel_source_hash as h
+    return h()
+
+
+def measured_traffic(name, launch_units):
+    """HBM bytes per launch of the dominant kernel from the committed
+    rocprofv3 counter summary, if it was taken on the current kernel source."""
+    path = os.path.join(ROOT, "profiles", name)
+    if not os.path.exists(path):
+        return None
+    with open(path) as fh:
+        d = json.load(fh)
+    if d.get("kernel_source_sha256_16") != kernel_source_hash():
+        return None
+    if d.get("launch_units") != launch_units:
+        return None
+    return d.get("hbm_bytes_per_launch")
+
+
 def cpu_baseline(net, states, seconds=12.0, max_states=200):
     """The CPU oracle (plain C + scipy triplet assembly) on a bounded sample."""
     from oracle import oracle as O
@@ -172,8 +210,10 @@ def run_c1(args, torch, dev):
                    "states": S, "variant": "batched (states as instances of one launch)"},
         "roofline": {"bound": "hbm", "kernel": "k_eval_batch",
                      "achieved": head["gbs"], "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": head["hbm_frac"], "traffic": None,
-                     "bytes_per_launch": head["launch_bytes"]},
+                     "frac": head["hbm_frac"],
+                     "traffic": measured_traffic("k_eval_batch_70k_x1000_traffic.json", S),
+                     "bytes_per_launch": head["launch_bytes"],
+                     "kernel_source_sha256_16": kernel_source_hash()},
         "variants": res,
         "paper_context": {"evals_per_s": 294, "note": "workflow 5 (serial + SIMD), 0.6 ms "
                           "residual + 2.8 ms Jacobian on a 6-core Xeon W-2133, real 70k grid"},
@@ -181,7 +221,110 @@ def run_c1(args, torch, dev):
     if not args.no_cpu:
         log("[bench] cpu baseline")
         out["cpu_baseline"] = cpu_baseline(net, Y, seconds=args.cpu_seconds)
+    if not args.no_others:
+        out["others"] = {}
+        for name, fn in (("scenarios_10k_x1024", run_c2), ("uneven_256_grids", run_c3),
+                         ("adjoint_70k_k64", run_c4)):
+            log(f"[bench] {name}")
+            out["others"][name] = fn(args, torch, dev, net70k=net,
+                                     plain_us=res.get("plain", {}).get("us_per_eval"))
+            log(f"[bench] {name}", json.dumps(out["others"][name]))
     return out
+
+
+def run_c2(args, torch, dev, **kw):
+    """10,000-bus grid, 1024 instances in one launch: 512 load/renewable
+    scenarios and 512 N-1 contingencies, against the plain single-instance
+    kernel on the same grid."""
+    from paper_2011_11880_amd import synth
+    from paper_2011_11880_amd.api import Plan
+    net = synth.grid_10k()
+    I = 1024
+    ls = np.ones((I, net.n_load))
+    ps = np.ones((I, net.n_pv))
+    a, b = synth.batch_scenarios(net, 512, seed=2001)
+    ls[:512], ps[:512] = a, b
+    out = np.full(I, -1, np.int32)
+    out[512:] = synth.contingencies(net, 512, seed=2002)
+    bp = Plan(net, batch=dict(n_inst=I, load_scale=ls, pv_scale=ps, outage=out), device=0)
+    Y = synth.random_states(net, I, seed=2003)
+    X = torch.from_numpy(np.ascontiguousarray(Y.T)).to(dev)
+    F = torch.empty((bp.n, I), dtype=torch.float64, device=dev)
+    J = torch.empty((bp.nnz, I), dtype=torch.float64, device=dev)
+    if args.autotune:
+        bp.autotune(X, F, J, reps=3)
+    ms = time_ms(torch, lambda: bp.eval_batch(X, F, J))
+    nb = I * (per_eval_bytes(bp.n, bp.nnz) + 8 * (net.n_load + net.n_pv) + 4) + \
+        statics_bytes(bp.info)
+    pp = Plan(net, device=0)
+    Xs = torch.from_numpy(Y[:64]).to(dev)
+    Fs = torch.empty((64, pp.n), dtype=torch.float64, device=dev)
+    Js = torch.empty((64, pp.nnz), dtype=torch.float64, device=dev)
+    if args.autotune:
+        pp.autotune(Xs[0], Fs[0], Js[0], reps=20)
+
+    def plain64():
+        for s in range(64):
+            pp.eval(Xs[s], Fs[s], Js[s])
+    g = torch.cuda.CUDAGraph()
+    st = torch.cuda.Stream()
+    st.wait_stream(torch.cuda.current_stream())
+    plain64()
+    torch.cuda.synchronize()
+    with torch.cuda.stream(st):
+        with torch.cuda.graph(g, stream=st):
+            plain64()
+    torch.cuda.synchronize()
+    ms_p = time_ms(torch, g.replay) / 64
+    return {"grid": "10,000 buses, 12,500 branches", "instances": I,
+            "batched_ms": ms, "batched_evals_per_s": I / (ms * 1e-3),
+            "batched_gbs": nb / (ms * 1e-3) / 1e9,
+            "batched_hbm_frac": nb / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS,
+            "plain_us_per_eval": ms_p * 1e3, "plain_evals_per_s": 1e3 / ms_p,
+            "batched_over_plain": (I / ms) / (1.0 / ms_p), "schedule": bp.schedule}
+
+
+def run_c3(args, torch, dev, **kw):
+    """256 grids with bus counts log-uniform in [500, 20000], one launch."""
+    from paper_2011_11880_amd import synth
+    from paper_2011_11880_amd.api import Plan
+    nets = synth.uneven_grids(256, seed=3000)
+    mp = Plan.multi(nets, device=0)
+    xs = np.concatenate([synth.random_states(n, seed=g) for g, n in enumerate(nets)])
+    x = torch.from_numpy(xs).to(dev)
+    F = torch.empty(mp.n, dtype=torch.float64, device=dev)
+    J = torch.empty(mp.nnz, dtype=torch.float64, device=dev)
+    best = mp.autotune(x, F, J, reps=5)
+    ms = time_ms(torch, lambda: mp.eval(x, F, J))
+    nb = per_eval_bytes(mp.n, mp.nnz) + statics_bytes(mp.info)
+    return {"grids": 256, "buses": int(sum(n.n_bus for n in nets)), "n": mp.n, "nnz": mp.nnz,
+            "ms": ms, "grid_evals_per_s": 256 / (ms * 1e-3), "gbs": nb / (ms * 1e-3) / 1e9,
+            "hbm_frac": nb / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS, "autotuned_schedule": best}
+
+
+def run_c4(args, torch, dev, net70k=None, plain_us=None, **kw):
+    """Adjoint on the 70,000-bus grid for 64 cotangents (state and parameter
+    gradients), against one forward residual + Jacobian evaluation."""
+    from paper_2011_11880_amd import synth
+    from paper_2011_11880_amd.api import Plan
+    net = net70k if net70k is not None else synth.grid_70k()
+    p = Plan(net, device=0)
+    K = 64
+    x = torch.from_numpy(synth.random_states(net, seed=4000)).to(dev)
+    W = torch.randn((p.n, K), dtype=torch.float64, device=dev,
+                    generator=torch.Generator(device=dev).manual_seed(4001))
+    gx = torch.empty((p.n, K), dtype=torch.float64, device=dev)
+    gp = torch.empty((p.n_params, K), dtype=torch.float64, device=dev)
+    ms = time_ms(torch, lambda: p.vjp(x, W, gx, gp))
+    F = torch.empty(p.n, dtype=torch.float64, device=dev)
+    J = torch.empty(p.nnz, dtype=torch.float64, device=dev)
+    p.autotune(x, F, J, reps=20)
+    ms_f = time_ms(torch, lambda: p.eval(x, F, J), reps=50)
+    nb = K * (8 * p.n * 2 + 8 * p.n_params) + 8 * p.n + statics_bytes(p.info) + \
+        64 * net.n_branch
+    return {"cotangents": K, "vjp_ms": ms, "forward_us": ms_f * 1e3,
+            "vjp_over_forward": ms / ms_f, "vjp_per_cotangent_over_forward": ms / ms_f / K,
+            "gbs": nb / (ms * 1e-3) / 1e9, "hbm_frac": nb / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS}
 
 
 def run_copy(args, torch, dev):
@@ -216,6 +359,8 @@ def main():
     ap.add_argument("--autotune", action="store_true")
     ap.add_argument("--no-plain", action="store_true")
     ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--no-others", action="store_true",
+                    help="skip the scenario-batch, uneven-grid and adjoint summaries")
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
     args = ap.parse_args()
     if args.gpus != 1:

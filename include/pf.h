@@ -105,8 +105,10 @@ typedef struct pf_network {
  *   tile_entries    single-instance kernel: admittance entries per wavefront
  *                   tile (multiple of 64; rows are never split)
  *   waves_per_block wavefronts per workgroup, 1..8
- *   grid_blocks     persistent grid size in workgroups (0 = one tile range
- *                   per wavefront, sized to the work)
+ *   grid_blocks     persistent grid size in workgroups, each wavefront
+ *                   walking a contiguous range of work; -1 = no persistence
+ *                   (one tile / work item per wavefront, grid sized to the
+ *                   work); 0 = library default
  *   batch_buses     batched kernel: buses per work item
  *   batch_order     batched kernel bus order: 1 natural, 2 breadth-first
  *                   from the lowest-numbered bus

@@ -64,6 +64,17 @@ def build(verbose: bool = False) -> str:
     return LIB
 
 
+def kernel_source_hash() -> str:
+    """Short hash of the device sources (ties counter summaries to the
+    kernel they were taken on)."""
+    import hashlib
+    h = hashlib.sha256()
+    for f in ("pf_device.hip", "pf_internal.hpp"):
+        with open(os.path.join(CSRC, f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
 def clean():
     shutil.rmtree(BUILD_DIR, ignore_errors=True)
 

@@ -238,6 +238,9 @@ __device__ __forceinline__ int xcd_logical_block(int bid, int nb) {
 // values are written once and never re-read by the kernel, and keeping them
 // out of L2 leaves it to the state gathers, which neighbouring buses reuse.
 __device__ __forceinline__ void st(double *p, double v) { __builtin_nontemporal_store(v, p); }
+// Scattered 8-byte output stores (single-instance kernel) stay cached so that
+// L2 can merge them into whole lines before they are written back.
+__device__ __forceinline__ void stc(double *p, double v) { *p = v; }
 
 __device__ __forceinline__ void wave_sync() {
     __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
@@ -280,34 +283,49 @@ k_eval_single(const int4 *__restrict__ tiles, int ntiles, int tiles_per_wave, in
         const double *xv = xt + gd.N;
         double cy[6] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
         int rows_seen = 0;
+        // entry data of the first chunk; later chunks are fetched one chunk
+        // ahead, while the current one computes
+        int raw_n = lane < e1 - e0 ? ycol[e0 + lane] : 0;
+        double G_n = lane < e1 - e0 ? yG[e0 + lane] : 0.0;
+        double B_n = lane < e1 - e0 ? yB[e0 + lane] : 0.0;
         for (int c0 = e0; c0 < e1; c0 += 64) {
             const int nvalid = min(64, e1 - c0);
             const bool valid = lane < nvalid;
             const int e = c0 + lane;
-            const int raw = valid ? ycol[e] : 0;
+            const int raw = raw_n;
+            const double Ge = G_n, Be = B_n;
             const bool start = raw < 0;
             const int j = raw & kColMask;
             const uint64_t smask = __ballot(start);
             const int r = rows_seen + __popcll(smask & le) - 1;
-            const int b = b0 + r;
+            // lanes past the tile end read a valid duplicate (the tile's
+            // first bus) so every per-bus load is issued at once, unmasked
+            const int b = valid ? b0 + r : b0;
             const int i = b - gd.bus_off;
+            const int4 bi = bus4[b];
+            const int2 b2 = bus2[b];
+            const double2 sp = spec[b];
+            const double thi = xt[i], vi = xv[i];
+            const double thj = xt[j], vj = xv[j];
+            const bool more = c0 + 64 < e1;
+            if (more) {
+                const int en = c0 + 64 + lane;
+                const bool vn = en < e1;
+                raw_n = vn ? ycol[en] : 0;
+                G_n = vn ? yG[en] : 0.0;
+                B_n = vn ? yB[en] : 0.0;
+            }
             double c[6] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
-            int4 bi = make_int4(0, 0, 0, 0);
-            double thi = 0.0, vi = 0.0;
             if (valid) {
-                bi = bus4[b];
-                thi = xt[i];
-                vi = xv[i];
-                const double thj = xt[j], vj = xv[j];
                 double o[4];
                 const bool diag = (j == i);
-                entry_eval(diag, yG[e], yB[e], thi, vi, thj, vj, c, o);
+                entry_eval(diag, Ge, Be, thi, vi, thj, vj, c, o);
                 if (WJ && !diag) {
                     const int p = e - bi.x, Lr = bi.y - bi.x;
-                    st(&J[bi.z + p], o[0]);
-                    st(&J[bi.z + Lr + p], o[1]);
-                    st(&J[bi.w + p], o[2]);
-                    st(&J[bi.w + Lr + p], o[3]);
+                    stc(&J[bi.z + p], o[0]);
+                    stc(&J[bi.z + Lr + p], o[1]);
+                    stc(&J[bi.w + p], o[2]);
+                    stc(&J[bi.w + Lr + p], o[3]);
                 }
             }
 #pragma unroll
@@ -317,7 +335,9 @@ k_eval_single(const int4 *__restrict__ tiles, int ntiles, int tiles_per_wave, in
             const bool folder = start || (lane == 0 && carry_row);
             const uint64_t after = smask & ~le;
             const int next = after ? (__ffsll((unsigned long long)after) - 1) : nvalid;
-            const bool next_is_start = (c0 + nvalid >= e1) ? true : (ycol[c0 + nvalid] < 0);
+            // the entry after this chunk opens a row iff its column carries
+            // the row-start flag (that entry is lane 0 of the prefetch)
+            const bool next_is_start = more ? (__shfl(raw_n, 0) < 0) : true;
             const bool complete = (next < nvalid) || next_is_start;
             double a[6];
 #pragma unroll
@@ -334,8 +354,6 @@ k_eval_single(const int4 *__restrict__ tiles, int ntiles, int tiles_per_wave, in
                 for (int k = 0; k < 6; ++k) cy[k] = __shfl(a[k], lastf);
             }
             if (folder && complete) {
-                const int2 b2 = bus2[b];
-                const double2 sp = spec[b];
                 const int Lr = bi.y - bi.x;
                 double fp = a[0] + sp.x;
                 double fq = a[1] + sp.y;
@@ -344,29 +362,29 @@ k_eval_single(const int4 *__restrict__ tiles, int ntiles, int tiles_per_wave, in
                     const int4 g4 = gen4[g];
                     const double2 gs = gen2[g];
                     fq = fq - x[g4.x];
-                    if (WF) st(&F[g4.x], vi - gs.x);
+                    if (WF) stc(&F[g4.x], vi - gs.x);
                     if (WJ) {
-                        st(&J[bi.w + 2 * Lr], -1.0);
-                        st(&J[g4.y], 1.0);
+                        stc(&J[bi.w + 2 * Lr], -1.0);
+                        stc(&J[g4.y], 1.0);
                     }
                     if (g4.z >= 0) {
                         fp = fp - x[g4.z];
-                        if (WF) st(&F[g4.z], thi - gs.y);
+                        if (WF) stc(&F[g4.z], thi - gs.y);
                         if (WJ) {
-                            st(&J[bi.z + 2 * Lr], -1.0);
-                            st(&J[g4.w], 1.0);
+                            stc(&J[bi.z + 2 * Lr], -1.0);
+                            stc(&J[g4.w], 1.0);
                         }
                     }
                 }
                 if (WF) {
-                    st(&F[gd.xoff + i], fp);
-                    st(&F[gd.xoff + gd.N + i], fq);
+                    stc(&F[gd.xoff + i], fp);
+                    stc(&F[gd.xoff + gd.N + i], fq);
                 }
                 if (WJ) {
-                    st(&J[bi.z + b2.x], a[2]);
-                    st(&J[bi.z + Lr + b2.x], a[3]);
-                    st(&J[bi.w + b2.x], a[4]);
-                    st(&J[bi.w + Lr + b2.x], a[5]);
+                    stc(&J[bi.z + b2.x], a[2]);
+                    stc(&J[bi.z + Lr + b2.x], a[3]);
+                    stc(&J[bi.w + b2.x], a[4]);
+                    stc(&J[bi.w + Lr + b2.x], a[5]);
                 }
             }
             rows_seen += __popcll(smask);
@@ -1267,7 +1285,7 @@ int dev_autotune(HostPlan &hp, DevPlan *dp, const double *x, double *F, double *
         axes.push_back({&pf_schedule::tile_entries, {64, 128, 256, 512, 1024, 2048}});
     }
     axes.push_back({&pf_schedule::waves_per_block, {1, 2, 4, 8}});
-    axes.push_back({&pf_schedule::grid_blocks, {0, 256, 512, 1024, 2048, 4096}});
+    axes.push_back({&pf_schedule::grid_blocks, {-1, 256, 512, 1024, 2048, 4096}});
     axes.push_back({&pf_schedule::xcd_remap, {1, 2}});
 
     pf_schedule best = hp.sched;

@@ -476,18 +476,19 @@ int normalise_schedule(const HostPlan &hp, const pf_schedule *in, pf_schedule &s
     // defaults: the fastest schedules measured on MI355X for the 70,000-bus
     // grid (single instance) and its 1000-state batch
     const bool batch = hp.kind == KIND_BATCH;
-    if (d.tile_entries == 0) d.tile_entries = 128;
+    if (d.tile_entries == 0) d.tile_entries = 64;
     if (d.waves_per_block == 0) d.waves_per_block = 4;
     if (d.batch_buses == 0) d.batch_buses = 1;
     if (d.batch_order == 0) d.batch_order = 1;
     if (d.xcd_remap == 0) d.xcd_remap = batch ? 2 : 1;
     if (d.batch_layout == 0) d.batch_layout = 2;
+    if (d.grid_blocks == 0) d.grid_blocks = -1;
     if (d.tile_entries < 64 || d.tile_entries % 64 || d.tile_entries > (1 << 20))
         return fail(PF_EINVAL, "tile_entries must be a multiple of 64 in [64, 2^20]");
     if (d.waves_per_block < 1 || d.waves_per_block > 8)
         return fail(PF_EINVAL, "waves_per_block must be in [1, 8]");
-    if (d.grid_blocks < 0 || d.grid_blocks > (1 << 20))
-        return fail(PF_EINVAL, "grid_blocks must be in [0, 2^20]");
+    if (d.grid_blocks < -1 || d.grid_blocks > (1 << 20))
+        return fail(PF_EINVAL, "grid_blocks must be -1, 0 or in [1, 2^20]");
     if (d.batch_buses < 1 || d.batch_buses > (1 << 16))
         return fail(PF_EINVAL, "batch_buses must be in [1, 65536]");
     if (d.batch_order < 1 || d.batch_order > 2) return fail(PF_EINVAL, "batch_order must be 1 or 2");

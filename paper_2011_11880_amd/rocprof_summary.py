@@ -1,0 +1,105 @@
+"""Summaries of rocprofv3 result databases (rocpd SQLite).
+
+  python -m paper_2011_11880_amd.rocprof_summary stats RUN_results.db [--match NAME]
+      per-kernel dispatch count and duration statistics (microseconds)
+
+  python -m paper_2011_11880_amd.rocprof_summary traffic \
+        --fetch F.db --write W.db --copy-fetch CF.db --copy-write CW.db \
+        --kernel NAME --copy-bytes BYTES --units U --out FILE.json
+      HBM bytes per dispatch of a kernel from FETCH_SIZE / WRITE_SIZE runs,
+      each scaled by what the same counter reads for a plain copy kernel of
+      known size (copy_bytes read and copy_bytes written per dispatch)
+"""
+
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sqlite3
+import sys
+
+
+def kernel_stats(db, match=None):
+    c = sqlite3.connect(db)
+    rows = c.execute("select name, duration from kernels").fetchall()
+    agg = {}
+    for name, dur in rows:
+        if match and match not in name:
+            continue
+        agg.setdefault(name, []).append(dur / 1000.0)
+    out = []
+    for name, d in agg.items():
+        d.sort()
+        out.append({"kernel": name, "calls": len(d), "total_us": sum(d),
+                    "avg_us": sum(d) / len(d), "median_us": d[len(d) // 2],
+                    "min_us": d[0], "max_us": d[-1]})
+    out.sort(key=lambda r: -r["total_us"])
+    return out
+
+
+def counter_per_dispatch(db, counter, match):
+    c = sqlite3.connect(db)
+    rows = c.execute("select kernel_name, dispatch_id, sum(value) from counters_collection "
+                     "where counter_name = ? group by kernel_name, dispatch_id",
+                     (counter,)).fetchall()
+    vals = [v for name, _, v in rows if match in name]
+    if not vals:
+        raise SystemExit(f"no {counter} rows for kernels matching {match!r} in {db}")
+    return sum(vals) / len(vals), len(vals)
+
+
+def traffic(a):
+    from .build import kernel_source_hash
+    kib = 1024.0
+    f_k, nf = counter_per_dispatch(a.fetch, "FETCH_SIZE", a.kernel)
+    w_k, nw = counter_per_dispatch(a.write, "WRITE_SIZE", a.kernel)
+    f_c, _ = counter_per_dispatch(a.copy_fetch, "FETCH_SIZE", a.copy_kernel)
+    w_c, _ = counter_per_dispatch(a.copy_write, "WRITE_SIZE", a.copy_kernel)
+    sf = a.copy_bytes / (f_c * kib)
+    sw = a.copy_bytes / (w_c * kib)
+    fetch = f_k * kib * sf
+    write = w_k * kib * sw
+    return {"kernel": a.kernel, "launch_units": a.units,
+            "fetch_size_kib_per_dispatch": f_k, "write_size_kib_per_dispatch": w_k,
+            "dispatches": [nf, nw],
+            "copy_calibration": {"copy_bytes": a.copy_bytes,
+                                 "fetch_size_kib": f_c, "write_size_kib": w_c,
+                                 "fetch_scale": sf, "write_scale": sw},
+            "hbm_read_bytes_per_launch": fetch, "hbm_write_bytes_per_launch": write,
+            "hbm_bytes_per_launch": fetch + write,
+            "kernel_source_sha256_16": kernel_source_hash(),
+            "note": "FETCH_SIZE/WRITE_SIZE count L2-to-fabric traffic (Infinity Cache hits "
+                    "included); scaled so that a plain copy reads and writes its own size"}
+
+
+def main(argv=None):
+    ap = argparse.ArgumentParser(description=__doc__,
+                                 formatter_class=argparse.RawDescriptionHelpFormatter)
+    sub = ap.add_subparsers(dest="cmd", required=True)
+    s = sub.add_parser("stats")
+    s.add_argument("db")
+    s.add_argument("--match")
+    t = sub.add_parser("traffic")
+    for k in ("fetch", "write", "copy_fetch", "copy_write", "kernel", "out"):
+        t.add_argument("--" + k.replace("_", "-"), required=True)
+    t.add_argument("--copy-kernel", default="copyBuffer")
+    t.add_argument("--copy-bytes", type=int, required=True)
+    t.add_argument("--units", type=int, required=True)
+    a = ap.parse_args(argv)
+    if a.cmd == "stats":
+        rows = kernel_stats(a.db, a.match)
+        print(f"{'calls':>7} {'avg_us':>11} {'median_us':>11} {'min_us':>11} {'max_us':>11}  kernel")
+        for r in rows:
+            print(f"{r['calls']:7d} {r['avg_us']:11.3f} {r['median_us']:11.3f} "
+                  f"{r['min_us']:11.3f} {r['max_us']:11.3f}  {r['kernel'][:100]}")
+    else:
+        d = traffic(a)
+        with open(a.out, "w") as fh:
+            json.dump(d, fh, indent=1)
+        json.dump(d, sys.stdout, indent=1)
+        print()
+
+
+if __name__ == "__main__":
+    main()

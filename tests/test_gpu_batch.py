@@ -121,10 +121,10 @@ def test_schedules_bitwise(cuda):
     bp = Plan(net, batch=dict(n_inst=I, load_scale=ls, pv_scale=ps, outage=out))
     X = torch.from_numpy(np.ascontiguousarray(synth.random_states(net, I, seed=3).T)).to(cuda)
     F0, J0 = bp.eval_batch(X)
-    for s in [dict(batch_buses=1, batch_order=1, waves_per_block=1, grid_blocks=0, xcd_remap=2),
+    for s in [dict(batch_buses=1, batch_order=1, waves_per_block=1, grid_blocks=-1, xcd_remap=2),
               dict(batch_buses=7, batch_order=2, waves_per_block=8, grid_blocks=5, xcd_remap=1),
               dict(batch_buses=64, batch_order=1, waves_per_block=2, grid_blocks=1000, xcd_remap=1),
-              dict(batch_buses=3, batch_order=2, waves_per_block=4, grid_blocks=0, xcd_remap=1)]:
+              dict(batch_buses=3, batch_order=2, waves_per_block=4, grid_blocks=-1, xcd_remap=1)]:
         bp.schedule = dict(bp.schedule, **s)
         F, J = bp.eval_batch(X)
         torch.cuda.synchronize()

@@ -121,8 +121,8 @@ def test_entry_points_agree_bitwise(cuda):
 
 
 SCHEDULES = [
-    dict(tile_entries=64, waves_per_block=1, grid_blocks=0, xcd_remap=2),
-    dict(tile_entries=128, waves_per_block=4, grid_blocks=0, xcd_remap=1),
+    dict(tile_entries=64, waves_per_block=1, grid_blocks=-1, xcd_remap=2),
+    dict(tile_entries=128, waves_per_block=4, grid_blocks=-1, xcd_remap=1),
     dict(tile_entries=256, waves_per_block=8, grid_blocks=3, xcd_remap=1),
     dict(tile_entries=1024, waves_per_block=2, grid_blocks=64, xcd_remap=2),
     dict(tile_entries=4096, waves_per_block=4, grid_blocks=9, xcd_remap=1),
