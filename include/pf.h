@@ -114,10 +114,13 @@ typedef struct pf_network {
  *                   from the lowest-numbered bus
  *   xcd_remap       1: give each of the 8 XCDs a contiguous range of work
  *                   items (L2 locality), 2: round-robin (hardware order)
- *   batch_layout    batched kernel work order: 1 instance-chunk major (all
- *                   buses of a 64-instance chunk, then the next chunk),
- *                   2 bus major (every chunk of a bus run back to back, so
- *                   whole instance rows of the outputs are written together)
+ *   batch_group     batched kernel work order: number of 64-instance chunks
+ *                   of a bus processed back to back (1..64).  Work runs over
+ *                   groups of this many chunks, and inside a group bus by
+ *                   bus: 1 = one chunk at a time over all buses (small state
+ *                   footprint per bus, good cache reuse between neighbouring
+ *                   buses); >= the chunk count = bus by bus (whole instance
+ *                   rows of the outputs written together)
  */
 typedef struct pf_schedule {
     int32_t tile_entries;
@@ -126,7 +129,7 @@ typedef struct pf_schedule {
     int32_t batch_buses;
     int32_t batch_order;
     int32_t xcd_remap;
-    int32_t batch_layout;
+    int32_t batch_group;
 } pf_schedule;
 
 /*

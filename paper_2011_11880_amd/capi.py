@@ -47,7 +47,7 @@ class pf_network(ctypes.Structure):
 class pf_schedule(ctypes.Structure):
     _fields_ = [("tile_entries", _i32), ("waves_per_block", _i32), ("grid_blocks", _i32),
                 ("batch_buses", _i32), ("batch_order", _i32), ("xcd_remap", _i32),
-                ("batch_layout", _i32)]
+                ("batch_group", _i32)]
 
     def as_dict(self):
         return {k: int(getattr(self, k)) for k, _ in self._fields_}

@@ -40,6 +40,12 @@ namespace pf {
 // entry group size minus one).
 constexpr int kEntryPad = 8;
 
+// Largest tile size whose Jacobian rows are assembled in LDS (6 x 256 values
+// = 12 KB per wavefront).
+constexpr int kStageMaxTile = 256;
+// LDS a workgroup of the single-instance kernel may claim.
+constexpr size_t kMaxBlockLds = 64 * 1024;
+
 struct DevPlan {
     int device = 0;
     std::vector<void *> allocs;
@@ -253,11 +259,14 @@ __device__ __forceinline__ void wave_sync() {
 // processed 64 entries (one per lane) at a time.  The six per-entry row
 // contributions are staged in LDS and left-folded by the lane that holds the
 // first entry of each row (or lane 0 for a row continuing from the previous
-// chunk, which picks up the carried partial sums).
+// chunk, which picks up the carried partial sums).  The tile's Jacobian rows
+// P_i and Q_i occupy two contiguous value ranges; when they fit the wave's
+// staging area they are assembled in LDS and written out as whole runs,
+// otherwise (a very long row) values go straight to their slots.
 template <bool WF, bool WJ>
 __global__ void __launch_bounds__(512)
 k_eval_single(const int4 *__restrict__ tiles, int ntiles, int tiles_per_wave, int remap,
-              const GridDev *__restrict__ grids, const int4 *__restrict__ bus4,
+              int stage_cap, const GridDev *__restrict__ grids, const int4 *__restrict__ bus4,
               const int2 *__restrict__ bus2, const double2 *__restrict__ spec,
               const int32_t *__restrict__ ycol, const double *__restrict__ yG,
               const double *__restrict__ yB, const int4 *__restrict__ gen4,
@@ -269,15 +278,32 @@ k_eval_single(const int4 *__restrict__ tiles, int ntiles, int tiles_per_wave, in
     // keeps the tile walk and every row-structure load in scalar registers
     const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     const int wpb = blockDim.x >> 6;
-    double *L = lds + wv * (6 * 64);
+    double *L = lds + size_t(wv) * (6 * 64 + stage_cap);
+    double *S = L + 6 * 64;
     const int lb = remap ? xcd_logical_block(blockIdx.x, gridDim.x) : blockIdx.x;
     const int lw = lb * wpb + wv;
     const int t_begin = lw * tiles_per_wave;
     const int t_end = min(ntiles, t_begin + tiles_per_wave);
     const uint64_t le = (lane == 63) ? ~0ull : ((2ull << lane) - 1ull);
     for (int t = t_begin; t < t_end; ++t) {
-        const int4 td = tiles[t];
+        const int4 td = tiles[2 * t];
+        const int4 tj = tiles[2 * t + 1];
         const int e0 = td.x, e1 = td.y, b0 = td.z;
+        const int jP0 = tj.x, nP = tj.y - tj.x, jQ0 = tj.z, nQ = tj.w - tj.z;
+        const bool staged = WJ && (nP + nQ <= stage_cap);
+        // Jacobian value of row P_i (slot s) / row Q_i: LDS image or global
+        auto putP = [&](int slot, double v) {
+            if (staged)
+                S[slot - jP0] = v;
+            else
+                stc(&J[slot], v);
+        };
+        auto putQ = [&](int slot, double v) {
+            if (staged)
+                S[nP + slot - jQ0] = v;
+            else
+                stc(&J[slot], v);
+        };
         const GridDev gd = grids[td.w];
         const double *xt = x + gd.xoff;
         const double *xv = xt + gd.N;
@@ -322,10 +348,10 @@ k_eval_single(const int4 *__restrict__ tiles, int ntiles, int tiles_per_wave, in
                 entry_eval(diag, Ge, Be, thi, vi, thj, vj, c, o);
                 if (WJ && !diag) {
                     const int p = e - bi.x, Lr = bi.y - bi.x;
-                    stc(&J[bi.z + p], o[0]);
-                    stc(&J[bi.z + Lr + p], o[1]);
-                    stc(&J[bi.w + p], o[2]);
-                    stc(&J[bi.w + Lr + p], o[3]);
+                    putP(bi.z + p, o[0]);
+                    putP(bi.z + Lr + p, o[1]);
+                    putQ(bi.w + p, o[2]);
+                    putQ(bi.w + Lr + p, o[3]);
                 }
             }
 #pragma unroll
@@ -364,14 +390,14 @@ k_eval_single(const int4 *__restrict__ tiles, int ntiles, int tiles_per_wave, in
                     fq = fq - x[g4.x];
                     if (WF) stc(&F[g4.x], vi - gs.x);
                     if (WJ) {
-                        stc(&J[bi.w + 2 * Lr], -1.0);
+                        putQ(bi.w + 2 * Lr, -1.0);
                         stc(&J[g4.y], 1.0);
                     }
                     if (g4.z >= 0) {
                         fp = fp - x[g4.z];
                         if (WF) stc(&F[g4.z], thi - gs.y);
                         if (WJ) {
-                            stc(&J[bi.z + 2 * Lr], -1.0);
+                            putP(bi.z + 2 * Lr, -1.0);
                             stc(&J[g4.w], 1.0);
                         }
                     }
@@ -381,13 +407,20 @@ k_eval_single(const int4 *__restrict__ tiles, int ntiles, int tiles_per_wave, in
                     stc(&F[gd.xoff + gd.N + i], fq);
                 }
                 if (WJ) {
-                    stc(&J[bi.z + b2.x], a[2]);
-                    stc(&J[bi.z + Lr + b2.x], a[3]);
-                    stc(&J[bi.w + b2.x], a[4]);
-                    stc(&J[bi.w + Lr + b2.x], a[5]);
+                    putP(bi.z + b2.x, a[2]);
+                    putP(bi.z + Lr + b2.x, a[3]);
+                    putQ(bi.w + b2.x, a[4]);
+                    putQ(bi.w + Lr + b2.x, a[5]);
                 }
             }
             rows_seen += __popcll(smask);
+            wave_sync();
+        }
+        if (staged) {
+            // every slot of both ranges has been written above; stream the
+            // assembled rows out as contiguous runs
+            for (int q = lane; q < nP; q += 64) st(&J[jP0 + q], S[q]);
+            for (int q = lane; q < nQ; q += 64) st(&J[jQ0 + q], S[nP + q]);
             wave_sync();
         }
     }
@@ -404,7 +437,7 @@ k_eval_single(const int4 *__restrict__ tiles, int ntiles, int tiles_per_wave, in
 template <bool WF, bool WJ, bool SCEN, bool OUTG>
 __global__ void __launch_bounds__(512)
 k_eval_batch(int N, int I, int n_btiles, int n_chunks, int TB, int n_items, int items_per_wave,
-             int remap, int bus_major,
+             int remap, int group,
              const int32_t *__restrict__ order, const int4 *__restrict__ bus4,
              const int2 *__restrict__ bus2, const double2 *__restrict__ spec,
              const int32_t *__restrict__ ycol, const double *__restrict__ yG,
@@ -429,14 +462,13 @@ k_eval_batch(int N, int I, int n_btiles, int n_chunks, int TB, int n_items, int 
     int of = -1, ot = -1;
     double oy[8] = {0, 0, 0, 0, 0, 0, 0, 0};
     for (int w = w_begin; w < w_end; ++w) {
-        int ch, bt;
-        if (bus_major) {
-            bt = w / n_chunks;
-            ch = w - bt * n_chunks;
-        } else {
-            ch = w / n_btiles;
-            bt = w - ch * n_btiles;
-        }
+        // item -> (chunk group, bus run, chunk inside the group)
+        const int per_group = n_btiles * group;
+        const int sg = w / per_group;
+        const int rem = w - sg * per_group;
+        const int bt = rem / group;
+        const int ch = sg * group + (rem - bt * group);
+        if (ch >= n_chunks) continue;
         const int k = ch * 64 + lane;
         const bool valid = k < I;
         if (OUTG && ch != cur_chunk) {
@@ -634,7 +666,7 @@ k_vjp_state(const int4 *__restrict__ tiles, int ntiles, int n_kchunks,
     const size_t SK = size_t(K);
     double(*C)[64] = sc[wv];
     int *PC = sp[wv];
-    const int4 td = tiles[t];
+    const int4 td = tiles[2 * t];
     const int e0 = td.x, e1 = td.y, b0 = td.z;
     const GridDev gd = grids[td.w];
     const double *xt = x + gd.xoff;
@@ -941,12 +973,12 @@ int dev_upload_tiles(HostPlan &hp, DevPlan *dp) {
     const int32_t nt = hp.n_tiles();
     if (nt > dp->ntiles_alloc) {
         int4 *p = nullptr;
-        int rc = dalloc(dp, &p, size_t(nt));
+        int rc = dalloc(dp, &p, 2 * size_t(nt));
         if (rc) return rc;
         dp->tiles = p;
         dp->ntiles_alloc = nt;
     }
-    if (nt) HIP_TRY(hipMemcpy(dp->tiles, hp.tiles.data(), size_t(nt) * sizeof(int4),
+    if (nt) HIP_TRY(hipMemcpy(dp->tiles, hp.tiles.data(), 2 * size_t(nt) * sizeof(int4),
                               hipMemcpyHostToDevice));
     return PF_OK;
 }
@@ -1070,12 +1102,18 @@ int dev_eval_single(HostPlan &hp, DevPlan *dp, const double *x, double *F, doubl
     wave_grid(hp.n_tiles(), s, blocks, tpw);
     if (blocks == 0) return PF_OK;
     const int threads = 64 * s.waves_per_block;
-    const size_t shm = size_t(s.waves_per_block) * 6 * 64 * sizeof(double);
+    // staging area per wave: a tile's P and Q row ranges hold at most
+    // 3 x tile_entries values each; larger tile sizes write directly
+    int stage_cap = (J && s.tile_entries <= kStageMaxTile) ? 6 * s.tile_entries : 0;
+    if (size_t(s.waves_per_block) * (6 * 64 + stage_cap) * sizeof(double) > kMaxBlockLds)
+        stage_cap = 0;
+    const size_t shm = size_t(s.waves_per_block) * (6 * 64 + stage_cap) * sizeof(double);
     const int remap = s.xcd_remap == 1 ? 1 : 0;
 #define LAUNCH(WF, WJ)                                                                       \
     hipLaunchKernelGGL((k_eval_single<WF, WJ>), dim3(blocks), dim3(threads), shm, st,       \
-                       dp->tiles, hp.n_tiles(), tpw, remap, dp->grids, dp->bus4, dp->bus2,  \
-                       dp->spec, dp->ycol, dp->yG, dp->yB, dp->gen4, dp->gen2, x, F, J)
+                       dp->tiles, hp.n_tiles(), tpw, remap, stage_cap, dp->grids, dp->bus4, \
+                       dp->bus2, dp->spec, dp->ycol, dp->yG, dp->yB, dp->gen4, dp->gen2, x, \
+                       F, J)
     if (F && J)
         LAUNCH(true, true);
     else if (F)
@@ -1098,7 +1136,8 @@ int dev_eval_batch(HostPlan &hp, DevPlan *dp, const double *X, double *F, double
     const int TB = s.batch_buses;
     const int n_btiles = (N + TB - 1) / TB;
     const int n_chunks = (I + 63) / 64;
-    const int64_t n_items = int64_t(n_btiles) * n_chunks;
+    const int group = std::min(s.batch_group, n_chunks);
+    const int64_t n_items = int64_t(n_btiles) * group * ((n_chunks + group - 1) / group);
     if (n_items > (int64_t(1) << 31) - 1) return fail(PF_EINVAL, "batch work list too long");
     int blocks, ipw;
     wave_grid(n_items, s, blocks, ipw);
@@ -1112,8 +1151,8 @@ int dev_eval_batch(HostPlan &hp, DevPlan *dp, const double *X, double *F, double
     const double *lq = lp + hp.NLt;
 #define LAUNCH(WF, WJ, SC, OG)                                                                 \
     hipLaunchKernelGGL((k_eval_batch<WF, WJ, SC, OG>), dim3(blocks), dim3(threads), 0, st, N, \
-                       I, n_btiles, n_chunks, TB, int(n_items), ipw, remap,                   \
-                       s.batch_layout == 2 ? 1 : 0, order, dp->bus4, dp->bus2,                \
+                       I, n_btiles, n_chunks, TB, int(n_items), ipw, remap, group, order,     \
+                       dp->bus4, dp->bus2,                                                    \
                        dp->spec, dp->ycol, dp->yG, dp->yB, dp->gen4, dp->gen2, dp->genpv,     \
                        dp->ldptr, dp->ldlist, lp, lq, dp->pv_p, dp->lscale, dp->pscale,       \
                        dp->outage, dp->br_f, dp->br_t, dp->otab, X, F, J)
@@ -1280,7 +1319,7 @@ int dev_autotune(HostPlan &hp, DevPlan *dp, const double *x, double *F, double *
     if (batch) {
         axes.push_back({&pf_schedule::batch_buses, {1, 2, 4, 8, 16, 32, 64}});
         axes.push_back({&pf_schedule::batch_order, {1, 2}});
-        axes.push_back({&pf_schedule::batch_layout, {1, 2}});
+        axes.push_back({&pf_schedule::batch_group, {1, 2, 4, 8, 64}});
     } else {
         axes.push_back({&pf_schedule::tile_entries, {64, 128, 256, 512, 1024, 2048}});
     }

@@ -87,7 +87,8 @@ struct HostPlan {
 
     // single-instance schedule
     pf_schedule sched{};
-    std::vector<int32_t> tiles;        // ntiles * 4: e0, e1, b0 (global bus), grid
+    std::vector<int32_t> tiles;        // ntiles * 8: e0, e1, b0 (global bus), grid,
+                                       //   J range of the P rows, J range of the Q rows
 
     // batched overlay
     std::vector<double> load_scale_t;  // [NL][I] or empty
@@ -96,7 +97,7 @@ struct HostPlan {
     std::vector<int32_t> order_natural, order_bfs;   // bus processing orders
 
     int64_t n_params() const { return 5LL * Bt + 2LL * NLt; }
-    int32_t n_tiles() const { return int32_t(tiles.size() / 4); }
+    int32_t n_tiles() const { return int32_t(tiles.size() / 8); }
 };
 
 // Host setup (pf_setup.cpp)

@@ -476,12 +476,12 @@ int normalise_schedule(const HostPlan &hp, const pf_schedule *in, pf_schedule &s
     // defaults: the fastest schedules measured on MI355X for the 70,000-bus
     // grid (single instance) and its 1000-state batch
     const bool batch = hp.kind == KIND_BATCH;
-    if (d.tile_entries == 0) d.tile_entries = 64;
-    if (d.waves_per_block == 0) d.waves_per_block = 4;
-    if (d.batch_buses == 0) d.batch_buses = 1;
-    if (d.batch_order == 0) d.batch_order = 1;
+    if (d.tile_entries == 0) d.tile_entries = 128;
+    if (d.batch_buses == 0) d.batch_buses = 2;
+    if (d.batch_order == 0) d.batch_order = 2;
     if (d.xcd_remap == 0) d.xcd_remap = batch ? 2 : 1;
-    if (d.batch_layout == 0) d.batch_layout = 2;
+    if (d.batch_group == 0) d.batch_group = 8;
+    if (d.waves_per_block == 0) d.waves_per_block = batch ? 8 : 2;
     if (d.grid_blocks == 0) d.grid_blocks = -1;
     if (d.tile_entries < 64 || d.tile_entries % 64 || d.tile_entries > (1 << 20))
         return fail(PF_EINVAL, "tile_entries must be a multiple of 64 in [64, 2^20]");
@@ -493,14 +493,16 @@ int normalise_schedule(const HostPlan &hp, const pf_schedule *in, pf_schedule &s
         return fail(PF_EINVAL, "batch_buses must be in [1, 65536]");
     if (d.batch_order < 1 || d.batch_order > 2) return fail(PF_EINVAL, "batch_order must be 1 or 2");
     if (d.xcd_remap < 1 || d.xcd_remap > 2) return fail(PF_EINVAL, "xcd_remap must be 1 or 2");
-    if (d.batch_layout < 1 || d.batch_layout > 2)
-        return fail(PF_EINVAL, "batch_layout must be 1 or 2");
+    if (d.batch_group < 1 || d.batch_group > 64)
+        return fail(PF_EINVAL, "batch_group must be in [1, 64]");
     s = d;
     return PF_OK;
 }
 
 // Wavefront tiles of whole admittance rows: greedy, at most tile_entries
-// entries unless a single row is longer.  Tiles never cross grids.
+// entries unless a single row is longer.  Tiles never cross grids.  Each
+// tile records its entry range, first bus, grid, and the contiguous ranges
+// of Jacobian values its P rows and Q rows occupy.
 void build_tiles(HostPlan &hp) {
     hp.tiles.clear();
     const int32_t cap = hp.sched.tile_entries;
@@ -517,10 +519,17 @@ void build_tiles(HostPlan &hp) {
                 e1 = hp.yptr[b + 1];
                 ++b;
             }
+            const int64_t r_first = gi.xoff + (b0 - gi.bus_off);
+            const int64_t r_last = gi.xoff + (b - 1 - gi.bus_off);
             hp.tiles.push_back(e0);
             hp.tiles.push_back(e1);
             hp.tiles.push_back(b0);
             hp.tiles.push_back(g);
+            // Jacobian value ranges of the tile's P rows and Q rows
+            hp.tiles.push_back(hp.rowptr[r_first]);
+            hp.tiles.push_back(hp.rowptr[r_last + 1]);
+            hp.tiles.push_back(hp.rowptr[r_first + gi.N]);
+            hp.tiles.push_back(hp.rowptr[r_last + 1 + gi.N]);
         }
     }
 }
