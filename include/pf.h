@@ -172,19 +172,24 @@ int pf_setup(const pf_network *net, const pf_setup_opts *opt, pf_plan **out);
  *                or -1; the branch must be in service in the base network.
  *                Its Jacobian slots keep their place in the shared pattern
  *                and receive 0 when nothing else connects the bus pair.
+ *   inst_stride  row pitch, in elements, of the batched X, F and Jval arrays
+ *                (>= n_inst; 0 = n_inst).  Padding rows to a multiple of 16
+ *                instances aligns every 64-instance segment to 128 B; the
+ *                padding columns are neither read for results nor written.
  */
 typedef struct pf_batch_spec {
     int32_t n_inst;
     const double *load_scale;
     const double *pv_scale;
     const int32_t *outage;
+    int32_t inst_stride;
 } pf_batch_spec;
 
 /*
  * Build a batched plan: n_inst instances that share the base network's
  * pattern and data, each with its own state and overlay.  All batched
- * arrays are instance-fastest: X[n][n_inst], F[n][n_inst],
- * Jval[nnz][n_inst] (instance k of variable i at i * n_inst + k).
+ * arrays are instance-fastest with row pitch ld = inst_stride:
+ * X[n][ld], F[n][ld], Jval[nnz][ld] (instance k of variable i at i*ld + k).
  * Errors as pf_setup, plus PF_EINVAL for a bad spec.
  */
 int pf_setup_batch(const pf_network *net, const pf_batch_spec *spec,
@@ -209,6 +214,7 @@ typedef struct pf_info_t {
     int64_t n_entries;     /* admittance-row entries (N + 2 B_u) */
     int32_t n_bus, n_branch, n_load, n_pv, n_slack, n_shunt;
     int32_t n_inst;        /* 1 unless batched */
+    int32_t inst_stride;   /* batched row pitch (elements); 1 unless batched */
     int32_t n_grids;       /* 1 unless multi-grid */
     int32_t n_tiles;       /* wavefront tiles of the single-instance kernel */
     int32_t kind;          /* 0 single, 1 batched, 2 multi-grid */
@@ -235,8 +241,9 @@ int pf_eval_jacobian(pf_plan *plan, const double *x, double *Jval, void *stream)
 /* Fused residual + Jacobian in one launch; F or Jval may be NULL (not both). */
 int pf_eval(pf_plan *plan, const double *x, double *F, double *Jval, void *stream);
 
-/* Batched fused evaluation: X [n][n_inst], F [n][n_inst] (nullable),
- * Jval [nnz][n_inst] (nullable, not both NULL).  Batched plans only. */
+/* Batched fused evaluation: X [n][ld], F [n][ld] (nullable), Jval [nnz][ld]
+ * (nullable, not both NULL), ld = the plan's inst_stride.  Batched plans
+ * only. */
 int pf_eval_batch(pf_plan *plan, const double *X, double *F, double *Jval,
                   void *stream);
 

@@ -118,7 +118,8 @@ class Plan:
                 check(L.pf_setup(ctypes.byref(ns.s), ctypes.byref(opts), ctypes.byref(h)))
             else:
                 n_inst = int(batch["n_inst"])
-                spec = capi.pf_batch_spec(n_inst=n_inst)
+                spec = capi.pf_batch_spec(n_inst=n_inst,
+                                          inst_stride=int(batch.get("inst_stride", 0)))
                 keep = []
                 if batch.get("load_scale") is not None:
                     a = _f64(batch["load_scale"])
@@ -167,6 +168,7 @@ class Plan:
         self.n = self.info["n"]
         self.nnz = self.info["nnz"]
         self.n_inst = self.info["n_inst"]
+        self.ld = self.info["inst_stride"]
         self.n_params = self.info["n_params"]
 
     # lifetime ---------------------------------------------------------------
@@ -241,11 +243,12 @@ class Plan:
         return J
 
     def eval_batch(self, X, F=None, J=None, want_F=True, want_J=True):
-        """Batched evaluation; X, F are (n, n_inst) and J is (nnz, n_inst),
-        instance-fastest (row-major contiguous)."""
+        """Batched evaluation; X, F are (n, ld) and J is (nnz, ld),
+        instance-fastest (row-major contiguous), ld = the plan's inst_stride
+        (= n_inst unless padded)."""
         import torch
         dev = self._dev(X)
-        I = self.n_inst
+        I = self.ld
         if want_F and F is None:
             F = torch.empty((self.n, I), dtype=torch.float64, device=dev)
         if want_J and J is None:
@@ -282,7 +285,7 @@ class Plan:
         dev = self._dev(x)
         best = capi.pf_schedule()
         if self.info["kind"] == "batch":
-            I = self.n_inst
+            I = self.ld
             xs = _ptr(x, self.n * I, "X")
             Fs = _ptr(F, self.n * I, "F")
             Js = _ptr(J, self.nnz * I, "J")

@@ -436,7 +436,8 @@ k_eval_single(const int4 *__restrict__ tiles, int ntiles, int tiles_per_wave, in
 // joins -- exactly cancelling them when no parallel branch remains.
 template <bool WF, bool WJ, bool SCEN, bool OUTG>
 __global__ void __launch_bounds__(512)
-k_eval_batch(int N, int I, int n_btiles, int n_chunks, int TB, int n_items, int items_per_wave,
+k_eval_batch(int N, int I, int LD, int n_btiles, int n_chunks, int TB, int n_items,
+             int items_per_wave,
              int remap, int group,
              const int32_t *__restrict__ order, const int4 *__restrict__ bus4,
              const int2 *__restrict__ bus2, const double2 *__restrict__ spec,
@@ -457,7 +458,7 @@ k_eval_batch(int N, int I, int n_btiles, int n_chunks, int TB, int n_items, int 
     const int lw = lb * wpb + wv;
     const int w_begin = lw * items_per_wave;
     const int w_end = min(n_items, w_begin + items_per_wave);
-    const size_t SI = size_t(I);
+    const size_t SI = size_t(LD);
     int cur_chunk = -1;
     int of = -1, ot = -1;
     double oy[8] = {0, 0, 0, 0, 0, 0, 0, 0};
@@ -1151,7 +1152,7 @@ int dev_eval_batch(HostPlan &hp, DevPlan *dp, const double *X, double *F, double
     const double *lq = lp + hp.NLt;
 #define LAUNCH(WF, WJ, SC, OG)                                                                 \
     hipLaunchKernelGGL((k_eval_batch<WF, WJ, SC, OG>), dim3(blocks), dim3(threads), 0, st, N, \
-                       I, n_btiles, n_chunks, TB, int(n_items), ipw, remap, group, order,     \
+                       I, hp.ld, n_btiles, n_chunks, TB, int(n_items), ipw, remap, group, order,     \
                        dp->bus4, dp->bus2,                                                    \
                        dp->spec, dp->ycol, dp->yG, dp->yB, dp->gen4, dp->gen2, dp->genpv,     \
                        dp->ldptr, dp->ldlist, lp, lq, dp->pv_p, dp->lscale, dp->pscale,       \

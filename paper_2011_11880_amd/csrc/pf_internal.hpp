@@ -44,6 +44,7 @@ enum PlanKind : int32_t { KIND_SINGLE = 0, KIND_BATCH = 1, KIND_MULTI = 2 };
 struct HostPlan {
     int32_t kind = KIND_SINGLE;
     int32_t n_inst = 1;
+    int32_t ld = 1;                    // batched row pitch (>= n_inst)
     bool host_only = false;
     int device = 0;
     std::vector<GridInfo> grids;
@@ -91,8 +92,8 @@ struct HostPlan {
                                        //   J range of the P rows, J range of the Q rows
 
     // batched overlay
-    std::vector<double> load_scale_t;  // [NL][I] or empty
-    std::vector<double> pv_scale_t;    // [NPV][I] or empty
+    std::vector<double> load_scale_t;  // [NL][ld] or empty
+    std::vector<double> pv_scale_t;    // [NPV][ld] or empty
     std::vector<int32_t> outage;       // [I] or empty
     std::vector<int32_t> order_natural, order_bfs;   // bus processing orders
 

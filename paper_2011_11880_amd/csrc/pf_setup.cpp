@@ -425,31 +425,35 @@ int attach_batch(const pf_batch_spec *spec, HostPlan &hp) {
     if (!spec) return fail(PF_EINVAL, "batch spec is NULL");
     if (spec->n_inst < 1) return fail(PF_EINVAL, "n_inst must be >= 1");
     const int64_t I = spec->n_inst;
+    if (spec->inst_stride != 0 && spec->inst_stride < spec->n_inst)
+        return fail(PF_EINVAL, "inst_stride must be 0 or >= n_inst");
     hp.kind = KIND_BATCH;
     hp.n_inst = spec->n_inst;
-    if (int64_t(hp.nnz) * I > (int64_t(1) << 40))
+    hp.ld = spec->inst_stride ? spec->inst_stride : spec->n_inst;
+    const int64_t LD = hp.ld;
+    if (int64_t(hp.nnz) * LD > (int64_t(1) << 40))
         return fail(PF_EINVAL, "batch too large");
     hp.load_scale_t.clear();
     hp.pv_scale_t.clear();
     hp.outage.clear();
     if (spec->load_scale && hp.NLt > 0) {
-        hp.load_scale_t.resize(size_t(hp.NLt) * I);
+        hp.load_scale_t.assign(size_t(hp.NLt) * LD, 1.0);
         for (int64_t k = 0; k < I; ++k)
             for (int64_t l = 0; l < hp.NLt; ++l) {
                 const double s = spec->load_scale[k * hp.NLt + l];
                 if (!finite(s)) return fail(PF_EINVAL, "load_scale[%lld][%lld] is not finite",
                                             (long long)k, (long long)l);
-                hp.load_scale_t[l * I + k] = s;
+                hp.load_scale_t[l * LD + k] = s;
             }
     }
     if (spec->pv_scale && hp.NPVt > 0) {
-        hp.pv_scale_t.resize(size_t(hp.NPVt) * I);
+        hp.pv_scale_t.assign(size_t(hp.NPVt) * LD, 1.0);
         for (int64_t k = 0; k < I; ++k)
             for (int64_t l = 0; l < hp.NPVt; ++l) {
                 const double s = spec->pv_scale[k * hp.NPVt + l];
                 if (!finite(s)) return fail(PF_EINVAL, "pv_scale[%lld][%lld] is not finite",
                                             (long long)k, (long long)l);
-                hp.pv_scale_t[l * I + k] = s;
+                hp.pv_scale_t[l * LD + k] = s;
             }
     }
     if (spec->outage) {
@@ -476,7 +480,7 @@ int normalise_schedule(const HostPlan &hp, const pf_schedule *in, pf_schedule &s
     // defaults: the fastest schedules measured on MI355X for the 70,000-bus
     // grid (single instance) and its 1000-state batch
     const bool batch = hp.kind == KIND_BATCH;
-    if (d.tile_entries == 0) d.tile_entries = 128;
+    if (d.tile_entries == 0) d.tile_entries = 64;
     if (d.batch_buses == 0) d.batch_buses = 2;
     if (d.batch_order == 0) d.batch_order = 2;
     if (d.xcd_remap == 0) d.xcd_remap = batch ? 2 : 1;

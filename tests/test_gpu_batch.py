@@ -181,3 +181,30 @@ def test_10k_1024_scenarios_and_contingencies(ora, cuda):
         Jo, Ao = ora.jacobian(nk, Y[k])
         check_close(Fb[:, k], Fo, So, f"inst {k} F")
         check_jacobian(rp, ci, Jb[:, k], Jo, Ao, f"inst {k} J")
+
+
+def test_padded_instance_stride(cuda):
+    """Rows padded to inst_stride: results equal the unpadded layout bit for
+    bit and the padding columns are left untouched."""
+    Plan = _Plan()
+    net = _net()
+    I, LD = 70, 80
+    Y = synth.random_states(net, I, seed=12)
+    ls, ps = synth.batch_scenarios(net, I, seed=12)
+    out = np.full(I, -1, np.int32)
+    out[::5] = synth.contingencies(net, len(out[::5]), seed=12)
+    spec = dict(n_inst=I, load_scale=ls, pv_scale=ps, outage=out)
+    ref = Plan(net, batch=spec)
+    F0, J0 = _batch_eval(ref, Y, cuda)
+    pp = Plan(net, batch=dict(spec, inst_stride=LD))
+    assert pp.ld == LD and pp.n_inst == I
+    Xp = np.full((net.n_var, LD), np.nan)
+    Xp[:, :I] = Y.T
+    X = torch.from_numpy(Xp).to(cuda)
+    F = torch.full((pp.n, LD), 7.0, dtype=torch.float64, device=cuda)
+    J = torch.full((pp.nnz, LD), 7.0, dtype=torch.float64, device=cuda)
+    pp.eval_batch(X, F, J)
+    torch.cuda.synchronize()
+    F, J = F.cpu().numpy(), J.cpu().numpy()
+    assert np.array_equal(F[:, :I], F0) and np.array_equal(J[:, :I], J0)
+    assert np.all(F[:, I:] == 7.0) and np.all(J[:, I:] == 7.0)

@@ -123,7 +123,10 @@ def test_batch_spec_validation():
     with pytest.raises(PFError):
         _plan(net, batch=dict(n_inst=3, load_scale=ls))
     p = _plan(net, batch=dict(n_inst=3, outage=[-1, e, -1]))
-    assert p.info["kind"] == "batch" and p.n_inst == 3
+    assert p.info["kind"] == "batch" and p.n_inst == 3 and p.ld == 3
+    with pytest.raises(PFError):
+        _plan(net, batch=dict(n_inst=3, inst_stride=2))
+    assert _plan(net, batch=dict(n_inst=3, inst_stride=16)).ld == 16
 
 
 def test_multi_grid_offsets(ora):
