@@ -176,13 +176,23 @@ int pf_setup(const pf_network *net, const pf_setup_opts *opt, pf_plan **out);
  *                (>= n_inst; 0 = n_inst).  Padding rows to a multiple of 16
  *                instances aligns every 64-instance segment to 128 B; the
  *                padding columns are neither read for results nor written.
+ *   layout       PF_LAYOUT_ROWS (0): X[n][ld], F[n][ld], Jval[nnz][ld];
+ *                PF_LAYOUT_PANELS (1): instances in panels of 64,
+ *                X[P][n][64], F[P][n][64], Jval[P][nnz][64] with
+ *                P = ceil(n_inst / 64); instance k lives in panel k / 64,
+ *                column k % 64 (inst_stride is ignored).  Each panel is one
+ *                contiguous block, so a pass over one panel streams its
+ *                outputs and keeps its state slice cache-resident.
  */
+#define PF_LAYOUT_ROWS 0
+#define PF_LAYOUT_PANELS 1
 typedef struct pf_batch_spec {
     int32_t n_inst;
     const double *load_scale;
     const double *pv_scale;
     const int32_t *outage;
     int32_t inst_stride;
+    int32_t layout;
 } pf_batch_spec;
 
 /*
@@ -215,6 +225,7 @@ typedef struct pf_info_t {
     int32_t n_bus, n_branch, n_load, n_pv, n_slack, n_shunt;
     int32_t n_inst;        /* 1 unless batched */
     int32_t inst_stride;   /* batched row pitch (elements); 1 unless batched */
+    int32_t layout;        /* batched layout: PF_LAYOUT_ROWS or PF_LAYOUT_PANELS */
     int32_t n_grids;       /* 1 unless multi-grid */
     int32_t n_tiles;       /* wavefront tiles of the single-instance kernel */
     int32_t kind;          /* 0 single, 1 batched, 2 multi-grid */
@@ -241,9 +252,9 @@ int pf_eval_jacobian(pf_plan *plan, const double *x, double *Jval, void *stream)
 /* Fused residual + Jacobian in one launch; F or Jval may be NULL (not both). */
 int pf_eval(pf_plan *plan, const double *x, double *F, double *Jval, void *stream);
 
-/* Batched fused evaluation: X [n][ld], F [n][ld] (nullable), Jval [nnz][ld]
- * (nullable, not both NULL), ld = the plan's inst_stride.  Batched plans
- * only. */
+/* Batched fused evaluation: X, F (nullable) and Jval (nullable, not both
+ * NULL) in the plan's batched layout (rows of pitch inst_stride, or panels
+ * of 64 instances).  Batched plans only. */
 int pf_eval_batch(pf_plan *plan, const double *X, double *F, double *Jval,
                   void *stream);
 

@@ -118,8 +118,11 @@ class Plan:
                 check(L.pf_setup(ctypes.byref(ns.s), ctypes.byref(opts), ctypes.byref(h)))
             else:
                 n_inst = int(batch["n_inst"])
+                layout = {"rows": capi.PF_LAYOUT_ROWS, "panels": capi.PF_LAYOUT_PANELS}[
+                    batch.get("layout", "rows")]
                 spec = capi.pf_batch_spec(n_inst=n_inst,
-                                          inst_stride=int(batch.get("inst_stride", 0)))
+                                          inst_stride=int(batch.get("inst_stride", 0)),
+                                          layout=layout)
                 keep = []
                 if batch.get("load_scale") is not None:
                     a = _f64(batch["load_scale"])
@@ -169,6 +172,7 @@ class Plan:
         self.nnz = self.info["nnz"]
         self.n_inst = self.info["n_inst"]
         self.ld = self.info["inst_stride"]
+        self.panels = self.info["layout"] == capi.PF_LAYOUT_PANELS
         self.n_params = self.info["n_params"]
 
     # lifetime ---------------------------------------------------------------
@@ -242,21 +246,51 @@ class Plan:
                                           _ptr(J, self.nnz, "J"), _stream(dev)))
         return J
 
+    def batch_shape(self, rows):
+        """Tensor shape of a batched array with ``rows`` rows (n or nnz):
+        (rows, ld) for the row layout, (P, rows, 64) for panels."""
+        if self.panels:
+            return (-(-self.n_inst // 64), rows, 64)
+        return (rows, self.ld)
+
     def eval_batch(self, X, F=None, J=None, want_F=True, want_J=True):
-        """Batched evaluation; X, F are (n, ld) and J is (nnz, ld),
-        instance-fastest (row-major contiguous), ld = the plan's inst_stride
-        (= n_inst unless padded)."""
+        """Batched evaluation in the plan's layout: X, F of batch_shape(n),
+        J of batch_shape(nnz), contiguous."""
+        import math
+
         import torch
         dev = self._dev(X)
-        I = self.ld
+        sx, sj = self.batch_shape(self.n), self.batch_shape(self.nnz)
         if want_F and F is None:
-            F = torch.empty((self.n, I), dtype=torch.float64, device=dev)
+            F = torch.empty(sx, dtype=torch.float64, device=dev)
         if want_J and J is None:
-            J = torch.empty((self.nnz, I), dtype=torch.float64, device=dev)
-        check(capi.lib().pf_eval_batch(self._h, _ptr(X, self.n * I, "X"),
-                                       _ptr(F, self.n * I, "F"), _ptr(J, self.nnz * I, "J"),
-                                       _stream(dev)))
+            J = torch.empty(sj, dtype=torch.float64, device=dev)
+        check(capi.lib().pf_eval_batch(self._h, _ptr(X, math.prod(sx), "X"),
+                                       _ptr(F, math.prod(sx), "F"),
+                                       _ptr(J, math.prod(sj), "J"), _stream(dev)))
         return F, J
+
+    def to_batch(self, Y):
+        """Host array (n_inst, n) of states -> numpy array in the plan's
+        batched layout (padding columns zero)."""
+        Y = np.asarray(Y, dtype=np.float64)
+        I, n = Y.shape
+        if self.panels:
+            P = -(-I // 64)
+            out = np.zeros((P * 64, n))
+            out[:I] = Y
+            return np.ascontiguousarray(out.reshape(P, 64, n).transpose(0, 2, 1))
+        out = np.zeros((n, self.ld))
+        out[:, :I] = Y.T
+        return out
+
+    def from_batch(self, A):
+        """Batched array (layout of this plan) -> (n_inst, rows) host array."""
+        A = A.cpu().numpy() if hasattr(A, "cpu") else np.asarray(A)
+        if self.panels:
+            P, rows, _ = A.shape
+            return A.transpose(0, 2, 1).reshape(P * 64, rows)[:self.n_inst]
+        return A[:, :self.n_inst].T
 
     def set_params(self, params):
         """Replace [r, x, b, tap, shift_deg, load_p, load_q] (device vector)."""
@@ -285,10 +319,11 @@ class Plan:
         dev = self._dev(x)
         best = capi.pf_schedule()
         if self.info["kind"] == "batch":
-            I = self.ld
-            xs = _ptr(x, self.n * I, "X")
-            Fs = _ptr(F, self.n * I, "F")
-            Js = _ptr(J, self.nnz * I, "J")
+            import math
+            sx, sj = self.batch_shape(self.n), self.batch_shape(self.nnz)
+            xs = _ptr(x, math.prod(sx), "X")
+            Fs = _ptr(F, math.prod(sx), "F")
+            Js = _ptr(J, math.prod(sj), "J")
         else:
             xs, Fs, Js = _ptr(x, self.n, "x"), _ptr(F, self.n, "F"), _ptr(J, self.nnz, "J")
         check(capi.lib().pf_autotune(self._h, xs, Fs, Js, int(reps), _stream(dev),

@@ -21,6 +21,9 @@ PF_ENOMEM = -4
 PF_ESOLVE = -5
 PF_ENOCONV = -6
 
+PF_LAYOUT_ROWS = 0
+PF_LAYOUT_PANELS = 1
+
 _i32 = ctypes.c_int32
 _i64 = ctypes.c_int64
 _d = ctypes.c_double
@@ -59,14 +62,14 @@ class pf_setup_opts(ctypes.Structure):
 
 class pf_batch_spec(ctypes.Structure):
     _fields_ = [("n_inst", _i32), ("load_scale", _pd), ("pv_scale", _pd), ("outage", _pi32),
-                ("inst_stride", _i32)]
+                ("inst_stride", _i32), ("layout", _i32)]
 
 
 class pf_info_t(ctypes.Structure):
     _fields_ = [("n", _i64), ("nnz", _i64), ("n_params", _i64), ("n_entries", _i64),
                 ("n_bus", _i32), ("n_branch", _i32), ("n_load", _i32), ("n_pv", _i32),
                 ("n_slack", _i32), ("n_shunt", _i32), ("n_inst", _i32), ("inst_stride", _i32),
-                ("n_grids", _i32),
+                ("layout", _i32), ("n_grids", _i32),
                 ("n_tiles", _i32), ("kind", _i32)]
 
 

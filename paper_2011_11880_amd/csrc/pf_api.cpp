@@ -132,7 +132,8 @@ int pf_info_ex(const pf_plan *plan, pf_info_t *info) {
     info->n_slack = h.NSt;
     info->n_shunt = h.NSHt;
     info->n_inst = h.n_inst;
-    info->inst_stride = h.ld;
+    info->inst_stride = h.panels ? 64 : h.ld;
+    info->layout = h.panels ? PF_LAYOUT_PANELS : PF_LAYOUT_ROWS;
     info->n_grids = int32_t(h.grids.size());
     info->n_tiles = h.n_tiles();
     info->kind = h.kind;

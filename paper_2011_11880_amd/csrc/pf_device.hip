@@ -436,8 +436,8 @@ k_eval_single(const int4 *__restrict__ tiles, int ntiles, int tiles_per_wave, in
 // joins -- exactly cancelling them when no parallel branch remains.
 template <bool WF, bool WJ, bool SCEN, bool OUTG>
 __global__ void __launch_bounds__(512)
-k_eval_batch(int N, int I, int LD, int n_btiles, int n_chunks, int TB, int n_items,
-             int items_per_wave,
+k_eval_batch(int N, int I, int LD, int panel, int64_t rows_x, int64_t rows_j, int n_btiles,
+             int n_chunks, int TB, int n_items, int items_per_wave,
              int remap, int group,
              const int32_t *__restrict__ order, const int4 *__restrict__ bus4,
              const int2 *__restrict__ bus2, const double2 *__restrict__ spec,
@@ -458,7 +458,7 @@ k_eval_batch(int N, int I, int LD, int n_btiles, int n_chunks, int TB, int n_ite
     const int lw = lb * wpb + wv;
     const int w_begin = lw * items_per_wave;
     const int w_end = min(n_items, w_begin + items_per_wave);
-    const size_t SI = size_t(LD);
+    const size_t OLD = size_t(LD);   // row pitch of the overlay tables
     int cur_chunk = -1;
     int of = -1, ot = -1;
     double oy[8] = {0, 0, 0, 0, 0, 0, 0, 0};
@@ -485,13 +485,22 @@ k_eval_batch(int N, int I, int LD, int n_btiles, int n_chunks, int TB, int n_ite
         }
         const int q0 = bt * TB;
         const int q1 = min(N, q0 + TB);
-        // masked lanes read a valid duplicate address so loads need no masking
-        const size_t kk = size_t(valid ? k : I - 1);
+        // rows of pitch LD (column k), or the chunk's panel of 64 (column lane)
+        const size_t SI = panel ? 64 : size_t(LD);
+        const size_t kq = panel ? size_t(lane) : size_t(k);
+        const size_t xo = panel ? size_t(ch) * size_t(rows_x) * 64 : 0;
+        const size_t jo = panel ? size_t(ch) * size_t(rows_j) * 64 : 0;
+        const double *Xc = X + xo;
+        double *Fc = F ? F + xo : nullptr;
+        double *Jc = J ? J + jo : nullptr;
+        // masked lanes read a valid duplicate address so loads need no
+        // masking (a panel is always 64 columns wide)
+        const size_t kk = panel ? kq : size_t(valid ? k : I - 1);
         // the next bus's row header and own state are fetched one bus ahead
         int b_nx = order[q0];
         int4 bi_nx = bus4[b_nx];
-        double thi_nx = X[size_t(b_nx) * SI + kk];
-        double vi_nx = X[size_t(N + b_nx) * SI + kk];
+        double thi_nx = Xc[size_t(b_nx) * SI + kk];
+        double vi_nx = Xc[size_t(N + b_nx) * SI + kk];
         for (int qq = q0; qq < q1; ++qq) {
             const int b = b_nx;
             const int4 bi = bi_nx;
@@ -499,8 +508,8 @@ k_eval_batch(int N, int I, int LD, int n_btiles, int n_chunks, int TB, int n_ite
             if (qq + 1 < q1) {
                 b_nx = order[qq + 1];
                 bi_nx = bus4[b_nx];
-                thi_nx = X[size_t(b_nx) * SI + kk];
-                vi_nx = X[size_t(N + b_nx) * SI + kk];
+                thi_nx = Xc[size_t(b_nx) * SI + kk];
+                vi_nx = Xc[size_t(N + b_nx) * SI + kk];
             }
             const int Lr = bi.y - bi.x;
             double a[6] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
@@ -521,8 +530,8 @@ k_eval_batch(int N, int I, int LD, int n_btiles, int n_chunks, int TB, int n_ite
 #pragma unroll
                 for (int u = 0; u < EU; ++u) {
                     if (e0 + u < bi.y) {
-                        thj[u] = X[size_t(jj[u]) * SI + kk];
-                        vj[u] = X[size_t(N + jj[u]) * SI + kk];
+                        thj[u] = Xc[size_t(jj[u]) * SI + kk];
+                        vj[u] = Xc[size_t(N + jj[u]) * SI + kk];
                     }
                 }
 #pragma unroll
@@ -555,10 +564,10 @@ k_eval_batch(int N, int I, int LD, int n_btiles, int n_chunks, int TB, int n_ite
                     entry_eval(diag, G, Bv, thi, vi, thj[u], vj[u], c, o);
                     if (WJ && !diag && valid) {
                         const int p = e - bi.x;
-                        st(&J[size_t(bi.z + p) * SI + k], o[0]);
-                        st(&J[size_t(bi.z + Lr + p) * SI + k], o[1]);
-                        st(&J[size_t(bi.w + p) * SI + k], o[2]);
-                        st(&J[size_t(bi.w + Lr + p) * SI + k], o[3]);
+                        st(&Jc[size_t(bi.z + p) * SI + kq], o[0]);
+                        st(&Jc[size_t(bi.z + Lr + p) * SI + kq], o[1]);
+                        st(&Jc[size_t(bi.w + p) * SI + kq], o[2]);
+                        st(&Jc[size_t(bi.w + Lr + p) * SI + kq], o[3]);
                     }
 #pragma unroll
                     for (int q = 0; q < 6; ++q) a[q] += c[q];
@@ -572,14 +581,14 @@ k_eval_batch(int N, int I, int LD, int n_btiles, int n_chunks, int TB, int n_ite
                 spy = 0.0;
                 for (int l = ldptr[b]; l < ldptr[b + 1]; ++l) {
                     const int ld = ldlist[l];
-                    const double s = lscale ? lscale[size_t(ld) * SI + k] : 1.0;
+                    const double s = lscale ? lscale[size_t(ld) * OLD + k] : 1.0;
                     spx += lp[ld] * s;
                     spy += lq[ld] * s;
                 }
                 if (b2.y >= 0) {
                     const int pv = genpv[b2.y];
                     if (pv >= 0) {
-                        const double s = pscale ? pscale[size_t(pv) * SI + k] : 1.0;
+                        const double s = pscale ? pscale[size_t(pv) * OLD + k] : 1.0;
                         spx = spx - pv_p[pv] * s;
                     }
                 }
@@ -594,30 +603,30 @@ k_eval_batch(int N, int I, int LD, int n_btiles, int n_chunks, int TB, int n_ite
             if (g >= 0) {
                 const int4 g4 = gen4[g];
                 const double2 gs = gen2[g];
-                fq = fq - X[size_t(g4.x) * SI + k];
-                if (WF) st(&F[size_t(g4.x) * SI + k], vi - gs.x);
+                fq = fq - Xc[size_t(g4.x) * SI + kq];
+                if (WF) st(&Fc[size_t(g4.x) * SI + kq], vi - gs.x);
                 if (WJ) {
-                    st(&J[size_t(bi.w + 2 * Lr) * SI + k], -1.0);
-                    st(&J[size_t(g4.y) * SI + k], 1.0);
+                    st(&Jc[size_t(bi.w + 2 * Lr) * SI + kq], -1.0);
+                    st(&Jc[size_t(g4.y) * SI + kq], 1.0);
                 }
                 if (g4.z >= 0) {
-                    fp = fp - X[size_t(g4.z) * SI + k];
-                    if (WF) st(&F[size_t(g4.z) * SI + k], thi - gs.y);
+                    fp = fp - Xc[size_t(g4.z) * SI + kq];
+                    if (WF) st(&Fc[size_t(g4.z) * SI + kq], thi - gs.y);
                     if (WJ) {
-                        st(&J[size_t(bi.z + 2 * Lr) * SI + k], -1.0);
-                        st(&J[size_t(g4.w) * SI + k], 1.0);
+                        st(&Jc[size_t(bi.z + 2 * Lr) * SI + kq], -1.0);
+                        st(&Jc[size_t(g4.w) * SI + kq], 1.0);
                     }
                 }
             }
             if (WF) {
-                st(&F[size_t(b) * SI + k], fp);
-                st(&F[size_t(N + b) * SI + k], fq);
+                st(&Fc[size_t(b) * SI + kq], fp);
+                st(&Fc[size_t(N + b) * SI + kq], fq);
             }
             if (WJ) {
-                st(&J[size_t(bi.z + b2.x) * SI + k], a[2]);
-                st(&J[size_t(bi.z + Lr + b2.x) * SI + k], a[3]);
-                st(&J[size_t(bi.w + b2.x) * SI + k], a[4]);
-                st(&J[size_t(bi.w + Lr + b2.x) * SI + k], a[5]);
+                st(&Jc[size_t(bi.z + b2.x) * SI + kq], a[2]);
+                st(&Jc[size_t(bi.z + Lr + b2.x) * SI + kq], a[3]);
+                st(&Jc[size_t(bi.w + b2.x) * SI + kq], a[4]);
+                st(&Jc[size_t(bi.w + Lr + b2.x) * SI + kq], a[5]);
             }
         }
     }
@@ -1152,7 +1161,7 @@ int dev_eval_batch(HostPlan &hp, DevPlan *dp, const double *X, double *F, double
     const double *lq = lp + hp.NLt;
 #define LAUNCH(WF, WJ, SC, OG)                                                                 \
     hipLaunchKernelGGL((k_eval_batch<WF, WJ, SC, OG>), dim3(blocks), dim3(threads), 0, st, N, \
-                       I, hp.ld, n_btiles, n_chunks, TB, int(n_items), ipw, remap, group, order,     \
+                       I, hp.ld, hp.panels, hp.n, hp.nnz, n_btiles, n_chunks, TB, int(n_items), ipw, remap, group, order,     \
                        dp->bus4, dp->bus2,                                                    \
                        dp->spec, dp->ycol, dp->yG, dp->yB, dp->gen4, dp->gen2, dp->genpv,     \
                        dp->ldptr, dp->ldlist, lp, lq, dp->pv_p, dp->lscale, dp->pscale,       \

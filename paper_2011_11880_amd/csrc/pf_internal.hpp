@@ -45,6 +45,7 @@ struct HostPlan {
     int32_t kind = KIND_SINGLE;
     int32_t n_inst = 1;
     int32_t ld = 1;                    // batched row pitch (>= n_inst)
+    int32_t panels = 0;                // 1: batched arrays in panels of 64 instances
     bool host_only = false;
     int device = 0;
     std::vector<GridInfo> grids;

@@ -427,9 +427,13 @@ int attach_batch(const pf_batch_spec *spec, HostPlan &hp) {
     const int64_t I = spec->n_inst;
     if (spec->inst_stride != 0 && spec->inst_stride < spec->n_inst)
         return fail(PF_EINVAL, "inst_stride must be 0 or >= n_inst");
+    if (spec->layout != PF_LAYOUT_ROWS && spec->layout != PF_LAYOUT_PANELS)
+        return fail(PF_EINVAL, "unknown batched layout %d", spec->layout);
     hp.kind = KIND_BATCH;
     hp.n_inst = spec->n_inst;
-    hp.ld = spec->inst_stride ? spec->inst_stride : spec->n_inst;
+    hp.panels = spec->layout == PF_LAYOUT_PANELS;
+    // panels: the overlay tables keep a row pitch of n_inst internally
+    hp.ld = (spec->inst_stride && !hp.panels) ? spec->inst_stride : spec->n_inst;
     const int64_t LD = hp.ld;
     if (int64_t(hp.nnz) * LD > (int64_t(1) << 40))
         return fail(PF_EINVAL, "batch too large");
@@ -481,11 +485,11 @@ int normalise_schedule(const HostPlan &hp, const pf_schedule *in, pf_schedule &s
     // grid (single instance) and its 1000-state batch
     const bool batch = hp.kind == KIND_BATCH;
     if (d.tile_entries == 0) d.tile_entries = 64;
-    if (d.batch_buses == 0) d.batch_buses = 2;
-    if (d.batch_order == 0) d.batch_order = 2;
+    if (d.batch_buses == 0) d.batch_buses = 1;
+    if (d.batch_order == 0) d.batch_order = 1;
     if (d.xcd_remap == 0) d.xcd_remap = batch ? 2 : 1;
-    if (d.batch_group == 0) d.batch_group = 8;
-    if (d.waves_per_block == 0) d.waves_per_block = batch ? 8 : 2;
+    if (d.batch_group == 0) d.batch_group = 64;
+    if (d.waves_per_block == 0) d.waves_per_block = batch ? 4 : 2;
     if (d.grid_blocks == 0) d.grid_blocks = -1;
     if (d.tile_entries < 64 || d.tile_entries % 64 || d.tile_entries > (1 << 20))
         return fail(PF_EINVAL, "tile_entries must be a multiple of 64 in [64, 2^20]");

@@ -208,3 +208,31 @@ def test_padded_instance_stride(cuda):
     F, J = F.cpu().numpy(), J.cpu().numpy()
     assert np.array_equal(F[:, :I], F0) and np.array_equal(J[:, :I], J0)
     assert np.all(F[:, I:] == 7.0) and np.all(J[:, I:] == 7.0)
+
+
+def test_panel_layout_matches_rows(cuda):
+    """Panels of 64 instances hold exactly the values of the row layout;
+    padding columns of the last panel stay untouched; every schedule agrees."""
+    Plan = _Plan()
+    net = _net()
+    I = 130
+    Y = synth.random_states(net, I, seed=21)
+    ls, ps = synth.batch_scenarios(net, I, seed=21)
+    out = np.full(I, -1, np.int32)
+    out[1::4] = synth.contingencies(net, len(out[1::4]), seed=21)
+    spec = dict(n_inst=I, load_scale=ls, pv_scale=ps, outage=out)
+    F0, J0 = _batch_eval(Plan(net, batch=spec), Y, cuda)
+    pp = Plan(net, batch=dict(spec, layout="panels"))
+    assert pp.panels and pp.batch_shape(pp.n) == (3, pp.n, 64)
+    X = torch.from_numpy(pp.to_batch(Y)).to(cuda)
+    for s in [dict(batch_group=1), dict(batch_group=2, batch_order=2, batch_buses=3),
+              dict(batch_group=64, waves_per_block=1, grid_blocks=7)]:
+        pp.schedule = dict(pp.schedule, **s)
+        F = torch.full(pp.batch_shape(pp.n), 7.0, dtype=torch.float64, device=cuda)
+        J = torch.full(pp.batch_shape(pp.nnz), 7.0, dtype=torch.float64, device=cuda)
+        pp.eval_batch(X, F, J)
+        torch.cuda.synchronize()
+        assert np.array_equal(pp.from_batch(F), F0.T), s
+        assert np.array_equal(pp.from_batch(J), J0.T), s
+        Fn, Jn = F.cpu().numpy(), J.cpu().numpy()
+        assert np.all(Fn[2, :, I - 128:] == 7.0) and np.all(Jn[2, :, I - 128:] == 7.0)
