@@ -322,21 +322,33 @@ def run_c4(args, torch, dev, net70k=None, plain_us=None, **kw):
     gx = torch.empty((p.n, K), dtype=torch.float64, device=dev)
     gp = torch.empty((p.n_params, K), dtype=torch.float64, device=dev)
     ms = time_ms(torch, lambda: p.vjp(x, W, gx, gp))
-    F = torch.empty(p.n, dtype=torch.float64, device=dev)
-    J = torch.empty(p.nnz, dtype=torch.float64, device=dev)
-    p.autotune(x, F, J, reps=20)
-    ms_f = time_ms(torch, lambda: p.eval(x, F, J), reps=50)
+    if plain_us is None:   # forward reference: one evaluation inside a captured graph
+        F = torch.empty(p.n, dtype=torch.float64, device=dev)
+        J = torch.empty(p.nnz, dtype=torch.float64, device=dev)
+        g = torch.cuda.CUDAGraph()
+        st = torch.cuda.Stream()
+        st.wait_stream(torch.cuda.current_stream())
+        p.eval(x, F, J)
+        torch.cuda.synchronize()
+        with torch.cuda.stream(st):
+            with torch.cuda.graph(g, stream=st):
+                for _ in range(20):
+                    p.eval(x, F, J)
+        torch.cuda.synchronize()
+        plain_us = time_ms(torch, g.replay) * 1e3 / 20
+    ms_f = plain_us * 1e-3
     nb = K * (8 * p.n * 2 + 8 * p.n_params) + 8 * p.n + statics_bytes(p.info) + \
         64 * net.n_branch
-    return {"cotangents": K, "vjp_ms": ms, "forward_us": ms_f * 1e3,
+    return {"cotangents": K, "vjp_ms": ms, "forward_us": plain_us,
             "vjp_over_forward": ms / ms_f, "vjp_per_cotangent_over_forward": ms / ms_f / K,
             "gbs": nb / (ms * 1e-3) / 1e9, "hbm_frac": nb / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS}
 
 
 def run_copy(args, torch, dev):
     """Calibration: a plain device-to-device copy of known size (torch's
-    copy kernel), the reference for HBM byte counters and achievable
-    bandwidth."""
+    copy kernel), the reference for HBM byte counters; also reports the
+    fill (write-only) and sum (read-only) bandwidth of the same buffer as
+    practical ceilings."""
     nbytes = args.copy_mib << 20
     a = torch.empty(nbytes // 8, dtype=torch.float64, device=dev).fill_(1.0)
     b = torch.empty_like(a)
@@ -347,7 +359,11 @@ def run_copy(args, torch, dev):
             b.copy_(a)
     ms = t.ms / args.steps
     gbs = 2 * nbytes / (ms * 1e-3) / 1e9
+    fill_ms = time_ms(torch, lambda: b.fill_(1.0))
+    sum_ms = time_ms(torch, lambda: a.sum())
     return {"metric": "device copy bandwidth (read + write)", "value": gbs, "unit": "GB/s",
+            "fill_gbs": nbytes / (fill_ms * 1e-3) / 1e9,
+            "read_gbs": nbytes / (sum_ms * 1e-3) / 1e9,
             "n_gpus": 1, "steps": args.steps, "warmup": args.warmup, "ms_per_step": ms,
             "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f64",
             "data": "synthetic", "config": {"workload": f"copy of {args.copy_mib} MiB",
