@@ -257,8 +257,7 @@ def run_c2(args, torch, dev, **kw):
     X = torch.from_numpy(np.ascontiguousarray(Y.T)).to(dev)
     F = torch.empty((bp.n, I), dtype=torch.float64, device=dev)
     J = torch.empty((bp.nnz, I), dtype=torch.float64, device=dev)
-    if args.autotune:
-        bp.autotune(X, F, J, reps=3)
+    bp.autotune(X, F, J, reps=3)
     ms = time_ms(torch, lambda: bp.eval_batch(X, F, J))
     nb = I * (per_eval_bytes(bp.n, bp.nnz) + 8 * (net.n_load + net.n_pv) + 4) + \
         statics_bytes(bp.info)
@@ -266,8 +265,7 @@ def run_c2(args, torch, dev, **kw):
     Xs = torch.from_numpy(Y[:64]).to(dev)
     Fs = torch.empty((64, pp.n), dtype=torch.float64, device=dev)
     Js = torch.empty((64, pp.nnz), dtype=torch.float64, device=dev)
-    if args.autotune:
-        pp.autotune(Xs[0], Fs[0], Js[0], reps=20)
+    pp.autotune(Xs[0], Fs[0], Js[0], reps=20)
 
     def plain64():
         for s in range(64):
