@@ -236,3 +236,30 @@ def test_panel_layout_matches_rows(cuda):
         assert np.array_equal(pp.from_batch(J), J0.T), s
         Fn, Jn = F.cpu().numpy(), J.cpu().numpy()
         assert np.all(Fn[2, :, I - 128:] == 7.0) and np.all(Jn[2, :, I - 128:] == 7.0)
+
+
+def test_70k_x1000_bench_configuration_sampled(ora, cuda):
+    """The benchmark's batched launch as timed (70,000-bus grid, 1000 random
+    states in rows padded to 1024, default schedule): sampled instances
+    against the oracle and bit-identical to the single-instance kernel."""
+    Plan = _Plan()
+    net = synth.grid_70k()
+    S = 1000
+    Y = synth.random_states(net, S, seed=1001)
+    bp = Plan(net, batch=dict(n_inst=S, inst_stride=1024))
+    X = torch.from_numpy(bp.to_batch(Y)).to(cuda)
+    F, J = bp.eval_batch(X)
+    sp = Plan(net)
+    rp, ci = bp.pattern()
+    for k in [0, 63, 64, 511, 999]:
+        Fk = F[:, k].cpu().numpy()
+        Jk = J[:, k].cpu().numpy()
+        Fo, So = ora.residual(net, Y[k])
+        Jo, Ao = ora.jacobian(net, Y[k])
+        check_close(Fk, Fo, So, f"inst {k} F")
+        check_jacobian(rp, ci, Jk, Jo, Ao, f"inst {k} J")
+        Fs, Js = sp.eval(torch.from_numpy(Y[k]).to(cuda))
+        torch.cuda.synchronize()
+        assert np.array_equal(Fs.cpu().numpy(), Fk) and np.array_equal(Js.cpu().numpy(), Jk)
+    del F, J, X
+    torch.cuda.empty_cache()

@@ -164,3 +164,33 @@ def test_nan_state_propagates(cuda):
     touched = {5} | set(net.br_to[net.br_from == 5].tolist()) | set(net.br_from[net.br_to == 5].tolist())
     far = [i for i in range(net.n_bus) if i not in touched]
     assert np.all(np.isfinite(F[far]))
+
+
+def test_single_instance_graph_replay(cuda):
+    """Launches of the single-instance kernel captured in a graph (as the
+    benchmark's plain leg runs them) replay to the eager results."""
+    from paper_2011_11880_amd.api import Plan
+    net = synth.grid_10k()
+    p = Plan(net)
+    Y = synth.random_states(net, 3, seed=5)
+    X = torch.from_numpy(Y).to(cuda)
+    F0 = torch.stack([p.eval(X[s])[0] for s in range(3)])
+    J0 = torch.stack([p.eval(X[s])[1] for s in range(3)])
+    F = torch.zeros_like(F0)
+    J = torch.zeros_like(J0)
+    torch.cuda.synchronize()
+    g = torch.cuda.CUDAGraph()
+    st = torch.cuda.Stream()
+    st.wait_stream(torch.cuda.current_stream())
+    with torch.cuda.stream(st):
+        with torch.cuda.graph(g, stream=st):
+            for s in range(3):
+                p.eval(X[s], F[s], J[s])
+    torch.cuda.synchronize()
+    for r in range(3):
+        F.fill_(-1.0)
+        J.zero_()
+        torch.cuda.synchronize()
+        g.replay()
+        torch.cuda.synchronize()
+        assert torch.equal(F, F0) and torch.equal(J, J0), r
