@@ -71,6 +71,7 @@ struct DevPlan {
     // batched overlay
     double *lscale = nullptr, *pscale = nullptr;
     int32_t *outage = nullptr;
+    int2 *out_ft = nullptr;   // per instance: buses of its outaged branch, or -1
     double *otab = nullptr;
     int32_t *order_nat = nullptr, *order_bfs = nullptr;
     // Newton scratch (allocated at setup for single-instance plans)
@@ -448,8 +449,8 @@ k_eval_batch(int N, int I, int LD, int panel, int64_t rows_x, int64_t rows_j, in
              const double *__restrict__ lp, const double *__restrict__ lq,
              const double *__restrict__ pv_p, const double *__restrict__ lscale,
              const double *__restrict__ pscale, const int32_t *__restrict__ outage,
-             const int32_t *__restrict__ br_f, const int32_t *__restrict__ br_t,
-             const double *__restrict__ otab, const double *__restrict__ X,
+             const int2 *__restrict__ out_ft, const double *__restrict__ otab,
+             const double *__restrict__ X,
              double *__restrict__ F, double *__restrict__ J) {
     const int lane = threadIdx.x & 63;
     const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
@@ -460,8 +461,7 @@ k_eval_batch(int N, int I, int LD, int panel, int64_t rows_x, int64_t rows_j, in
     const int w_end = min(n_items, w_begin + items_per_wave);
     const size_t OLD = size_t(LD);   // row pitch of the overlay tables
     int cur_chunk = -1;
-    int of = -1, ot = -1;
-    double oy[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+    int of = -1, ot = -1;   // buses of this lane's outaged branch
     for (int w = w_begin; w < w_end; ++w) {
         // item -> (chunk group, bus run, chunk inside the group)
         const int per_group = n_btiles * group;
@@ -474,14 +474,9 @@ k_eval_batch(int N, int I, int LD, int panel, int64_t rows_x, int64_t rows_j, in
         const bool valid = k < I;
         if (OUTG && ch != cur_chunk) {
             cur_chunk = ch;
-            of = ot = -1;
-            const int o = valid ? outage[k] : -1;
-            if (o >= 0) {
-                of = br_f[o];
-                ot = br_t[o];
-#pragma unroll
-                for (int q = 0; q < 8; ++q) oy[q] = otab[8 * size_t(o) + q];
-            }
+            const int2 ft = valid ? out_ft[k] : make_int2(-1, -1);
+            of = ft.x;
+            ot = ft.y;
         }
         const int q0 = bt * TB;
         const int q1 = min(N, q0 + TB);
@@ -512,6 +507,19 @@ k_eval_batch(int N, int I, int LD, int panel, int64_t rows_x, int64_t rows_j, in
                 vi_nx = Xc[size_t(N + b_nx) * SI + kk];
             }
             const int Lr = bi.y - bi.x;
+            // a lane whose outaged branch touches this bus fetches the terms
+            // that branch adds to the diagonal and to the other end's entry
+            int oc = -1;
+            double dGd = 0.0, dBd = 0.0, dGo = 0.0, dBo = 0.0;
+            if (OUTG && (of == b || ot == b)) {
+                const size_t o8 = 8 * size_t(outage[k]);
+                const bool from = of == b;
+                oc = from ? ot : of;
+                dGd = otab[o8 + (from ? 0 : 6)];
+                dBd = otab[o8 + (from ? 1 : 7)];
+                dGo = otab[o8 + (from ? 2 : 4)];
+                dBo = otab[o8 + (from ? 3 : 5)];
+            }
             double a[6] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
             // entries in groups of EU: all gathers of a group are issued
             // before any of its arithmetic, so they are in flight together
@@ -541,23 +549,13 @@ k_eval_batch(int N, int I, int LD, int panel, int64_t rows_x, int64_t rows_j, in
                     const int j = jj[u];
                     double G = GG[u], Bv = BB[u];
                     const bool diag = (j == b);
-                    if (OUTG) {
-                        if (of == b) {
-                            if (diag) {
-                                G -= oy[0];
-                                Bv -= oy[1];
-                            } else if (j == ot) {
-                                G -= oy[2];
-                                Bv -= oy[3];
-                            }
-                        } else if (ot == b) {
-                            if (diag) {
-                                G -= oy[6];
-                                Bv -= oy[7];
-                            } else if (j == of) {
-                                G -= oy[4];
-                                Bv -= oy[5];
-                            }
+                    if (OUTG && oc >= 0) {
+                        if (diag) {
+                            G -= dGd;
+                            Bv -= dBd;
+                        } else if (j == oc) {
+                            G -= dGo;
+                            Bv -= dBo;
                         }
                     }
                     double c[6], o[4];
@@ -1053,6 +1051,15 @@ int dev_create(HostPlan &hp, DevPlan **out) {
         if (!rc) rc = dupload(dp, &dp->lscale, hp.load_scale_t);
         if (!rc) rc = dupload(dp, &dp->pscale, hp.pv_scale_t);
         if (!rc) rc = dupload(dp, &dp->outage, hp.outage);
+        if (!rc && !hp.outage.empty()) {
+            std::vector<int32_t> ft(2 * hp.outage.size(), -1);
+            for (size_t k = 0; k < hp.outage.size(); ++k)
+                if (hp.outage[k] >= 0) {
+                    ft[2 * k] = hp.br_f[hp.outage[k]];
+                    ft[2 * k + 1] = hp.br_t[hp.outage[k]];
+                }
+            rc = dupload(dp, &dp->out_ft, ft);
+        }
         if (!rc && !hp.outage.empty()) rc = dalloc(dp, &dp->otab, size_t(hp.Bt) * 8);
         if (!rc) rc = dupload(dp, &dp->order_nat, hp.order_natural);
         if (!rc) rc = dupload(dp, &dp->order_bfs, hp.order_bfs);
@@ -1165,7 +1172,7 @@ int dev_eval_batch(HostPlan &hp, DevPlan *dp, const double *X, double *F, double
                        dp->bus4, dp->bus2,                                                    \
                        dp->spec, dp->ycol, dp->yG, dp->yB, dp->gen4, dp->gen2, dp->genpv,     \
                        dp->ldptr, dp->ldlist, lp, lq, dp->pv_p, dp->lscale, dp->pscale,       \
-                       dp->outage, dp->br_f, dp->br_t, dp->otab, X, F, J)
+                       dp->outage, dp->out_ft, dp->otab, X, F, J)
 #define LAUNCH_OV(WF, WJ)              \
     if (scen && outg)                  \
         LAUNCH(WF, WJ, true, true);    \
