@@ -46,7 +46,10 @@
  *  - Evaluation calls are asynchronous on the given HIP stream (NULL = the
  *    default stream), allocate nothing, and check their arguments
  *    synchronously; faults inside a kernel surface at the caller's next
- *    synchronisation.  A plan serves one stream at a time.
+ *    synchronisation.  Evaluation calls (pf_eval*, pf_vjp) only read the
+ *    plan's device data, so several may run at once on different streams;
+ *    pf_set_params, pf_set_schedule, pf_autotune and pf_newton must not
+ *    overlap any other call on the same plan.
  *  - All floating-point data are IEEE FP64, all indices int32, 0-based.
  *  - Results are deterministic: every bus sum is a fixed-order left fold, no
  *    floating-point atomics are used, and every schedule gives bit-identical
