@@ -15,9 +15,11 @@ step are measured:
 Prints one JSON line with the headline value, a roofline object for the
 dominant kernel and the CPU oracle timed on a bounded sample.
 
-Other workloads (--config): c2 = 10,000-bus grid x 1024 scenario and N-1
+The default run also summarises the other workloads under "others"; each
+can be run alone with --config: c2 = 10,000-bus grid x 1024 scenario and N-1
 instances; c3 = 256 grids of uneven size in one launch; c4 = adjoint (VJP)
-with 64 cotangents on the 70,000-bus grid.
+with 64 cotangents on the 70,000-bus grid; newton = Newton power flow on the
+70,000-bus grid with every step on the device; copy = HBM calibration.
 """
 
 from __future__ import annotations
@@ -281,7 +283,7 @@ def run_c1(args, torch, dev):
     if not args.no_others:
         out["others"] = {}
         for name, fn in (("scenarios_10k_x1024", run_c2), ("uneven_256_grids", run_c3),
-                         ("adjoint_70k_k64", run_c4)):
+                         ("adjoint_70k_k64", run_c4), ("newton_device_70k", run_newton)):
             log(f"[bench] {name}")
             out["others"][name] = fn(args, torch, dev, net70k=net,
                                      plain_us=res.get("plain", {}).get("us_per_eval"))
@@ -393,6 +395,67 @@ def run_c4(args, torch, dev, net70k=None, plain_us=None, **kw):
             "gbs": nb / (ms * 1e-3) / 1e9, "hbm_frac": nb / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS}
 
 
+def run_newton(args, torch, dev, **kw):
+    """Newton power flow on the 70,000-bus grid (a zero load added at every
+    bus without injection) toward a manufactured solution y*: loads and
+    generator set-points chosen so that F(y*) = 0, small angles at y*, start
+    within 1e-4 of it.  Every step on the device (evaluation, norm,
+    rocSOLVER re-factorisation along one host LU's pattern, triangular
+    solves, update) against the same Newton with the host sparse solve."""
+    from paper_2011_11880_amd import synth
+    from paper_2011_11880_amd.api import Plan
+    net = synth.fill_zero_injection_buses(synth.grid_70k())
+    N, NPV, NG = net.n_bus, net.n_pv, net.n_gen
+    ystar = synth.random_states(net, seed=4100)
+    ystar[:N] *= 0.03
+    p0 = Plan(net, device=0)
+    F0 = p0.eval_residual(torch.from_numpy(ystar).to(dev)).cpu().numpy()
+    p0.close()
+    has_load = np.zeros(N, bool)
+    has_load[net.load_bus] = True
+    net.load_p -= F0[net.load_bus]
+    net.load_q -= F0[N + net.load_bus]
+    pv_free = ~has_load[net.pv_bus]
+    net.pv_p[pv_free] += F0[net.pv_bus[pv_free]]
+    ystar[2 * N:2 * N + NPV][pv_free] += F0[N + net.pv_bus[pv_free]]
+    sl_free = ~has_load[net.slack_bus]
+    ystar[2 * N + NG:][sl_free] += F0[net.slack_bus[sl_free]]
+    ystar[2 * N + NPV:2 * N + NG][sl_free] += F0[N + net.slack_bus[sl_free]]
+    net.pv_v[:] = ystar[N + net.pv_bus]
+    net.slack_v[:] = ystar[N + net.slack_bus]
+    net.slack_theta[:] = ystar[net.slack_bus]
+    rng = np.random.default_rng(4101)
+    y0 = ystar + np.concatenate([rng.normal(0, 1e-4, 2 * N),
+                                 rng.normal(0, 2.5e-4, net.n_var - 2 * N)])
+    p = Plan(net, device=0)
+    x = torch.from_numpy(y0).to(dev)
+    t0 = time.perf_counter()
+    lu = p.device_lu(x)
+    t_lu = time.perf_counter() - t0
+    p.newton_device(x, lu)  # warm-up (first rocSOLVER calls)
+    reps = []
+    for _ in range(3):
+        x = torch.from_numpy(y0).to(dev)
+        reps.append(p.newton_device(x, lu))
+    rep = min(reps, key=lambda r: r["t_total_s"])
+    err = float(np.max(np.abs(x.cpu().numpy() - ystar)))
+    xh = torch.from_numpy(y0).to(dev)
+    reph = p.newton(xh)
+    it, ith = rep["iterations"], reph["iterations"]
+    return {"grid": "70,000 buses, 88,207 branches, zero loads on empty buses",
+            "n": p.n, "nnz": p.nnz, "nnz_lu": lu.nnzT, "host_lu_s": t_lu,
+            "device": {"iterations": it, "converged": rep["converged"],
+                       "final_norm": rep["norms"][-1], "max_error_vs_solution": err,
+                       "total_ms": rep["t_total_s"] * 1e3,
+                       "eval_ms_per_iter": rep["t_eval_s"] * 1e3 / (it + 1),
+                       "solve_ms_per_iter": rep["t_solve_s"] * 1e3 / max(it, 1)},
+            "host_solve": {"iterations": ith, "converged": reph["converged"],
+                           "total_ms": reph["t_total_s"] * 1e3,
+                           "eval_ms_per_iter": reph["t_eval_s"] * 1e3 / (ith + 1),
+                           "solve_ms_per_iter": reph["t_solve_s"] * 1e3 / max(ith, 1)},
+            "speedup_total": reph["t_total_s"] / rep["t_total_s"]}
+
+
 def run_copy(args, torch, dev):
     """Calibration: a plain device-to-device copy of known size (torch's
     copy kernel), the reference for HBM byte counters; also reports the
@@ -424,14 +487,14 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--config", default="c1", choices=["c1", "copy"])
+    ap.add_argument("--config", default="c1", choices=["c1", "c2", "c3", "c4", "newton", "copy"])
     ap.add_argument("--copy-mib", type=int, default=1024)
     ap.add_argument("--states", type=int, default=1000)
     ap.add_argument("--autotune", action="store_true")
     ap.add_argument("--no-plain", action="store_true")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-others", action="store_true",
-                    help="skip the scenario-batch, uneven-grid and adjoint summaries")
+                    help="skip the scenario-batch, uneven-grid, adjoint and Newton summaries")
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
     args = ap.parse_args()
     if args.gpus != 1:
@@ -444,7 +507,8 @@ def main():
         print("bench.py: no GPU available", file=sys.stderr)
         sys.exit(1)
     dev = torch.device("cuda", 0)
-    out = {"c1": run_c1, "copy": run_copy}[args.config](args, torch, dev)
+    out = {"c1": run_c1, "c2": run_c2, "c3": run_c3, "c4": run_c4, "newton": run_newton,
+           "copy": run_copy}[args.config](args, torch, dev)
     print(json.dumps(out), flush=True)
 
 

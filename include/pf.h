@@ -325,6 +325,57 @@ typedef struct pf_newton_report {
 int pf_newton(pf_plan *plan, double *x, const pf_newton_opts *opts,
               pf_linsolve_fn solve, void *user, pf_newton_report *report);
 
+/*
+ * Device-resident Newton (tasks 1-4 of Section I with task 3 on the GPU).
+ * The Jacobian pattern of a plan never changes, so one LU factorisation with
+ * pivoting of one Jacobian M of the plan,  P M Q = L U,  fixes the pattern of
+ * T = (L - I) + U and the row and column orders; rocSOLVER's sparse
+ * re-factorisation (csrrf) then factorises every later Jacobian of the plan
+ * on the device along that pattern, without pivoting again, and solves there.
+ *
+ * pf_refact_create: host inputs, read during the call only.
+ *   Jval_host  [nnz]   the values of M in pf_pattern order
+ *   T_rowptr   [n+1], T_colidx [nnzT], T_val [nnzT]: CSR of (L - I) + U, the
+ *              strictly lower part holding L without its unit diagonal;
+ *              columns strictly increasing within a row, diagonal present
+ *   pivP, pivQ [n]     row k of P M Q is row pivP[k] of M; column k is column
+ *              pivQ[k] of M
+ * The plan must be a non-batched device plan; the object keeps a pointer to
+ * it (destroy the object first) and owns its own device buffers (F, J, step,
+ * the factors).  rocSOLVER is loaded on the first call (PF_EDEVICE if it
+ * cannot be).  Malformed T or permutations -> PF_EINVAL.  Synchronises.
+ */
+typedef struct pf_refact pf_refact;
+
+int pf_refact_create(pf_plan *plan, const double *Jval_host, int64_t nnzT,
+                     const int32_t *T_rowptr, const int32_t *T_colidx,
+                     const double *T_val, const int32_t *pivP, const int32_t *pivQ,
+                     pf_refact **out);
+
+/* Refactorise with the Jacobian values Jval (device [nnz], pf_pattern order)
+ * and solve J y = b in place (b: device [n]).  Asynchronous on the stream;
+ * the factors are held in the object, so calls on one object must not
+ * overlap.  A zero pivot gives non-finite results rather than an error. */
+int pf_refact_solve(pf_refact *rf, const double *Jval, double *b, void *stream);
+
+/*
+ * Newton power flow with every step on the device: per iteration one fused
+ * evaluation (pf_eval), ||F||_inf by a device reduction (the only value
+ * copied to the host, for the convergence test), refactorisation and solve
+ * by rf, and x <- x - dx.  x: device [n], updated in place; opts and report
+ * as pf_newton, with t_eval_s the device time of the evaluations and
+ * t_solve_s the device time from the end of each evaluation to the end of
+ * its step (norm, refactorisation, triangular solves, update).  Runs on the
+ * given stream and synchronises it once per iteration.  Returns PF_ENOCONV if
+ * max_iter is reached.
+ */
+int pf_newton_device(pf_plan *plan, pf_refact *rf, double *x,
+                     const pf_newton_opts *opts, pf_newton_report *report,
+                     void *stream);
+
+/* Release the refactorisation object.  NULL is ignored. */
+void pf_refact_destroy(pf_refact *rf);
+
 /* Release the plan and all its device memory.  NULL is ignored. */
 void pf_destroy(pf_plan *plan);
 

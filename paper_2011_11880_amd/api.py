@@ -63,6 +63,25 @@ def params_vector(nets):
                 for k in ("br_r", "br_x", "br_b", "br_tap", "br_shift_deg", "load_p", "load_q")])
 
 
+def host_lu(rowptr, colidx, values, n, permc_spec="MMD_AT_PLUS_A"):
+    """One sparse LU with pivoting of the CSR matrix M on the host (SuperLU),
+    in the form the device re-factorisation takes:
+    (T_rowptr, T_colidx, T_val, pivP, pivQ) with T = (L - I) + U in CSR
+    (sorted columns) and M[pivP][:, pivQ] = L U."""
+    import scipy.sparse as sp
+    import scipy.sparse.linalg as spla
+    M = sp.csr_matrix((_f64(values), _i32(colidx), _i32(rowptr)), shape=(n, n))
+    lu = spla.splu(M.tocsc(), permc_spec=permc_spec)
+    # SuperLU: Pr M Pc = L U with (Pr M)[perm_r[i]] = M[i], (M Pc)[:, perm_c[j]] = M[:, j]
+    pivP = np.argsort(lu.perm_r).astype(np.int32)
+    pivQ = np.argsort(lu.perm_c).astype(np.int32)
+    T = (lu.L - sp.identity(n, format="csc") + lu.U).tocsr()
+    T.sum_duplicates()
+    T.sort_indices()
+    return (T.indptr.astype(np.int32), T.indices.astype(np.int32), T.data.astype(np.float64),
+            pivP, pivQ)
+
+
 def _opts(host_only=False, device=None, schedule=None):
     o = capi.pf_setup_opts()
     o.host_only = 1 if host_only else 0
@@ -177,6 +196,10 @@ class Plan:
 
     # lifetime ---------------------------------------------------------------
     def close(self):
+        for ref in getattr(self, "_lus", ()):
+            lu = ref()
+            if lu is not None:
+                lu.close()
         if self._h is not None and self._h.value:
             capi.lib().pf_destroy(self._h)
         self._h = None
@@ -377,3 +400,76 @@ class Plan:
                 "norms": [float(v) for v in rep.norm[:min(it + 1, 65)]],
                 "t_eval_s": rep.t_eval_s, "t_solve_s": rep.t_solve_s,
                 "t_total_s": rep.t_total_s, "solver_errors": errors}
+
+    def device_lu(self, x, permc_spec="MMD_AT_PLUS_A"):
+        """A DeviceLU for this plan, its pattern and pivots taken from one host
+        LU of the Jacobian at ``x`` (device [n])."""
+        return DeviceLU(self, x, permc_spec=permc_spec)
+
+    def newton_device(self, x, lu=None, tol=1e-10, max_iter=10):
+        """Newton power flow with every step on the device (pf_newton_device).
+        ``lu`` (a DeviceLU of this plan) is created at ``x`` when not given.
+        ``x`` is updated in place.  Returns a dict report (as ``newton``, plus
+        the time of the host LU if one was made)."""
+        import time
+        t_lu = 0.0
+        if lu is None:
+            t0 = time.perf_counter()
+            lu = DeviceLU(self, x)
+            t_lu = time.perf_counter() - t0
+        opts = capi.pf_newton_opts(tol=float(tol), max_iter=int(max_iter))
+        rep = capi.pf_newton_report()
+        rc = capi.lib().pf_newton_device(self._h, lu._h, _ptr(x, self.n, "x"),
+                                         ctypes.byref(opts), ctypes.byref(rep),
+                                         _stream(self._dev(x)))
+        if rc not in (capi.PF_OK, capi.PF_ENOCONV):
+            check(rc)
+        it = int(rep.iterations)
+        return {"iterations": it, "converged": bool(rep.converged),
+                "norms": [float(v) for v in rep.norm[:min(it + 1, 65)]],
+                "t_eval_s": rep.t_eval_s, "t_solve_s": rep.t_solve_s,
+                "t_total_s": rep.t_total_s, "t_host_lu_s": t_lu, "nnz_lu": lu.nnzT}
+
+
+class DeviceLU:
+    """Device re-factorisation (pf_refact_*) bound to one non-batched plan:
+    pattern and pivots from one host LU of the plan's Jacobian at ``x``,
+    every later factorisation and solve on the GPU (rocSOLVER csrrf)."""
+
+    def __init__(self, plan, x, permc_spec="MMD_AT_PLUS_A"):
+        import weakref
+        self.plan = plan
+        self._h = None
+        J = plan.eval_jacobian(x)
+        Jh = J.cpu().numpy()
+        rp, ci = plan.pattern()
+        trp, tci, tv, pivP, pivQ = host_lu(rp, ci, Jh, plan.n, permc_spec)
+        self.nnzT = int(trp[-1])
+        h = capi._vp()
+        check(capi.lib().pf_refact_create(
+            plan._h, Jh.ctypes.data_as(capi._pd), self.nnzT, trp.ctypes.data_as(capi._pi32),
+            tci.ctypes.data_as(capi._pi32), tv.ctypes.data_as(capi._pd),
+            pivP.ctypes.data_as(capi._pi32), pivQ.ctypes.data_as(capi._pi32), ctypes.byref(h)))
+        self._h = h
+        if not hasattr(plan, "_lus"):
+            plan._lus = []
+        plan._lus.append(weakref.ref(self))
+
+    def solve(self, J, b):
+        """Refactorise with the Jacobian values J (device [nnz]) and solve
+        J y = b in place (b: device [n]); returns b."""
+        n, nnz = self.plan.n, self.plan.nnz
+        check(capi.lib().pf_refact_solve(self._h, _ptr(J, nnz, "J"), _ptr(b, n, "b"),
+                                         _stream(b.device)))
+        return b
+
+    def close(self):
+        if self._h is not None and self._h.value:
+            capi.lib().pf_refact_destroy(self._h)
+        self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

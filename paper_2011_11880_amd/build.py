@@ -22,7 +22,7 @@ HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 ARCH = "gfx950"
 
 HOST_SRCS = ["pf_setup.cpp", "pf_api.cpp"]
-DEVICE_SRCS = ["pf_device.hip"]
+DEVICE_SRCS = ["pf_device.hip", "pf_lu.hip"]
 
 HIP_FLAGS = [
     f"--offload-arch={ARCH}", "-O3", "-std=c++17", "-fPIC",
@@ -59,7 +59,7 @@ def build(verbose: bool = False) -> str:
             print(out)
         objs.append(o)
     tmp = LIB + ".tmp%d" % os.getpid()
-    _run([HIPCC, f"--offload-arch={ARCH}", "-shared", "-fPIC", *objs, "-o", tmp])
+    _run([HIPCC, f"--offload-arch={ARCH}", "-shared", "-fPIC", *objs, "-ldl", "-o", tmp])
     os.replace(tmp, LIB)
     return LIB
 

@@ -108,6 +108,12 @@ SIGNATURES = {
     "pf_autotune": (ctypes.c_int, [_P, _vp, _vp, _vp, _i32, _vp, ctypes.POINTER(pf_schedule)]),
     "pf_newton": (ctypes.c_int, [_P, _vp, ctypes.POINTER(pf_newton_opts), pf_linsolve_fn, _vp,
                                  ctypes.POINTER(pf_newton_report)]),
+    "pf_refact_create": (ctypes.c_int, [_P, _pd, _i64, _pi32, _pi32, _pd, _pi32, _pi32,
+                                        ctypes.POINTER(_vp)]),
+    "pf_refact_solve": (ctypes.c_int, [_vp, _vp, _vp, _vp]),
+    "pf_newton_device": (ctypes.c_int, [_P, _vp, _vp, ctypes.POINTER(pf_newton_opts),
+                                        ctypes.POINTER(pf_newton_report), _vp]),
+    "pf_refact_destroy": (None, [_vp]),
     "pf_destroy": (None, [_P]),
     "pf_last_error": (ctypes.c_char_p, []),
 }

@@ -459,3 +459,19 @@ def with_parallel_branches(net: Network, n_par: int, seed: int) -> Network:
     out.br_shift_deg = cat([net.br_shift_deg, shift])
     out.br_status = _i32(cat([net.br_status, np.ones(n_par)]))
     return out
+
+
+def fill_zero_injection_buses(net: Network) -> Network:
+    """Copy of ``net`` with a zero load added at every bus that has neither a
+    load nor a generator, so that every bus row has an injection that a
+    manufactured solution can set."""
+    busy = np.zeros(net.n_bus, bool)
+    busy[net.load_bus] = True
+    busy[net.pv_bus] = True
+    busy[net.slack_bus] = True
+    add = np.nonzero(~busy)[0]
+    out = net.copy()
+    out.load_bus = _i32(np.concatenate([net.load_bus, add]))
+    out.load_p = np.concatenate([net.load_p, np.zeros(add.size)])
+    out.load_q = np.concatenate([net.load_q, np.zeros(add.size)])
+    return out
