@@ -35,13 +35,13 @@ class _Topo(ctypes.Structure):
                 ("n_slack", _i), ("n_shunt", _i),
                 ("br_from", _pi), ("br_to", _pi), ("br_status", _pi),
                 ("load_bus", _pi), ("pv_bus", _pi), ("slack_bus", _pi),
-                ("shunt_bus", _pi)]
+                ("shunt_bus", _pi), ("pv_mode", _pi)]
 
 
 class _Data(ctypes.Structure):
     _fields_ = [(k, _pd) for k in (
         "br_r", "br_x", "br_b", "br_tap", "br_shift_deg", "load_p", "load_q",
-        "pv_p", "pv_v", "slack_v", "slack_theta", "shunt_g", "shunt_b")]
+        "pv_p", "pv_v", "slack_v", "slack_theta", "shunt_g", "shunt_b", "pv_qtarget")]
 
 
 PARAM_FIELDS = ("br_r", "br_x", "br_b", "br_tap", "br_shift_deg", "load_p",
@@ -68,7 +68,7 @@ def _load(path):
     L = ctypes.CDLL(path)
     L.ora_residual.argtypes = [ctypes.POINTER(_Topo), ctypes.POINTER(_Data),
                                _pd, _pd, _pd]
-    L.ora_residual_cs.argtypes = [ctypes.POINTER(_Topo)] + [_pd] * 15
+    L.ora_residual_cs.argtypes = [ctypes.POINTER(_Topo)] + [_pd] * 16
     L.ora_branch_flows.argtypes = [ctypes.c_double] * 9 + [_pd]
     L.ora_jacobian_size.argtypes = [ctypes.POINTER(_Topo)]
     L.ora_jacobian_size.restype = ctypes.c_long
@@ -111,7 +111,7 @@ def _dp(a):
 class _Bound:
     """Keeps the numpy arrays behind the ctypes structures alive."""
 
-    def __init__(self, net, data=None):
+    def __init__(self, net, data=None, modes=None):
         self.arrs = {}
         keep = self.arrs
 
@@ -125,21 +125,34 @@ class _Bound:
             keep[name] = a
             return _dp(a)
 
+        # modes = (pv_mode, pv_qtarget): per PV generator 0 = voltage
+        # control, 1 = reactive output held at pv_qtarget
+        if modes is None:
+            mode = np.zeros(net.n_pv, np.int32)
+            qt = np.zeros(net.n_pv)
+        else:
+            mode = np.asarray(modes[0], dtype=np.int32)
+            qt = np.asarray(modes[1], dtype=np.float64)
+            assert mode.shape == (net.n_pv,) and qt.shape == (net.n_pv,)
+        mode = np.ascontiguousarray(mode)
+        keep["pv_mode"] = mode
         self.topo = _Topo(net.n_bus, net.n_branch, net.n_load, net.n_pv,
                           net.n_slack, net.n_shunt, I("br_from"), I("br_to"),
                           I("br_status"), I("load_bus"), I("pv_bus"),
-                          I("slack_bus"), I("shunt_bus"))
+                          I("slack_bus"), I("shunt_bus"), _ip(mode))
         data = data or {}
-        self.data = _Data(*[D(k, data.get(k, getattr(net, k))) for k in PARAM_FIELDS])
+        self.data = _Data(*[D(k, data.get(k, getattr(net, k))) for k in PARAM_FIELDS],
+                          D("pv_qtarget", qt))
 
 
 def n_var(net) -> int:
     return 2 * net.n_bus + net.n_pv + 2 * net.n_slack
 
 
-def residual(net, y, data=None):
-    """F(y) and the per-row sum of |terms| S (eq. 2)."""
-    b = _Bound(net, data)
+def residual(net, y, data=None, modes=None):
+    """F(y) and the per-row sum of |terms| S (eq. 2).  ``modes`` =
+    (pv_mode, pv_qtarget) switches PV generators to a held reactive output."""
+    b = _Bound(net, data, modes)
     y = np.ascontiguousarray(y, dtype=np.float64)
     n = n_var(net)
     assert y.shape == (n,)
@@ -149,9 +162,9 @@ def residual(net, y, data=None):
     return F, S
 
 
-def residual_complex(net, y, data=None):
+def residual_complex(net, y, data=None, modes=None):
     """F in complex arithmetic: ``y`` and any entry of ``data`` may be complex."""
-    b = _Bound(net)
+    b = _Bound(net, None, modes)
     data = data or {}
     keep = []
 
@@ -161,6 +174,7 @@ def residual_complex(net, y, data=None):
         return z.view(np.float64).ctypes.data_as(_pd)
 
     args = [Z(data.get(k, getattr(net, k))) for k in PARAM_FIELDS]
+    args.append(Z(np.zeros(net.n_pv) if modes is None else modes[1]))
     yz = Z(y)
     F = np.zeros(n_var(net), dtype=np.complex128)
     lib().ora_residual_cs(ctypes.byref(b.topo), *args, yz,
@@ -174,8 +188,8 @@ def branch_flows(r, x, bc, tap, shift_deg, vf, vt, thf, tht):
     return out
 
 
-def jacobian_coo(net, y, data=None):
-    b = _Bound(net, data)
+def jacobian_coo(net, y, data=None, modes=None):
+    b = _Bound(net, data, modes)
     y = np.ascontiguousarray(y, dtype=np.float64)
     m = lib().ora_jacobian_size(ctypes.byref(b.topo))
     rows = np.empty(m, np.int32)
@@ -186,11 +200,11 @@ def jacobian_coo(net, y, data=None):
     return rows[:k], cols[:k], vals[:k]
 
 
-def jacobian(net, y, data=None):
+def jacobian(net, y, data=None, modes=None):
     """(J, |J|-scale) as scipy CSR: triplets summed into a sparse matrix; the
     second matrix sums the absolute triplet values (used for tolerances)."""
     n = n_var(net)
-    r, c, v = jacobian_coo(net, y, data)
+    r, c, v = jacobian_coo(net, y, data, modes)
     J = sp.csr_matrix((v, (r, c)), shape=(n, n))
     A = sp.csr_matrix((np.abs(v), (r, c)), shape=(n, n))
     J.sort_indices()
@@ -198,13 +212,13 @@ def jacobian(net, y, data=None):
     return J, A
 
 
-def vjp(net, y, w, data=None):
+def vjp(net, y, w, data=None, modes=None):
     """(g_state, g_params) for the loss w.F: g_state = J^T w with the explicit
     Jacobian; g_params is a dict keyed by parameter name."""
     b = _Bound(net, data)
     y = np.ascontiguousarray(y, dtype=np.float64)
     w = np.ascontiguousarray(w, dtype=np.float64)
-    J, _ = jacobian(net, y, data)
+    J, _ = jacobian(net, y, data, modes)
     gx = J.T @ w
     B, L = net.n_branch, net.n_load
     out = {k: np.empty(B) for k in ("br_r", "br_x", "br_b", "br_tap", "br_shift_deg")}
@@ -231,19 +245,68 @@ def vjp_params_scale(net, y, w, data=None):
     return out
 
 
-def newton(net, y0, tol=1e-10, max_iter=10, data=None):
+def newton(net, y0, tol=1e-10, max_iter=10, data=None, modes=None):
     """Full-step Newton (tasks 1-4): returns (y, list of ||F||_inf per
     iteration, list of iterates).  The list of norms starts at y0."""
     y = np.array(y0, dtype=np.float64)
     norms, iters = [], [y.copy()]
     for it in range(max_iter + 1):
-        F, _ = residual(net, y, data)
+        F, _ = residual(net, y, data, modes)
         nf = float(np.max(np.abs(F))) if F.size else 0.0
         norms.append(nf)
         if nf < tol or it == max_iter:
             break
-        J, _ = jacobian(net, y, data)
+        J, _ = jacobian(net, y, data, modes)
         dx = spla.spsolve(J.tocsc(), F)
         y = y - dx
         iters.append(y.copy())
     return y, norms, iters
+
+
+def q_limit_switch(net, y, mode, qt, qmin, qmax, tol=1e-9):
+    """One check of the PV generators' reactive limits (Section II-A: the
+    formulation lets the limits be checked during the iterations, and a PV
+    generator that reaches one becomes a PQ injection under the same
+    equations).  A generator under voltage control whose Q_g has left
+    [qmin, qmax] by more than tol is held at the violated limit.  A held
+    generator returns to voltage control when its bus voltage has crossed
+    the set point to the side where less reactive output would hold it:
+    above V_set when held at qmax, below V_set when held at qmin.
+    Returns (mode, qt, number of switches) as new arrays."""
+    N = net.n_bus
+    mode = np.array(mode, dtype=np.int32)
+    qt = np.array(qt, dtype=np.float64)
+    switched = 0
+    for k in range(net.n_pv):
+        q = y[2 * N + k]
+        v = y[N + net.pv_bus[k]]
+        if mode[k] == 0:
+            if q > qmax[k] + tol:
+                mode[k], qt[k] = 1, qmax[k]
+                switched += 1
+            elif q < qmin[k] - tol:
+                mode[k], qt[k] = 1, qmin[k]
+                switched += 1
+        else:
+            at_max = qt[k] == qmax[k]
+            if (at_max and v > net.pv_v[k] + tol) or (not at_max and v < net.pv_v[k] - tol):
+                mode[k], qt[k] = 0, 0.0
+                switched += 1
+    return mode, qt, switched
+
+
+def newton_qlim(net, y0, qmin, qmax, tol=1e-10, max_iter=10, max_outer=10):
+    """Newton power flow with reactive limits: solve, check the limits,
+    switch, and solve again from the last state until no generator
+    switches.  Returns (y, mode, qt, outer rounds, converged)."""
+    y = np.array(y0, dtype=np.float64)
+    mode = np.zeros(net.n_pv, np.int32)
+    qt = np.zeros(net.n_pv)
+    for outer in range(1, max_outer + 1):
+        y, norms, _ = newton(net, y, tol, max_iter, modes=(mode, qt))
+        if not norms[-1] < tol:
+            return y, mode, qt, outer, False
+        mode, qt, ns = q_limit_switch(net, y, mode, qt, qmin, qmax)
+        if ns == 0:
+            return y, mode, qt, outer, True
+    return y, mode, qt, max_outer, False

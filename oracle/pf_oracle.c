@@ -33,6 +33,9 @@ typedef struct {
     int n_bus, n_branch, n_load, n_pv, n_slack, n_shunt;
     const int *br_from, *br_to, *br_status;
     const int *load_bus, *pv_bus, *slack_bus, *shunt_bus;
+    /* per PV generator: 0 = voltage control, 1 = reactive output held at a
+       target (a PV generator switched to a PQ injection); NULL = all 0 */
+    const int *pv_mode;
 } ora_topo;
 
 /* numeric data of a network, real build */
@@ -40,6 +43,7 @@ typedef struct {
     const double *br_r, *br_x, *br_b, *br_tap, *br_shift_deg;
     const double *load_p, *load_q, *pv_p, *pv_v, *slack_v, *slack_theta;
     const double *shunt_g, *shunt_b;
+    const double *pv_qtarget;   /* per PV generator; read where pv_mode is 1 */
 } ora_data;
 
 /* ---- real instantiation ---- */
@@ -73,7 +77,7 @@ void ora_residual(const ora_topo *tp, const ora_data *d, const double *y,
 {
     residual_d(tp, d->br_r, d->br_x, d->br_b, d->br_tap, d->br_shift_deg,
                d->load_p, d->load_q, d->pv_p, d->pv_v, d->slack_v,
-               d->slack_theta, d->shunt_g, d->shunt_b, y, F, S);
+               d->slack_theta, d->shunt_g, d->shunt_b, d->pv_qtarget, y, F, S);
 }
 
 /*
@@ -87,12 +91,13 @@ void ora_residual_cs(const ora_topo *tp, const double *br_r, const double *br_x,
                      const double *load_q, const double *pv_p,
                      const double *pv_v, const double *slack_v,
                      const double *slack_theta, const double *shunt_g,
-                     const double *shunt_b, const double *y, double *F)
+                     const double *shunt_b, const double *pv_qtarget,
+                     const double *y, double *F)
 {
 #define Z(p) ((const double complex *)(const void *)(p))
     residual_z(tp, Z(br_r), Z(br_x), Z(br_b), Z(br_tap), Z(br_shift_deg),
                Z(load_p), Z(load_q), Z(pv_p), Z(pv_v), Z(slack_v),
-               Z(slack_theta), Z(shunt_g), Z(shunt_b), Z(y),
+               Z(slack_theta), Z(shunt_g), Z(shunt_b), Z(pv_qtarget), Z(y),
                (double complex *)(void *)F, NULL);
 #undef Z
 }
@@ -151,7 +156,10 @@ long ora_jacobian(const ora_topo *tp, const ora_data *dd, const double *y,
     for (e = 0; e < NPV; ++e) {
         i = tp->pv_bus[e];
         k = put(rows, cols, vals, k, N + i, 2 * N + e, -1.0);     /* dFq/dQg */
-        k = put(rows, cols, vals, k, 2 * N + e, N + i, 1.0);      /* dFV/dV */
+        if (tp->pv_mode && tp->pv_mode[e])
+            k = put(rows, cols, vals, k, 2 * N + e, 2 * N + e, 1.0);  /* d(Qg - Qt)/dQg */
+        else
+            k = put(rows, cols, vals, k, 2 * N + e, N + i, 1.0);      /* dFV/dV */
     }
     /* Slack generators */
     for (e = 0; e < NS; ++e) {

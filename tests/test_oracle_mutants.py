@@ -14,6 +14,7 @@ import subprocess
 import pytest
 
 import test_oracle_pins as P
+import test_oracle_qlim as Q
 
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 ORA = os.path.join(ROOT, "oracle")
@@ -55,6 +56,9 @@ MUTANTS = [
     ("vjp shift unit", "pf_oracle.c", "g_shift[e] = -(wpf * B1 + wqf * (-A1) + wpt * B2 + wqt * A2) *\n                     (ORA_PI / 180.0);",
      "g_shift[e] = -(wpf * B1 + wqf * (-A1) + wpt * B2 + wqt * A2);"),
     ("vjp load index", "pf_oracle.c", "g_lq[e] = w[N + tp->load_bus[e]];", "g_lq[e] = w[tp->load_bus[e]];"),
+    ("held PV row uses V", "ora_core.inc", "FV[k] = Qg[k] - pv_qt[k];", "FV[k] = V[i] - pv_qt[k];"),
+    ("J held PV column", "pf_oracle.c", "k = put(rows, cols, vals, k, 2 * N + e, 2 * N + e, 1.0);",
+     "k = put(rows, cols, vals, k, 2 * N + e, N + i, 1.0);"),
 ]
 
 PINS = [
@@ -71,6 +75,8 @@ PINS = [
     P.test_sizes_and_pattern,
     P.test_vjp_state_is_transpose_product,
     P.test_vjp_params_complex_step,
+    Q.test_held_output_equals_pq_injection,
+    lambda o: Q.test_jacobian_complex_step_with_held_outputs(o, "tiny"),
 ]
 
 
