@@ -142,11 +142,16 @@ typedef struct pf_schedule {
  *              with PF_EINVAL.  Used for CPU-side checks.
  *   device     HIP device ordinal; -1 = the calling thread's current device
  *   sched      initial schedule
+ *   q_limits   1: every PV generator's control row also holds its Q_g column
+ *              (the row then has two slots, V then Q_g; nnz grows by the
+ *              number of PV units), so that pf_set_gen_modes can hold the
+ *              generator at a reactive target without changing the pattern
  */
 typedef struct pf_setup_opts {
     int32_t host_only;
     int32_t device;
     pf_schedule sched;
+    int32_t q_limits;
 } pf_setup_opts;
 
 typedef struct pf_plan pf_plan;
@@ -324,6 +329,36 @@ typedef struct pf_newton_report {
 
 int pf_newton(pf_plan *plan, double *x, const pf_newton_opts *opts,
               pf_linsolve_fn solve, void *user, pf_newton_report *report);
+
+/*
+ * Reactive limits of PV generators (Section II-A: the extended formulation
+ * lets the limits be checked during the iterations, and the same equations
+ * serve before and after a PV generator becomes a PQ injection).  A held
+ * generator keeps its Q_g variable; its control row becomes
+ * Q_g - Q_target (slot values 0 at V, 1 at Q_g) instead of V - V_set (1 at
+ * V, 0 at Q_g).  Needs a plan set up with q_limits = 1 (else PF_EINVAL).
+ * Modes apply to every instance of a batched plan.
+ *
+ * pf_set_gen_modes: host arrays over the plan's PV units (grid by grid, in
+ *   input order): mode[k] 0 = voltage control, 1 = held at q_target[k]
+ *   (q_target may be NULL when every mode is 0).  Synchronous; must not
+ *   overlap an evaluation on the plan.
+ * pf_get_gen_modes: the current modes and targets (either pointer may be
+ *   NULL).
+ * pf_q_limit_check: one check against q_min, q_max (host [n_pv]) at the
+ *   state x (device [n], non-batched plans): a unit under voltage control
+ *   whose Q_g is outside [q_min - tol, q_max + tol] is held at the violated
+ *   limit; a held unit returns to voltage control when its bus voltage
+ *   exceeds V_set + tol while held at q_max, or falls below V_set - tol
+ *   while held at q_min.  The new modes are applied as by pf_set_gen_modes;
+ *   *n_switched (nullable) receives the number of changes.  Copies x to the
+ *   host (synchronous, default stream).  A Newton solve with limits repeats
+ *   solve -> check until nothing switches.
+ */
+int pf_set_gen_modes(pf_plan *plan, const int32_t *mode, const double *q_target);
+int pf_get_gen_modes(const pf_plan *plan, int32_t *mode, double *q_target);
+int pf_q_limit_check(pf_plan *plan, const double *x, const double *q_min,
+                     const double *q_max, double tol, int32_t *n_switched);
 
 /*
  * Device-resident Newton (tasks 1-4 of Section I with task 3 on the GPU).

@@ -82,9 +82,10 @@ def host_lu(rowptr, colidx, values, n, permc_spec="MMD_AT_PLUS_A"):
             pivP, pivQ)
 
 
-def _opts(host_only=False, device=None, schedule=None):
+def _opts(host_only=False, device=None, schedule=None, q_limits=False):
     o = capi.pf_setup_opts()
     o.host_only = 1 if host_only else 0
+    o.q_limits = 1 if q_limits else 0
     o.device = -1 if device is None else int(device)
     if schedule:
         for k, v in schedule.items():
@@ -124,14 +125,14 @@ class Plan:
     """
 
     def __init__(self, net=None, *, batch=None, host_only=False, device=None, schedule=None,
-                 _handle=None):
+                 q_limits=False, _handle=None):
         self._h = None
         L = capi.lib()
         if _handle is not None:
             self._h = _handle
         else:
             ns = _NetStruct(net)
-            opts = _opts(host_only, device, schedule)
+            opts = _opts(host_only, device, schedule, q_limits)
             h = capi._P()
             if batch is None:
                 check(L.pf_setup(ctypes.byref(ns.s), ctypes.byref(opts), ctypes.byref(h)))
@@ -168,10 +169,10 @@ class Plan:
         self.device = device
 
     @classmethod
-    def multi(cls, nets, *, host_only=False, device=None, schedule=None):
+    def multi(cls, nets, *, host_only=False, device=None, schedule=None, q_limits=False):
         structs = [_NetStruct(n) for n in nets]
         arr = (capi.pf_network * len(structs))(*[s.s for s in structs])
-        opts = _opts(host_only, device, schedule)
+        opts = _opts(host_only, device, schedule, q_limits)
         h = capi._P()
         check(capi.lib().pf_setup_multi(arr, len(structs), ctypes.byref(opts), ctypes.byref(h)))
         p = cls(_handle=h, device=device)
@@ -400,6 +401,65 @@ class Plan:
                 "norms": [float(v) for v in rep.norm[:min(it + 1, 65)]],
                 "t_eval_s": rep.t_eval_s, "t_solve_s": rep.t_solve_s,
                 "t_total_s": rep.t_total_s, "solver_errors": errors}
+
+    # reactive limits ------------------------------------------------------
+    def set_gen_modes(self, mode, q_target=None):
+        """Hold PV units at reactive targets (mode 1) or return them to
+        voltage control (mode 0); arrays over the plan's PV units."""
+        m = _i32(mode)
+        if m.shape != (self.info["n_pv"],):
+            raise ValueError("mode must have one entry per PV unit")
+        qt = None if q_target is None else _f64(q_target)
+        if qt is not None and qt.shape != m.shape:
+            raise ValueError("q_target must match mode")
+        check(capi.lib().pf_set_gen_modes(self._h, m.ctypes.data_as(capi._pi32),
+                                          None if qt is None else qt.ctypes.data_as(capi._pd)))
+
+    def gen_modes(self):
+        """(mode, q_target) of the plan's PV units."""
+        k = self.info["n_pv"]
+        m = np.zeros(k, np.int32)
+        qt = np.zeros(k)
+        check(capi.lib().pf_get_gen_modes(self._h, m.ctypes.data_as(capi._pi32),
+                                          qt.ctypes.data_as(capi._pd)))
+        return m, qt
+
+    def q_limit_check(self, x, q_min, q_max, tol=1e-9):
+        """One reactive-limit check at the state x (pf_q_limit_check); returns
+        the number of PV units that switched."""
+        lo, hi = _f64(q_min), _f64(q_max)
+        ns = ctypes.c_int32(0)
+        check(capi.lib().pf_q_limit_check(self._h, _ptr(x, self.n, "x"),
+                                          lo.ctypes.data_as(capi._pd),
+                                          hi.ctypes.data_as(capi._pd), float(tol),
+                                          ctypes.byref(ns)))
+        return int(ns.value)
+
+    def newton_qlim(self, x, q_min, q_max, device=False, tol=1e-10, max_iter=10,
+                    max_outer=10, switch_tol=1e-9):
+        """Newton power flow with reactive limits: solve (host or device
+        solve), check the limits, and solve again from the last state until
+        no unit switches.  After a switch a held row's nonzero moves from
+        the V column to the Q_g column, so the device path takes a fresh
+        host LU (new pivots) for the next solve.  ``x`` is updated in place."""
+        rounds = []
+        lu = None
+        for outer in range(1, max_outer + 1):
+            if device:
+                if lu is None:
+                    lu = DeviceLU(self, x)
+                rep = self.newton_device(x, lu, tol=tol, max_iter=max_iter)
+            else:
+                rep = self.newton(x, tol=tol, max_iter=max_iter)
+            rounds.append(rep)
+            if not rep["converged"]:
+                return {"converged": False, "outer": outer, "rounds": rounds}
+            if self.q_limit_check(x, q_min, q_max, switch_tol) == 0:
+                return {"converged": True, "outer": outer, "rounds": rounds}
+            if lu is not None:
+                lu.close()
+                lu = None
+        return {"converged": False, "outer": max_outer, "rounds": rounds}
 
     def device_lu(self, x, permc_spec="MMD_AT_PLUS_A"):
         """A DeviceLU for this plan, its pattern and pivots taken from one host

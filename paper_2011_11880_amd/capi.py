@@ -57,7 +57,8 @@ class pf_schedule(ctypes.Structure):
 
 
 class pf_setup_opts(ctypes.Structure):
-    _fields_ = [("host_only", _i32), ("device", _i32), ("sched", pf_schedule)]
+    _fields_ = [("host_only", _i32), ("device", _i32), ("sched", pf_schedule),
+                ("q_limits", _i32)]
 
 
 class pf_batch_spec(ctypes.Structure):
@@ -108,6 +109,9 @@ SIGNATURES = {
     "pf_autotune": (ctypes.c_int, [_P, _vp, _vp, _vp, _i32, _vp, ctypes.POINTER(pf_schedule)]),
     "pf_newton": (ctypes.c_int, [_P, _vp, ctypes.POINTER(pf_newton_opts), pf_linsolve_fn, _vp,
                                  ctypes.POINTER(pf_newton_report)]),
+    "pf_set_gen_modes": (ctypes.c_int, [_P, _pi32, _pd]),
+    "pf_get_gen_modes": (ctypes.c_int, [_P, _pi32, _pd]),
+    "pf_q_limit_check": (ctypes.c_int, [_P, _vp, _pd, _pd, ctypes.c_double, _pi32]),
     "pf_refact_create": (ctypes.c_int, [_P, _pd, _i64, _pi32, _pi32, _pd, _pi32, _pi32,
                                         ctypes.POINTER(_vp)]),
     "pf_refact_solve": (ctypes.c_int, [_vp, _vp, _vp, _vp]),

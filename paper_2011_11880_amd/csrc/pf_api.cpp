@@ -53,6 +53,7 @@ int pf_setup(const pf_network *net, const pf_setup_opts *opt, pf_plan **out) {
     if (!p) return fail(PF_ENOMEM, "host allocation failed");
     int rc;
     try {
+        p->host.q_slots = (opt && opt->q_limits) ? 1 : 0;
         rc = build_host_plan(net, 1, p->host);
     } catch (const std::bad_alloc &) {
         rc = fail(PF_ENOMEM, "host allocation failed");
@@ -72,6 +73,7 @@ int pf_setup_batch(const pf_network *net, const pf_batch_spec *spec, const pf_se
     if (!p) return fail(PF_ENOMEM, "host allocation failed");
     int rc;
     try {
+        p->host.q_slots = (opt && opt->q_limits) ? 1 : 0;
         rc = build_host_plan(net, 1, p->host);
         if (!rc) rc = attach_batch(spec, p->host);
     } catch (const std::bad_alloc &) {
@@ -92,6 +94,7 @@ int pf_setup_multi(const pf_network *nets, int32_t n_grids, const pf_setup_opts 
     if (!p) return fail(PF_ENOMEM, "host allocation failed");
     int rc;
     try {
+        p->host.q_slots = (opt && opt->q_limits) ? 1 : 0;
         rc = build_host_plan(nets, n_grids, p->host);
         p->host.kind = KIND_MULTI;
     } catch (const std::bad_alloc &) {

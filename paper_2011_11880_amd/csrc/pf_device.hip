@@ -388,11 +388,14 @@ k_eval_single(const int4 *__restrict__ tiles, int ntiles, int tiles_per_wave, in
                 if (g >= 0) {
                     const int4 g4 = gen4[g];
                     const double2 gs = gen2[g];
-                    fq = fq - x[g4.x];
-                    if (WF) stc(&F[g4.x], vi - gs.x);
+                    const double qg = x[g4.x];
+                    const bool held = g4.z == kGenHeld;
+                    fq = fq - qg;
+                    if (WF) stc(&F[g4.x], held ? qg - gs.x : vi - gs.x);
                     if (WJ) {
                         putQ(bi.w + 2 * Lr, -1.0);
-                        stc(&J[g4.y], 1.0);
+                        stc(&J[g4.y], held ? 0.0 : 1.0);
+                        if (g4.z <= kGenVoltageSlot) stc(&J[g4.y + 1], held ? 1.0 : 0.0);
                     }
                     if (g4.z >= 0) {
                         fp = fp - x[g4.z];
@@ -601,11 +604,15 @@ k_eval_batch(int N, int I, int LD, int panel, int64_t rows_x, int64_t rows_j, in
             if (g >= 0) {
                 const int4 g4 = gen4[g];
                 const double2 gs = gen2[g];
-                fq = fq - Xc[size_t(g4.x) * SI + kq];
-                if (WF) st(&Fc[size_t(g4.x) * SI + kq], vi - gs.x);
+                const double qg = Xc[size_t(g4.x) * SI + kq];
+                const bool held = g4.z == kGenHeld;
+                fq = fq - qg;
+                if (WF) st(&Fc[size_t(g4.x) * SI + kq], held ? qg - gs.x : vi - gs.x);
                 if (WJ) {
                     st(&Jc[size_t(bi.w + 2 * Lr) * SI + kq], -1.0);
-                    st(&Jc[size_t(g4.y) * SI + kq], 1.0);
+                    st(&Jc[size_t(g4.y) * SI + kq], held ? 0.0 : 1.0);
+                    if (g4.z <= kGenVoltageSlot)
+                        st(&Jc[size_t(g4.y + 1) * SI + kq], held ? 1.0 : 0.0);
                 }
                 if (g4.z >= 0) {
                     fp = fp - Xc[size_t(g4.z) * SI + kq];
@@ -690,8 +697,12 @@ k_vjp_state(const int4 *__restrict__ tiles, int ntiles, int n_kchunks,
         double gt = accT, gv = accV;
         if (b2.y >= 0) {
             const int4 g4 = gen4[b2.y];
-            gv = gv + W[size_t(g4.x) * SK + kk];   // V-control row: +1 at (V row, V_a)
-            if (kvalid) st(&gx[size_t(g4.x) * SK + k], -wQa);   // Q_g column: -1 in row Q_a
+            const double wv = W[size_t(g4.x) * SK + kk];
+            const bool held = g4.z == kGenHeld;
+            // control row: +1 at (V row, V_a) under voltage control, +1 at
+            // (V row, Q_g) when the output is held; Q_g column: -1 in row Q_a
+            if (!held) gv = gv + wv;
+            if (kvalid) st(&gx[size_t(g4.x) * SK + k], held ? wv - wQa : -wQa);
             if (g4.z >= 0) {
                 gt = gt + W[size_t(g4.z) * SK + kk];   // angle row: +1 at (theta row, theta_a)
                 if (kvalid) st(&gx[size_t(g4.z) * SK + k], -wPa);   // P_s column
@@ -988,6 +999,17 @@ int dev_upload_tiles(HostPlan &hp, DevPlan *dp) {
     }
     if (nt) HIP_TRY(hipMemcpy(dp->tiles, hp.tiles.data(), 2 * size_t(nt) * sizeof(int4),
                               hipMemcpyHostToDevice));
+    return PF_OK;
+}
+
+int dev_upload_gens(const HostPlan &hp, DevPlan *dp) {
+    DeviceGuard g(dp->device);
+    if (!g.ok) return fail(PF_EDEVICE, "cannot select device %d", dp->device);
+    if (hp.NGt == 0) return PF_OK;
+    HIP_TRY(hipMemcpy(dp->gen4, hp.gen4.data(), hp.gen4.size() * sizeof(int32_t),
+                      hipMemcpyHostToDevice));
+    HIP_TRY(hipMemcpy(dp->gen2, hp.gen2.data(), hp.gen2.size() * sizeof(double),
+                      hipMemcpyHostToDevice));
     return PF_OK;
 }
 

@@ -41,6 +41,11 @@ struct GridDev {
 
 enum PlanKind : int32_t { KIND_SINGLE = 0, KIND_BATCH = 1, KIND_MULTI = 2 };
 
+// Third field of a PV unit's gen4 record (a slack's holds its P_s index):
+// voltage control with a single control-row slot, voltage control with the
+// Q_g slot present (written 0), or reactive output held at gen2.x.
+constexpr int32_t kGenVoltage = -1, kGenVoltageSlot = -2, kGenHeld = -3;
+
 struct HostPlan {
     int32_t kind = KIND_SINGLE;
     int32_t n_inst = 1;
@@ -75,9 +80,16 @@ struct HostPlan {
 
     // per generator (global: grid by grid, PV units then slacks)
     std::vector<int32_t> gen4;      // NGt * 4: Q_g var (= V row), V-row slot,
-                                    //          P_s var (= theta row) or -1, theta-row slot
-    std::vector<double> gen2;       // NGt * 2: V setpoint, theta setpoint
+                                    //          P_s var (= theta row) or a PV mode (kGen*),
+                                    //          theta-row slot (-1 for PV units)
+    std::vector<double> gen2;       // NGt * 2: V setpoint (Q target when held), theta setpoint
     std::vector<int32_t> genpv;     // NGt: PV unit id (global) or -1 for a slack
+    // reactive-limit support: with q_slots every PV unit's control row also
+    // holds its Q_g column (the row's second slot), so the unit can be held
+    // at a reactive target; pv_gen maps PV unit -> generator
+    int32_t q_slots = 0;
+    std::vector<int32_t> pv_gen, pv_mode;   // NPVt each
+    std::vector<double> pv_vset, pv_qt;      // NPVt each
 
     // per branch / device (global ids)
     std::vector<int32_t> br_f, br_t;   // global bus ids
@@ -114,6 +126,7 @@ int dev_create(HostPlan &hp, DevPlan **out);
 void dev_destroy(DevPlan *dp);
 int dev_upload_tiles(HostPlan &hp, DevPlan *dp);
 int dev_set_params(HostPlan &hp, DevPlan *dp, const double *params_dev, void *stream);
+int dev_upload_gens(const HostPlan &hp, DevPlan *dp);
 int dev_eval_single(HostPlan &hp, DevPlan *dp, const double *x, double *F,
                     double *J, void *stream);
 int dev_eval_batch(HostPlan &hp, DevPlan *dp, const double *X, double *F,

@@ -1,0 +1,127 @@
+// Reactive limits of PV generators (Section II-A): the extended formulation
+// keeps a generator's Q_g variable when it stops controlling its voltage, so
+// holding it at a reactive target only changes its control row from
+// V - V_set to Q_g - Q_target.  Plans set up with q_limits carry both slots
+// in that row; the mode lives in the generator table the kernels already
+// read (see kGenHeld).  This file holds the host side: setting modes and
+// one check of the limits against a state.
+#include <cmath>
+#include <vector>
+
+#include <hip/hip_runtime.h>
+
+#include "pf_internal.hpp"
+
+using namespace pf;
+
+namespace {
+
+int need_slots(const pf_plan *plan) {
+    if (!plan) return fail(PF_EINVAL, "plan is NULL");
+    if (!plan->host.q_slots)
+        return fail(PF_EINVAL, "the plan was set up without q_limits (no Q_g slot in PV rows)");
+    return PF_OK;
+}
+
+// Write the modes into the generator table (host) and upload it.
+int apply(pf_plan *plan) {
+    HostPlan &hp = plan->host;
+    for (int32_t k = 0; k < hp.NPVt; ++k) {
+        const size_t g = size_t(hp.pv_gen[size_t(k)]);
+        const bool held = hp.pv_mode[size_t(k)] != 0;
+        hp.gen4[4 * g + 2] = held ? kGenHeld : kGenVoltageSlot;
+        hp.gen2[2 * g] = held ? hp.pv_qt[size_t(k)] : hp.pv_vset[size_t(k)];
+    }
+    if (hp.host_only || !plan->dev) return PF_OK;
+    return dev_upload_gens(hp, plan->dev);
+}
+
+}  // namespace
+
+extern "C" {
+
+int pf_set_gen_modes(pf_plan *plan, const int32_t *mode, const double *q_target) {
+    clear_error();
+    int rc = need_slots(plan);
+    if (rc) return rc;
+    HostPlan &hp = plan->host;
+    const size_t NPV = size_t(hp.NPVt);
+    if (NPV && !mode) return fail(PF_EINVAL, "mode is NULL");
+    for (size_t k = 0; k < NPV; ++k) {
+        if (mode[k] != 0 && mode[k] != 1) return fail(PF_EINVAL, "mode[%zu] must be 0 or 1", k);
+        if (mode[k] == 1) {
+            if (!q_target) return fail(PF_EINVAL, "q_target is NULL but mode[%zu] is 1", k);
+            if (!std::isfinite(q_target[k]))
+                return fail(PF_EINVAL, "q_target[%zu] is not finite", k);
+        }
+    }
+    for (size_t k = 0; k < NPV; ++k) {
+        hp.pv_mode[k] = mode[k];
+        hp.pv_qt[k] = mode[k] ? q_target[k] : 0.0;
+    }
+    return apply(plan);
+}
+
+int pf_get_gen_modes(const pf_plan *plan, int32_t *mode, double *q_target) {
+    clear_error();
+    if (!plan) return fail(PF_EINVAL, "plan is NULL");
+    const HostPlan &hp = plan->host;
+    for (size_t k = 0; k < size_t(hp.NPVt); ++k) {
+        if (mode) mode[k] = hp.pv_mode.empty() ? 0 : hp.pv_mode[k];
+        if (q_target) q_target[k] = hp.pv_qt.empty() ? 0.0 : hp.pv_qt[k];
+    }
+    return PF_OK;
+}
+
+int pf_q_limit_check(pf_plan *plan, const double *x, const double *q_min, const double *q_max,
+                     double tol, int32_t *n_switched) {
+    clear_error();
+    int rc = need_slots(plan);
+    if (rc) return rc;
+    HostPlan &hp = plan->host;
+    if (hp.host_only || !plan->dev) return fail(PF_EINVAL, "plan is host-only");
+    if (hp.kind == KIND_BATCH) return fail(PF_EINVAL, "pf_q_limit_check needs a non-batched plan");
+    if (!x || (hp.NPVt && (!q_min || !q_max))) return fail(PF_EINVAL, "NULL argument");
+    if (!(tol >= 0.0)) return fail(PF_EINVAL, "tol must be >= 0");
+    const size_t NPV = size_t(hp.NPVt);
+    for (size_t k = 0; k < NPV; ++k)
+        if (!(q_min[k] <= q_max[k])) return fail(PF_EINVAL, "q_min[%zu] > q_max[%zu]", k, k);
+    std::vector<double> xh(size_t(hp.n));
+    int prev = -1;
+    if (hipGetDevice(&prev) != hipSuccess) return fail(PF_EDEVICE, "hipGetDevice failed");
+    if (prev != hp.device && hipSetDevice(hp.device) != hipSuccess)
+        return fail(PF_EDEVICE, "cannot select device %d", hp.device);
+    hipError_t e = hipMemcpy(xh.data(), x, xh.size() * sizeof(double), hipMemcpyDeviceToHost);
+    if (prev != hp.device) (void)hipSetDevice(prev);
+    if (e != hipSuccess) return fail(PF_EDEVICE, "copy of x failed: %s", hipGetErrorString(e));
+    int32_t switched = 0;
+    for (size_t k = 0; k < NPV; ++k) {
+        const size_t g = size_t(hp.pv_gen[k]);
+        const double qg = xh[size_t(hp.gen4[4 * g])];
+        // the unit's bus: its V variable is the only V column of its row,
+        // i.e. the first slot's column
+        const double v = xh[size_t(hp.colidx[size_t(hp.gen4[4 * g + 1])])];
+        if (hp.pv_mode[k] == 0) {
+            if (qg > q_max[k] + tol) {
+                hp.pv_mode[k] = 1;
+                hp.pv_qt[k] = q_max[k];
+                ++switched;
+            } else if (qg < q_min[k] - tol) {
+                hp.pv_mode[k] = 1;
+                hp.pv_qt[k] = q_min[k];
+                ++switched;
+            }
+        } else {
+            const bool at_max = hp.pv_qt[k] == q_max[k];
+            if ((at_max && v > hp.pv_vset[k] + tol) || (!at_max && v < hp.pv_vset[k] - tol)) {
+                hp.pv_mode[k] = 0;
+                hp.pv_qt[k] = 0.0;
+                ++switched;
+            }
+        }
+    }
+    if (n_switched) *n_switched = switched;
+    return switched ? apply(plan) : PF_OK;
+}
+
+}  // extern "C"

@@ -144,6 +144,10 @@ int build_host_plan(const pf_network *nets, int32_t n_grids, HostPlan &hp) {
     hp.gen4.clear();
     hp.gen2.clear();
     hp.genpv.clear();
+    hp.pv_gen.clear();
+    hp.pv_vset.clear();
+    hp.pv_mode.assign(size_t(hp.NPVt), 0);
+    hp.pv_qt.assign(size_t(hp.NPVt), 0.0);
     hp.br_f.resize(hp.Bt);
     hp.br_t.resize(hp.Bt);
     hp.br_on.resize(hp.Bt);
@@ -229,7 +233,7 @@ int build_host_plan(const pf_network *nets, int32_t n_grids, HostPlan &hp) {
             rp[i + 1] = 2LL * rl[i] + (slack_at[i] >= 0 ? 1 : 0);
             rp[N + i + 1] = 2LL * rl[i] + (gen_at[i] >= 0 ? 1 : 0);
         }
-        for (int k = 0; k < NG + NS; ++k) rp[2LL * N + k + 1] = 1;
+        for (int k = 0; k < NG + NS; ++k) rp[2LL * N + k + 1] = (hp.q_slots && k < NPV) ? 2 : 1;
         for (int64_t r = 0; r < nloc; ++r) rp[r + 1] += rp[r];
         const int64_t nnz = rp[nloc];
         if (joff + nnz >= std::numeric_limits<int32_t>::max())
@@ -253,6 +257,8 @@ int build_host_plan(const pf_network *nets, int32_t n_grids, HostPlan &hp) {
         for (int k = 0; k < NG; ++k) {
             const int bus = k < NPV ? n.pv_bus[k] : n.slack_bus[k - NPV];
             hp.colidx[size_t(joff + rp[2LL * N + k])] = int32_t(xoff + N + bus);
+            if (hp.q_slots && k < NPV)   // the unit's own Q_g column (the diagonal)
+                hp.colidx[size_t(joff + rp[2LL * N + k]) + 1] = int32_t(xoff + 2LL * N + k);
         }
         for (int s = 0; s < NS; ++s)
             hp.colidx[size_t(joff + rp[2LL * N + NG + s])] = int32_t(xoff + n.slack_bus[s]);
@@ -349,11 +355,16 @@ int build_host_plan(const pf_network *nets, int32_t n_grids, HostPlan &hp) {
             const int s = k - NPV;
             hp.gen4.push_back(int32_t(xoff + 2LL * N + k));
             hp.gen4.push_back(int32_t(joff + rp[2LL * N + k]));
-            hp.gen4.push_back(pv ? -1 : int32_t(xoff + 2LL * N + NG + s));
+            hp.gen4.push_back(pv ? (hp.q_slots ? kGenVoltageSlot : kGenVoltage)
+                                 : int32_t(xoff + 2LL * N + NG + s));
             hp.gen4.push_back(pv ? -1 : int32_t(joff + rp[2LL * N + NG + s]));
             hp.gen2.push_back(pv ? n.pv_v[k] : n.slack_v[s]);
             hp.gen2.push_back(pv ? 0.0 : n.slack_theta[s]);
             hp.genpv.push_back(pv ? pv_off + k : -1);
+            if (pv) {
+                hp.pv_gen.push_back(gen_off + k);
+                hp.pv_vset.push_back(n.pv_v[k]);
+            }
         }
         // shunts and loads per bus (stable: input order within a bus)
         for (int k = 0; k < n.n_shunt; ++k) hp.shptr[bus_off + n.shunt_bus[k] + 1]++;

@@ -1,0 +1,200 @@
+"""GPU parity of reactive-limit support: evaluation with PV units held at
+reactive targets (single, batched, multi-grid, adjoint) against the
+oracle, the library's limit check against the oracle's rule, and Newton
+with limits (host and device solves) against the oracle's outer loop."""
+
+import numpy as np
+import pytest
+
+from paper_2011_11880_amd import synth
+from parity import check_close, check_jacobian
+from test_oracle_pins import _net_with_everything
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+
+@pytest.fixture(scope="module")
+def cuda():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    return torch.device("cuda", 0)
+
+
+def _modes(net, seed, frac=0.4):
+    rng = np.random.default_rng(seed)
+    mode = (rng.random(net.n_pv) < frac).astype(np.int32)
+    qt = np.where(mode == 1, rng.normal(0, 0.5, net.n_pv), 0.0)
+    return mode, qt
+
+
+@pytest.mark.parametrize("which", ["tiny", "everything", "10k"])
+def test_eval_with_held_units(ora, cuda, which):
+    from paper_2011_11880_amd.api import Plan
+    net = {"tiny": lambda: synth.tiny_grid(6), "everything": _net_with_everything,
+           "10k": synth.grid_10k}[which]()
+    p = Plan(net, q_limits=True)
+    rp, ci = p.pattern()
+    y = synth.random_states(net, seed=8)
+    x = torch.from_numpy(y).to(cuda)
+    for mode, qt in ((np.zeros(net.n_pv, np.int32), np.zeros(net.n_pv)), _modes(net, 1),
+                     (np.ones(net.n_pv, np.int32), np.linspace(-1, 1, net.n_pv))):
+        p.set_gen_modes(mode, qt)
+        F, J = p.eval(x)
+        torch.cuda.synchronize()
+        Fo, So = ora.residual(net, y, modes=(mode, qt))
+        Jo, Ao = ora.jacobian(net, y, modes=(mode, qt))
+        check_close(F.cpu().numpy(), Fo, So, f"{which} F")
+        check_jacobian(rp, ci, J.cpu().numpy(), Jo, Ao, f"{which} J")
+    # voltage control with the slot present equals the plain plan's values
+    p.set_gen_modes(np.zeros(net.n_pv, np.int32))
+    F1, J1 = p.eval(x)
+    p0 = Plan(net)
+    F0, J0 = p0.eval(x)
+    torch.cuda.synchronize()
+    assert torch.equal(F0, F1)
+    rp0, ci0 = p0.pattern()
+    N = net.n_bus
+    extra = np.zeros(p.nnz, bool)
+    for k in range(net.n_pv):
+        extra[rp[2 * N + k] + 1] = True
+    assert torch.equal(J0.cpu(), J1.cpu()[torch.from_numpy(~extra)])
+    assert not J1.cpu()[torch.from_numpy(extra)].any()
+
+
+def test_batched_and_multi_with_held_units(ora, cuda):
+    from paper_2011_11880_amd.api import Plan
+    net = synth.tiny_grid(12)
+    mode, qt = _modes(net, 3)
+    I = 70
+    Y = synth.random_states(net, I, seed=9)
+    bp = Plan(net, batch=dict(n_inst=I), q_limits=True)
+    bp.set_gen_modes(mode, qt)
+    F, J = bp.eval_batch(torch.from_numpy(bp.to_batch(Y)).to(cuda))
+    torch.cuda.synchronize()
+    Fi, Ji = bp.from_batch(F), bp.from_batch(J)
+    sp_ = Plan(net, q_limits=True)
+    sp_.set_gen_modes(mode, qt)
+    rp, ci = sp_.pattern()
+    for i in (0, 33, 69):
+        Fs, Js = sp_.eval(torch.from_numpy(Y[i]).to(cuda))
+        torch.cuda.synchronize()
+        assert np.array_equal(Fs.cpu().numpy(), Fi[i]) and np.array_equal(Js.cpu().numpy(), Ji[i])
+        Fo, So = ora.residual(net, Y[i], modes=(mode, qt))
+        Jo, Ao = ora.jacobian(net, Y[i], modes=(mode, qt))
+        check_close(Fi[i], Fo, So, f"inst {i} F")
+        check_jacobian(rp, ci, Ji[i], Jo, Ao, f"inst {i} J")
+    # two grids: modes over the concatenated PV units
+    nets = [synth.tiny_grid(13, n_bus=60, n_branch=80, n_pv=9), net]
+    mp = Plan.multi(nets, q_limits=True)
+    m2, q2 = _modes(nets[0], 5)
+    mp.set_gen_modes(np.concatenate([m2, mode]), np.concatenate([q2, qt]))
+    ys = [synth.random_states(n, seed=20 + g) for g, n in enumerate(nets)]
+    F, J = mp.eval(torch.from_numpy(np.concatenate(ys)).to(cuda))
+    torch.cuda.synchronize()
+    F, J = F.cpu().numpy(), J.cpu().numpy()
+    for g, (n, md) in enumerate(zip(nets, [(m2, q2), (mode, qt)])):
+        Fo, So = ora.residual(n, ys[g], modes=md)
+        Jo, Ao = ora.jacobian(n, ys[g], modes=md)
+        check_close(F[mp.x_off[g]:mp.x_off[g + 1]], Fo, So, f"grid {g} F")
+        pg = Plan(n, host_only=True, q_limits=True)
+        rpg, cig = pg.pattern()
+        check_jacobian(rpg, cig, J[mp.j_off[g]:mp.j_off[g + 1]], Jo, Ao, f"grid {g} J")
+
+
+def test_adjoint_with_held_units(ora, cuda):
+    from paper_2011_11880_amd.api import Plan
+    net = _net_with_everything()
+    mode, qt = _modes(net, 7, frac=0.5)
+    p = Plan(net, q_limits=True)
+    p.set_gen_modes(mode, qt)
+    y = synth.random_states(net, seed=3)
+    K = 5
+    W = np.random.default_rng(2).normal(size=(p.n, K))
+    gx, _ = p.vjp(torch.from_numpy(y).to(cuda), torch.from_numpy(W).to(cuda))
+    torch.cuda.synchronize()
+    gx = gx.cpu().numpy()
+    Jo, Ao = ora.jacobian(net, y, modes=(mode, qt))
+    for k in range(K):
+        ref = Jo.T @ W[:, k]
+        scale = abs(Ao).T @ np.abs(W[:, k])
+        check_close(gx[:, k], ref, scale, f"J^T w[{k}]")
+
+
+def test_limit_check_matches_oracle_rule(ora, cuda):
+    from paper_2011_11880_amd.api import Plan
+    net = synth.tiny_grid(14)
+    N = net.n_bus
+    p = Plan(net, q_limits=True)
+    rng = np.random.default_rng(6)
+    y = synth.random_states(net, seed=6)
+    qmin = rng.uniform(-1.0, -0.2, net.n_pv)
+    qmax = rng.uniform(0.2, 1.0, net.n_pv)
+    # start: some units held at either limit, the rest under voltage control
+    mode0 = np.zeros(net.n_pv, np.int32)
+    qt0 = np.zeros(net.n_pv)
+    mode0[::5] = 1
+    qt0[::10] = qmax[::10]
+    qt0[5::10] = qmin[5::10]
+    for trial in range(3):
+        y[2 * N:2 * N + net.n_pv] = rng.uniform(-1.5, 1.5, net.n_pv)
+        y[N + net.pv_bus] = net.pv_v + rng.uniform(-0.02, 0.02, net.n_pv)
+        p.set_gen_modes(mode0, qt0)
+        ns = p.q_limit_check(torch.from_numpy(y).to(cuda), qmin, qmax, tol=1e-9)
+        m_o, qt_o, ns_o = ora.q_limit_switch(net, y, mode0, qt0, qmin, qmax, tol=1e-9)
+        m, qt = p.gen_modes()
+        assert ns == ns_o and ns > 0
+        assert np.array_equal(m, m_o) and np.array_equal(qt, qt_o)
+
+
+def _limits_case(ora, net0, seed, ang, pert, lo_idx, hi_idx, margin):
+    import test_gpu_newton_device as D
+    net, ystar, y0 = D._manufactured(ora, net0, seed, ang=ang, pert=pert)
+    N, NPV = net.n_bus, net.n_pv
+    q = ystar[2 * N:2 * N + NPV]
+    qmin, qmax = q - 10.0, q + 10.0
+    qmax[hi_idx] = q[hi_idx] - margin
+    qmin[lo_idx] = q[lo_idx] + margin
+    return net, y0, qmin, qmax
+
+
+@pytest.mark.parametrize("device", [False, True])
+def test_newton_with_limits_matches_oracle(ora, cuda, device):
+    from paper_2011_11880_amd.api import Plan
+    net, y0, qmin, qmax = _limits_case(ora, synth.tiny_grid(11), 11, 0.3, (0.02, 0.05),
+                                       [2, 30], [1, 4, 9, 20], 0.05)
+    y_o, m_o, qt_o, outer_o, ok_o = ora.newton_qlim(net, y0, qmin, qmax)
+    assert ok_o and m_o.any()
+    p = Plan(net, q_limits=True)
+    x = torch.from_numpy(y0).to(cuda)
+    rep = p.newton_qlim(x, qmin, qmax, device=device)
+    assert rep["converged"] and rep["outer"] == outer_o
+    m, qt = p.gen_modes()
+    assert np.array_equal(m, m_o) and np.array_equal(qt, qt_o)
+    np.testing.assert_allclose(x.cpu().numpy(), y_o, rtol=0, atol=1e-9)
+
+
+def test_newton_with_limits_10k_device(ora, cuda):
+    """10k grid: ten units above their upper limit at the solution, by
+    0.002.  Larger shifts of held outputs make Newton wander on the
+    synthetic grid's weak corridors. The plain switching rule can also
+    cycle: a unit forced up by its lower limit raises a capped neighbour's
+    voltage, and on some corridors a unit's voltage rises as its output is
+    cut. So upper limits only, on units where the oracle's outer loop
+    settles. Device Newton with limits ends where that loop does."""
+    from paper_2011_11880_amd.api import Plan
+    net0 = synth.grid_10k()
+    rng = np.random.default_rng(16)
+    pick = rng.choice(net0.n_pv, 10, replace=False)
+    net, y0, qmin, qmax = _limits_case(ora, net0, 3, 0.03, (1e-4, 2.5e-4),
+                                       [], pick, 0.002)
+    y_o, m_o, qt_o, outer_o, ok_o = ora.newton_qlim(net, y0, qmin, qmax)
+    assert ok_o and m_o.sum() >= 10
+    p = Plan(net, q_limits=True)
+    x = torch.from_numpy(y0).to(cuda)
+    rep = p.newton_qlim(x, qmin, qmax, device=True)
+    assert rep["converged"] and rep["outer"] == outer_o
+    m, qt = p.gen_modes()
+    assert np.array_equal(m, m_o) and np.array_equal(qt, qt_o)
+    np.testing.assert_allclose(x.cpu().numpy(), y_o, rtol=0, atol=1e-8)

@@ -1,0 +1,80 @@
+"""Host side of reactive-limit support (no GPU): the pattern of a plan set
+up with q_limits, and the mode entry points' checks."""
+
+import numpy as np
+import pytest
+import scipy.sparse as sp
+
+from paper_2011_11880_amd import capi, synth
+from paper_2011_11880_amd.api import Plan
+from paper_2011_11880_amd.capi import PFError
+from test_oracle_pins import _net_with_everything
+
+
+@pytest.mark.parametrize("which", ["tiny", "everything"])
+def test_pattern_is_union_of_both_modes(ora, which):
+    net = synth.tiny_grid(3) if which == "tiny" else _net_with_everything()
+    p0 = Plan(net, host_only=True)
+    p = Plan(net, host_only=True, q_limits=True)
+    assert p.nnz == p0.nnz + net.n_pv and p.n == p0.n
+    y = synth.random_states(net, seed=2)
+    ones = np.ones(net.n_pv, np.int32)
+    J0, _ = ora.jacobian(net, y)
+    J1, _ = ora.jacobian(net, y, modes=(ones, np.zeros(net.n_pv)))
+    U = (abs(J0) + abs(J1)).tocsr()
+    U.data[:] = 1
+    U.sort_indices()
+    rp, ci = p.pattern()
+    # structural pattern of the union (explicit zeros of either side kept)
+    S0 = sp.csr_matrix((np.ones(J0.nnz), J0.indices, J0.indptr), shape=J0.shape)
+    S1 = sp.csr_matrix((np.ones(J1.nnz), J1.indices, J1.indptr), shape=J1.shape)
+    Su = (S0 + S1).tocsr()
+    Su.sort_indices()
+    assert np.array_equal(rp, Su.indptr) and np.array_equal(ci, Su.indices)
+    # each PV control row: V column, then the unit's own Q_g column
+    N = net.n_bus
+    for k in range(net.n_pv):
+        r = 2 * N + k
+        assert list(ci[rp[r]:rp[r + 1]]) == [N + net.pv_bus[k], 2 * N + k]
+
+
+def test_multi_grid_pattern_with_slots():
+    nets = [synth.tiny_grid(1, n_bus=30, n_branch=40, n_pv=4), synth.tiny_grid(2)]
+    p0 = Plan.multi(nets, host_only=True)
+    p = Plan.multi(nets, host_only=True, q_limits=True)
+    assert p.nnz == p0.nnz + sum(n.n_pv for n in nets)
+
+
+def test_mode_entry_points():
+    net = synth.tiny_grid(4)
+    p = Plan(net, host_only=True, q_limits=True)
+    m, qt = p.gen_modes()
+    assert not m.any() and not qt.any()
+    mode = np.zeros(net.n_pv, np.int32)
+    mode[[0, 7]] = 1
+    target = np.linspace(-1, 1, net.n_pv)
+    p.set_gen_modes(mode, target)
+    m, qt = p.gen_modes()
+    assert np.array_equal(m, mode)
+    assert qt[0] == target[0] and qt[7] == target[7] and not np.delete(qt, [0, 7]).any()
+    p.set_gen_modes(np.zeros(net.n_pv, np.int32))   # all back to voltage control
+    assert not p.gen_modes()[0].any()
+    bad = mode.copy()
+    bad[3] = 2
+    with pytest.raises(PFError) as ei:
+        p.set_gen_modes(bad, target)
+    assert ei.value.code == capi.PF_EINVAL
+    with pytest.raises(PFError):
+        p.set_gen_modes(mode, None)           # held without a target
+    t2 = target.copy()
+    t2[7] = np.nan
+    with pytest.raises(PFError):
+        p.set_gen_modes(mode, t2)
+    assert not p.gen_modes()[0].any()         # a rejected call changes nothing
+    plain = Plan(net, host_only=True)
+    with pytest.raises(PFError) as ei:
+        plain.set_gen_modes(mode, target)
+    assert "q_limits" in str(ei.value)
+    with pytest.raises(PFError) as ei:          # the check needs a device plan
+        p.q_limit_check(None, np.zeros(net.n_pv), np.ones(net.n_pv))
+    assert ei.value.code == capi.PF_EINVAL
