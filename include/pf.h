@@ -411,6 +411,65 @@ int pf_newton_device(pf_plan *plan, pf_refact *rf, double *x,
 /* Release the refactorisation object.  NULL is ignored. */
 void pf_refact_destroy(pf_refact *rf);
 
+/*
+ * Fast decoupled power flow, XB variant (the conclusion names it as another
+ * method that reuses the same equation evaluation).  Constant matrices,
+ * built from the network given at setup (single-grid plans):
+ *   B'  over the buses without a slack: per in-service branch the weight
+ *       1/x only (the weighted Laplacian, slack rows and columns removed);
+ *   B'' over the buses without a voltage controller: -Im(Y_bus) of the full
+ *       pi-models with taps, charging and bus shunts, phase shifts left out.
+ * Rows follow ascending bus number; columns are sorted.
+ *
+ * pf_fdlf_matrices: host outputs, all nullable; call once with NULL arrays
+ *   to learn nnz_bp and nnz_bpp.  Row counts are N - N_slack (B') and
+ *   N - N_gen (B'').  bp_bus / bpp_bus receive the bus of every row.
+ */
+int pf_fdlf_matrices(const pf_plan *plan, int64_t *nnz_bp, int32_t *bp_rowptr,
+                     int32_t *bp_colidx, double *bp_val, int32_t *bp_bus,
+                     int64_t *nnz_bpp, int32_t *bpp_rowptr, int32_t *bpp_colidx,
+                     double *bpp_val, int32_t *bpp_bus);
+
+/*
+ * A constant sparse factorisation on the device: the n x n CSR matrix M and
+ * one host LU of it (P M Q = L U in the form pf_refact_create takes), all
+ * host arrays read during the call.  device < 0: the current device.
+ * pf_lu_solve solves M y = b in place (b: device [n]) on the stream; calls
+ * on one object must not overlap.  Errors as pf_refact_create.
+ */
+typedef struct pf_lu pf_lu;
+
+int pf_lu_create(int32_t device, int64_t n, int64_t nnz, const int32_t *rowptr,
+                 const int32_t *colidx, const double *val, int64_t nnzT,
+                 const int32_t *T_rowptr, const int32_t *T_colidx,
+                 const double *T_val, const int32_t *pivP, const int32_t *pivQ,
+                 pf_lu **out);
+int pf_lu_solve(pf_lu *lu, double *b, void *stream);
+void pf_lu_destroy(pf_lu *lu);
+
+/*
+ * pf_fdlf_create: bind a plan and the factorisations of its B' and B'' (NULL
+ * for an empty matrix); the object keeps pointers to all three (destroy it
+ * first) and owns its device buffers.
+ * pf_fdlf_solve: x (device [n]) updated in place.  Controlled voltages and
+ * slack angles are set to their set points (the method never steps them);
+ * then per iteration, each step from a fresh residual (pf_eval_residual's
+ * kernel), theta[B' buses] -= B'^-1 (F_p / V) and V[B'' buses] -=
+ * B''^-1 (F_q / V), until max |F| over those rows < tol; then Q_g and P_s
+ * take the values that zero their buses' rows.  report: norm[k] = that
+ * maximum before iteration k (k = 0..iterations), norm[iterations + 1] =
+ * ||F||_inf at the end; converged if that is below tol too; t_eval_s the
+ * device time of the residual evaluations, t_solve_s the wall time of the
+ * half-steps.  Needs every PV unit under voltage control.  PF_ENOCONV if
+ * max_iter (<= 64) is reached.  Synchronises the stream once per iteration.
+ */
+typedef struct pf_fdlf pf_fdlf;
+
+int pf_fdlf_create(pf_plan *plan, pf_lu *bp, pf_lu *bpp, pf_fdlf **out);
+int pf_fdlf_solve(pf_fdlf *fd, double *x, const pf_newton_opts *opts,
+                  pf_newton_report *report, void *stream);
+void pf_fdlf_destroy(pf_fdlf *fd);
+
 /* Release the plan and all its device memory.  NULL is ignored. */
 void pf_destroy(pf_plan *plan);
 

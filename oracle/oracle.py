@@ -310,3 +310,104 @@ def newton_qlim(net, y0, qmin, qmax, tol=1e-10, max_iter=10, max_outer=10):
         if ns == 0:
             return y, mode, qt, outer, True
     return y, mode, qt, max_outer, False
+
+
+def fdlf_matrices(net):
+    """Constant matrices of the fast decoupled method, XB variant (the
+    method the paper's conclusion names as another user of the same
+    residual evaluation).  B' (angle step) over the buses without a slack:
+    per in-service branch the weight 1/x only (resistance, taps, shifts and
+    charging left out), so B' is the weighted Laplacian of the network with
+    the slack rows and columns removed.  B'' (voltage step) over the buses
+    with no voltage controller: -Im(Y_bus) of the full pi-models with taps,
+    charging and bus shunts, phase shifts left out.  Returns
+    (Bp, Bpp, buses of B' rows, buses of B'' rows) with CSR matrices."""
+    N = net.n_bus
+    ctrl = np.zeros(N, bool)
+    ctrl[net.pv_bus] = True
+    ctrl[net.slack_bus] = True
+    slack = np.zeros(N, bool)
+    slack[net.slack_bus] = True
+    rows_p = np.nonzero(~slack)[0]
+    rows_q = np.nonzero(~ctrl)[0]
+    ip = -np.ones(N, np.int64)
+    ip[rows_p] = np.arange(rows_p.size)
+    iq = -np.ones(N, np.int64)
+    iq[rows_q] = np.arange(rows_q.size)
+    P = {}
+    Q = {}
+
+    def add(D, idx, i, j, v):
+        a, b = idx[i], idx[j]
+        if a >= 0 and b >= 0:
+            D[(a, b)] = D.get((a, b), 0.0) + v
+
+    for e in range(net.n_branch):
+        if net.br_status is not None and not net.br_status[e]:
+            continue
+        f, t = int(net.br_from[e]), int(net.br_to[e])
+        w = 1.0 / net.br_x[e]
+        add(P, ip, f, f, w)
+        add(P, ip, t, t, w)
+        add(P, ip, f, t, -w)
+        add(P, ip, t, f, -w)
+        r, x, bc, tap = net.br_r[e], net.br_x[e], net.br_b[e], net.br_tap[e]
+        b = -x / (r * r + x * x)          # Im of the series admittance
+        add(Q, iq, f, f, -(b + bc / 2) / (tap * tap))
+        add(Q, iq, t, t, -(b + bc / 2))
+        add(Q, iq, f, t, b / tap)
+        add(Q, iq, t, f, b / tap)
+    for k in range(net.n_shunt):
+        i = int(net.shunt_bus[k])
+        add(Q, iq, i, i, -net.shunt_b[k])
+
+    def csr(D, m):
+        if not D:
+            return sp.csr_matrix((m, m))
+        keys = np.array(list(D.keys()))
+        M = sp.csr_matrix((np.array(list(D.values())), (keys[:, 0], keys[:, 1])), shape=(m, m))
+        M.sort_indices()
+        return M
+
+    return csr(P, rows_p.size), csr(Q, rows_q.size), rows_p, rows_q
+
+
+def fdlf(net, y0, tol=1e-10, max_iter=50):
+    """Fast decoupled power flow (XB): per iteration an angle half-step
+    theta <- theta - B'^-1 (F_p / V) over the non-slack buses, then a voltage
+    half-step V <- V - B''^-1 (F_q / V) over the buses without a voltage
+    controller, each from a fresh residual.  The generator variables are
+    not stepped: once the bus mismatches are below tol, Q_g and P_s take the
+    values that zero their buses' rows.  Controlled voltages and slack
+    angles are never stepped, so they start at their set points.  Returns
+    (y, norms, iterates) with norms[k] the largest mismatch of the stepped
+    rows before iteration k and the last entry ||F||_inf after the
+    generator update."""
+    N, NPV, NG = net.n_bus, net.n_pv, net.n_gen
+    Bp, Bpp, rp, rq = fdlf_matrices(net)
+    lup = spla.splu(Bp.tocsc()) if rp.size else None
+    luq = spla.splu(Bpp.tocsc()) if rq.size else None
+    y = np.array(y0, dtype=np.float64)
+    y[N + net.pv_bus] = net.pv_v
+    y[N + net.slack_bus] = net.slack_v
+    y[net.slack_bus] = net.slack_theta
+    norms, iters = [], [y.copy()]
+    for it in range(max_iter + 1):
+        F, _ = residual(net, y)
+        m = max(np.max(np.abs(F[rp]), initial=0.0), np.max(np.abs(F[N + rq]), initial=0.0))
+        norms.append(float(m))
+        if m < tol or it == max_iter:
+            break
+        if lup is not None:
+            y[rp] -= lup.solve(F[rp] / y[N + rp])
+        F, _ = residual(net, y)
+        if luq is not None:
+            y[N + rq] -= luq.solve(F[N + rq] / y[N + rq])
+        iters.append(y.copy())
+    F, _ = residual(net, y)
+    y[2 * N:2 * N + NPV] += F[N + net.pv_bus]
+    y[2 * N + NPV:2 * N + NG] += F[N + net.slack_bus]
+    y[2 * N + NG:] += F[net.slack_bus]
+    F, _ = residual(net, y)
+    norms.append(float(np.max(np.abs(F))))
+    return y, norms, iters

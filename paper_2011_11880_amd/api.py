@@ -197,6 +197,13 @@ class Plan:
 
     # lifetime ---------------------------------------------------------------
     def close(self):
+        fd = getattr(self, "_fd", None)
+        if fd is not None:
+            capi.lib().pf_fdlf_destroy(fd[0])
+            for lu in fd[1]:
+                if lu is not None:
+                    lu.close()
+            self._fd = None
         for ref in getattr(self, "_lus", ()):
             lu = ref()
             if lu is not None:
@@ -461,6 +468,58 @@ class Plan:
                 lu = None
         return {"converged": False, "outer": max_outer, "rounds": rounds}
 
+    # fast decoupled method -------------------------------------------------
+    def fdlf_matrices(self):
+        """(B', B'', buses of B' rows, buses of B'' rows) as scipy CSR
+        (pf_fdlf_matrices)."""
+        import scipy.sparse as sp
+        L = capi.lib()
+        n1, n2 = ctypes.c_int64(0), ctypes.c_int64(0)
+        check(L.pf_fdlf_matrices(self._h, ctypes.byref(n1), None, None, None, None,
+                                 ctypes.byref(n2), None, None, None, None))
+        N = self.info["n_bus"]
+        m1 = N - self.info["n_slack"]
+        m2 = N - self.info["n_pv"] - self.info["n_slack"]
+        a = [np.zeros(m1 + 1, np.int32), np.zeros(n1.value, np.int32), np.zeros(n1.value),
+             np.zeros(m1, np.int32)]
+        b = [np.zeros(m2 + 1, np.int32), np.zeros(n2.value, np.int32), np.zeros(n2.value),
+             np.zeros(m2, np.int32)]
+        P = (capi._pi32, capi._pi32, capi._pd, capi._pi32)
+        check(L.pf_fdlf_matrices(self._h, None, *[v.ctypes.data_as(t) for v, t in zip(a, P)],
+                                 None, *[v.ctypes.data_as(t) for v, t in zip(b, P)]))
+        Bp = sp.csr_matrix((a[2], a[1], a[0]), shape=(m1, m1))
+        Bpp = sp.csr_matrix((b[2], b[1], b[0]), shape=(m2, m2))
+        return Bp, Bpp, a[3], b[3]
+
+    def fdlf(self, x, tol=1e-10, max_iter=50):
+        """Fast decoupled power flow (XB) with every iteration on the device
+        (pf_fdlf_solve).  B' and B'' are factorised once per plan (host LU,
+        then constant device factors).  ``x`` is updated in place."""
+        import time
+        t_setup = 0.0
+        if getattr(self, "_fd", None) is None:
+            t0 = time.perf_counter()
+            Bp, Bpp, _, _ = self.fdlf_matrices()
+            dev = self.device if self.device is not None else -1
+            lus = [DeviceSparseLU(M, dev) if M.shape[0] else None for M in (Bp, Bpp)]
+            h = capi._vp()
+            check(capi.lib().pf_fdlf_create(self._h, lus[0] and lus[0]._h,
+                                            lus[1] and lus[1]._h, ctypes.byref(h)))
+            self._fd = (h, lus)
+            t_setup = time.perf_counter() - t0
+        opts = capi.pf_newton_opts(tol=float(tol), max_iter=int(max_iter))
+        rep = capi.pf_newton_report()
+        rc = capi.lib().pf_fdlf_solve(self._fd[0], _ptr(x, self.n, "x"), ctypes.byref(opts),
+                                      ctypes.byref(rep), _stream(self._dev(x)))
+        if rc not in (capi.PF_OK, capi.PF_ENOCONV):
+            check(rc)
+        it = int(rep.iterations)
+        conv = rc == capi.PF_OK
+        return {"iterations": it, "converged": conv,
+                "norms": [float(v) for v in rep.norm[:min(it + 2 if conv else it + 1, 65)]],
+                "t_eval_s": rep.t_eval_s, "t_solve_s": rep.t_solve_s,
+                "t_total_s": rep.t_total_s, "t_setup_s": t_setup}
+
     def device_lu(self, x, permc_spec="MMD_AT_PLUS_A"):
         """A DeviceLU for this plan, its pattern and pivots taken from one host
         LU of the Jacobian at ``x`` (device [n])."""
@@ -526,6 +585,44 @@ class DeviceLU:
     def close(self):
         if self._h is not None and self._h.value:
             capi.lib().pf_refact_destroy(self._h)
+        self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class DeviceSparseLU:
+    """Constant device factorisation of a host CSR matrix (pf_lu_*): one host
+    LU (SuperLU) fixes the factors, solves run on the GPU."""
+
+    def __init__(self, M, device=-1, permc_spec="MMD_AT_PLUS_A"):
+        M = M.tocsr()
+        M.sort_indices()
+        n = M.shape[0]
+        rp, ci, v = M.indptr.astype(np.int32), M.indices.astype(np.int32), _f64(M.data)
+        trp, tci, tv, pivP, pivQ = host_lu(rp, ci, v, n, permc_spec)
+        self.n = n
+        self._h = None
+        h = capi._vp()
+        check(capi.lib().pf_lu_create(
+            int(device), n, int(M.nnz), rp.ctypes.data_as(capi._pi32),
+            ci.ctypes.data_as(capi._pi32), v.ctypes.data_as(capi._pd), int(trp[-1]),
+            trp.ctypes.data_as(capi._pi32), tci.ctypes.data_as(capi._pi32),
+            tv.ctypes.data_as(capi._pd), pivP.ctypes.data_as(capi._pi32),
+            pivQ.ctypes.data_as(capi._pi32), ctypes.byref(h)))
+        self._h = h
+
+    def solve(self, b):
+        """Solve M y = b in place (b: device [n]); returns b."""
+        check(capi.lib().pf_lu_solve(self._h, _ptr(b, self.n, "b"), _stream(b.device)))
+        return b
+
+    def close(self):
+        if self._h is not None and self._h.value:
+            capi.lib().pf_lu_destroy(self._h)
         self._h = None
 
     def __del__(self):

@@ -16,6 +16,7 @@
 #include <cmath>
 #include <cstdint>
 #include <cstdio>
+#include <cstring>
 #include <mutex>
 #include <new>
 #include <vector>
@@ -396,6 +397,532 @@ int pf_newton_device(pf_plan *plan, pf_refact *rf, double *x, const pf_newton_op
     }
     for (auto &e : ev)
         if (e) (void)hipEventDestroy(e);
+    if (report) *report = r;
+    return rc;
+}
+
+}  // extern "C"
+
+// ===========================================================================
+// Fast decoupled power flow, XB variant (the conclusion names the method as
+// another user of the same residual evaluation).  The constant matrices
+// B' (angle step, over the buses without a slack) and B'' (voltage step, over
+// the buses without a voltage controller) are built here from the network
+// data of the plan; each is factorised once (one host LU handed over as for
+// pf_refact_create) and every iteration reuses the residual kernel:
+//   F = F(x);  theta[B' buses] -= B'^-1 (F_p / V);
+//   F = F(x);  V[B'' buses]    -= B''^-1 (F_q / V);
+// until the stepped rows are below tol, then Q_g and P_s take the values that
+// zero their buses' rows.
+// ===========================================================================
+
+struct pf_lu {
+    int device = 0;
+    int n = 0, nnzM = 0, nnzT = 0;
+    int *ptrM = nullptr, *indM = nullptr, *ptrT = nullptr, *indT = nullptr;
+    double *valM = nullptr, *valT = nullptr;
+    int *pivP = nullptr, *pivQ = nullptr;
+    rocblas_handle handle = nullptr;
+    rocsolver_rfinfo info = nullptr;
+};
+
+struct pf_fdlf {
+    pf_plan *plan = nullptr;
+    pf_lu *bp = nullptr, *bpp = nullptr;
+    int device = 0;
+    int np = 0, nq = 0, ng = 0;
+    int32_t *bus_p = nullptr, *bus_q = nullptr;  // row -> bus of B', B''
+    int4 *gens = nullptr;                        // {bus, Q_g index, P_s index or -1, 0}
+    double2 *setp = nullptr;                     // per generator (V_set, theta_set)
+    double *F = nullptr, *rp = nullptr, *rq = nullptr, *part = nullptr, *norm = nullptr;
+    double *norm_host = nullptr;
+};
+
+namespace {
+
+// B' and B'' of a single-grid plan in CSR (columns sorted), with the bus of
+// every row.  Entries are summed branch by branch in input order, then the
+// bus shunts (B'' only).
+struct FdMats {
+    std::vector<int32_t> rp_p, ci_p, bus_p, rp_q, ci_q, bus_q;
+    std::vector<double> v_p, v_q;
+};
+
+void csr_from_rows(std::vector<std::vector<std::pair<int32_t, double>>> &rows,
+                   std::vector<int32_t> &rp, std::vector<int32_t> &ci, std::vector<double> &v) {
+    rp.assign(1, 0);
+    ci.clear();
+    v.clear();
+    for (auto &r : rows) {
+        std::stable_sort(r.begin(), r.end(),
+                         [](const std::pair<int32_t, double> &a,
+                            const std::pair<int32_t, double> &b) { return a.first < b.first; });
+        for (size_t k = 0; k < r.size();) {
+            const int32_t c = r[k].first;
+            double s = 0.0;
+            for (; k < r.size() && r[k].first == c; ++k) s += r[k].second;
+            ci.push_back(c);
+            v.push_back(s);
+        }
+        rp.push_back(int32_t(ci.size()));
+    }
+}
+
+int build_fd(const HostPlan &hp, FdMats &m) {
+    if (hp.kind != KIND_SINGLE) return fail(PF_EINVAL, "the fast decoupled method needs a single-grid plan");
+    const int N = hp.Nt;
+    const int64_t B = hp.Bt;
+    std::vector<int32_t> ip(size_t(N), -1), iq(size_t(N), -1);
+    m.bus_p.clear();
+    m.bus_q.clear();
+    for (int i = 0; i < N; ++i) {
+        const int g = hp.bus2[2 * size_t(i) + 1];
+        const bool ctrl = g >= 0;
+        const bool slack = ctrl && hp.gen4[4 * size_t(g) + 2] >= 0;
+        if (!slack) {
+            ip[size_t(i)] = int32_t(m.bus_p.size());
+            m.bus_p.push_back(i);
+        }
+        if (!ctrl) {
+            iq[size_t(i)] = int32_t(m.bus_q.size());
+            m.bus_q.push_back(i);
+        }
+    }
+    std::vector<std::vector<std::pair<int32_t, double>>> P(m.bus_p.size()), Q(m.bus_q.size());
+    auto add = [](std::vector<std::vector<std::pair<int32_t, double>>> &D,
+                  const std::vector<int32_t> &idx, int i, int j, double v) {
+        const int32_t a = idx[size_t(i)], b = idx[size_t(j)];
+        if (a >= 0 && b >= 0) D[size_t(a)].push_back({b, v});
+    };
+    for (int64_t e = 0; e < B; ++e) {
+        if (!hp.br_on[size_t(e)]) continue;
+        const int f = hp.br_f[size_t(e)], t = hp.br_t[size_t(e)];
+        const double r = hp.params[size_t(e)], x = hp.params[size_t(B + e)];
+        const double bc = hp.params[size_t(2 * B + e)], tap = hp.params[size_t(3 * B + e)];
+        const double w = 1.0 / x;
+        add(P, ip, f, f, w);
+        add(P, ip, t, t, w);
+        add(P, ip, f, t, -w);
+        add(P, ip, t, f, -w);
+        const double b = -x / (r * r + x * x);
+        add(Q, iq, f, f, -(b + bc / 2) / (tap * tap));
+        add(Q, iq, t, t, -(b + bc / 2));
+        add(Q, iq, f, t, b / tap);
+        add(Q, iq, t, f, b / tap);
+    }
+    for (int i = 0; i < N; ++i)
+        for (int32_t k = hp.shptr[size_t(i)]; k < hp.shptr[size_t(i) + 1]; ++k)
+            add(Q, iq, i, i, -hp.shunt_b[size_t(hp.shlist[size_t(k)])]);
+    csr_from_rows(P, m.rp_p, m.ci_p, m.v_p);
+    csr_from_rows(Q, m.rp_q, m.ci_q, m.v_q);
+    return PF_OK;
+}
+
+void release_lu(pf_lu *lu) {
+    if (!lu) return;
+    const RfApi &api = rf_api();
+    int prev = -1;
+    (void)hipGetDevice(&prev);
+    (void)hipSetDevice(lu->device);
+    if (lu->info && api.ok) (void)api.destroy_rfinfo(lu->info);
+    if (lu->handle && api.ok) (void)api.destroy_handle(lu->handle);
+    for (void *p : {(void *)lu->ptrM, (void *)lu->indM, (void *)lu->valM, (void *)lu->ptrT,
+                    (void *)lu->indT, (void *)lu->valT, (void *)lu->pivP, (void *)lu->pivQ})
+        if (p) (void)hipFree(p);
+    if (prev >= 0) (void)hipSetDevice(prev);
+    delete lu;
+}
+
+void release_fd(pf_fdlf *fd) {
+    if (!fd) return;
+    int prev = -1;
+    (void)hipGetDevice(&prev);
+    (void)hipSetDevice(fd->device);
+    for (void *p : {(void *)fd->bus_p, (void *)fd->bus_q, (void *)fd->gens, (void *)fd->setp, (void *)fd->F,
+                    (void *)fd->rp, (void *)fd->rq, (void *)fd->part, (void *)fd->norm})
+        if (p) (void)hipFree(p);
+    if (fd->norm_host) (void)hipHostFree(fd->norm_host);
+    if (prev >= 0) (void)hipSetDevice(prev);
+    delete fd;
+}
+
+const char *check_csr(int n, int64_t nnz, const int32_t *rp, const int32_t *ci) {
+    if (rp[0] != 0 || rp[n] != nnz) return "rowptr must start at 0 and end at nnz";
+    for (int i = 0; i < n; ++i) {
+        if (rp[i + 1] < rp[i]) return "rowptr is not non-decreasing";
+        for (int32_t k = rp[i]; k < rp[i + 1]; ++k) {
+            if (ci[k] < 0 || ci[k] >= n) return "column index out of range";
+            if (k > rp[i] && ci[k] <= ci[k - 1]) return "columns not strictly increasing in a row";
+        }
+    }
+    return nullptr;
+}
+
+int create_lu(int device, int n, int64_t nnz, const int32_t *rowptr, const int32_t *colidx,
+              const double *val, int64_t nnzT, const int32_t *T_rowptr, const int32_t *T_colidx,
+              const double *T_val, const int32_t *pivP, const int32_t *pivQ, pf_lu *lu) {
+    const RfApi &api = rf_api();
+    if (!api.ok) return fail(PF_EDEVICE, "%s", api.why);
+    Guard g(device);
+    if (!g.ok) return fail(PF_EDEVICE, "cannot select device %d", device);
+    lu->device = device;
+    lu->n = n;
+    lu->nnzM = int(nnz);
+    lu->nnzT = int(nnzT);
+    int rc = PF_OK;
+    if (!rc) rc = alloc_copy(&lu->ptrM, rowptr, size_t(n) + 1);
+    if (!rc) rc = alloc_copy(&lu->indM, colidx, size_t(nnz));
+    if (!rc) rc = alloc_copy(&lu->valM, val, size_t(nnz));
+    if (!rc) rc = alloc_copy(&lu->ptrT, T_rowptr, size_t(n) + 1);
+    if (!rc) rc = alloc_copy(&lu->indT, T_colidx, size_t(nnzT));
+    if (!rc) rc = alloc_copy(&lu->valT, T_val, size_t(nnzT));
+    if (!rc) rc = alloc_copy(&lu->pivP, pivP, size_t(n));
+    if (!rc) rc = alloc_copy(&lu->pivQ, pivQ, size_t(n));
+    if (rc) return rc;
+    double *b = nullptr;
+    LU_HIP(hipMalloc(&b, size_t(n) * sizeof(double)));
+    LU_HIP(hipMemset(b, 0, size_t(n) * sizeof(double)));
+    rocblas_status s = api.create_handle(&lu->handle);
+    if (s == rocblas_status_success) s = api.create_rfinfo(&lu->info, lu->handle);
+    if (s == rocblas_status_success)
+        s = api.analysis(lu->handle, n, 1, lu->nnzM, lu->ptrM, lu->indM, lu->valM, lu->nnzT,
+                         lu->ptrT, lu->indT, lu->valT, lu->pivP, lu->pivQ, b, n, lu->info);
+    // factor values recomputed on the device along the same pivots
+    if (s == rocblas_status_success)
+        s = api.refactlu(lu->handle, n, lu->nnzM, lu->ptrM, lu->indM, lu->valM, lu->nnzT,
+                         lu->ptrT, lu->indT, lu->valT, lu->pivP, lu->pivQ, lu->info);
+    (void)hipDeviceSynchronize();
+    (void)hipFree(b);
+    if (s != rocblas_status_success) return fail(PF_ESOLVE, "rocSOLVER setup failed: status %d", int(s));
+    return PF_OK;
+}
+
+int lu_solve(pf_lu *lu, double *b, hipStream_t st) {
+    const RfApi &api = rf_api();
+    LU_RS(api.set_stream(lu->handle, st));
+    LU_RS(api.solve(lu->handle, lu->n, 1, lu->nnzT, lu->ptrT, lu->indT, lu->valT, lu->pivP,
+                    lu->pivQ, b, lu->n, lu->info));
+    return PF_OK;
+}
+
+// rhs[r] = F[bus[r]] / V[bus[r]] (when rhs is not NULL); part[block] = max |F[bus]|
+__global__ void __launch_bounds__(256) k_fd_gather(int m, const int32_t *__restrict__ bus,
+                                                   const double *__restrict__ Fpart,
+                                                   const double *__restrict__ V,
+                                                   double *__restrict__ rhs,
+                                                   double *__restrict__ part) {
+    __shared__ double red[256];
+    double mx = 0.0;
+    for (int r = blockIdx.x * 256 + threadIdx.x; r < m; r += gridDim.x * 256) {
+        const int i = bus[r];
+        const double f = Fpart[i];
+        if (rhs) rhs[r] = f / V[i];
+        mx = absmax2(mx, fabs(f));
+    }
+    red[threadIdx.x] = mx;
+    __syncthreads();
+    for (int s = 128; s > 0; s >>= 1) {
+        if (int(threadIdx.x) < s) red[threadIdx.x] = absmax2(red[threadIdx.x], red[threadIdx.x + s]);
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) part[blockIdx.x] = red[0];
+}
+
+// xpart[bus[r]] -= d[r]
+__global__ void __launch_bounds__(256) k_fd_scatter(int m, const int32_t *__restrict__ bus,
+                                                    double *__restrict__ xpart,
+                                                    const double *__restrict__ d) {
+    const int r = blockIdx.x * 256 + threadIdx.x;
+    if (r < m) xpart[bus[r]] -= d[r];
+}
+
+// generator variables that zero their buses' rows: Q_g += F_q[bus], P_s += F_p[bus]
+__global__ void __launch_bounds__(256) k_fd_gens(int ng, int N, const int4 *__restrict__ gens,
+                                                 const double *__restrict__ F,
+                                                 double *__restrict__ x) {
+    const int g = blockIdx.x * 256 + threadIdx.x;
+    if (g >= ng) return;
+    const int4 q = gens[g];
+    x[q.y] += F[N + q.x];
+    if (q.z >= 0) x[q.z] += F[q.x];
+}
+
+// the method never steps controlled voltages or slack angles: put them at
+// their set points
+__global__ void __launch_bounds__(256) k_fd_init(int ng, int N, const int4 *__restrict__ gens,
+                                                 const double2 *__restrict__ setp,
+                                                 double *__restrict__ x) {
+    const int g = blockIdx.x * 256 + threadIdx.x;
+    if (g >= ng) return;
+    const int4 q = gens[g];
+    x[N + q.x] = setp[g].x;
+    if (q.z >= 0) x[q.x] = setp[g].y;
+}
+
+int fd_blocks(int m) { return std::max(1, std::min(kAbsBlocks, (m + 255) / 256)); }
+
+}  // namespace
+
+extern "C" {
+
+int pf_fdlf_matrices(const pf_plan *plan, int64_t *nnz_bp, int32_t *bp_rowptr,
+                     int32_t *bp_colidx, double *bp_val, int32_t *bp_bus, int64_t *nnz_bpp,
+                     int32_t *bpp_rowptr, int32_t *bpp_colidx, double *bpp_val,
+                     int32_t *bpp_bus) {
+    clear_error();
+    if (!plan) return fail(PF_EINVAL, "plan is NULL");
+    FdMats m;
+    int rc;
+    try {
+        rc = build_fd(plan->host, m);
+    } catch (const std::bad_alloc &) {
+        rc = fail(PF_ENOMEM, "host allocation failed");
+    }
+    if (rc) return rc;
+    if (nnz_bp) *nnz_bp = int64_t(m.ci_p.size());
+    if (nnz_bpp) *nnz_bpp = int64_t(m.ci_q.size());
+    auto put = [](auto *dst, const auto &src) {
+        if (dst && !src.empty()) std::memcpy(dst, src.data(), src.size() * sizeof(src[0]));
+    };
+    put(bp_rowptr, m.rp_p);
+    put(bp_colidx, m.ci_p);
+    put(bp_val, m.v_p);
+    put(bp_bus, m.bus_p);
+    put(bpp_rowptr, m.rp_q);
+    put(bpp_colidx, m.ci_q);
+    put(bpp_val, m.v_q);
+    put(bpp_bus, m.bus_q);
+    return PF_OK;
+}
+
+int pf_lu_create(int32_t device, int64_t n, int64_t nnz, const int32_t *rowptr,
+                 const int32_t *colidx, const double *val, int64_t nnzT, const int32_t *T_rowptr,
+                 const int32_t *T_colidx, const double *T_val, const int32_t *pivP,
+                 const int32_t *pivQ, pf_lu **out) {
+    clear_error();
+    if (!out) return fail(PF_EINVAL, "out is NULL");
+    *out = nullptr;
+    if (!rowptr || !colidx || !val || !T_rowptr || !T_colidx || !T_val || !pivP || !pivQ)
+        return fail(PF_EINVAL, "NULL argument");
+    if (n < 1 || n > INT32_MAX - 1) return fail(PF_EINVAL, "n must be in [1, 2^31 - 1)");
+    if (nnz < 0 || nnz > INT32_MAX || nnzT < n || nnzT > INT32_MAX)
+        return fail(PF_EINVAL, "nnz must be in [0, 2^31), nnzT in [n, 2^31)");
+    if (const char *why = check_csr(int(n), nnz, rowptr, colidx))
+        return fail(PF_EINVAL, "matrix: %s", why);
+    if (const char *why = check_T(int(n), nnzT, T_rowptr, T_colidx)) return fail(PF_EINVAL, "%s", why);
+    if (!is_permutation(pivP, int(n)) || !is_permutation(pivQ, int(n)))
+        return fail(PF_EINVAL, "pivP and pivQ must be permutations of 0..n-1");
+    int dev = device;
+    if (dev < 0 && hipGetDevice(&dev) != hipSuccess) return fail(PF_EDEVICE, "no current device");
+    pf_lu *lu = new (std::nothrow) pf_lu();
+    if (!lu) return fail(PF_ENOMEM, "host allocation failed");
+    int rc = create_lu(dev, int(n), nnz, rowptr, colidx, val, nnzT, T_rowptr, T_colidx, T_val,
+                       pivP, pivQ, lu);
+    if (rc) {
+        release_lu(lu);
+        return rc;
+    }
+    *out = lu;
+    return PF_OK;
+}
+
+int pf_lu_solve(pf_lu *lu, double *b, void *stream) {
+    clear_error();
+    if (!lu || !b) return fail(PF_EINVAL, "NULL argument");
+    Guard g(lu->device);
+    if (!g.ok) return fail(PF_EDEVICE, "cannot select device %d", lu->device);
+    return lu_solve(lu, b, static_cast<hipStream_t>(stream));
+}
+
+void pf_lu_destroy(pf_lu *lu) { release_lu(lu); }
+
+int pf_fdlf_create(pf_plan *plan, pf_lu *bp, pf_lu *bpp, pf_fdlf **out) {
+    clear_error();
+    if (!out) return fail(PF_EINVAL, "out is NULL");
+    *out = nullptr;
+    if (!plan) return fail(PF_EINVAL, "plan is NULL");
+    const HostPlan &hp = plan->host;
+    if (hp.host_only || !plan->dev) return fail(PF_EINVAL, "plan is host-only");
+    FdMats m;
+    int rc = build_fd(hp, m);
+    if (rc) return rc;
+    const int np = int(m.bus_p.size()), nq = int(m.bus_q.size());
+    if ((np > 0) != (bp != nullptr) || (nq > 0) != (bpp != nullptr))
+        return fail(PF_EINVAL, "give a factorisation exactly for each non-empty matrix");
+    if ((bp && bp->n != np) || (bpp && bpp->n != nq))
+        return fail(PF_EINVAL, "factorisation size does not match B' (%d) / B'' (%d)", np, nq);
+    if ((bp && bp->device != hp.device) || (bpp && bpp->device != hp.device))
+        return fail(PF_EINVAL, "factorisations live on another device than the plan");
+    pf_fdlf *fd = new (std::nothrow) pf_fdlf();
+    if (!fd) return fail(PF_ENOMEM, "host allocation failed");
+    fd->plan = plan;
+    fd->bp = bp;
+    fd->bpp = bpp;
+    fd->device = hp.device;
+    fd->np = np;
+    fd->nq = nq;
+    std::vector<int4> gens;
+    std::vector<double2> setp;
+    for (int i = 0; i < hp.Nt; ++i) {
+        const int g = hp.bus2[2 * size_t(i) + 1];
+        if (g < 0) continue;
+        const int32_t ps = hp.gen4[4 * size_t(g) + 2];
+        gens.push_back(make_int4(i, hp.gen4[4 * size_t(g)], ps >= 0 ? ps : -1, 0));
+        const int32_t pv = hp.genpv[size_t(g)];
+        setp.push_back(make_double2(pv >= 0 ? hp.pv_vset[size_t(pv)] : hp.gen2[2 * size_t(g)],
+                                    hp.gen2[2 * size_t(g) + 1]));
+    }
+    fd->ng = int(gens.size());
+    {
+        Guard g(hp.device);
+        if (!g.ok) rc = fail(PF_EDEVICE, "cannot select device %d", hp.device);
+        if (!rc) rc = alloc_copy(&fd->bus_p, m.bus_p.data(), m.bus_p.size());
+        if (!rc) rc = alloc_copy(&fd->bus_q, m.bus_q.data(), m.bus_q.size());
+        if (!rc) rc = alloc_copy(&fd->gens, gens.data(), gens.size());
+        if (!rc) rc = alloc_copy(&fd->setp, setp.data(), setp.size());
+        if (!rc) rc = alloc_copy<double>(&fd->F, nullptr, size_t(hp.n));
+        if (!rc) rc = alloc_copy<double>(&fd->rp, nullptr, size_t(np));
+        if (!rc) rc = alloc_copy<double>(&fd->rq, nullptr, size_t(nq));
+        if (!rc) rc = alloc_copy<double>(&fd->part, nullptr, 2 * kAbsBlocks);
+        if (!rc) rc = alloc_copy<double>(&fd->norm, nullptr, 1);
+        if (!rc && hipHostMalloc(&fd->norm_host, sizeof(double), hipHostMallocDefault) != hipSuccess)
+            rc = fail(PF_ENOMEM, "pinned allocation failed");
+    }
+    if (rc) {
+        release_fd(fd);
+        return rc;
+    }
+    *out = fd;
+    return PF_OK;
+}
+
+void pf_fdlf_destroy(pf_fdlf *fd) { release_fd(fd); }
+
+int pf_fdlf_solve(pf_fdlf *fd, double *x, const pf_newton_opts *opts, pf_newton_report *report,
+                  void *stream) {
+    clear_error();
+    if (!fd || !x) return fail(PF_EINVAL, "NULL argument");
+    if (opts && opts->max_iter > 64) return fail(PF_EINVAL, "max_iter must be <= 64");
+    HostPlan &hp = fd->plan->host;
+    for (int32_t k = 0; k < hp.NPVt; ++k)
+        if (!hp.pv_mode.empty() && hp.pv_mode[size_t(k)])
+            return fail(PF_EINVAL, "the fast decoupled method needs every PV unit under voltage control");
+    Guard g(fd->device);
+    if (!g.ok) return fail(PF_EDEVICE, "cannot select device %d", fd->device);
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    const double tol = (opts && opts->tol > 0) ? opts->tol : 1e-10;
+    const int max_iter = (opts && opts->max_iter > 0) ? opts->max_iter : 10;
+    const int N = hp.Nt;
+    const int bp_blocks = fd_blocks(fd->np), bq_blocks = fd_blocks(fd->nq);
+    pf_newton_report r{};
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    (void)hipEventCreate(&e0);
+    (void)hipEventCreate(&e1);
+    float ms = 0.f;
+    auto t_start = std::chrono::steady_clock::now();
+    auto eval = [&]() -> int {
+        if (e0) (void)hipEventRecord(e0, st);
+        int rc = dev_eval_single(hp, fd->plan->dev, x, fd->F, nullptr, st);
+        if (e1) (void)hipEventRecord(e1, st);
+        return rc;
+    };
+    auto eval_time = [&]() {
+        if (e0 && e1 && hipEventSynchronize(e1) == hipSuccess &&
+            hipEventElapsedTime(&ms, e0, e1) == hipSuccess)
+            r.t_eval_s += ms * 1e-3;
+    };
+    int rc = PF_OK;
+    int it = 0;
+    if (fd->ng) {
+        hipLaunchKernelGGL(k_fd_init, dim3((fd->ng + 255) / 256), dim3(256), 0, st, fd->ng, N,
+                           fd->gens, fd->setp, x);
+        if (hipGetLastError() != hipSuccess) rc = fail(PF_EDEVICE, "launch failed");
+    }
+    bool stepped_ok = false;
+    for (; !rc; ++it) {
+        rc = eval();
+        if (rc) break;
+        // mismatch of the stepped rows, and the angle-step right-hand side
+        if (fd->np)
+            hipLaunchKernelGGL(k_fd_gather, dim3(bp_blocks), dim3(256), 0, st, fd->np, fd->bus_p,
+                               fd->F, x + N, fd->rp, fd->part);
+        if (fd->nq)
+            hipLaunchKernelGGL(k_fd_gather, dim3(bq_blocks), dim3(256), 0, st, fd->nq, fd->bus_q,
+                               fd->F + N, x + N, nullptr, fd->part + bp_blocks);
+        hipLaunchKernelGGL(k_absmax_fold, dim3(1), dim3(256), 0, st,
+                           (fd->np ? bp_blocks : 0) + (fd->nq ? bq_blocks : 0),
+                           fd->np ? fd->part : fd->part + bp_blocks, fd->norm);
+        if (hipGetLastError() != hipSuccess ||
+            hipMemcpyAsync(fd->norm_host, fd->norm, sizeof(double), hipMemcpyDeviceToHost, st) !=
+                hipSuccess ||
+            hipStreamSynchronize(st) != hipSuccess) {
+            rc = fail(PF_EDEVICE, "device step failed in iteration %d", it);
+            break;
+        }
+        eval_time();
+        const double nf = *fd->norm_host;
+        if (it < 65) r.norm[it] = nf;
+        if (nf < tol) {
+            stepped_ok = true;
+            break;
+        }
+        if (it >= max_iter) {
+            rc = fail(PF_ENOCONV, "fast decoupled iteration did not converge in %d iterations (%g)",
+                      max_iter, nf);
+            break;
+        }
+        auto ts = std::chrono::steady_clock::now();
+        if (fd->np) {
+            rc = lu_solve(fd->bp, fd->rp, st);
+            if (rc) break;
+            hipLaunchKernelGGL(k_fd_scatter, dim3((fd->np + 255) / 256), dim3(256), 0, st, fd->np,
+                               fd->bus_p, x, fd->rp);
+        }
+        rc = eval();
+        if (rc) break;
+        if (fd->nq) {
+            hipLaunchKernelGGL(k_fd_gather, dim3(bq_blocks), dim3(256), 0, st, fd->nq, fd->bus_q,
+                               fd->F + N, x + N, fd->rq, fd->part);
+            rc = lu_solve(fd->bpp, fd->rq, st);
+            if (rc) break;
+            hipLaunchKernelGGL(k_fd_scatter, dim3((fd->nq + 255) / 256), dim3(256), 0, st, fd->nq,
+                               fd->bus_q, x + N, fd->rq);
+        }
+        if (hipStreamSynchronize(st) != hipSuccess) {
+            rc = fail(PF_EDEVICE, "device step failed in iteration %d", it);
+            break;
+        }
+        eval_time();
+        r.t_solve_s += std::chrono::duration<double>(std::chrono::steady_clock::now() - ts).count();
+        r.iterations = it + 1;
+    }
+    if (rc == PF_OK && stepped_ok) {
+        // generator variables, then the full norm of F
+        rc = eval();
+        if (!rc && fd->ng)
+            hipLaunchKernelGGL(k_fd_gens, dim3((fd->ng + 255) / 256), dim3(256), 0, st, fd->ng, N,
+                               fd->gens, fd->F, x);
+        if (!rc) rc = eval();
+        if (!rc) {
+            const int nb = fd_blocks(int(hp.n));
+            hipLaunchKernelGGL(k_absmax_part, dim3(nb), dim3(256), 0, st, hp.n, fd->F, fd->part);
+            hipLaunchKernelGGL(k_absmax_fold, dim3(1), dim3(256), 0, st, nb, fd->part, fd->norm);
+            if (hipMemcpyAsync(fd->norm_host, fd->norm, sizeof(double), hipMemcpyDeviceToHost,
+                               st) != hipSuccess ||
+                hipStreamSynchronize(st) != hipSuccess)
+                rc = fail(PF_EDEVICE, "final norm failed");
+        }
+        if (!rc) {
+            r.norm[std::min(it + 1, 64)] = *fd->norm_host;
+            r.converged = *fd->norm_host < tol;
+            if (!r.converged)
+                rc = fail(PF_ENOCONV, "generator rows did not close (|F| = %g)", *fd->norm_host);
+        }
+    }
+    (void)hipStreamSynchronize(st);
+    r.t_total_s = std::chrono::duration<double>(std::chrono::steady_clock::now() - t_start).count();
+    if (e0) (void)hipEventDestroy(e0);
+    if (e1) (void)hipEventDestroy(e1);
     if (report) *report = r;
     return rc;
 }

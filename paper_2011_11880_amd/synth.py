@@ -475,3 +475,16 @@ def fill_zero_injection_buses(net: Network) -> Network:
     out.load_p = np.concatenate([net.load_p, np.zeros(add.size)])
     out.load_q = np.concatenate([net.load_q, np.zeros(add.size)])
     return out
+
+
+def grid_meshed(n_bus: int, seed: int, mesh: float = 2.5, rx=(0.05, 0.3)) -> Network:
+    """A well-meshed, transmission-like variant of the geometric grid for
+    the fast decoupled method: ``mesh * n_bus`` branches (the MST plus the
+    shortest remaining Delaunay edges, so no long thin corridors remain) and
+    resistances r = x * U(rx) (R/X well below 1, where decoupling holds);
+    other data as :func:`geometric_grid` with the 70k proportions."""
+    n_pv, n_load, n_sh = _fractions(n_bus)
+    net = geometric_grid(n_bus, int(round(mesh * n_bus)), n_pv, n_load, n_sh, seed)
+    rng = np.random.default_rng(seed + 1)
+    net.br_r = net.br_x * rng.uniform(rx[0], rx[1], net.n_branch)
+    return net

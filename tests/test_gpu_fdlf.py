@@ -1,0 +1,103 @@
+"""GPU parity of the fast decoupled method: constant device factorisations
+against host solves, and pf_fdlf_solve iterate by iterate against the
+oracle's fast decoupled iteration, on meshed transmission-like grids."""
+
+import numpy as np
+import pytest
+import scipy.sparse.linalg as spla
+
+from paper_2011_11880_amd import synth
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+
+@pytest.fixture(scope="module")
+def cuda():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    return torch.device("cuda", 0)
+
+
+def _case(ora, n_bus, seed, ang, pert):
+    import test_gpu_newton_device as D
+    net0 = synth.grid_meshed(n_bus, seed)
+    return D._manufactured(ora, net0, seed, ang=ang, pert=pert)
+
+
+def test_device_sparse_lu_solves(ora, cuda):
+    from paper_2011_11880_amd.api import DeviceSparseLU, Plan
+    net = synth.grid_meshed(10000, 2100)
+    p = Plan(net)
+    Bp, Bpp, _, _ = p.fdlf_matrices()
+    rng = np.random.default_rng(3)
+    for M in (Bp, Bpp):
+        lu = DeviceSparseLU(M)
+        b = rng.normal(size=M.shape[0])
+        y = torch.from_numpy(b).to(cuda)
+        lu.solve(y)
+        torch.cuda.synchronize()
+        y = y.cpu().numpy()
+        ref = spla.spsolve(M.tocsc(), b)
+        assert np.max(np.abs(M @ y - b)) <= 1e-11 * (abs(M).max() * np.max(np.abs(y)) + 1)
+        assert np.max(np.abs(y - ref)) <= 1e-9 * np.max(np.abs(ref))
+        lu.close()
+
+
+def test_fdlf_iterates_match_oracle(ora, cuda):
+    """Iterate by iterate on a 200-bus meshed grid: the device's stepped-row
+    mismatches equal the oracle's, and the end state equals the oracle's."""
+    from paper_2011_11880_amd.api import Plan
+    net, ystar, y0 = _case(ora, 200, 5, 0.3, (0.02, 0.05))
+    y_o, norms_o, iters_o = ora.fdlf(net, y0, tol=1e-10, max_iter=60)
+    assert norms_o[-1] < 1e-10
+    p = Plan(net)
+    for m in (1, 2, 5):
+        x = torch.from_numpy(y0).to(cuda)
+        rep = p.fdlf(x, tol=1e-300, max_iter=m)
+        assert not rep["converged"] and rep["iterations"] == m
+        np.testing.assert_allclose(x.cpu().numpy()[:2 * net.n_bus], iters_o[m][:2 * net.n_bus],
+                                   rtol=0, atol=1e-10)
+        np.testing.assert_allclose(rep["norms"], norms_o[:m + 1], rtol=1e-6, atol=1e-13)
+    x = torch.from_numpy(y0).to(cuda)
+    rep = p.fdlf(x, tol=1e-10, max_iter=60)
+    assert rep["converged"] and rep["iterations"] == len(iters_o) - 1
+    assert rep["norms"][-1] < 1e-10 and len(rep["norms"]) == rep["iterations"] + 2
+    np.testing.assert_allclose(x.cpu().numpy(), y_o, rtol=0, atol=1e-10)
+    np.testing.assert_allclose(x.cpu().numpy(), ystar, rtol=0, atol=1e-9)
+
+
+@pytest.mark.parametrize("n_bus", [10000, 70000])
+def test_fdlf_converges_large(ora, cuda, n_bus):
+    from paper_2011_11880_amd.api import Plan
+    net, ystar, y0 = _case(ora, n_bus, 2100, 0.03, (1e-4, 2.5e-4))
+    p = Plan(net)
+    x = torch.from_numpy(y0).to(cuda)
+    rep = p.fdlf(x, tol=1e-10, max_iter=60)
+    assert rep["converged"], rep["norms"]
+    assert np.max(np.abs(x.cpu().numpy() - ystar)) < 1e-8
+    if n_bus == 10000:
+        _, norms_o, iters_o = ora.fdlf(net, y0, tol=1e-10, max_iter=60)
+        assert abs(rep["iterations"] - (len(iters_o) - 1)) <= 1
+        assert abs(rep["norms"][0] - norms_o[0]) <= 1e-12 * norms_o[0]
+
+
+def test_fdlf_failure_paths(ora, cuda):
+    from paper_2011_11880_amd.api import Plan
+    from paper_2011_11880_amd.capi import PF_EINVAL, PFError
+    net, ystar, y0 = _case(ora, 200, 6, 0.3, (0.02, 0.05))
+    p = Plan(net, q_limits=True)
+    x = torch.from_numpy(y0).to(cuda)
+    rep = p.fdlf(x, tol=1e-10, max_iter=2)   # too few iterations: no error, not converged
+    assert not rep["converged"] and rep["iterations"] == 2
+    with pytest.raises(PFError) as ei:
+        p.fdlf(x, max_iter=65)
+    assert ei.value.code == PF_EINVAL
+    mode = np.zeros(net.n_pv, np.int32)
+    mode[0] = 1
+    p.set_gen_modes(mode, np.zeros(net.n_pv))
+    with pytest.raises(PFError) as ei:       # a held unit: not supported
+        p.fdlf(x)
+    assert ei.value.code == PF_EINVAL
+    p.close()
