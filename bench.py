@@ -19,7 +19,8 @@ The default run also summarises the other workloads under "others"; each
 can be run alone with --config: c2 = 10,000-bus grid x 1024 scenario and N-1
 instances; c3 = 256 grids of uneven size in one launch; c4 = adjoint (VJP)
 with 64 cotangents on the 70,000-bus grid; newton = Newton power flow on the
-70,000-bus grid with every step on the device; copy = HBM calibration.
+70,000-bus grid with every step on the device; fdlf = fast decoupled power
+flow on a meshed 70,000-bus grid; copy = HBM calibration.
 """
 
 from __future__ import annotations
@@ -283,7 +284,8 @@ def run_c1(args, torch, dev):
     if not args.no_others:
         out["others"] = {}
         for name, fn in (("scenarios_10k_x1024", run_c2), ("uneven_256_grids", run_c3),
-                         ("adjoint_70k_k64", run_c4), ("newton_device_70k", run_newton)):
+                         ("adjoint_70k_k64", run_c4), ("newton_device_70k", run_newton),
+                         ("fdlf_70k_meshed", run_fdlf)):
             log(f"[bench] {name}")
             out["others"][name] = fn(args, torch, dev, net70k=net,
                                      plain_us=res.get("plain", {}).get("us_per_eval"))
@@ -395,19 +397,18 @@ def run_c4(args, torch, dev, net70k=None, plain_us=None, **kw):
             "gbs": nb / (ms * 1e-3) / 1e9, "hbm_frac": nb / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS}
 
 
-def run_newton(args, torch, dev, **kw):
-    """Newton power flow on the 70,000-bus grid (a zero load added at every
-    bus without injection) toward a manufactured solution y*: loads and
-    generator set-points chosen so that F(y*) = 0, small angles at y*, start
-    within 1e-4 of it.  Every step on the device (evaluation, norm,
-    rocSOLVER re-factorisation along one host LU's pattern, triangular
-    solves, update) against the same Newton with the host sparse solve."""
+def manufactured_case(torch, dev, net, seed, ang=0.03, sigma=1e-4):
+    """A solvable case on ``net``: a zero load at every bus without
+    injection, a state y* (angles scaled by ``ang``), and loads, PV
+    set-points and generator outputs shifted so that F(y*) = 0 (the residual
+    from the library); the start is y* plus N(0, sigma) on angles and
+    voltages and N(0, 2.5 sigma) on the generator variables."""
     from paper_2011_11880_amd import synth
     from paper_2011_11880_amd.api import Plan
-    net = synth.fill_zero_injection_buses(synth.grid_70k())
+    net = synth.fill_zero_injection_buses(net)
     N, NPV, NG = net.n_bus, net.n_pv, net.n_gen
-    ystar = synth.random_states(net, seed=4100)
-    ystar[:N] *= 0.03
+    ystar = synth.random_states(net, seed=seed)
+    ystar[:N] *= ang
     p0 = Plan(net, device=0)
     F0 = p0.eval_residual(torch.from_numpy(ystar).to(dev)).cpu().numpy()
     p0.close()
@@ -424,9 +425,64 @@ def run_newton(args, torch, dev, **kw):
     net.pv_v[:] = ystar[N + net.pv_bus]
     net.slack_v[:] = ystar[N + net.slack_bus]
     net.slack_theta[:] = ystar[net.slack_bus]
-    rng = np.random.default_rng(4101)
-    y0 = ystar + np.concatenate([rng.normal(0, 1e-4, 2 * N),
-                                 rng.normal(0, 2.5e-4, net.n_var - 2 * N)])
+    rng = np.random.default_rng(seed + 1)
+    y0 = ystar + np.concatenate([rng.normal(0, sigma, 2 * N),
+                                 rng.normal(0, 2.5 * sigma, net.n_var - 2 * N)])
+    return net, ystar, y0
+
+
+def run_fdlf(args, torch, dev, **kw):
+    """Fast decoupled power flow (XB) on a meshed, transmission-like 70,000-bus
+    grid (175,000 branches, R/X in 0.05..0.3: the method's domain; on the
+    paper-shaped grid it diverges), toward a manufactured solution, against
+    device Newton on the same case."""
+    from paper_2011_11880_amd import synth
+    from paper_2011_11880_amd.api import Plan
+    log("[bench] fdlf: meshed 70k grid and manufactured solution")
+    net, ystar, y0 = manufactured_case(torch, dev, synth.grid_meshed(70000, 1100), 4200)
+    p = Plan(net, device=0)
+    x = torch.from_numpy(y0).to(dev)
+    log("[bench] fdlf: B', B'' and their factorisations, first solve")
+    r0 = p.fdlf(x, tol=1e-10, max_iter=60)   # builds and factorises B', B''
+    log("[bench] fdlf: timed solves")
+    reps = []
+    for _ in range(3):
+        x = torch.from_numpy(y0).to(dev)
+        reps.append(p.fdlf(x, tol=1e-10, max_iter=60))
+    r = min(reps, key=lambda q: q["t_total_s"])
+    err = float(np.max(np.abs(x.cpu().numpy() - ystar)))
+    it = r["iterations"]
+    Bp, Bpp, _, _ = p.fdlf_matrices()
+    log("[bench] fdlf: device Newton on the same case (host LU first)")
+    xn = torch.from_numpy(y0).to(dev)
+    lu = p.device_lu(xn)
+    p.newton_device(xn, lu)
+    xn = torch.from_numpy(y0).to(dev)
+    rn = p.newton_device(xn, lu)
+    return {"grid": "70,000 buses, 175,000 branches (meshed), R/X 0.05..0.3",
+            "n": p.n, "nnz_bp": int(Bp.nnz), "nnz_bpp": int(Bpp.nnz),
+            "setup_s": r0["t_setup_s"],
+            "fdlf": {"iterations": it, "converged": r["converged"], "final_norm": r["norms"][-1],
+                     "max_error_vs_solution": err, "total_ms": r["t_total_s"] * 1e3,
+                     "residual_eval_ms_per_iter": r["t_eval_s"] * 1e3 / max(2 * it + 1, 1),
+                     "half_steps_ms_per_iter": r["t_solve_s"] * 1e3 / max(it, 1)},
+            "newton_device": {"iterations": rn["iterations"], "converged": rn["converged"],
+                              "total_ms": rn["t_total_s"] * 1e3,
+                              "solve_ms_per_iter": rn["t_solve_s"] * 1e3 / max(rn["iterations"], 1)}}
+
+
+def run_newton(args, torch, dev, **kw):
+    """Newton power flow on the 70,000-bus grid (a zero load added at every
+    bus without injection) toward a manufactured solution y*: loads and
+    generator set-points chosen so that F(y*) = 0, small angles at y*, start
+    within 1e-4 of it.  Every step on the device (evaluation, norm,
+    rocSOLVER re-factorisation along one host LU's pattern, triangular
+    solves, update) against the same Newton with the host sparse solve."""
+    from paper_2011_11880_amd import synth
+    from paper_2011_11880_amd.api import Plan
+    log("[bench] newton: 70k grid and manufactured solution")
+    net, ystar, y0 = manufactured_case(torch, dev, synth.grid_70k(), 4100)
+    N, NPV = net.n_bus, net.n_pv
     p = Plan(net, device=0)
     x = torch.from_numpy(y0).to(dev)
     t0 = time.perf_counter()
@@ -439,6 +495,7 @@ def run_newton(args, torch, dev, **kw):
         reps.append(p.newton_device(x, lu))
     rep = min(reps, key=lambda r: r["t_total_s"])
     err = float(np.max(np.abs(x.cpu().numpy() - ystar)))
+    log("[bench] newton: host-solve Newton")
     xh = torch.from_numpy(y0).to(dev)
     reph = p.newton(xh)
     it, ith = rep["iterations"], reph["iterations"]
@@ -449,6 +506,7 @@ def run_newton(args, torch, dev, **kw):
     pick = np.random.default_rng(4103).choice(NPV, 20, replace=False)
     qmin, qmax = q - 10.0, q + 10.0
     qmax[pick] = q[pick] - 0.002
+    log("[bench] newton: with reactive limits")
     pq = Plan(net, device=0, q_limits=True)
     lim = {}
     for name, on_dev in (("device", True), ("host_solve", False)):
@@ -509,7 +567,8 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--config", default="c1", choices=["c1", "c2", "c3", "c4", "newton", "copy"])
+    ap.add_argument("--config", default="c1",
+                    choices=["c1", "c2", "c3", "c4", "newton", "fdlf", "copy"])
     ap.add_argument("--copy-mib", type=int, default=1024)
     ap.add_argument("--states", type=int, default=1000)
     ap.add_argument("--autotune", action="store_true")
@@ -530,7 +589,7 @@ def main():
         sys.exit(1)
     dev = torch.device("cuda", 0)
     out = {"c1": run_c1, "c2": run_c2, "c3": run_c3, "c4": run_c4, "newton": run_newton,
-           "copy": run_copy}[args.config](args, torch, dev)
+           "fdlf": run_fdlf, "copy": run_copy}[args.config](args, torch, dev)
     print(json.dumps(out), flush=True)
 
 

@@ -63,9 +63,10 @@ def params_vector(nets):
                 for k in ("br_r", "br_x", "br_b", "br_tap", "br_shift_deg", "load_p", "load_q")])
 
 
-def host_lu(rowptr, colidx, values, n, permc_spec="MMD_AT_PLUS_A"):
-    """One sparse LU with pivoting of the CSR matrix M on the host (SuperLU),
-    in the form the device re-factorisation takes:
+def host_lu(rowptr, colidx, values, n, permc_spec="COLAMD"):
+    """One sparse LU with pivoting of the CSR matrix M on the host (SuperLU;
+    COLAMD ordering: SuperLU's minimum-degree orderings take minutes on
+    well-meshed grids), in the form the device re-factorisation takes:
     (T_rowptr, T_colidx, T_val, pivP, pivQ) with T = (L - I) + U in CSR
     (sorted columns) and M[pivP][:, pivQ] = L U."""
     import scipy.sparse as sp
@@ -520,7 +521,7 @@ class Plan:
                 "t_eval_s": rep.t_eval_s, "t_solve_s": rep.t_solve_s,
                 "t_total_s": rep.t_total_s, "t_setup_s": t_setup}
 
-    def device_lu(self, x, permc_spec="MMD_AT_PLUS_A"):
+    def device_lu(self, x, permc_spec="COLAMD"):
         """A DeviceLU for this plan, its pattern and pivots taken from one host
         LU of the Jacobian at ``x`` (device [n])."""
         return DeviceLU(self, x, permc_spec=permc_spec)
@@ -555,7 +556,7 @@ class DeviceLU:
     pattern and pivots from one host LU of the plan's Jacobian at ``x``,
     every later factorisation and solve on the GPU (rocSOLVER csrrf)."""
 
-    def __init__(self, plan, x, permc_spec="MMD_AT_PLUS_A"):
+    def __init__(self, plan, x, permc_spec="COLAMD"):
         import weakref
         self.plan = plan
         self._h = None
@@ -598,7 +599,7 @@ class DeviceSparseLU:
     """Constant device factorisation of a host CSR matrix (pf_lu_*): one host
     LU (SuperLU) fixes the factors, solves run on the GPU."""
 
-    def __init__(self, M, device=-1, permc_spec="MMD_AT_PLUS_A"):
+    def __init__(self, M, device=-1, permc_spec="COLAMD"):
         M = M.tocsr()
         M.sort_indices()
         n = M.shape[0]
