@@ -20,7 +20,8 @@ can be run alone with --config: c2 = 10,000-bus grid x 1024 scenario and N-1
 instances; c3 = 256 grids of uneven size in one launch; c4 = adjoint (VJP)
 with 64 cotangents on the 70,000-bus grid; newton = Newton power flow on the
 70,000-bus grid with every step on the device; fdlf = fast decoupled power
-flow on a meshed 70,000-bus grid; copy = HBM calibration.
+flow on a meshed 70,000-bus grid; models = per-model cost (the 70k grid built
+up model by model); copy = HBM calibration.
 """
 
 from __future__ import annotations
@@ -285,7 +286,7 @@ def run_c1(args, torch, dev):
         out["others"] = {}
         for name, fn in (("scenarios_10k_x1024", run_c2), ("uneven_256_grids", run_c3),
                          ("adjoint_70k_k64", run_c4), ("newton_device_70k", run_newton),
-                         ("fdlf_70k_meshed", run_fdlf)):
+                         ("fdlf_70k_meshed", run_fdlf), ("per_model_70k", run_models)):
             log(f"[bench] {name}")
             out["others"][name] = fn(args, torch, dev, net70k=net,
                                      plain_us=res.get("plain", {}).get("us_per_eval"))
@@ -536,6 +537,68 @@ def run_newton(args, torch, dev, **kw):
             "with_q_limits": lim}
 
 
+def run_models(args, torch, dev, **kw):
+    """Per-model cost on the GPU (the analogue of the paper's Table IV): the
+    70k grid rebuilt model by model -- lines and the slack only, then with
+    its 40,000 PQ loads, then its 3,500 shunts, then its 10,000 PV units (the
+    full grid) -- each evaluated at 1000 states with the same kernels
+    (batched launch, and 1000 single-instance launches in a graph).  The
+    differences are what each model adds."""
+    from paper_2011_11880_amd import synth
+    from paper_2011_11880_amd.api import Plan
+    full = synth.grid_70k()
+    S = 1000
+    Y = synth.random_states(full, S, seed=1001)
+    N = full.n_bus
+    e_i, e_d = np.zeros(0, np.int32), np.zeros(0)
+
+    def variant(loads, shunts, pv):
+        v = full.copy()
+        if not loads:
+            v.load_bus, v.load_p, v.load_q = e_i, e_d, e_d
+        if not shunts:
+            v.shunt_bus, v.shunt_g, v.shunt_b = e_i, e_d, e_d
+        if not pv:
+            v.pv_bus, v.pv_p, v.pv_v = e_i, e_d, e_d
+        return v
+
+    out = {}
+    for name, v in (("line_slack", variant(False, False, False)),
+                    ("+pq_loads", variant(True, False, False)),
+                    ("+shunts", variant(True, True, False)),
+                    ("+pv_units", variant(True, True, True))):
+        # states of this variant: theta, V, then the generator variables
+        Yv = np.concatenate([Y[:, :2 * N], Y[:, 2 * N + full.n_pv - v.n_pv:]], axis=1)
+        bp = Plan(v, batch=dict(n_inst=S, inst_stride=1008), device=0)
+        X = torch.from_numpy(np.ascontiguousarray(np.pad(Yv.T, ((0, 0), (0, 8))))).to(dev)
+        Fb = torch.empty((bp.n, 1008), dtype=torch.float64, device=dev)
+        Jb = torch.empty((bp.nnz, 1008), dtype=torch.float64, device=dev)
+        ms_b = time_ms(torch, lambda: bp.eval_batch(X, Fb, Jb))
+        del X, Fb, Jb
+        pp = Plan(v, device=0)
+        Xs = torch.from_numpy(Yv).to(dev)
+        Fs = torch.empty((S, pp.n), dtype=torch.float64, device=dev)
+        Js = torch.empty((S, pp.nnz), dtype=torch.float64, device=dev)
+        g = torch.cuda.CUDAGraph()
+        st = torch.cuda.Stream()
+        st.wait_stream(torch.cuda.current_stream())
+        for k in range(S):
+            pp.eval(Xs[k], Fs[k], Js[k])
+        torch.cuda.synchronize()
+        with torch.cuda.stream(st):
+            with torch.cuda.graph(g, stream=st):
+                for k in range(S):
+                    pp.eval(Xs[k], Fs[k], Js[k])
+        torch.cuda.synchronize()
+        ms_p = time_ms(torch, g.replay, reps=5, warmup=1)
+        del g, Xs, Fs, Js
+        out[name] = {"n": pp.n, "nnz": pp.nnz, "batched_ms_1000": ms_b,
+                     "plain_us_per_eval": ms_p * 1e3 / S}
+        log("[bench] models", name, json.dumps(out[name]))
+    return {"grid": "70,000-bus grid built up model by model, 1000 random states",
+            "variants": out}
+
+
 def run_copy(args, torch, dev):
     """Calibration: a plain device-to-device copy of known size (torch's
     copy kernel), the reference for HBM byte counters; also reports the
@@ -568,7 +631,7 @@ def main():
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--config", default="c1",
-                    choices=["c1", "c2", "c3", "c4", "newton", "fdlf", "copy"])
+                    choices=["c1", "c2", "c3", "c4", "newton", "fdlf", "models", "copy"])
     ap.add_argument("--copy-mib", type=int, default=1024)
     ap.add_argument("--states", type=int, default=1000)
     ap.add_argument("--autotune", action="store_true")
@@ -589,7 +652,7 @@ def main():
         sys.exit(1)
     dev = torch.device("cuda", 0)
     out = {"c1": run_c1, "c2": run_c2, "c3": run_c3, "c4": run_c4, "newton": run_newton,
-           "fdlf": run_fdlf, "copy": run_copy}[args.config](args, torch, dev)
+           "fdlf": run_fdlf, "models": run_models, "copy": run_copy}[args.config](args, torch, dev)
     print(json.dumps(out), flush=True)
 
 
