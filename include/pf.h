@@ -248,6 +248,22 @@ int pf_info_multi(const pf_plan *plan, int64_t *x_off, int64_t *j_off);
 int pf_pattern(const pf_plan *plan, int32_t *rowptr, int32_t *colidx);
 
 /*
+ * A row order of the Jacobian (host output [n]: row k of the reordered
+ * matrix is row order[k]) under which every diagonal entry is a structural
+ * nonzero that no branch outage can remove: each generator's voltage-control
+ * row (+1 at its bus voltage) trades places with its bus's Q row (whose -1 at
+ * Q_g then sits on the diagonal), each slack angle row with its bus's P row;
+ * the other diagonals are the buses' own sums over their branches.  A PV
+ * unit held at a reactive target (pf_set_gen_modes) keeps its row, whose +1
+ * at its own Q_g is then the diagonal; the order follows the current modes.
+ * An LU
+ * that pivots on the diagonal of the reordered matrix therefore keeps usable
+ * pivots for every instance of a batch (outages, scenarios) and for later
+ * Newton iterates.  Works on host-only plans.
+ */
+int pf_jacobian_row_order(const pf_plan *plan, int32_t *order);
+
+/*
  * Residual F(x) (task 1 of the Newton loop, Section I).  x, F: device [n].
  * Errors: PF_EINVAL (NULL buffer, batched plan, host-only plan), PF_EDEVICE.
  */
@@ -439,6 +455,16 @@ int pf_fdlf_matrices(const pf_plan *plan, int64_t *nnz_bp, int32_t *bp_rowptr,
  */
 typedef struct pf_lu pf_lu;
 
+/* Symbolic LU without pivoting of P M Q for the n x n CSR pattern
+ * (rowptr, colidx) of M and the orders pivP, pivQ (as above): the CSR
+ * pattern of T = (L - I) + U that holds every entry an elimination along it
+ * can reach, whatever the values (a numeric LU may return fewer entries
+ * where values happen to vanish; the device re-factorisations need the full
+ * pattern).  Call with NULL T arrays to learn *nnzT.  Host arrays. */
+int pf_lu_symbolic(int64_t n, const int32_t *rowptr, const int32_t *colidx,
+                   const int32_t *pivP, const int32_t *pivQ, int64_t *nnzT,
+                   int32_t *T_rowptr, int32_t *T_colidx);
+
 int pf_lu_create(int32_t device, int64_t n, int64_t nnz, const int32_t *rowptr,
                  const int32_t *colidx, const double *val, int64_t nnzT,
                  const int32_t *T_rowptr, const int32_t *T_colidx,
@@ -469,6 +495,48 @@ int pf_fdlf_create(pf_plan *plan, pf_lu *bp, pf_lu *bpp, pf_fdlf **out);
 int pf_fdlf_solve(pf_fdlf *fd, double *x, const pf_newton_opts *opts,
                   pf_newton_report *report, void *stream);
 void pf_fdlf_destroy(pf_fdlf *fd);
+
+/*
+ * Batched Newton (every instance of a batched plan solved together, e.g. N-1
+ * contingencies).  The Jacobians of a batched plan share one pattern, so one
+ * host LU with pivoting of one of them, P M Q = L U (T = (L - I) + U and
+ * pivP, pivQ as for pf_refact_create; T must hold every Jacobian entry and be
+ * closed under elimination, as the filled pattern of an LU is), serves every
+ * instance: each is factorised on the device along T without pivoting again
+ * (a zero pivot gives non-finite values for that instance only).
+ *
+ * pf_batch_lu_create: batched plan in the row layout; host arrays read
+ *   during the call; the object keeps a pointer to the plan (destroy it
+ *   first) and owns its device buffers (T values for every instance: nnzT x
+ *   the plan's row pitch doubles, plus F, J and work rows).  Rows of T
+ *   longer than the device's LDS allows for 16 instances give PF_EINVAL.
+ * pf_batch_lu_factor: factorise every instance from J (device, the plan's
+ *   batched Jacobian layout [nnz][pitch]).
+ * pf_batch_lu_solve: after a factorisation, Xout[., i] = J_i^-1 B[., i] for
+ *   every instance (device [n][pitch], must not alias).  Asynchronous.
+ * pf_newton_batch: X (device [n][pitch]) updated in place; per iteration one
+ *   batched evaluation (pf_eval_batch's kernel), per-instance ||F||_inf (the
+ *   norms are copied to the host), the factorisation and solves, and
+ *   x <- x - dx for the instances still above tol; an instance that reaches
+ *   tol is not stepped again.  inst_iters / inst_norm (host [n_inst],
+ *   nullable) receive each instance's steps and last norm.  report:
+ *   iterations = steps taken, converged = number of converged instances,
+ *   norm[k] = largest norm among unconverged instances before step k,
+ *   t_eval_s = evaluations, t_solve_s = factorisations + solves + updates
+ *   (device time).  PF_ENOCONV if some instance has not converged after
+ *   max_iter (<= 64) steps.  Calls on one object must not overlap.
+ */
+typedef struct pf_batch_lu pf_batch_lu;
+
+int pf_batch_lu_create(pf_plan *plan, int64_t nnzT, const int32_t *T_rowptr,
+                       const int32_t *T_colidx, const int32_t *pivP,
+                       const int32_t *pivQ, pf_batch_lu **out);
+int pf_batch_lu_factor(pf_batch_lu *b, const double *J, void *stream);
+int pf_batch_lu_solve(pf_batch_lu *b, const double *B, double *Xout, void *stream);
+int pf_newton_batch(pf_plan *plan, pf_batch_lu *b, double *X, const pf_newton_opts *opts,
+                    int32_t *inst_iters, double *inst_norm, pf_newton_report *report,
+                    void *stream);
+void pf_batch_lu_destroy(pf_batch_lu *b);
 
 /* Release the plan and all its device memory.  NULL is ignored. */
 void pf_destroy(pf_plan *plan);

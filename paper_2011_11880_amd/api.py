@@ -63,24 +63,50 @@ def params_vector(nets):
                 for k in ("br_r", "br_x", "br_b", "br_tap", "br_shift_deg", "load_p", "load_q")])
 
 
-def host_lu(rowptr, colidx, values, n, permc_spec="COLAMD"):
-    """One sparse LU with pivoting of the CSR matrix M on the host (SuperLU;
-    COLAMD ordering: SuperLU's minimum-degree orderings take minutes on
-    well-meshed grids), in the form the device re-factorisation takes:
+def host_lu(rowptr, colidx, values, n, permc_spec="COLAMD", row_order=None):
+    """One sparse LU of the CSR matrix M on the host (SuperLU; COLAMD
+    ordering: SuperLU's minimum-degree orderings take minutes on well-meshed
+    grids), in the form the device re-factorisations take:
     (T_rowptr, T_colidx, T_val, pivP, pivQ) with T = (L - I) + U in CSR
-    (sorted columns) and M[pivP][:, pivQ] = L U."""
+    (sorted columns, the full symbolic pattern) and M[pivP][:, pivQ] = L U.
+    With ``row_order`` (a Jacobian's pf_jacobian_row_order) the rows are
+    reordered first and pivots are taken on the diagonal, so that they stay
+    usable for every matrix of the same pattern; otherwise partial pivoting."""
     import scipy.sparse as sp
     import scipy.sparse.linalg as spla
-    M = sp.csr_matrix((_f64(values), _i32(colidx), _i32(rowptr)), shape=(n, n))
-    lu = spla.splu(M.tocsc(), permc_spec=permc_spec)
-    # SuperLU: Pr M Pc = L U with (Pr M)[perm_r[i]] = M[i], (M Pc)[:, perm_c[j]] = M[:, j]
-    pivP = np.argsort(lu.perm_r).astype(np.int32)
+    rowptr, colidx = _i32(rowptr), _i32(colidx)
+    M = sp.csr_matrix((_f64(values), colidx, rowptr), shape=(n, n))
+    R = np.arange(n) if row_order is None else np.asarray(row_order, dtype=np.int64)
+    thresh = 1.0 if row_order is None else 0.0
+    lu = spla.splu(M[R].tocsc(), permc_spec=permc_spec, diag_pivot_thresh=thresh)
+    # SuperLU: Pr A Pc = L U with (Pr A)[perm_r[i]] = A[i], (A Pc)[:, perm_c[j]] = A[:, j],
+    # here A = M[R]
+    pivP = R[np.argsort(lu.perm_r)].astype(np.int32)
     pivQ = np.argsort(lu.perm_c).astype(np.int32)
     T = (lu.L - sp.identity(n, format="csc") + lu.U).tocsr()
     T.sum_duplicates()
     T.sort_indices()
-    return (T.indptr.astype(np.int32), T.indices.astype(np.int32), T.data.astype(np.float64),
-            pivP, pivQ)
+    # the full symbolic pattern of the factors (SuperLU's factors leave out
+    # entries whose values vanish for this matrix), SuperLU's values in it
+    nz = ctypes.c_int64(0)
+    L = capi.lib()
+    args = (n, rowptr.ctypes.data_as(capi._pi32), colidx.ctypes.data_as(capi._pi32),
+            pivP.ctypes.data_as(capi._pi32), pivQ.ctypes.data_as(capi._pi32))
+    check(L.pf_lu_symbolic(*args, ctypes.byref(nz), None, None))
+    trp = np.empty(n + 1, np.int32)
+    tci = np.empty(nz.value, np.int32)
+    check(L.pf_lu_symbolic(*args, ctypes.byref(nz), trp.ctypes.data_as(capi._pi32),
+                           tci.ctypes.data_as(capi._pi32)))
+    rows = np.repeat(np.arange(n, dtype=np.int64), np.diff(trp))
+    keys = rows * n + tci
+    trow = np.repeat(np.arange(n, dtype=np.int64), np.diff(T.indptr))
+    tkeys = trow * n + T.indices
+    pos = np.searchsorted(keys, tkeys)
+    if np.any(pos >= keys.size) or np.any(keys[np.minimum(pos, keys.size - 1)] != tkeys):
+        raise RuntimeError("the numeric LU has entries outside the symbolic pattern")
+    tv = np.zeros(nz.value)
+    tv[pos] = T.data
+    return trp, tci, tv, pivP, pivQ
 
 
 def _opts(host_only=False, device=None, schedule=None, q_limits=False):
@@ -521,6 +547,45 @@ class Plan:
                 "t_eval_s": rep.t_eval_s, "t_solve_s": rep.t_solve_s,
                 "t_total_s": rep.t_total_s, "t_setup_s": t_setup}
 
+    # batched Newton ---------------------------------------------------------
+    def batch_lu(self, X, inst=0, permc_spec="COLAMD"):
+        """A BatchLU for this batched plan: pattern and pivots from one host LU
+        of instance ``inst``'s Jacobian at the batched state X."""
+        return BatchLU(self, X, inst=inst, permc_spec=permc_spec)
+
+    def newton_batch(self, X, lu=None, tol=1e-10, max_iter=10):
+        """Newton power flow for every instance of this batched plan at once
+        (pf_newton_batch).  X (batch_shape(n)) is updated in place.  Returns a
+        dict report with per-instance step counts and last norms."""
+        if lu is None:
+            lu = BatchLU(self, X)
+        I = self.n_inst
+        its = np.zeros(I, np.int32)
+        nrm = np.zeros(I)
+        opts = capi.pf_newton_opts(tol=float(tol), max_iter=int(max_iter))
+        rep = capi.pf_newton_report()
+        import math
+        rc = capi.lib().pf_newton_batch(self._h, lu._h,
+                                        _ptr(X, math.prod(self.batch_shape(self.n)), "X"),
+                                        ctypes.byref(opts), its.ctypes.data_as(capi._pi32),
+                                        nrm.ctypes.data_as(capi._pd), ctypes.byref(rep),
+                                        _stream(self._dev(X)))
+        if rc not in (capi.PF_OK, capi.PF_ENOCONV):
+            check(rc)
+        it = int(rep.iterations)
+        return {"iterations": it, "n_converged": int(rep.converged),
+                "inst_iterations": its, "inst_norm": nrm,
+                "norms": [float(v) for v in rep.norm[:min(it + 1, 65)]],
+                "t_eval_s": rep.t_eval_s, "t_solve_s": rep.t_solve_s,
+                "t_total_s": rep.t_total_s, "nnz_lu": lu.nnzT}
+
+    def jacobian_row_order(self):
+        """pf_jacobian_row_order: the row order under which the Jacobian's
+        diagonal pivots survive outages and later iterates."""
+        order = np.empty(self.n, np.int32)
+        check(capi.lib().pf_jacobian_row_order(self._h, order.ctypes.data_as(capi._pi32)))
+        return order
+
     def device_lu(self, x, permc_spec="COLAMD"):
         """A DeviceLU for this plan, its pattern and pivots taken from one host
         LU of the Jacobian at ``x`` (device [n])."""
@@ -563,7 +628,8 @@ class DeviceLU:
         J = plan.eval_jacobian(x)
         Jh = J.cpu().numpy()
         rp, ci = plan.pattern()
-        trp, tci, tv, pivP, pivQ = host_lu(rp, ci, Jh, plan.n, permc_spec)
+        trp, tci, tv, pivP, pivQ = host_lu(rp, ci, Jh, plan.n, permc_spec,
+                                           row_order=plan.jacobian_row_order())
         self.nnzT = int(trp[-1])
         h = capi._vp()
         check(capi.lib().pf_refact_create(
@@ -624,6 +690,64 @@ class DeviceSparseLU:
     def close(self):
         if self._h is not None and self._h.value:
             capi.lib().pf_lu_destroy(self._h)
+        self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class BatchLU:
+    """Batched factorisation (pf_batch_lu_*) of every instance of a batched
+    plan along the pattern and pivots of one host LU of one instance's
+    Jacobian."""
+
+    def __init__(self, plan, X, inst=0, permc_spec="COLAMD"):
+        import weakref
+        if plan.panels:
+            raise ValueError("the batched factorisation needs the row layout")
+        self.plan = plan
+        self._h = None
+        _, J = plan.eval_batch(X, want_F=False)
+        Jh = plan.from_batch(J)[inst]
+        rp, ci = plan.pattern()
+        trp, tci, _, pivP, pivQ = host_lu(rp, ci, Jh, plan.n, permc_spec,
+                                          row_order=plan.jacobian_row_order())
+        self.nnzT = int(trp[-1])
+        h = capi._vp()
+        check(capi.lib().pf_batch_lu_create(
+            plan._h, self.nnzT, trp.ctypes.data_as(capi._pi32), tci.ctypes.data_as(capi._pi32),
+            pivP.ctypes.data_as(capi._pi32), pivQ.ctypes.data_as(capi._pi32), ctypes.byref(h)))
+        self._h = h
+        if not hasattr(plan, "_lus"):
+            plan._lus = []
+        plan._lus.append(weakref.ref(self))
+
+    def factor(self, J):
+        """Factorise every instance from the batched Jacobian J."""
+        import math
+        p = self.plan
+        check(capi.lib().pf_batch_lu_factor(self._h, _ptr(J, math.prod(p.batch_shape(p.nnz)), "J"),
+                                            _stream(J.device)))
+
+    def solve(self, B, out=None):
+        """Per-instance solves J_i x = B[:, i] after factor(); returns out."""
+        import math
+
+        import torch
+        p = self.plan
+        sh = p.batch_shape(p.n)
+        if out is None:
+            out = torch.empty(sh, dtype=torch.float64, device=B.device)
+        check(capi.lib().pf_batch_lu_solve(self._h, _ptr(B, math.prod(sh), "B"),
+                                           _ptr(out, math.prod(sh), "out"), _stream(B.device)))
+        return out
+
+    def close(self):
+        if self._h is not None and self._h.value:
+            capi.lib().pf_batch_lu_destroy(self._h)
         self._h = None
 
     def __del__(self):

@@ -22,7 +22,7 @@ HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 ARCH = "gfx950"
 
 HOST_SRCS = ["pf_setup.cpp", "pf_api.cpp"]
-DEVICE_SRCS = ["pf_device.hip", "pf_lu.hip", "pf_qlim.hip"]
+DEVICE_SRCS = ["pf_device.hip", "pf_lu.hip", "pf_qlim.hip", "pf_batchlu.hip"]
 
 HIP_FLAGS = [
     f"--offload-arch={ARCH}", "-O3", "-std=c++17", "-fPIC",

@@ -98,6 +98,7 @@ SIGNATURES = {
     "pf_info_ex": (ctypes.c_int, [_P, ctypes.POINTER(pf_info_t)]),
     "pf_info_multi": (ctypes.c_int, [_P, _pi64, _pi64]),
     "pf_pattern": (ctypes.c_int, [_P, _pi32, _pi32]),
+    "pf_jacobian_row_order": (ctypes.c_int, [_P, _pi32]),
     "pf_eval_residual": (ctypes.c_int, [_P, _vp, _vp, _vp]),
     "pf_eval_jacobian": (ctypes.c_int, [_P, _vp, _vp, _vp]),
     "pf_eval": (ctypes.c_int, [_P, _vp, _vp, _vp, _vp]),
@@ -120,6 +121,7 @@ SIGNATURES = {
     "pf_refact_destroy": (None, [_vp]),
     "pf_fdlf_matrices": (ctypes.c_int, [_P, _pi64, _pi32, _pi32, _pd, _pi32, _pi64, _pi32,
                                         _pi32, _pd, _pi32]),
+    "pf_lu_symbolic": (ctypes.c_int, [_i64, _pi32, _pi32, _pi32, _pi32, _pi64, _pi32, _pi32]),
     "pf_lu_create": (ctypes.c_int, [_i32, _i64, _i64, _pi32, _pi32, _pd, _i64, _pi32, _pi32,
                                     _pd, _pi32, _pi32, ctypes.POINTER(_vp)]),
     "pf_lu_solve": (ctypes.c_int, [_vp, _vp, _vp]),
@@ -128,6 +130,13 @@ SIGNATURES = {
     "pf_fdlf_solve": (ctypes.c_int, [_vp, _vp, ctypes.POINTER(pf_newton_opts),
                                      ctypes.POINTER(pf_newton_report), _vp]),
     "pf_fdlf_destroy": (None, [_vp]),
+    "pf_batch_lu_create": (ctypes.c_int, [_P, _i64, _pi32, _pi32, _pi32, _pi32,
+                                          ctypes.POINTER(_vp)]),
+    "pf_batch_lu_factor": (ctypes.c_int, [_vp, _vp, _vp]),
+    "pf_batch_lu_solve": (ctypes.c_int, [_vp, _vp, _vp, _vp]),
+    "pf_newton_batch": (ctypes.c_int, [_P, _vp, _vp, ctypes.POINTER(pf_newton_opts), _pi32, _pd,
+                                       ctypes.POINTER(pf_newton_report), _vp]),
+    "pf_batch_lu_destroy": (None, [_vp]),
     "pf_destroy": (None, [_P]),
     "pf_last_error": (ctypes.c_char_p, []),
 }

@@ -166,6 +166,32 @@ int pf_pattern(const pf_plan *plan, int32_t *rowptr, int32_t *colidx) {
     return PF_OK;
 }
 
+int pf_jacobian_row_order(const pf_plan *plan, int32_t *order) {
+    clear_error();
+    if (!plan || !order) return fail(PF_EINVAL, "NULL argument");
+    const HostPlan &h = plan->host;
+    for (int64_t r = 0; r < h.n; ++r) order[r] = int32_t(r);
+    // a control row's first slot is its V (angle) column, whose index equals
+    // that of the bus's Q (P) row
+    for (size_t g = 0; g < size_t(h.NGt); ++g) {
+        const int32_t v_row = h.gen4[4 * g];
+        const int32_t th_row = h.gen4[4 * g + 2];
+        // a unit held at a reactive target keeps its row: its +1 sits on
+        // its own Q_g column, the diagonal
+        if (th_row != kGenHeld) {
+            const int32_t q_row = h.colidx[size_t(h.rowptr[size_t(v_row)])];
+            order[q_row] = v_row;
+            order[v_row] = q_row;
+        }
+        if (th_row >= 0) {
+            const int32_t p_row = h.colidx[size_t(h.rowptr[size_t(th_row)])];
+            order[p_row] = th_row;
+            order[th_row] = p_row;
+        }
+    }
+    return PF_OK;
+}
+
 int pf_eval(pf_plan *plan, const double *x, double *F, double *Jval, void *stream) {
     clear_error();
     int rc = check_eval(plan, false);

@@ -1,0 +1,567 @@
+// Batched Newton power flow: thousands of instances of one grid (N-1
+// contingencies, scenarios) solved together, every step on the device.  The
+// Jacobians of a batched plan share one pattern, so one host LU with pivoting
+// of one of them (P M Q = L U) fixes the pattern of T = (L - I) + U and both
+// orders for all instances; every instance is then factorised along that
+// pattern without pivoting again, in the same instance-fastest layout as the
+// evaluation (a wavefront's lanes are instances, so every access to a T entry
+// is one contiguous segment and the row structure is wave-uniform).
+//
+// Factorisation, row by row (row r of T in the permuted order):
+//   t_r. <- the permuted Jacobian row (0 on fill entries);
+//   for each k < r with t_rk in the pattern, in increasing k:
+//       t_rk <- t_rk / t_kk;   t_rj <- t_rj - t_rk t_kj  for every j > k of row k;
+// rows are grouped into levels (a row only needs rows of earlier levels) and
+// each level is one launch; a wave keeps its row in LDS for all instances of
+// its chunk.  Solves: forward over the same levels, backward over levels of
+// U, then the update x[pivQ[k]] -= z[k].
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <cstdint>
+#include <cstring>
+#include <new>
+#include <vector>
+
+#include <hip/hip_runtime.h>
+
+#include "pf_internal.hpp"
+
+#define BL_HIP(expr)                                                               \
+    do {                                                                           \
+        hipError_t e_ = (expr);                                                    \
+        if (e_ != hipSuccess)                                                      \
+            return fail(PF_EDEVICE, "%s failed: %s", #expr, hipGetErrorString(e_)); \
+    } while (0)
+
+using namespace pf;
+
+struct pf_batch_lu {
+    pf_plan *plan = nullptr;
+    int device = 0;
+    int n = 0, nnzT = 0, n_inst = 0, ld = 0;
+    // host copies of the level structure
+    std::vector<int32_t> flev_ptr, blev_ptr;  // levels -> rows (offsets into the row lists)
+    std::vector<int32_t> flev_w, blev_w;      // lanes used per wave (64, 32 or 16) per level
+    std::vector<int32_t> flev_maxr;           // longest row per factor level
+    // device structure
+    int32_t *trp = nullptr;   // n + 1
+    int32_t *tci = nullptr;   // nnzT
+    int32_t *tsrc = nullptr;  // nnzT: Jacobian slot of each T entry, -1 for fill
+    int32_t *tdiag = nullptr; // n
+    int4 *step = nullptr;     // per L entry: {local index in row, diag position of k, update begin, end}
+    int32_t *step_ptr = nullptr;  // n + 1: steps of each row
+    int2 *upd = nullptr;      // {local index in row r, T position of (k, j)}
+    int32_t *frows = nullptr, *brows = nullptr;  // rows in level order
+    int32_t *pivP = nullptr, *pivQ = nullptr;
+    // device work arrays, instance-fastest with row pitch ld
+    double *T = nullptr, *F = nullptr, *J = nullptr, *Y = nullptr;
+    double *part = nullptr, *norm = nullptr;  // per-instance norms
+    int32_t *active = nullptr;
+    double *norm_host = nullptr;              // pinned [ld]
+    int part_rows = 0;
+};
+
+namespace {
+
+constexpr int kNormRowBlocks = 64;  // row blocks of the per-instance norm
+
+struct BGuard {
+    int prev = -1;
+    bool ok = true;
+    explicit BGuard(int dev) {
+        if (hipGetDevice(&prev) != hipSuccess) {
+            ok = false;
+            return;
+        }
+        if (prev != dev && hipSetDevice(dev) != hipSuccess) ok = false;
+    }
+    ~BGuard() {
+        int cur = -1;
+        if (prev >= 0 && hipGetDevice(&cur) == hipSuccess && cur != prev) (void)hipSetDevice(prev);
+    }
+};
+
+template <class T>
+int balloc(T **dst, const T *src, size_t count) {
+    BL_HIP(hipMalloc(dst, (count ? count : 1) * sizeof(T)));
+    if (src && count) BL_HIP(hipMemcpy(*dst, src, count * sizeof(T), hipMemcpyHostToDevice));
+    return PF_OK;
+}
+
+void release(pf_batch_lu *b) {
+    if (!b) return;
+    int prev = -1;
+    (void)hipGetDevice(&prev);
+    (void)hipSetDevice(b->device);
+    for (void *p : {(void *)b->trp, (void *)b->tci, (void *)b->tsrc, (void *)b->tdiag,
+                    (void *)b->step, (void *)b->step_ptr, (void *)b->upd, (void *)b->frows,
+                    (void *)b->brows, (void *)b->pivP, (void *)b->pivQ, (void *)b->T,
+                    (void *)b->F, (void *)b->J, (void *)b->Y, (void *)b->part, (void *)b->norm,
+                    (void *)b->active})
+        if (p) (void)hipFree(p);
+    if (b->norm_host) (void)hipHostFree(b->norm_host);
+    if (prev >= 0) (void)hipSetDevice(prev);
+    delete b;
+}
+
+bool is_perm(const int32_t *p, int n) {
+    std::vector<char> seen(size_t(n), 0);
+    for (int i = 0; i < n; ++i) {
+        if (p[i] < 0 || p[i] >= n || seen[size_t(p[i])]) return false;
+        seen[size_t(p[i])] = 1;
+    }
+    return true;
+}
+
+// lanes per wave for rows of length maxr so that a block's LDS row fits
+int lanes_for(int maxr, size_t lds_limit) {
+    for (int w = 64; w >= 16; w >>= 1)
+        if (size_t(maxr) * size_t(w) * sizeof(double) <= lds_limit) return w;
+    return 0;
+}
+
+// ---------------------------------------------------------------------------
+// kernels (one wavefront per block; lane < W handles instance chunk*W + lane)
+// ---------------------------------------------------------------------------
+
+__global__ void __launch_bounds__(64) k_blu_factor(
+    const int32_t *__restrict__ rows, int n_chunks, int W, int n_inst, int SI,
+    const int32_t *__restrict__ trp, const int32_t *__restrict__ tsrc,
+    const int32_t *__restrict__ tdiag, const int32_t *__restrict__ step_ptr,
+    const int4 *__restrict__ step, const int2 *__restrict__ upd,
+    const double *__restrict__ J, double *__restrict__ T) {
+    extern __shared__ double Lrow[];
+    const int lane = threadIdx.x;
+    const int r = rows[blockIdx.x / n_chunks];
+    const int inst = (blockIdx.x % n_chunks) * W + lane;
+    const bool live = lane < W && inst < n_inst;
+    const int r0 = trp[r], R = trp[r + 1] - r0;
+    if (live) {
+        for (int q = 0; q < R; ++q) {
+            const int s = tsrc[r0 + q];
+            Lrow[q * W + lane] = s >= 0 ? J[size_t(s) * SI + inst] : 0.0;
+        }
+        const int s0 = step_ptr[r], s1 = step_ptr[r + 1];
+        for (int st = s0; st < s1; ++st) {
+            const int4 sp = step[st];
+            const double lik = Lrow[sp.x * W + lane] / T[size_t(sp.y) * SI + inst];
+            Lrow[sp.x * W + lane] = lik;
+            for (int u = sp.z; u < sp.w; ++u) {
+                const int2 p = upd[u];
+                Lrow[p.x * W + lane] = fma(-lik, T[size_t(p.y) * SI + inst], Lrow[p.x * W + lane]);
+            }
+        }
+        for (int q = 0; q < R; ++q) T[size_t(r0 + q) * SI + inst] = Lrow[q * W + lane];
+    }
+}
+
+// forward: Y[r] = F[pivP[r]] - sum_{k < r} t_rk Y[k]
+__global__ void __launch_bounds__(64) k_blu_fwd(
+    const int32_t *__restrict__ rows, int n_chunks, int W, int n_inst, int SI,
+    const int32_t *__restrict__ trp, const int32_t *__restrict__ tci,
+    const int32_t *__restrict__ pivP, const double *__restrict__ T,
+    const double *__restrict__ F, double *__restrict__ Y) {
+    const int lane = threadIdx.x;
+    const int r = rows[blockIdx.x / n_chunks];
+    const int inst = (blockIdx.x % n_chunks) * W + lane;
+    if (lane >= W || inst >= n_inst) return;
+    double s = F[size_t(pivP[r]) * SI + inst];
+    for (int e = trp[r]; e < trp[r + 1]; ++e) {
+        const int c = tci[e];
+        if (c >= r) break;
+        s = fma(-T[size_t(e) * SI + inst], Y[size_t(c) * SI + inst], s);
+    }
+    Y[size_t(r) * SI + inst] = s;
+}
+
+// backward: Y[r] = (Y[r] - sum_{j > r} t_rj Y[j]) / t_rr
+__global__ void __launch_bounds__(64) k_blu_bwd(
+    const int32_t *__restrict__ rows, int n_chunks, int W, int n_inst, int SI,
+    const int32_t *__restrict__ trp, const int32_t *__restrict__ tci,
+    const int32_t *__restrict__ tdiag, const double *__restrict__ T, double *__restrict__ Y) {
+    const int lane = threadIdx.x;
+    const int r = rows[blockIdx.x / n_chunks];
+    const int inst = (blockIdx.x % n_chunks) * W + lane;
+    if (lane >= W || inst >= n_inst) return;
+    double s = Y[size_t(r) * SI + inst];
+    for (int e = tdiag[r] + 1; e < trp[r + 1]; ++e)
+        s = fma(-T[size_t(e) * SI + inst], Y[size_t(tci[e]) * SI + inst], s);
+    Y[size_t(r) * SI + inst] = s / T[size_t(tdiag[r]) * SI + inst];
+}
+
+// x[pivQ[k]] -= z[k] for active instances (subtract = 1), or x[pivQ[k]] = z[k]
+// (subtract = 0); one block per (row k, 256 instances)
+__global__ void __launch_bounds__(256) k_blu_step(int n, int n_inst, int SI, int inst_blocks,
+                                                  int subtract,
+                                                  const int32_t *__restrict__ pivQ,
+                                                  const int32_t *__restrict__ active,
+                                                  const double *__restrict__ Z,
+                                                  double *__restrict__ X) {
+    const int k = blockIdx.x / inst_blocks;
+    const int inst = (blockIdx.x % inst_blocks) * 256 + threadIdx.x;
+    if (inst >= n_inst || k >= n) return;
+    const size_t dst = size_t(pivQ[k]) * SI + inst;
+    const double z = Z[size_t(k) * SI + inst];
+    if (!subtract)
+        X[dst] = z;
+    else if (active[inst])
+        X[dst] -= z;
+}
+
+__device__ __forceinline__ double bmax(double m, double a) {
+    return (a > m || a != a) && !(m != m) ? a : m;
+}
+
+// per-instance max |F| over rows: part[rb][inst] over row block rb
+__global__ void __launch_bounds__(256) k_blu_norm_part(int n, int n_inst, int SI, int rows_per,
+                                                       const double *__restrict__ F,
+                                                       double *__restrict__ part) {
+    const int inst = blockIdx.x * 256 + threadIdx.x;
+    if (inst >= n_inst) return;
+    const int r0 = blockIdx.y * rows_per, r1 = min(n, r0 + rows_per);
+    double m = 0.0;
+    for (int r = r0; r < r1; ++r) m = bmax(m, fabs(F[size_t(r) * SI + inst]));
+    part[size_t(blockIdx.y) * SI + inst] = m;
+}
+
+__global__ void __launch_bounds__(256) k_blu_norm_fold(int nb, int n_inst, int SI,
+                                                       const double *__restrict__ part,
+                                                       double *__restrict__ norm) {
+    const int inst = blockIdx.x * 256 + threadIdx.x;
+    if (inst >= n_inst) return;
+    double m = 0.0;
+    for (int b = 0; b < nb; ++b) m = bmax(m, part[size_t(b) * SI + inst]);
+    norm[inst] = m;
+}
+
+// ---------------------------------------------------------------------------
+// host-side structure
+// ---------------------------------------------------------------------------
+
+int build(pf_batch_lu *b, const HostPlan &hp, int64_t nnzT, const int32_t *trp,
+          const int32_t *tci, const int32_t *pivP, const int32_t *pivQ, size_t lds_limit) {
+    const int n = int(hp.n);
+    std::vector<int32_t> tdiag(size_t(n), -1), tsrc(size_t(nnzT), -1);
+    // Jacobian slot of each T entry: entry (r, c) of P M Q is (pivP[r], pivQ[c]) of M
+    for (int r = 0; r < n; ++r) {
+        const int32_t mr = pivP[r];
+        const int32_t *b0 = hp.colidx.data() + hp.rowptr[size_t(mr)];
+        const int32_t *b1 = hp.colidx.data() + hp.rowptr[size_t(mr) + 1];
+        for (int32_t e = trp[r]; e < trp[r + 1]; ++e) {
+            if (tci[e] == r) tdiag[size_t(r)] = e;
+            const int32_t mc = pivQ[tci[e]];
+            const int32_t *p = std::lower_bound(b0, b1, mc);
+            if (p != b1 && *p == mc) tsrc[size_t(e)] = int32_t(p - hp.colidx.data());
+        }
+        if (tdiag[size_t(r)] < 0) return fail(PF_EINVAL, "T lacks the diagonal of row %d", r);
+    }
+    // every Jacobian slot must land in T
+    {
+        std::vector<char> hit(size_t(hp.nnz), 0);
+        for (int32_t s : tsrc)
+            if (s >= 0) hit[size_t(s)] = 1;
+        for (int64_t s = 0; s < hp.nnz; ++s)
+            if (!hit[size_t(s)])
+                return fail(PF_EINVAL, "T does not hold every Jacobian entry (slot %lld)", (long long)s);
+    }
+    // elimination steps and updates; T must be closed under elimination
+    std::vector<int4> step;
+    std::vector<int32_t> step_ptr(size_t(n) + 1, 0);
+    std::vector<int2> upd;
+    std::vector<int32_t> flev(size_t(n), 0);
+    for (int r = 0; r < n; ++r) {
+        const int32_t r0 = trp[r], r1 = trp[r + 1];
+        int lev = 0;
+        for (int32_t e = r0; e < r1 && tci[e] < r; ++e) {
+            const int k = tci[e];
+            lev = std::max(lev, flev[size_t(k)] + 1);
+            const int32_t ub = int32_t(upd.size());
+            for (int32_t f = tdiag[size_t(k)] + 1; f < trp[k + 1]; ++f) {
+                const int32_t j = tci[f];
+                const int32_t *p = std::lower_bound(tci + r0, tci + r1, j);
+                if (p == tci + r1 || *p != j)
+                    return fail(PF_EINVAL, "T is not closed under elimination (row %d, column %d)", r, j);
+                upd.push_back(make_int2(int32_t(p - (tci + r0)), f));
+            }
+            step.push_back(make_int4(e - r0, tdiag[size_t(k)], ub, int32_t(upd.size())));
+        }
+        flev[size_t(r)] = lev;
+        step_ptr[size_t(r) + 1] = int32_t(step.size());
+        if (upd.size() > size_t(INT32_MAX)) return fail(PF_EINVAL, "elimination too large");
+    }
+    // backward levels over U
+    std::vector<int32_t> blev(size_t(n), 0);
+    for (int r = n - 1; r >= 0; --r) {
+        int lev = 0;
+        for (int32_t e = tdiag[size_t(r)] + 1; e < trp[r + 1]; ++e)
+            lev = std::max(lev, blev[size_t(tci[e])] + 1);
+        blev[size_t(r)] = lev;
+    }
+    auto group = [&](const std::vector<int32_t> &lev, std::vector<int32_t> &ptr,
+                     std::vector<int32_t> &rows) {
+        const int nl = n ? 1 + *std::max_element(lev.begin(), lev.end()) : 0;
+        ptr.assign(size_t(nl) + 1, 0);
+        for (int r = 0; r < n; ++r) ptr[size_t(lev[size_t(r)]) + 1]++;
+        for (int l = 0; l < nl; ++l) ptr[size_t(l) + 1] += ptr[size_t(l)];
+        rows.assign(size_t(n), 0);
+        std::vector<int32_t> fill(ptr.begin(), ptr.end() - 1);
+        for (int r = 0; r < n; ++r) rows[size_t(fill[size_t(lev[size_t(r)])]++)] = r;
+    };
+    std::vector<int32_t> frows, brows;
+    group(flev, b->flev_ptr, frows);
+    group(blev, b->blev_ptr, brows);
+    const size_t nfl = b->flev_ptr.size() - 1;
+    b->flev_w.assign(nfl, 64);
+    b->flev_maxr.assign(nfl, 0);
+    for (size_t l = 0; l < nfl; ++l) {
+        int maxr = 0;
+        for (int32_t q = b->flev_ptr[l]; q < b->flev_ptr[l + 1]; ++q) {
+            const int r = frows[size_t(q)];
+            maxr = std::max(maxr, trp[r + 1] - trp[r]);
+        }
+        b->flev_maxr[l] = maxr;
+        b->flev_w[l] = lanes_for(maxr, lds_limit);
+        if (!b->flev_w[l])
+            return fail(PF_EINVAL, "a row of T has %d entries: too long for the batched factorisation", maxr);
+    }
+    b->blev_w.assign(b->blev_ptr.size() - 1, 64);
+    int rc = PF_OK;
+    if (!rc) rc = balloc(&b->trp, trp, size_t(n) + 1);
+    if (!rc) rc = balloc(&b->tci, tci, size_t(nnzT));
+    if (!rc) rc = balloc(&b->tsrc, tsrc.data(), tsrc.size());
+    if (!rc) rc = balloc(&b->tdiag, tdiag.data(), tdiag.size());
+    if (!rc) rc = balloc(&b->step, step.data(), step.size());
+    if (!rc) rc = balloc(&b->step_ptr, step_ptr.data(), step_ptr.size());
+    if (!rc) rc = balloc(&b->upd, upd.data(), upd.size());
+    if (!rc) rc = balloc(&b->frows, frows.data(), frows.size());
+    if (!rc) rc = balloc(&b->brows, brows.data(), brows.size());
+    if (!rc) rc = balloc(&b->pivP, pivP, size_t(n));
+    if (!rc) rc = balloc(&b->pivQ, pivQ, size_t(n));
+    return rc;
+}
+
+int factor_levels(pf_batch_lu *b, const double *J, hipStream_t st) {
+    const int I = b->n_inst, SI = b->ld;
+    for (size_t l = 0; l + 1 < b->flev_ptr.size(); ++l) {
+        const int nr = b->flev_ptr[l + 1] - b->flev_ptr[l];
+        const int W = b->flev_w[l];
+        const int nc = (I + W - 1) / W;
+        const size_t shm = size_t(b->flev_maxr[l]) * size_t(W) * sizeof(double);
+        hipLaunchKernelGGL(k_blu_factor, dim3(unsigned(int64_t(nr) * nc)), dim3(64), shm, st,
+                           b->frows + b->flev_ptr[l], nc, W, I, SI, b->trp, b->tsrc, b->tdiag,
+                           b->step_ptr, b->step, b->upd, J, b->T);
+    }
+    BL_HIP(hipGetLastError());
+    return PF_OK;
+}
+
+int solve_levels(pf_batch_lu *b, const double *Fin, double *Y, hipStream_t st) {
+    const int I = b->n_inst, SI = b->ld;
+    const int nc = (I + 63) / 64;
+    for (size_t l = 0; l + 1 < b->flev_ptr.size(); ++l) {
+        const int nr = b->flev_ptr[l + 1] - b->flev_ptr[l];
+        hipLaunchKernelGGL(k_blu_fwd, dim3(unsigned(int64_t(nr) * nc)), dim3(64), 0, st,
+                           b->frows + b->flev_ptr[l], nc, 64, I, SI, b->trp, b->tci, b->pivP,
+                           b->T, Fin, Y);
+    }
+    for (size_t l = 0; l + 1 < b->blev_ptr.size(); ++l) {
+        const int nr = b->blev_ptr[l + 1] - b->blev_ptr[l];
+        hipLaunchKernelGGL(k_blu_bwd, dim3(unsigned(int64_t(nr) * nc)), dim3(64), 0, st,
+                           b->brows + b->blev_ptr[l], nc, 64, I, SI, b->trp, b->tci, b->tdiag,
+                           b->T, Y);
+    }
+    BL_HIP(hipGetLastError());
+    return PF_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int pf_batch_lu_create(pf_plan *plan, int64_t nnzT, const int32_t *T_rowptr,
+                       const int32_t *T_colidx, const int32_t *pivP, const int32_t *pivQ,
+                       pf_batch_lu **out) {
+    clear_error();
+    if (!out) return fail(PF_EINVAL, "out is NULL");
+    *out = nullptr;
+    if (!plan) return fail(PF_EINVAL, "plan is NULL");
+    const HostPlan &hp = plan->host;
+    if (hp.kind != KIND_BATCH) return fail(PF_EINVAL, "pf_batch_lu_create needs a batched plan");
+    if (hp.panels) return fail(PF_EINVAL, "the batched factorisation needs the row layout");
+    if (!T_rowptr || !T_colidx || !pivP || !pivQ) return fail(PF_EINVAL, "NULL argument");
+    const int64_t n = hp.n;
+    if (n < 1 || n > INT32_MAX - 1) return fail(PF_EINVAL, "bad system size");
+    if (nnzT < n || nnzT > INT32_MAX) return fail(PF_EINVAL, "nnzT must be in [n, 2^31)");
+    if (T_rowptr[0] != 0 || T_rowptr[n] != nnzT) return fail(PF_EINVAL, "T_rowptr must start at 0 and end at nnzT");
+    for (int64_t r = 0; r < n; ++r) {
+        if (T_rowptr[r + 1] < T_rowptr[r]) return fail(PF_EINVAL, "T_rowptr is not non-decreasing");
+        for (int32_t e = T_rowptr[r]; e < T_rowptr[r + 1]; ++e) {
+            if (T_colidx[e] < 0 || T_colidx[e] >= n) return fail(PF_EINVAL, "T_colidx out of range");
+            if (e > T_rowptr[r] && T_colidx[e] <= T_colidx[e - 1])
+                return fail(PF_EINVAL, "T_colidx not strictly increasing in a row");
+        }
+    }
+    if (!is_perm(pivP, int(n)) || !is_perm(pivQ, int(n)))
+        return fail(PF_EINVAL, "pivP and pivQ must be permutations of 0..n-1");
+    if (hp.host_only || !plan->dev) return fail(PF_EINVAL, "plan is host-only");
+    BGuard g(hp.device);
+    if (!g.ok) return fail(PF_EDEVICE, "cannot select device %d", hp.device);
+    int lds = 0;
+    BL_HIP(hipDeviceGetAttribute(&lds, hipDeviceAttributeMaxSharedMemoryPerBlock, hp.device));
+    // rows of the factorisation live in dynamic LDS, up to the device's limit
+    (void)hipFuncSetAttribute(reinterpret_cast<const void *>(&k_blu_factor),
+                              hipFuncAttributeMaxDynamicSharedMemorySize, lds);
+    pf_batch_lu *b = new (std::nothrow) pf_batch_lu();
+    if (!b) return fail(PF_ENOMEM, "host allocation failed");
+    b->plan = plan;
+    b->device = hp.device;
+    b->n = int(n);
+    b->nnzT = int(nnzT);
+    b->n_inst = hp.n_inst;
+    b->ld = hp.ld;
+    int rc;
+    try {
+        rc = build(b, hp, nnzT, T_rowptr, T_colidx, pivP, pivQ, size_t(lds));
+    } catch (const std::bad_alloc &) {
+        rc = fail(PF_ENOMEM, "host allocation failed");
+    }
+    const size_t SI = size_t(hp.ld);
+    b->part_rows = int((n + kNormRowBlocks - 1) / kNormRowBlocks);
+    if (!rc) rc = balloc<double>(&b->T, nullptr, size_t(nnzT) * SI);
+    if (!rc) rc = balloc<double>(&b->F, nullptr, size_t(n) * SI);
+    if (!rc) rc = balloc<double>(&b->J, nullptr, size_t(hp.nnz) * SI);
+    if (!rc) rc = balloc<double>(&b->Y, nullptr, size_t(n) * SI);
+    if (!rc) rc = balloc<double>(&b->part, nullptr, size_t(kNormRowBlocks) * SI);
+    if (!rc) rc = balloc<double>(&b->norm, nullptr, SI);
+    if (!rc) rc = balloc<int32_t>(&b->active, nullptr, SI);
+    if (!rc && hipHostMalloc(&b->norm_host, SI * sizeof(double), hipHostMallocDefault) != hipSuccess)
+        rc = fail(PF_ENOMEM, "pinned allocation failed");
+    if (rc) {
+        release(b);
+        return rc;
+    }
+    *out = b;
+    return PF_OK;
+}
+
+void pf_batch_lu_destroy(pf_batch_lu *b) { release(b); }
+
+int pf_batch_lu_factor(pf_batch_lu *b, const double *J, void *stream) {
+    clear_error();
+    if (!b || !J) return fail(PF_EINVAL, "NULL argument");
+    BGuard g(b->device);
+    if (!g.ok) return fail(PF_EDEVICE, "cannot select device %d", b->device);
+    return factor_levels(b, J, static_cast<hipStream_t>(stream));
+}
+
+int pf_batch_lu_solve(pf_batch_lu *b, const double *B, double *Xout, void *stream) {
+    clear_error();
+    if (!b || !B || !Xout) return fail(PF_EINVAL, "NULL argument");
+    if (B == Xout) return fail(PF_EINVAL, "B and Xout must not alias");
+    BGuard g(b->device);
+    if (!g.ok) return fail(PF_EDEVICE, "cannot select device %d", b->device);
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    int rc = solve_levels(b, B, b->Y, st);
+    if (rc) return rc;
+    const int ib = (b->n_inst + 255) / 256;
+    hipLaunchKernelGGL(k_blu_step, dim3(unsigned(int64_t(ib) * b->n)), dim3(256), 0, st, b->n,
+                       b->n_inst, b->ld, ib, 0, b->pivQ, b->active, b->Y, Xout);
+    BL_HIP(hipGetLastError());
+    return PF_OK;
+}
+
+int pf_newton_batch(pf_plan *plan, pf_batch_lu *b, double *X, const pf_newton_opts *opts,
+                    int32_t *inst_iters, double *inst_norm, pf_newton_report *report,
+                    void *stream) {
+    clear_error();
+    if (!plan || !b || !X) return fail(PF_EINVAL, "NULL argument");
+    if (b->plan != plan) return fail(PF_EINVAL, "the factorisation belongs to another plan");
+    if (opts && opts->max_iter > 64) return fail(PF_EINVAL, "max_iter must be <= 64");
+    HostPlan &hp = plan->host;
+    BGuard g(b->device);
+    if (!g.ok) return fail(PF_EDEVICE, "cannot select device %d", b->device);
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    const double tol = (opts && opts->tol > 0) ? opts->tol : 1e-10;
+    const int max_iter = (opts && opts->max_iter > 0) ? opts->max_iter : 10;
+    const int I = b->n_inst, SI = b->ld, n = b->n;
+    std::vector<int32_t> act(size_t(SI), 0), iters(size_t(I), 0);
+    for (int i = 0; i < I; ++i) act[size_t(i)] = 1;
+    pf_newton_report r{};
+    hipEvent_t ev[4];
+    for (auto &e : ev) BL_HIP(hipEventCreate(&e));
+    float ms = 0.f;
+    auto t_start = std::chrono::steady_clock::now();
+    int rc = PF_OK;
+    int it = 0;
+    int n_conv = 0;
+    for (;; ++it) {
+        (void)hipEventRecord(ev[0], st);
+        rc = dev_eval_batch(hp, plan->dev, X, b->F, b->J, st);
+        if (rc) break;
+        (void)hipEventRecord(ev[1], st);
+        hipLaunchKernelGGL(k_blu_norm_part, dim3(unsigned((I + 255) / 256), kNormRowBlocks),
+                           dim3(256), 0, st, n, I, SI, b->part_rows, b->F, b->part);
+        hipLaunchKernelGGL(k_blu_norm_fold, dim3(unsigned((I + 255) / 256)), dim3(256), 0, st,
+                           kNormRowBlocks, I, SI, b->part, b->norm);
+        if (hipGetLastError() != hipSuccess ||
+            hipMemcpyAsync(b->norm_host, b->norm, size_t(I) * sizeof(double),
+                           hipMemcpyDeviceToHost, st) != hipSuccess ||
+            hipStreamSynchronize(st) != hipSuccess) {
+            rc = fail(PF_EDEVICE, "device step failed in iteration %d", it);
+            break;
+        }
+        if (hipEventElapsedTime(&ms, ev[0], ev[1]) == hipSuccess) r.t_eval_s += ms * 1e-3;
+        // an instance stops once its norm is below tol; it is not stepped again
+        n_conv = 0;
+        double worst = 0.0;
+        for (int i = 0; i < I; ++i) {
+            const double v = b->norm_host[i];
+            if (act[size_t(i)] && v < tol) act[size_t(i)] = 0;
+            if (!act[size_t(i)]) ++n_conv;
+            else if (!(v <= worst)) worst = v;
+        }
+        if (it < 65) r.norm[it] = worst;
+        if (n_conv == I) {
+            rc = PF_OK;
+            break;
+        }
+        if (it >= max_iter) {
+            rc = fail(PF_ENOCONV, "%d of %d instances did not converge in %d iterations", I - n_conv,
+                      I, max_iter);
+            break;
+        }
+        for (int i = 0; i < I; ++i)
+            if (act[size_t(i)]) iters[size_t(i)] = it + 1;
+        if (hipMemcpyAsync(b->active, act.data(), size_t(SI) * sizeof(int32_t),
+                           hipMemcpyHostToDevice, st) != hipSuccess) {
+            rc = fail(PF_EDEVICE, "copy of the active mask failed");
+            break;
+        }
+        (void)hipEventRecord(ev[2], st);
+        rc = factor_levels(b, b->J, st);
+        if (rc) break;
+        rc = solve_levels(b, b->F, b->Y, st);
+        if (rc) break;
+        const int ib = (I + 255) / 256;
+        hipLaunchKernelGGL(k_blu_step, dim3(unsigned(int64_t(ib) * n)), dim3(256), 0, st, n, I,
+                           SI, ib, 1, b->pivQ, b->active, b->Y, X);
+        (void)hipEventRecord(ev[3], st);
+        if (hipGetLastError() != hipSuccess || hipStreamSynchronize(st) != hipSuccess) {
+            rc = fail(PF_EDEVICE, "device step failed in iteration %d", it);
+            break;
+        }
+        if (hipEventElapsedTime(&ms, ev[2], ev[3]) == hipSuccess) r.t_solve_s += ms * 1e-3;
+        r.iterations = it + 1;
+    }
+    (void)hipStreamSynchronize(st);
+    r.converged = n_conv;
+    r.t_total_s = std::chrono::duration<double>(std::chrono::steady_clock::now() - t_start).count();
+    for (auto &e : ev) (void)hipEventDestroy(e);
+    if (inst_iters) std::memcpy(inst_iters, iters.data(), size_t(I) * sizeof(int32_t));
+    if (inst_norm) std::memcpy(inst_norm, b->norm_host, size_t(I) * sizeof(double));
+    if (report) *report = r;
+    return rc;
+}
+
+}  // extern "C"

@@ -17,6 +17,7 @@
 #include <cstdint>
 #include <cstdio>
 #include <cstring>
+#include <functional>
 #include <mutex>
 #include <new>
 #include <vector>
@@ -663,7 +664,81 @@ int fd_blocks(int m) { return std::max(1, std::min(kAbsBlocks, (m + 255) / 256))
 
 }  // namespace
 
+namespace {
+
+// Symbolic LU without pivoting of B = P M Q (row k of B is row pivP[k] of M,
+// column k is column pivQ[k]): row by row, the pattern of row r is that of
+// B's row r united with the upper part of every earlier row k it reaches
+// (k < r in the pattern, in increasing k, including entries that this union
+// itself adds).  The result holds every entry an elimination along it can
+// touch, whatever the values.
+int symbolic(int n, const int32_t *rp, const int32_t *ci, const int32_t *pivP,
+             const int32_t *pivQ, std::vector<int32_t> &trp, std::vector<int32_t> &tci) {
+    std::vector<int32_t> qinv(static_cast<size_t>(n));
+    for (int k = 0; k < n; ++k) qinv[size_t(pivQ[k])] = k;
+    std::vector<int32_t> mark(size_t(n), -1);
+    std::vector<int32_t> udiag(size_t(n), 0);  // start of row k's upper part in tci
+    std::vector<int32_t> row, heap;
+    trp.assign(1, 0);
+    tci.clear();
+    for (int r = 0; r < n; ++r) {
+        row.clear();
+        heap.clear();
+        auto add = [&](int32_t c) {
+            if (mark[size_t(c)] == r) return;
+            mark[size_t(c)] = r;
+            row.push_back(c);
+            if (c < r) {
+                heap.push_back(c);
+                std::push_heap(heap.begin(), heap.end(), std::greater<int32_t>());
+            }
+        };
+        const int32_t m = pivP[r];
+        for (int32_t e = rp[m]; e < rp[m + 1]; ++e) add(qinv[size_t(ci[e])]);
+        add(r);
+        while (!heap.empty()) {
+            std::pop_heap(heap.begin(), heap.end(), std::greater<int32_t>());
+            const int32_t k = heap.back();
+            heap.pop_back();
+            for (int32_t f = udiag[size_t(k)]; f < trp[size_t(k) + 1]; ++f) add(tci[size_t(f)]);
+        }
+        std::sort(row.begin(), row.end());
+        const size_t base = tci.size();
+        if (base + row.size() > size_t(INT32_MAX)) return fail(PF_EINVAL, "LU pattern too large");
+        tci.insert(tci.end(), row.begin(), row.end());
+        trp.push_back(int32_t(tci.size()));
+        const auto d = std::upper_bound(row.begin(), row.end(), r);   // first entry past the diagonal
+        udiag[size_t(r)] = int32_t(base + size_t(d - row.begin()));
+    }
+    return PF_OK;
+}
+
+}  // namespace
+
 extern "C" {
+
+int pf_lu_symbolic(int64_t n, const int32_t *rowptr, const int32_t *colidx, const int32_t *pivP,
+                   const int32_t *pivQ, int64_t *nnzT, int32_t *T_rowptr, int32_t *T_colidx) {
+    clear_error();
+    if (!rowptr || !colidx || !pivP || !pivQ || !nnzT) return fail(PF_EINVAL, "NULL argument");
+    if (n < 1 || n > INT32_MAX - 1) return fail(PF_EINVAL, "n must be in [1, 2^31 - 1)");
+    if (const char *why = check_csr(int(n), rowptr[n], rowptr, colidx))
+        return fail(PF_EINVAL, "matrix: %s", why);
+    if (!is_permutation(pivP, int(n)) || !is_permutation(pivQ, int(n)))
+        return fail(PF_EINVAL, "pivP and pivQ must be permutations of 0..n-1");
+    std::vector<int32_t> trp, tci;
+    int rc;
+    try {
+        rc = symbolic(int(n), rowptr, colidx, pivP, pivQ, trp, tci);
+    } catch (const std::bad_alloc &) {
+        rc = fail(PF_ENOMEM, "host allocation failed");
+    }
+    if (rc) return rc;
+    *nnzT = int64_t(tci.size());
+    if (T_rowptr) std::memcpy(T_rowptr, trp.data(), trp.size() * sizeof(int32_t));
+    if (T_colidx) std::memcpy(T_colidx, tci.data(), tci.size() * sizeof(int32_t));
+    return PF_OK;
+}
 
 int pf_fdlf_matrices(const pf_plan *plan, int64_t *nnz_bp, int32_t *bp_rowptr,
                      int32_t *bp_colidx, double *bp_val, int32_t *bp_bus, int64_t *nnz_bpp,

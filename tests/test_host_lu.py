@@ -116,3 +116,126 @@ def test_newton_device_argument_checks():
     assert L.pf_newton_device(None, None, None, None, None, None) == capi.PF_EINVAL
     assert L.pf_refact_solve(None, None, None, None) == capi.PF_EINVAL
     L.pf_refact_destroy(None)
+
+
+def _eliminate(A, trp, tci):
+    """Plain row-by-row elimination of the dense matrix A along the pattern
+    (trp, tci); returns the factor values (a test reference)."""
+    n = A.shape[0]
+    T = np.zeros(trp[-1])
+    diag = np.zeros(n, int)
+    for r in range(n):
+        cols = tci[trp[r]:trp[r + 1]]
+        pos = {int(c): q for q, c in enumerate(cols)}
+        row = A[r, cols].astype(float)
+        diag[r] = trp[r] + pos[r]
+        for q, k in enumerate(cols):
+            if k >= r:
+                break
+            row[q] /= T[diag[k]]
+            for f in range(diag[k] + 1, trp[k + 1]):
+                row[pos[int(tci[f])]] -= row[q] * T[f]
+        T[trp[r]:trp[r + 1]] = row
+    return T
+
+
+def test_symbolic_pattern_is_closed(ora):
+    """The pattern from pf_lu_symbolic holds SuperLU's factors and every
+    entry that elimination along it reaches: refactorising another Jacobian
+    of the same grid along it with the same orders reproduces P J Q = L U."""
+    net = synth.tiny_grid(3)
+    J, _ = ora.jacobian(net, synth.random_states(net, seed=1))
+    n = J.shape[0]
+    trp, tci, tv, P, Q = host_lu(J.indptr, J.indices, J.data, n)
+    import scipy.sparse.linalg as spla
+    lu = spla.splu(J.tocsc(), permc_spec="COLAMD")
+    assert trp[-1] >= lu.L.nnz + lu.U.nnz - n
+    # the values placed in the pattern still factor J
+    T = sp.csr_matrix((tv, tci, trp), shape=(n, n))
+    L = sp.tril(T, -1) + sp.identity(n)
+    U = sp.triu(T)
+    assert abs(J[P][:, Q] - L @ U).max() <= 1e-12 * abs(J).max()
+    J2, _ = ora.jacobian(net, synth.random_states(net, seed=2))
+    A2 = J2.toarray()[P][:, Q]
+    T2 = sp.csr_matrix((_eliminate(A2, trp, tci), tci, trp), shape=(n, n))
+    L2 = sp.tril(T2, -1) + sp.identity(n)
+    U2 = sp.triu(T2)
+    assert np.abs(A2 - (L2 @ U2).toarray()).max() <= 1e-12 * np.abs(A2).max()
+
+
+def test_symbolic_argument_checks():
+    L = capi.lib()
+    rp = np.array([0, 1, 2], np.int32)
+    ci = np.array([0, 1], np.int32)
+    p = np.array([0, 0], np.int32)
+    q = np.array([0, 1], np.int32)
+    nz = ctypes.c_int64(0)
+    rc = L.pf_lu_symbolic(2, rp.ctypes.data_as(capi._pi32), ci.ctypes.data_as(capi._pi32),
+                          p.ctypes.data_as(capi._pi32), q.ctypes.data_as(capi._pi32),
+                          ctypes.byref(nz), None, None)
+    assert rc == capi.PF_EINVAL and "permutation" in L.pf_last_error().decode()
+    p[1] = 1
+    rc = L.pf_lu_symbolic(2, rp.ctypes.data_as(capi._pi32), ci.ctypes.data_as(capi._pi32),
+                          p.ctypes.data_as(capi._pi32), q.ctypes.data_as(capi._pi32),
+                          ctypes.byref(nz), None, None)
+    assert rc == capi.PF_OK and nz.value == 2
+
+
+def test_batch_lu_create_checks(ora):
+    net = synth.tiny_grid(6)
+    single = Plan(net, host_only=True)
+    batch = Plan(net, host_only=True, batch=dict(n_inst=5))
+    M = _csr(ora, net, 2)
+    trp, tci, _, pivP, pivQ = host_lu(M.indptr, M.indices, M.data, single.n)
+    L = capi.lib()
+
+    def create(plan, P=pivP):
+        h = capi._vp()
+        rc = L.pf_batch_lu_create(plan._h, int(trp[-1]), trp.ctypes.data_as(capi._pi32),
+                                  tci.ctypes.data_as(capi._pi32), P.ctypes.data_as(capi._pi32),
+                                  pivQ.ctypes.data_as(capi._pi32), ctypes.byref(h))
+        return rc, L.pf_last_error().decode()
+
+    rc, msg = create(single)
+    assert rc == capi.PF_EINVAL and "batched" in msg
+    bad = pivP.copy()
+    bad[0] = bad[1]
+    rc, msg = create(batch, bad)
+    assert rc == capi.PF_EINVAL and "permutation" in msg
+    rc, msg = create(batch)
+    assert rc == capi.PF_EINVAL and "host-only" in msg
+    assert L.pf_newton_batch(None, None, None, None, None, None, None, None) == capi.PF_EINVAL
+    assert L.pf_batch_lu_factor(None, None, None) == capi.PF_EINVAL
+    L.pf_batch_lu_destroy(None)
+
+
+@pytest.mark.parametrize("which", ["tiny", "everything", "10k"])
+def test_jacobian_row_order_gives_robust_diagonal(ora, which):
+    """Under pf_jacobian_row_order every diagonal entry of the Jacobian is a
+    structural nonzero: constant +-1 on the control rows' new places, a sum
+    over branches elsewhere.  An LU pivoting on that diagonal factors J."""
+    from test_oracle_pins import _net_with_everything
+    net = {"tiny": lambda: synth.tiny_grid(5), "everything": _net_with_everything,
+           "10k": synth.grid_10k}[which]()
+    p = Plan(net, host_only=True)
+    R = p.jacobian_row_order()
+    assert sorted(R) == list(range(p.n))
+    J, _ = ora.jacobian(net, synth.random_states(net, seed=3))
+    d = J.tocsr()[R].diagonal()
+    assert np.all(d != 0)
+    N = net.n_bus
+    moved = R != np.arange(p.n)
+    assert moved.sum() == 2 * (net.n_gen + net.n_slack)
+    assert np.all(np.abs(d[moved]) == 1.0)
+    trp, tci, tv, pivP, pivQ = host_lu(J.indptr, J.indices, J.data, p.n, row_order=R)
+    assert np.array_equal(pivP, R[pivQ])          # pivots on the reordered diagonal
+    T = sp.csr_matrix((tv, tci, trp), shape=(p.n, p.n))
+    L = sp.tril(T, -1) + sp.identity(p.n)
+    U = sp.triu(T)
+    assert abs(J[pivP][:, pivQ] - L @ U).max() <= 1e-12 * abs(J).max()
+    # multi-grid plans: the order stays inside each grid's block
+    nets = [synth.tiny_grid(1, n_bus=30, n_branch=40, n_pv=4), net]
+    m = Plan.multi(nets, host_only=True)
+    Rm = m.jacobian_row_order()
+    off = nets[0].n_var
+    assert np.array_equal(Rm[off:] - off, R) and np.all(Rm[:off] < off)

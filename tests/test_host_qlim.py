@@ -78,3 +78,31 @@ def test_mode_entry_points():
     with pytest.raises(PFError) as ei:          # the check needs a device plan
         p.q_limit_check(None, np.zeros(net.n_pv), np.ones(net.n_pv))
     assert ei.value.code == capi.PF_EINVAL
+
+
+def test_row_order_follows_modes(ora):
+    """Held units keep their control row (its +1 at the unit's own Q_g is
+    then the diagonal); units under voltage control trade rows with their
+    bus's Q row.  Every diagonal entry of the reordered Jacobian is nonzero
+    in both modes."""
+    net = synth.tiny_grid(4)
+    p = Plan(net, host_only=True, q_limits=True)
+    N = net.n_bus
+    mode = np.zeros(net.n_pv, np.int32)
+    mode[[0, 3]] = 1
+    qt = np.zeros(net.n_pv)
+    p.set_gen_modes(mode, qt)
+    R = p.jacobian_row_order()
+    for k in range(net.n_pv):
+        if mode[k]:
+            assert R[2 * N + k] == 2 * N + k and R[N + net.pv_bus[k]] == N + net.pv_bus[k]
+        else:
+            assert R[2 * N + k] == N + net.pv_bus[k] and R[N + net.pv_bus[k]] == 2 * N + k
+    y = synth.random_states(net, seed=2)
+    J, _ = ora.jacobian(net, y, modes=(mode, qt))
+    rp, ci = p.pattern()
+    from parity import oracle_on_pattern
+    v, _, _ = oracle_on_pattern(rp, ci, J, abs(J))
+    import scipy.sparse as sp
+    Jp = sp.csr_matrix((v, ci, rp), shape=(p.n, p.n))
+    assert np.all(Jp[R].diagonal() != 0)
