@@ -21,7 +21,8 @@ instances; c3 = 256 grids of uneven size in one launch; c4 = adjoint (VJP)
 with 64 cotangents on the 70,000-bus grid; newton = Newton power flow on the
 70,000-bus grid with every step on the device; fdlf = fast decoupled power
 flow on a meshed 70,000-bus grid; models = per-model cost (the 70k grid built
-up model by model); copy = HBM calibration.
+up model by model); newton_batch = N-1 contingency analysis (1024 Newton
+solves at once) on the 10,000-bus grid; copy = HBM calibration.
 """
 
 from __future__ import annotations
@@ -286,7 +287,8 @@ def run_c1(args, torch, dev):
         out["others"] = {}
         for name, fn in (("scenarios_10k_x1024", run_c2), ("uneven_256_grids", run_c3),
                          ("adjoint_70k_k64", run_c4), ("newton_device_70k", run_newton),
-                         ("fdlf_70k_meshed", run_fdlf), ("per_model_70k", run_models)):
+                         ("fdlf_70k_meshed", run_fdlf), ("per_model_70k", run_models),
+                         ("newton_batch_10k_n1", run_newton_batch)):
             log(f"[bench] {name}")
             out["others"][name] = fn(args, torch, dev, net70k=net,
                                      plain_us=res.get("plain", {}).get("us_per_eval"))
@@ -599,6 +601,63 @@ def run_models(args, torch, dev, **kw):
             "variants": out}
 
 
+def run_newton_batch(args, torch, dev, **kw):
+    """N-1 contingency analysis on the 10,000-bus grid: 1024 branch outages
+    (non-bridges), each a Newton power flow warm-started at the base-case
+    solution, all solved together (pf_newton_batch: one batched evaluation
+    and one batched factorisation per iteration), against device Newton
+    run instance by instance on a sample."""
+    from paper_2011_11880_amd import synth
+    from paper_2011_11880_amd.api import Plan
+    log("[bench] newton batch: 10k grid, base solution, 1024 outages")
+    net, ystar, _ = manufactured_case(torch, dev, synth.grid_10k(), 4300, sigma=0.0)
+    I = 1024
+    out = synth.contingencies(net, I, seed=2002)
+    p = Plan(net, batch=dict(n_inst=I, outage=out), device=0)
+    X0 = torch.from_numpy(p.to_batch(np.tile(ystar, (I, 1)))).to(dev)
+    t0 = time.perf_counter()
+    lu = p.batch_lu(X0)
+    t_lu = time.perf_counter() - t0
+    X = X0.clone()
+    p.newton_batch(X, lu, tol=1e-10, max_iter=12)     # warm-up
+    reps = []
+    for _ in range(3):
+        X = X0.clone()
+        torch.cuda.synchronize()
+        reps.append(p.newton_batch(X, lu, tol=1e-10, max_iter=12))
+    r = min(reps, key=lambda q: q["t_total_s"])
+    its = r["inst_iterations"]
+    it = r["iterations"]
+    log("[bench] newton batch: instance by instance on a sample")
+    sample = np.linspace(0, I - 1, 16).astype(int)
+    t_one, it_one = [], []
+    for i in sample:
+        v = net.without_branch(int(out[i]))
+        q = Plan(v, device=0)
+        x = torch.from_numpy(ystar).to(dev)
+        luq = q.device_lu(x)
+        q.newton_device(x, luq, tol=1e-10, max_iter=12)
+        x = torch.from_numpy(ystar).to(dev)
+        rq = q.newton_device(x, luq, tol=1e-10, max_iter=12)
+        t_one.append(rq["t_total_s"])
+        it_one.append(rq["iterations"])
+        q.close()
+    per_inst_ms = float(np.mean(t_one)) * 1e3
+    return {"grid": "10,000 buses, 12,500 branches; base case solved, 1024 N-1 outages",
+            "instances": I, "nnz_lu": r["nnz_lu"], "host_lu_s": t_lu,
+            "batched": {"iterations": it, "n_converged": r["n_converged"],
+                        "steps_histogram": np.bincount(its).tolist(),
+                        "total_ms": r["t_total_s"] * 1e3,
+                        "eval_ms_per_iter": r["t_eval_s"] * 1e3 / (it + 1),
+                        "factor_solve_ms_per_iter": r["t_solve_s"] * 1e3 / max(it, 1),
+                        "us_per_instance": r["t_total_s"] * 1e6 / I},
+            "one_by_one_device_newton": {"sample": len(sample),
+                                         "mean_iterations": float(np.mean(it_one)),
+                                         "mean_ms_per_instance": per_inst_ms,
+                                         "extrapolated_total_ms": per_inst_ms * I},
+            "speedup": per_inst_ms * I / (r["t_total_s"] * 1e3)}
+
+
 def run_copy(args, torch, dev):
     """Calibration: a plain device-to-device copy of known size (torch's
     copy kernel), the reference for HBM byte counters; also reports the
@@ -631,7 +690,8 @@ def main():
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--config", default="c1",
-                    choices=["c1", "c2", "c3", "c4", "newton", "fdlf", "models", "copy"])
+                    choices=["c1", "c2", "c3", "c4", "newton", "fdlf", "models", "newton_batch",
+                             "copy"])
     ap.add_argument("--copy-mib", type=int, default=1024)
     ap.add_argument("--states", type=int, default=1000)
     ap.add_argument("--autotune", action="store_true")
@@ -652,7 +712,8 @@ def main():
         sys.exit(1)
     dev = torch.device("cuda", 0)
     out = {"c1": run_c1, "c2": run_c2, "c3": run_c3, "c4": run_c4, "newton": run_newton,
-           "fdlf": run_fdlf, "models": run_models, "copy": run_copy}[args.config](args, torch, dev)
+           "fdlf": run_fdlf, "models": run_models, "newton_batch": run_newton_batch,
+           "copy": run_copy}[args.config](args, torch, dev)
     print(json.dumps(out), flush=True)
 
 
