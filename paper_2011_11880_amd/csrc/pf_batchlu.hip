@@ -65,6 +65,7 @@ struct pf_batch_lu {
 namespace {
 
 constexpr int kNormRowBlocks = 64;  // row blocks of the per-instance norm
+constexpr int kG = 8;               // loads issued together in the inner loops
 
 struct BGuard {
     int prev = -1;
@@ -138,18 +139,39 @@ __global__ void __launch_bounds__(64) k_blu_factor(
     const bool live = lane < W && inst < n_inst;
     const int r0 = trp[r], R = trp[r + 1] - r0;
     if (live) {
-        for (int q = 0; q < R; ++q) {
-            const int s = tsrc[r0 + q];
-            Lrow[q * W + lane] = s >= 0 ? J[size_t(s) * SI + inst] : 0.0;
+        // the row's Jacobian values, kG loads in flight at a time
+        for (int q0 = 0; q0 < R; q0 += kG) {
+            double v[kG];
+#pragma unroll
+            for (int q = 0; q < kG; ++q) {
+                const int s = q0 + q < R ? tsrc[r0 + q0 + q] : -1;
+                v[q] = s >= 0 ? J[size_t(s) * SI + inst] : 0.0;
+            }
+#pragma unroll
+            for (int q = 0; q < kG; ++q)
+                if (q0 + q < R) Lrow[(q0 + q) * W + lane] = v[q];
         }
         const int s0 = step_ptr[r], s1 = step_ptr[r + 1];
         for (int st = s0; st < s1; ++st) {
             const int4 sp = step[st];
             const double lik = Lrow[sp.x * W + lane] / T[size_t(sp.y) * SI + inst];
             Lrow[sp.x * W + lane] = lik;
-            for (int u = sp.z; u < sp.w; ++u) {
-                const int2 p = upd[u];
-                Lrow[p.x * W + lane] = fma(-lik, T[size_t(p.y) * SI + inst], Lrow[p.x * W + lane]);
+            // updates in groups: the group's loads of row k are issued before
+            // its read-modify-writes of the LDS row (one wait per group); the
+            // order of the updates, and so every result, is unchanged
+            for (int u0 = sp.z; u0 < sp.w; u0 += kG) {
+                double t[kG];
+                int px[kG];
+#pragma unroll
+                for (int q = 0; q < kG; ++q) {
+                    const bool in = u0 + q < sp.w;
+                    const int2 p = in ? upd[u0 + q] : make_int2(0, 0);
+                    px[q] = in ? p.x : -1;
+                    t[q] = in ? T[size_t(p.y) * SI + inst] : 0.0;
+                }
+#pragma unroll
+                for (int q = 0; q < kG; ++q)
+                    if (px[q] >= 0) Lrow[px[q] * W + lane] = fma(-lik, t[q], Lrow[px[q] * W + lane]);
             }
         }
         for (int q = 0; q < R; ++q) T[size_t(r0 + q) * SI + inst] = Lrow[q * W + lane];
@@ -160,17 +182,25 @@ __global__ void __launch_bounds__(64) k_blu_factor(
 __global__ void __launch_bounds__(64) k_blu_fwd(
     const int32_t *__restrict__ rows, int n_chunks, int W, int n_inst, int SI,
     const int32_t *__restrict__ trp, const int32_t *__restrict__ tci,
-    const int32_t *__restrict__ pivP, const double *__restrict__ T,
-    const double *__restrict__ F, double *__restrict__ Y) {
+    const int32_t *__restrict__ tdiag, const int32_t *__restrict__ pivP,
+    const double *__restrict__ T, const double *__restrict__ F, double *__restrict__ Y) {
     const int lane = threadIdx.x;
     const int r = rows[blockIdx.x / n_chunks];
     const int inst = (blockIdx.x % n_chunks) * W + lane;
     if (lane >= W || inst >= n_inst) return;
     double s = F[size_t(pivP[r]) * SI + inst];
-    for (int e = trp[r]; e < trp[r + 1]; ++e) {
-        const int c = tci[e];
-        if (c >= r) break;
-        s = fma(-T[size_t(e) * SI + inst], Y[size_t(c) * SI + inst], s);
+    const int e1 = tdiag[r];   // the strictly lower part ends at the diagonal
+    for (int e0 = trp[r]; e0 < e1; e0 += kG) {
+        double t[kG], y[kG];
+#pragma unroll
+        for (int q = 0; q < kG; ++q) {
+            const bool in = e0 + q < e1;
+            t[q] = in ? T[size_t(e0 + q) * SI + inst] : 0.0;
+            y[q] = in ? Y[size_t(tci[e0 + q]) * SI + inst] : 0.0;
+        }
+#pragma unroll
+        for (int q = 0; q < kG; ++q)
+            if (e0 + q < e1) s = fma(-t[q], y[q], s);
     }
     Y[size_t(r) * SI + inst] = s;
 }
@@ -185,8 +215,19 @@ __global__ void __launch_bounds__(64) k_blu_bwd(
     const int inst = (blockIdx.x % n_chunks) * W + lane;
     if (lane >= W || inst >= n_inst) return;
     double s = Y[size_t(r) * SI + inst];
-    for (int e = tdiag[r] + 1; e < trp[r + 1]; ++e)
-        s = fma(-T[size_t(e) * SI + inst], Y[size_t(tci[e]) * SI + inst], s);
+    const int e1 = trp[r + 1];
+    for (int e0 = tdiag[r] + 1; e0 < e1; e0 += kG) {
+        double t[kG], y[kG];
+#pragma unroll
+        for (int q = 0; q < kG; ++q) {
+            const bool in = e0 + q < e1;
+            t[q] = in ? T[size_t(e0 + q) * SI + inst] : 0.0;
+            y[q] = in ? Y[size_t(tci[e0 + q]) * SI + inst] : 0.0;
+        }
+#pragma unroll
+        for (int q = 0; q < kG; ++q)
+            if (e0 + q < e1) s = fma(-t[q], y[q], s);
+    }
     Y[size_t(r) * SI + inst] = s / T[size_t(tdiag[r]) * SI + inst];
 }
 
@@ -362,8 +403,8 @@ int solve_levels(pf_batch_lu *b, const double *Fin, double *Y, hipStream_t st) {
     for (size_t l = 0; l + 1 < b->flev_ptr.size(); ++l) {
         const int nr = b->flev_ptr[l + 1] - b->flev_ptr[l];
         hipLaunchKernelGGL(k_blu_fwd, dim3(unsigned(int64_t(nr) * nc)), dim3(64), 0, st,
-                           b->frows + b->flev_ptr[l], nc, 64, I, SI, b->trp, b->tci, b->pivP,
-                           b->T, Fin, Y);
+                           b->frows + b->flev_ptr[l], nc, 64, I, SI, b->trp, b->tci, b->tdiag,
+                           b->pivP, b->T, Fin, Y);
     }
     for (size_t l = 0; l + 1 < b->blev_ptr.size(); ++l) {
         const int nr = b->blev_ptr[l + 1] - b->blev_ptr[l];
@@ -519,7 +560,8 @@ int pf_newton_batch(pf_plan *plan, pf_batch_lu *b, double *X, const pf_newton_op
             const double v = b->norm_host[i];
             if (act[size_t(i)] && v < tol) act[size_t(i)] = 0;
             if (!act[size_t(i)]) ++n_conv;
-            else if (!(v <= worst)) worst = v;
+            else if (v != v || worst != worst) worst = NAN;
+            else if (v > worst) worst = v;
         }
         if (it < 65) r.norm[it] = worst;
         if (n_conv == I) {

@@ -1247,7 +1247,11 @@ int dev_newton(HostPlan &hp, DevPlan *dp, double *x, const pf_newton_opts *opts,
         double nf = 0.0;
         for (int64_t q = 0; q < n; ++q) {
             const double v = std::fabs(Fh[q]);
-            if (!(v <= nf)) nf = v;  // NaN propagates
+            if (v != v) {  // a NaN anywhere makes the norm NaN
+                nf = v;
+                break;
+            }
+            if (v > nf) nf = v;
         }
         if (it < 65) r.norm[it] = nf;
         if (nf < tol) {

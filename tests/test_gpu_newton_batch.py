@@ -134,5 +134,12 @@ def test_newton_batch_failure_paths(ora, cuda):
     # a random state on this grid does not converge in 2 steps: no error
     rep = q.newton_batch(X, lu_q, max_iter=2)
     assert rep["n_converged"] < I and rep["iterations"] == 2
+    # a NaN in one instance: its norm and the largest norm are NaN
+    Y = synth.random_states(net, I, seed=1)
+    Y[2, 3] = np.nan
+    X = torch.from_numpy(q.to_batch(Y)).to(cuda)
+    rep = q.newton_batch(X, lu_q, max_iter=1)
+    assert np.isnan(rep["inst_norm"][2]) and np.isnan(rep["norms"][0])
+    assert np.all(np.isfinite(np.delete(rep["inst_norm"], 2)))
     q.close()
     assert lu_q._h is None
