@@ -368,13 +368,14 @@ int pf_newton(pf_plan *plan, double *x, const pf_newton_opts *opts,
  *   exceeds V_set + tol while held at q_max, or falls below V_set - tol
  *   while held at q_min.  The new modes are applied as by pf_set_gen_modes;
  *   *n_switched (nullable) receives the number of changes.  Copies x to the
- *   host (synchronous, default stream).  A Newton solve with limits repeats
- *   solve -> check until nothing switches.
+ *   host on the given stream (after the work queued there) and synchronises
+ *   it.  A Newton solve with limits repeats solve -> check until nothing
+ *   switches.
  */
 int pf_set_gen_modes(pf_plan *plan, const int32_t *mode, const double *q_target);
 int pf_get_gen_modes(const pf_plan *plan, int32_t *mode, double *q_target);
 int pf_q_limit_check(pf_plan *plan, const double *x, const double *q_min,
-                     const double *q_max, double tol, int32_t *n_switched);
+                     const double *q_max, double tol, int32_t *n_switched, void *stream);
 
 /*
  * Device-resident Newton (tasks 1-4 of Section I with task 3 on the GPU).
@@ -388,7 +389,11 @@ int pf_q_limit_check(pf_plan *plan, const double *x, const double *q_min,
  *   Jval_host  [nnz]   the values of M in pf_pattern order
  *   T_rowptr   [n+1], T_colidx [nnzT], T_val [nnzT]: CSR of (L - I) + U, the
  *              strictly lower part holding L without its unit diagonal;
- *              columns strictly increasing within a row, diagonal present
+ *              columns strictly increasing within a row, diagonal present,
+ *              and every fill entry of the symbolic factorisation present
+ *              (pf_lu_symbolic; a numeric LU may omit entries whose values
+ *              vanish for M, and the re-factorisation would then be
+ *              incomplete for other matrices -> PF_EINVAL)
  *   pivP, pivQ [n]     row k of P M Q is row pivP[k] of M; column k is column
  *              pivQ[k] of M
  * The plan must be a non-batched device plan; the object keeps a pointer to

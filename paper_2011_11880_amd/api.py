@@ -466,7 +466,8 @@ class Plan:
         check(capi.lib().pf_q_limit_check(self._h, _ptr(x, self.n, "x"),
                                           lo.ctypes.data_as(capi._pd),
                                           hi.ctypes.data_as(capi._pd), float(tol),
-                                          ctypes.byref(ns)))
+                                          ctypes.byref(ns),
+                                          None if x is None else _stream(self._dev(x))))
         return int(ns.value)
 
     def newton_qlim(self, x, q_min, q_max, device=False, tol=1e-10, max_iter=10,

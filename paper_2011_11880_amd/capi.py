@@ -112,7 +112,7 @@ SIGNATURES = {
                                  ctypes.POINTER(pf_newton_report)]),
     "pf_set_gen_modes": (ctypes.c_int, [_P, _pi32, _pd]),
     "pf_get_gen_modes": (ctypes.c_int, [_P, _pi32, _pd]),
-    "pf_q_limit_check": (ctypes.c_int, [_P, _vp, _pd, _pd, ctypes.c_double, _pi32]),
+    "pf_q_limit_check": (ctypes.c_int, [_P, _vp, _pd, _pd, ctypes.c_double, _pi32, _vp]),
     "pf_refact_create": (ctypes.c_int, [_P, _pd, _i64, _pi32, _pi32, _pd, _pi32, _pi32,
                                         ctypes.POINTER(_vp)]),
     "pf_refact_solve": (ctypes.c_int, [_vp, _vp, _vp, _vp]),

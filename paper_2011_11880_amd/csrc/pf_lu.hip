@@ -208,6 +208,35 @@ const char *check_T(int n, int64_t nnz, const int32_t *rp, const int32_t *ci) {
     return nullptr;
 }
 
+int symbolic(int n, const int32_t *rp, const int32_t *ci, const int32_t *pivP,
+             const int32_t *pivQ, std::vector<int32_t> &trp, std::vector<int32_t> &tci);
+
+// T must hold every entry that elimination along it reaches for matrices of
+// M's pattern (the full symbolic pattern); a pattern with missing fill would
+// make the device re-factorisation an incomplete one.
+int check_closure(int n, const int32_t *rp, const int32_t *ci, const int32_t *pivP,
+                  const int32_t *pivQ, const int32_t *T_rowptr, const int32_t *T_colidx) {
+    std::vector<int32_t> srp, sci;
+    int rc;
+    try {
+        rc = symbolic(n, rp, ci, pivP, pivQ, srp, sci);
+    } catch (const std::bad_alloc &) {
+        rc = fail(PF_ENOMEM, "host allocation failed");
+    }
+    if (rc) return rc;
+    for (int r = 0; r < n; ++r) {
+        int32_t t = T_rowptr[r];
+        for (int32_t e = srp[size_t(r)]; e < srp[size_t(r) + 1]; ++e) {
+            while (t < T_rowptr[r + 1] && T_colidx[t] < sci[size_t(e)]) ++t;
+            if (t == T_rowptr[r + 1] || T_colidx[t] != sci[size_t(e)])
+                return fail(PF_EINVAL,
+                            "T lacks fill entry (%d, %d) of the symbolic factorisation "
+                            "(pf_lu_symbolic gives the full pattern)", r, sci[size_t(e)]);
+        }
+    }
+    return PF_OK;
+}
+
 int solve_on_stream(pf_refact *rf, const double *Jval, double *b, hipStream_t st) {
     const RfApi &api = rf_api();
     LU_RS(api.set_stream(rf->handle, st));
@@ -303,6 +332,9 @@ int pf_refact_create(pf_plan *plan, const double *Jval_host, int64_t nnzT,
     if (const char *why = check_T(int(n), nnzT, T_rowptr, T_colidx)) return fail(PF_EINVAL, "%s", why);
     if (!is_permutation(pivP, int(n)) || !is_permutation(pivQ, int(n)))
         return fail(PF_EINVAL, "pivP and pivQ must be permutations of 0..n-1");
+    if (int e = check_closure(int(n), hp.rowptr.data(), hp.colidx.data(), pivP, pivQ, T_rowptr,
+                              T_colidx))
+        return e;
     if (hp.host_only || !plan->dev) return fail(PF_EINVAL, "plan is host-only");
     pf_refact *rf = new (std::nothrow) pf_refact();
     if (!rf) return fail(PF_ENOMEM, "host allocation failed");
@@ -787,6 +819,7 @@ int pf_lu_create(int32_t device, int64_t n, int64_t nnz, const int32_t *rowptr,
     if (const char *why = check_T(int(n), nnzT, T_rowptr, T_colidx)) return fail(PF_EINVAL, "%s", why);
     if (!is_permutation(pivP, int(n)) || !is_permutation(pivQ, int(n)))
         return fail(PF_EINVAL, "pivP and pivQ must be permutations of 0..n-1");
+    if (int e = check_closure(int(n), rowptr, colidx, pivP, pivQ, T_rowptr, T_colidx)) return e;
     int dev = device;
     if (dev < 0 && hipGetDevice(&dev) != hipSuccess) return fail(PF_EDEVICE, "no current device");
     pf_lu *lu = new (std::nothrow) pf_lu();

@@ -74,7 +74,7 @@ int pf_get_gen_modes(const pf_plan *plan, int32_t *mode, double *q_target) {
 }
 
 int pf_q_limit_check(pf_plan *plan, const double *x, const double *q_min, const double *q_max,
-                     double tol, int32_t *n_switched) {
+                     double tol, int32_t *n_switched, void *stream) {
     clear_error();
     int rc = need_slots(plan);
     if (rc) return rc;
@@ -91,7 +91,9 @@ int pf_q_limit_check(pf_plan *plan, const double *x, const double *q_min, const 
     if (hipGetDevice(&prev) != hipSuccess) return fail(PF_EDEVICE, "hipGetDevice failed");
     if (prev != hp.device && hipSetDevice(hp.device) != hipSuccess)
         return fail(PF_EDEVICE, "cannot select device %d", hp.device);
-    hipError_t e = hipMemcpy(xh.data(), x, xh.size() * sizeof(double), hipMemcpyDeviceToHost);
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    hipError_t e = hipMemcpyAsync(xh.data(), x, xh.size() * sizeof(double), hipMemcpyDeviceToHost, st);
+    if (e == hipSuccess) e = hipStreamSynchronize(st);
     if (prev != hp.device) (void)hipSetDevice(prev);
     if (e != hipSuccess) return fail(PF_EDEVICE, "copy of x failed: %s", hipGetErrorString(e));
     int32_t switched = 0;

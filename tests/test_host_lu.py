@@ -239,3 +239,31 @@ def test_jacobian_row_order_gives_robust_diagonal(ora, which):
     Rm = m.jacobian_row_order()
     off = nets[0].n_var
     assert np.array_equal(Rm[off:] - off, R) and np.all(Rm[:off] < off)
+
+
+def test_refact_rejects_pattern_without_fill(ora):
+    """A numeric LU's pattern can miss fill entries; pf_refact_create
+    rejects such a T instead of refactorising incompletely."""
+    import scipy.sparse.linalg as spla
+    net = synth.tiny_grid(3)
+    plan = Plan(net, host_only=True)
+    M = _csr(ora, net, 1)
+    n = plan.n
+    trp, tci, tv, pivP, pivQ = host_lu(M.indptr, M.indices, M.data, n,
+                                       row_order=plan.jacobian_row_order())
+    # drop one fill entry (a T entry that is not in P M Q)
+    A = M[pivP][:, pivQ].tocsr()
+    A.sort_indices()
+    for r in range(n):
+        cols = set(A.indices[A.indptr[r]:A.indptr[r + 1]])
+        fill = [e for e in range(trp[r], trp[r + 1]) if tci[e] not in cols]
+        if fill:
+            e = fill[0]
+            break
+    tci2, tv2 = np.delete(tci, e), np.delete(tv, e)
+    trp2 = trp.copy()
+    trp2[r + 1:] -= 1
+    rc, msg, _ = _create(plan, M.data, trp2, tci2, tv2, pivP, pivQ)
+    assert rc == capi.PF_EINVAL and "fill" in msg
+    rc, msg, _ = _create(plan, M.data, trp, tci, tv, pivP, pivQ)
+    assert rc == capi.PF_EINVAL and "host-only" in msg
