@@ -493,14 +493,16 @@ int normalise_schedule(const HostPlan &hp, const pf_schedule *in, pf_schedule &s
     pf_schedule d{};
     if (in) d = *in;
     // defaults: the fastest schedules measured on MI355X for the 70,000-bus
-    // grid (single instance) and its 1000-state batch
+    // grid (single instance) and its 1000-state batch (batched: groups of 8
+    // instance chunks, 4 buses per work item in breadth-first order, 8 waves
+    // per block, contiguous work per XCD)
     const bool batch = hp.kind == KIND_BATCH;
     if (d.tile_entries == 0) d.tile_entries = 64;
-    if (d.batch_buses == 0) d.batch_buses = 1;
-    if (d.batch_order == 0) d.batch_order = 1;
-    if (d.xcd_remap == 0) d.xcd_remap = batch ? 2 : 1;
-    if (d.batch_group == 0) d.batch_group = 64;
-    if (d.waves_per_block == 0) d.waves_per_block = batch ? 4 : 2;
+    if (d.batch_buses == 0) d.batch_buses = batch ? 4 : 1;
+    if (d.batch_order == 0) d.batch_order = batch ? 2 : 1;
+    if (d.xcd_remap == 0) d.xcd_remap = 1;
+    if (d.batch_group == 0) d.batch_group = batch ? 8 : 64;
+    if (d.waves_per_block == 0) d.waves_per_block = batch ? 8 : 2;
     if (d.grid_blocks == 0) d.grid_blocks = -1;
     if (d.tile_entries < 64 || d.tile_entries % 64 || d.tile_entries > (1 << 20))
         return fail(PF_EINVAL, "tile_entries must be a multiple of 64 in [64, 2^20]");
