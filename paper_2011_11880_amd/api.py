@@ -63,21 +63,27 @@ def params_vector(nets):
                 for k in ("br_r", "br_x", "br_b", "br_tap", "br_shift_deg", "load_p", "load_q")])
 
 
-def host_lu(rowptr, colidx, values, n, permc_spec="COLAMD", row_order=None):
-    """One sparse LU of the CSR matrix M on the host (SuperLU; COLAMD
-    ordering: SuperLU's minimum-degree orderings take minutes on well-meshed
-    grids), in the form the device re-factorisations take:
-    (T_rowptr, T_colidx, T_val, pivP, pivQ) with T = (L - I) + U in CSR
-    (sorted columns, the full symbolic pattern) and M[pivP][:, pivQ] = L U.
-    With ``row_order`` (a Jacobian's pf_jacobian_row_order) the rows are
-    reordered first and pivots are taken on the diagonal, so that they stay
-    usable for every matrix of the same pattern; otherwise partial pivoting."""
+def host_lu(rowptr, colidx, values, n, permc_spec=None, row_order=None):
+    """One sparse LU of the CSR matrix M on the host (SuperLU), in the form
+    the device re-factorisations take: (T_rowptr, T_colidx, T_val, pivP,
+    pivQ) with T = (L - I) + U in CSR (sorted columns, the full symbolic
+    pattern) and M[pivP][:, pivQ] = L U.  With ``row_order`` (a Jacobian's
+    pf_jacobian_row_order) the rows are reordered first and pivots are taken
+    on the diagonal, so that they stay usable for every matrix of the same
+    pattern; otherwise partial pivoting.  ``permc_spec`` None picks the
+    ordering: minimum degree on A + A^T with diagonal pivots (a third of
+    COLAMD's elimination levels on power-flow Jacobians), unless the matrix
+    has more than 9 nonzeros per row (well-meshed grids, where SuperLU's
+    minimum degree takes minutes), and COLAMD otherwise."""
     import scipy.sparse as sp
     import scipy.sparse.linalg as spla
     rowptr, colidx = _i32(rowptr), _i32(colidx)
     M = sp.csr_matrix((_f64(values), colidx, rowptr), shape=(n, n))
     R = np.arange(n) if row_order is None else np.asarray(row_order, dtype=np.int64)
     thresh = 1.0 if row_order is None else 0.0
+    if permc_spec is None:
+        dense = M.nnz > 9 * n
+        permc_spec = "MMD_AT_PLUS_A" if (row_order is not None and not dense) else "COLAMD"
     lu = spla.splu(M[R].tocsc(), permc_spec=permc_spec, diag_pivot_thresh=thresh)
     # SuperLU: Pr A Pc = L U with (Pr A)[perm_r[i]] = A[i], (A Pc)[:, perm_c[j]] = A[:, j],
     # here A = M[R]
@@ -549,7 +555,7 @@ class Plan:
                 "t_total_s": rep.t_total_s, "t_setup_s": t_setup}
 
     # batched Newton ---------------------------------------------------------
-    def batch_lu(self, X, inst=0, permc_spec="COLAMD"):
+    def batch_lu(self, X, inst=0, permc_spec=None):
         """A BatchLU for this batched plan: pattern and pivots from one host LU
         of instance ``inst``'s Jacobian at the batched state X."""
         return BatchLU(self, X, inst=inst, permc_spec=permc_spec)
@@ -587,7 +593,7 @@ class Plan:
         check(capi.lib().pf_jacobian_row_order(self._h, order.ctypes.data_as(capi._pi32)))
         return order
 
-    def device_lu(self, x, permc_spec="COLAMD"):
+    def device_lu(self, x, permc_spec=None):
         """A DeviceLU for this plan, its pattern and pivots taken from one host
         LU of the Jacobian at ``x`` (device [n])."""
         return DeviceLU(self, x, permc_spec=permc_spec)
@@ -622,7 +628,7 @@ class DeviceLU:
     pattern and pivots from one host LU of the plan's Jacobian at ``x``,
     every later factorisation and solve on the GPU (rocSOLVER csrrf)."""
 
-    def __init__(self, plan, x, permc_spec="COLAMD"):
+    def __init__(self, plan, x, permc_spec=None):
         import weakref
         self.plan = plan
         self._h = None
@@ -666,7 +672,7 @@ class DeviceSparseLU:
     """Constant device factorisation of a host CSR matrix (pf_lu_*): one host
     LU (SuperLU) fixes the factors, solves run on the GPU."""
 
-    def __init__(self, M, device=-1, permc_spec="COLAMD"):
+    def __init__(self, M, device=-1, permc_spec=None):
         M = M.tocsr()
         M.sort_indices()
         n = M.shape[0]
@@ -705,7 +711,7 @@ class BatchLU:
     plan along the pattern and pivots of one host LU of one instance's
     Jacobian."""
 
-    def __init__(self, plan, X, inst=0, permc_spec="COLAMD"):
+    def __init__(self, plan, X, inst=0, permc_spec=None):
         import weakref
         if plan.panels:
             raise ValueError("the batched factorisation needs the row layout")
