@@ -64,7 +64,7 @@ struct pf_batch_lu {
 
 namespace {
 
-constexpr int kNormRowBlocks = 64;  // row blocks of the per-instance norm
+constexpr int kNormRowBlocks = 512;  // row blocks of the per-instance norm
 constexpr int kG = 8;               // loads issued together in the inner loops
 
 struct BGuard {
@@ -266,14 +266,28 @@ __global__ void __launch_bounds__(256) k_blu_norm_part(int n, int n_inst, int SI
     part[size_t(blockIdx.y) * SI + inst] = m;
 }
 
+// fold the row blocks' maxima: 64 instances per block, 4 slices of the row
+// blocks per instance (loads issued kG at a time), combined in LDS
 __global__ void __launch_bounds__(256) k_blu_norm_fold(int nb, int n_inst, int SI,
                                                        const double *__restrict__ part,
                                                        double *__restrict__ norm) {
-    const int inst = blockIdx.x * 256 + threadIdx.x;
-    if (inst >= n_inst) return;
+    __shared__ double red[4][64];
+    const int lane = threadIdx.x & 63, sl = threadIdx.x >> 6;
+    const int inst = blockIdx.x * 64 + lane;
     double m = 0.0;
-    for (int b = 0; b < nb; ++b) m = bmax(m, part[size_t(b) * SI + inst]);
-    norm[inst] = m;
+    if (inst < n_inst) {
+        for (int b0 = sl * kG; b0 < nb; b0 += 4 * kG) {
+            double v[kG];
+#pragma unroll
+            for (int q = 0; q < kG; ++q) v[q] = b0 + q < nb ? part[size_t(b0 + q) * SI + inst] : 0.0;
+#pragma unroll
+            for (int q = 0; q < kG; ++q) m = bmax(m, v[q]);
+        }
+    }
+    red[sl][lane] = m;
+    __syncthreads();
+    if (sl == 0 && inst < n_inst)
+        norm[inst] = bmax(bmax(red[0][lane], red[1][lane]), bmax(red[2][lane], red[3][lane]));
 }
 
 // ---------------------------------------------------------------------------
@@ -543,7 +557,7 @@ int pf_newton_batch(pf_plan *plan, pf_batch_lu *b, double *X, const pf_newton_op
         (void)hipEventRecord(ev[1], st);
         hipLaunchKernelGGL(k_blu_norm_part, dim3(unsigned((I + 255) / 256), kNormRowBlocks),
                            dim3(256), 0, st, n, I, SI, b->part_rows, b->F, b->part);
-        hipLaunchKernelGGL(k_blu_norm_fold, dim3(unsigned((I + 255) / 256)), dim3(256), 0, st,
+        hipLaunchKernelGGL(k_blu_norm_fold, dim3(unsigned((I + 63) / 64)), dim3(256), 0, st,
                            kNormRowBlocks, I, SI, b->part, b->norm);
         if (hipGetLastError() != hipSuccess ||
             hipMemcpyAsync(b->norm_host, b->norm, size_t(I) * sizeof(double),
