@@ -313,7 +313,7 @@ void ora_vjp_params(const ora_topo *tp, const ora_data *dd, const double *y,
 /*
  * Tolerance scale for ora_vjp_params: the same chain of products with every
  * factor replaced by its absolute value, i.e. the sum of |terms| that the
- * gradient of each parameter adds up.  Used only to judge rounding
+ * gradient of each parameter adds up.  Used only to bound rounding
  * differences under cancellation; it is not part of the reference values.
  */
 void ora_vjp_params_scale(const ora_topo *tp, const ora_data *dd, const double *y,

@@ -150,8 +150,8 @@ def lib():
     if _lib is None:
         if not os.path.exists(LIB_PATH):
             raise RuntimeError(
-                "libpf.so is missing: build it with `python -m paper_2011_11880_amd.build` "
-                "(or __graft_entry__.build()); there is no fallback path")
+                "libpf.so is missing: build it with `python -m paper_2011_11880_amd.build`; "
+                "there is no fallback path")
         L = ctypes.CDLL(LIB_PATH)
         for name, (res, args) in SIGNATURES.items():
             fn = getattr(L, name)
