@@ -256,6 +256,32 @@ def run_c1(args, torch, dev):
         res["plain_4_streams"]["hbm_frac"] = res["plain_4_streams"]["gbs"] / HBM_PEAK_GBS
         log("[bench] plain 4 streams", json.dumps(res["plain_4_streams"]))
         del gc
+        # per-launch floors for context, replayed the same way: an empty
+        # launch (64 B fill) and a device copy moving the bytes of one
+        # evaluation (half read, half written)
+        half = int(bytes_p // 16)
+        src = torch.randn((S, half), dtype=torch.float64, device=dev)
+        dst = torch.empty_like(src)
+        tiny = torch.empty((S, 8), dtype=torch.float64, device=dev)
+        for name, fn in (("empty_launch_us", lambda s: tiny[s].fill_(1.0)),
+                         ("copy_same_bytes_us", lambda s: dst[s].copy_(src[s]))):
+            for s in range(S):
+                fn(s)
+            torch.cuda.synchronize()
+            gf = torch.cuda.CUDAGraph()
+            with torch.cuda.stream(st):
+                with torch.cuda.graph(gf, stream=st):
+                    for s in range(S):
+                        fn(s)
+            torch.cuda.synchronize()
+            gf.replay()
+            with Timer(torch) as tf:
+                for _ in range(args.steps):
+                    gf.replay()
+            res["plain"][name] = tf.ms * 1e3 / (args.steps * S)
+            del gf
+        log("[bench] plain floors", res["plain"]["empty_launch_us"], res["plain"]["copy_same_bytes_us"])
+        del src, dst, tiny
         del g, Fs, Js, Xs
 
     head = res["batched"]

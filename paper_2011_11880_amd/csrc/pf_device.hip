@@ -74,6 +74,9 @@ struct DevPlan {
     int2 *out_ft = nullptr;   // per instance: buses of its outaged branch, or -1
     double *otab = nullptr;
     int32_t *order_nat = nullptr, *order_bfs = nullptr;
+    // adjoint work lists (single-instance and multi-grid plans)
+    int4 *adj_tiles = nullptr;
+    int32_t *adj_src = nullptr, *adj_br = nullptr, *adj_ld = nullptr;
     // Newton scratch (allocated at setup for single-instance plans)
     double *nw_F = nullptr, *nw_J = nullptr, *nw_dx = nullptr;
 };
@@ -651,6 +654,8 @@ __global__ void __launch_bounds__(256) k_newton_update(int64_t n, double *__rest
 // Entries (or branches) per adjoint work tile and cotangent group of the
 // second phase (gathers of a group are issued together).
 constexpr int kVjpGroup = 8;
+// Branches (or loads) per wavefront of the parameter adjoint.
+constexpr int kVjpTile = 16;
 
 // State part of the adjoint, gx = J(x)^T W, one wavefront per (tile of whole
 // admittance rows, 64-cotangent chunk).  Column a of J collects, for every
@@ -659,9 +664,13 @@ constexpr int kVjpGroup = 8;
 // transpose-partner entry (c, a).  Phase 1 (lane = entry) evaluates these
 // eight state-only coefficients once per entry into LDS; phase 2 (lane =
 // cotangent) walks the entries in row order, folding them against the W rows
-// of P_a, Q_a, P_c, Q_c, and writes column a when its row ends.
+// of P_a, Q_a, P_c, Q_c, and writes column a when its row ends.  Rows are
+// taken in breadth-first order (tiles over `src`, the entry indices in that
+// order) and each XCD runs a contiguous range of tiles, so the partner rows
+// of W that neighbouring buses share are read once per XCD.
 __global__ void __launch_bounds__(256)
 k_vjp_state(const int4 *__restrict__ tiles, int ntiles, int n_kchunks,
+            const int32_t *__restrict__ order, const int32_t *__restrict__ src,
             const GridDev *__restrict__ grids, const int2 *__restrict__ bus2,
             const int32_t *__restrict__ ycol, const int32_t *__restrict__ ytr,
             const double *__restrict__ yG, const double *__restrict__ yB,
@@ -669,9 +678,10 @@ k_vjp_state(const int4 *__restrict__ tiles, int ntiles, int n_kchunks,
             const double *__restrict__ W, int K, double *__restrict__ gx) {
     __shared__ double sc[4][8][64];
     __shared__ int sp[4][64];
+    __shared__ int sb[4][64];
     const int lane = threadIdx.x & 63;
     const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
-    const int wid = blockIdx.x * 4 + wv;
+    const int wid = xcd_logical_block(blockIdx.x, gridDim.x) * 4 + wv;
     if (wid >= ntiles * n_kchunks) return;
     const int t = wid / n_kchunks;
     const int kc = wid - t * n_kchunks;
@@ -681,8 +691,9 @@ k_vjp_state(const int4 *__restrict__ tiles, int ntiles, int n_kchunks,
     const size_t SK = size_t(K);
     double(*C)[64] = sc[wv];
     int *PC = sp[wv];
-    const int4 td = tiles[2 * t];
-    const int e0 = td.x, e1 = td.y, b0 = td.z;
+    int *PB = sb[wv];
+    const int4 td = tiles[t];
+    const int e0 = td.x, e1 = td.y, p0 = td.z;
     const GridDev gd = grids[td.w];
     const double *xt = x + gd.xoff;
     const double *xv = xt + gd.N;
@@ -719,13 +730,14 @@ k_vjp_state(const int4 *__restrict__ tiles, int ntiles, int n_kchunks,
         uint64_t smask;
         {
             const bool valid = lane < nvalid;
-            const int e = c0 + lane;
+            const int e = valid ? src[c0 + lane] : 0;
             const int raw = valid ? ycol[e] : 0;
             const bool start = raw < 0;
             const int ic = raw & kColMask;
             smask = __ballot(start);
             const int r = rows_seen + __popcll(smask & le) - 1;
-            const int ia = b0 + r - gd.bus_off;
+            const int b = valid ? order[p0 + r] : 0;   // bus of the entry's row
+            const int ia = b - gd.bus_off;
             double cf[8] = {0, 0, 0, 0, 0, 0, 0, 0};
             int partner = -1;
             if (valid) {
@@ -759,6 +771,7 @@ k_vjp_state(const int4 *__restrict__ tiles, int ntiles, int n_kchunks,
 #pragma unroll
             for (int q = 0; q < 8; ++q) C[q][lane] = cf[q];
             PC[lane] = partner;
+            PB[lane] = b;
         }
         wave_sync();
         // ---- phase 2: one cotangent per lane, entries in order; the W rows
@@ -785,7 +798,7 @@ k_vjp_state(const int4 *__restrict__ tiles, int ntiles, int n_kchunks,
                 if (q >= nvalid) break;
                 if ((smask >> q) & 1ull) {   // a row starts here
                     if (row_bus >= 0) flush(row_bus);
-                    row_bus = b0 + rows_seen;
+                    row_bus = PB[q];
                     ++rows_seen;
                     const int ia = row_bus - gd.bus_off;
                     wPa = W[size_t(gd.xoff + ia) * SK + kk];
@@ -813,18 +826,23 @@ k_vjp_state(const int4 *__restrict__ tiles, int ntiles, int n_kchunks,
 //   gradient row is the four partials dotted with the W rows of the branch's
 //   bus equations.  Out-of-service branches get zero rows.  Load rows are
 //   copies of the W rows of their bus (dF_p/dP_load = dF_q/dQ_load = 1).
+//   Branches and loads are taken in the breadth-first order of their bus
+//   (`bsort`, `lsort`) with a contiguous range per XCD, so each XCD reads the
+//   W rows of one region of the grid.
 __global__ void __launch_bounds__(256)
 k_vjp_params(int B, int NL, int n_btiles, int n_ltiles, int n_kchunks,
+             const int32_t *__restrict__ bsort, const int32_t *__restrict__ lsort,
              const int32_t *__restrict__ br_f, const int32_t *__restrict__ br_t,
              const int32_t *__restrict__ br_on, const int2 *__restrict__ busx,
              const int32_t *__restrict__ load_bus, const double *__restrict__ P,
              const double *__restrict__ x, const double *__restrict__ W, int K,
              double *__restrict__ gp) {
-    __shared__ double sd[4][20][64];
-    __shared__ int4 sr[4][64];
+    __shared__ double sd[4][20][kVjpTile];
+    __shared__ int4 sr[4][kVjpTile];
+    __shared__ int se[4][kVjpTile];
     const int lane = threadIdx.x & 63;
     const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
-    const int wid = blockIdx.x * 4 + wv;
+    const int wid = xcd_logical_block(blockIdx.x, gridDim.x) * 4 + wv;
     if (wid >= (n_btiles + n_ltiles) * n_kchunks) return;
     const int t = wid / n_kchunks;
     const int kc = wid - t * n_kchunks;
@@ -834,21 +852,24 @@ k_vjp_params(int B, int NL, int n_btiles, int n_ltiles, int n_kchunks,
     const size_t SK = size_t(K);
     const int64_t B64 = B;
     if (t >= n_btiles) {   // loads
-        const int l0 = (t - n_btiles) * 64;
-        const int nl = min(64, NL - l0);
+        const int l0 = (t - n_btiles) * kVjpTile;
+        const int nl = min(kVjpTile, NL - l0);
         for (int q0 = 0; q0 < nl; q0 += kVjpGroup) {
             double wp[kVjpGroup], wq[kVjpGroup];
+            int ls[kVjpGroup];
 #pragma unroll
             for (int u = 0; u < kVjpGroup; ++u) {
+                ls[u] = 0;
                 if (q0 + u < nl) {
-                    const int2 bx = busx[load_bus[l0 + q0 + u]];
+                    ls[u] = lsort[l0 + q0 + u];
+                    const int2 bx = busx[load_bus[ls[u]]];
                     wp[u] = W[size_t(bx.x) * SK + kk];
                     wq[u] = W[size_t(bx.y) * SK + kk];
                 }
             }
 #pragma unroll
             for (int u = 0; u < kVjpGroup; ++u) {
-                const int l = l0 + q0 + u;
+                const int l = ls[u];
                 if (q0 + u < nl && kvalid) {
                     st(&gp[size_t(5 * B64 + l) * SK + k], wp[u]);
                     st(&gp[size_t(5 * B64 + NL + l) * SK + k], wq[u]);
@@ -857,12 +878,13 @@ k_vjp_params(int B, int NL, int n_btiles, int n_ltiles, int n_kchunks,
         }
         return;
     }
-    double(*D)[64] = sd[wv];
+    double(*D)[kVjpTile] = sd[wv];
     int4 *R = sr[wv];
-    const int e0 = t * 64;
-    const int nb = min(64, B - e0);
+    int *RE = se[wv];
+    const int e0 = t * kVjpTile;
+    const int nb = min(kVjpTile, B - e0);
     {   // phase 1
-        const int e = e0 + lane;
+        const int e = lane < nb ? bsort[e0 + lane] : 0;
         double d[20];
 #pragma unroll
         for (int q = 0; q < 20; ++q) d[q] = 0.0;
@@ -907,9 +929,12 @@ k_vjp_params(int B, int NL, int n_btiles, int n_ltiles, int n_kchunks,
             d[18] = deg * B2;
             d[19] = deg * A2;
         }
+        if (lane < kVjpTile) {
 #pragma unroll
-        for (int q = 0; q < 20; ++q) D[q][lane] = d[q];
-        R[lane] = rows;
+            for (int q = 0; q < 20; ++q) D[q][lane] = d[q];
+            R[lane] = rows;
+            RE[lane] = e;
+        }
     }
     wave_sync();
     for (int q0 = 0; q0 < nb; q0 += kVjpGroup) {   // phase 2
@@ -928,7 +953,7 @@ k_vjp_params(int B, int NL, int n_btiles, int n_ltiles, int n_kchunks,
         for (int u = 0; u < kVjpGroup; ++u) {
             const int q = q0 + u;
             if (q >= nb) break;
-            const int e = e0 + q;
+            const int e = RE[q];
 #pragma unroll
             for (int pr = 0; pr < 5; ++pr) {
                 const double v = D[4 * pr][q] * w[u][0] + D[4 * pr + 1][q] * w[u][1] +
@@ -1086,6 +1111,11 @@ int dev_create(HostPlan &hp, DevPlan **out) {
         if (!rc) rc = dupload(dp, &dp->order_nat, hp.order_natural);
         if (!rc) rc = dupload(dp, &dp->order_bfs, hp.order_bfs);
     } else {
+        if (!rc) rc = dupload(dp, &dp->order_bfs, hp.order_bfs);
+        if (!rc) rc = dupload(dp, &dp->adj_tiles, hp.adj_tiles);
+        if (!rc) rc = dupload(dp, &dp->adj_src, hp.adj_src);
+        if (!rc) rc = dupload(dp, &dp->adj_br, hp.adj_br);
+        if (!rc) rc = dupload(dp, &dp->adj_ld, hp.adj_ld);
         if (!rc) rc = dalloc(dp, &dp->nw_F, size_t(hp.n));
         if (!rc) rc = dalloc(dp, &dp->nw_J, size_t(hp.nnz));
         if (!rc) rc = dalloc(dp, &dp->nw_dx, size_t(hp.n));
@@ -1328,19 +1358,21 @@ int dev_vjp(HostPlan &hp, DevPlan *dp, const double *x, const double *W, int32_t
     if (!g.ok) return fail(PF_EDEVICE, "cannot select device %d", dp->device);
     hipStream_t st = static_cast<hipStream_t>(stream);
     const int n_kchunks = (K + 63) / 64;
-    if (gx && hp.n_tiles() > 0) {
-        const int64_t waves = int64_t(hp.n_tiles()) * n_kchunks;
+    if (gx && hp.n_adj_tiles() > 0) {
+        const int64_t waves = int64_t(hp.n_adj_tiles()) * n_kchunks;
         hipLaunchKernelGGL(k_vjp_state, dim3(unsigned((waves + 3) / 4)), dim3(256), 0, st,
-                           dp->tiles, hp.n_tiles(), n_kchunks, dp->grids, dp->bus2, dp->ycol,
-                           dp->ytr, dp->yG, dp->yB, dp->gen4, x, W, int(K), gx);
+                           dp->adj_tiles, hp.n_adj_tiles(), n_kchunks, dp->order_bfs,
+                           dp->adj_src, dp->grids, dp->bus2, dp->ycol, dp->ytr, dp->yG, dp->yB,
+                           dp->gen4, x, W, int(K), gx);
         HIP_TRY(hipGetLastError());
     }
     if (gp) {
-        const int nbt = (hp.Bt + 63) / 64, nlt = (hp.NLt + 63) / 64;
+        const int nbt = (hp.Bt + kVjpTile - 1) / kVjpTile, nlt = (hp.NLt + kVjpTile - 1) / kVjpTile;
         const int64_t waves = int64_t(nbt + nlt) * n_kchunks;
         if (waves > 0) {
             hipLaunchKernelGGL(k_vjp_params, dim3(unsigned((waves + 3) / 4)), dim3(256), 0, st,
-                               hp.Bt, hp.NLt, nbt, nlt, n_kchunks, dp->br_f, dp->br_t, dp->br_on,
+                               hp.Bt, hp.NLt, nbt, nlt, n_kchunks, dp->adj_br, dp->adj_ld,
+                               dp->br_f, dp->br_t, dp->br_on,
                                dp->busx, dp->load_bus, dp->params, x, W, int(K), gp);
             HIP_TRY(hipGetLastError());
         }

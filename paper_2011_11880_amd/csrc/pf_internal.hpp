@@ -46,6 +46,10 @@ enum PlanKind : int32_t { KIND_SINGLE = 0, KIND_BATCH = 1, KIND_MULTI = 2 };
 // Q_g slot present (written 0), or reactive output held at gen2.x.
 constexpr int32_t kGenVoltage = -1, kGenVoltageSlot = -2, kGenHeld = -3;
 
+// Entries per tile of the adjoint's row walk (a longer row forms a tile of
+// its own); small tiles give more, shorter wavefronts.
+constexpr int32_t kAdjTileEntries = 16;
+
 struct HostPlan {
     int32_t kind = KIND_SINGLE;
     int32_t n_inst = 1;
@@ -110,8 +114,19 @@ struct HostPlan {
     std::vector<int32_t> outage;       // [I] or empty
     std::vector<int32_t> order_natural, order_bfs;   // bus processing orders
 
+    // adjoint work order (single-instance and multi-grid plans): admittance
+    // rows taken in breadth-first order, so that a contiguous range of work,
+    // which one XCD runs, covers neighbouring buses and its L2 serves the
+    // cotangent rows they share
+    std::vector<int32_t> adj_src;      // n_y: entry index, rows in order_bfs order
+    std::vector<int32_t> adj_tiles;    // n * 4: e0, e1 (positions in adj_src),
+                                       //   position of the first row in order_bfs, grid
+    std::vector<int32_t> adj_br;       // Bt: branches by breadth-first position of br_f
+    std::vector<int32_t> adj_ld;       // NLt: loads by breadth-first position of their bus
+
     int64_t n_params() const { return 5LL * Bt + 2LL * NLt; }
     int32_t n_tiles() const { return int32_t(tiles.size() / 8); }
+    int32_t n_adj_tiles() const { return int32_t(adj_tiles.size() / 4); }
 };
 
 // Host setup (pf_setup.cpp)
@@ -119,6 +134,7 @@ int build_host_plan(const pf_network *nets, int32_t n_grids, HostPlan &hp);
 int attach_batch(const pf_batch_spec *spec, HostPlan &hp);
 int normalise_schedule(const HostPlan &hp, const pf_schedule *in, pf_schedule &out);
 void build_tiles(HostPlan &hp);
+void build_adjoint_order(HostPlan &hp);
 
 // Device side (pf_device.hip)
 struct DevPlan;

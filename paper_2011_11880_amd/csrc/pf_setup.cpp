@@ -429,7 +429,52 @@ int build_host_plan(const pf_network *nets, int32_t n_grids, HostPlan &hp) {
             }
         }
     }
+    build_adjoint_order(hp);
     return PF_OK;
+}
+
+// Adjoint work lists.  Each grid's buses fill positions [bus_off, bus_off +
+// N) of order_bfs, so tiles of whole rows taken along that order (at most
+// kAdjTileEntries entries unless one row is longer) never cross grids.
+// Branches and loads follow the breadth-first position of their bus
+// (stable, so ties keep input order).
+void build_adjoint_order(HostPlan &hp) {
+    hp.adj_src.clear();
+    hp.adj_tiles.clear();
+    hp.adj_src.reserve(size_t(hp.n_y));
+    for (int g = 0; g < int(hp.grids.size()); ++g) {
+        const GridInfo &gi = hp.grids[g];
+        int32_t q = gi.bus_off;
+        const int32_t qend = gi.bus_off + gi.N;
+        while (q < qend) {
+            const int32_t q0 = q;
+            const int32_t e0 = int32_t(hp.adj_src.size());
+            int32_t cnt = 0;
+            while (q < qend) {
+                const int32_t b = hp.order_bfs[q];
+                const int32_t len = hp.yptr[b + 1] - hp.yptr[b];
+                if (cnt > 0 && cnt + len > kAdjTileEntries) break;
+                for (int32_t e = hp.yptr[b]; e < hp.yptr[b + 1]; ++e) hp.adj_src.push_back(e);
+                cnt += len;
+                ++q;
+            }
+            hp.adj_tiles.push_back(e0);
+            hp.adj_tiles.push_back(e0 + cnt);
+            hp.adj_tiles.push_back(q0);
+            hp.adj_tiles.push_back(g);
+        }
+    }
+    std::vector<int32_t> pos(size_t(hp.Nt));
+    for (int32_t q = 0; q < hp.Nt; ++q) pos[size_t(hp.order_bfs[q])] = q;
+    hp.adj_br.resize(size_t(hp.Bt));
+    std::iota(hp.adj_br.begin(), hp.adj_br.end(), 0);
+    std::stable_sort(hp.adj_br.begin(), hp.adj_br.end(),
+                     [&](int32_t a, int32_t b) { return pos[hp.br_f[a]] < pos[hp.br_f[b]]; });
+    hp.adj_ld.resize(size_t(hp.NLt));
+    std::iota(hp.adj_ld.begin(), hp.adj_ld.end(), 0);
+    std::stable_sort(hp.adj_ld.begin(), hp.adj_ld.end(), [&](int32_t a, int32_t b) {
+        return pos[hp.load_bus[a]] < pos[hp.load_bus[b]];
+    });
 }
 
 int attach_batch(const pf_batch_spec *spec, HostPlan &hp) {
