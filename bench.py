@@ -132,6 +132,51 @@ def cpu_baseline(net, states, seconds=12.0, max_states=200):
                       f"(triplets summed into CSR), {dt:.1f} s"}
 
 
+def _oracle_share(task):
+    """Worker process: the oracle's residual + Jacobian on a share of
+    independent instances, until the share or the time budget ends.  An
+    instance is (network, state) or, for a batched plan, (load scale row,
+    PV scale row, outaged branch, state) applied to the base network."""
+    base, items, seconds = task
+    from oracle import oracle as O
+    O.build()
+    t0 = time.perf_counter()
+    done = 0
+    for it in items:
+        if base is None:
+            net, y = it
+        else:
+            ls, ps, outage, y = it
+            net = base if outage < 0 else base.without_branch(int(outage))
+            if ls is not None:
+                net = net.copy()
+                net.load_p = base.load_p * ls
+                net.load_q = base.load_q * ls
+                net.pv_p = base.pv_p * ps
+        O.residual(net, y)
+        O.jacobian(net, y)
+        done += 1
+        if time.perf_counter() - t0 > seconds:
+            break
+    return done, time.perf_counter() - t0
+
+
+def cpu_baseline_parallel(base, items, seconds, what):
+    """The CPU oracle over independent instances in one process per host core
+    (at most 16), each timed by its own clock; throughput is the sum of the
+    processes' rates (process start-up excluded)."""
+    import multiprocessing as mp
+    workers = max(1, min(16, len(os.sched_getaffinity(0)), len(items)))
+    shares = [items[w::workers] for w in range(workers)]
+    with mp.get_context("spawn").Pool(workers) as pool:
+        res = pool.map(_oracle_share, [(base, sh, seconds) for sh in shares])
+    done = sum(r[0] for r in res)
+    rate = sum(r[0] / r[1] for r in res if r[1] > 0)
+    return {"value": rate, "unit": "evals/s", "cores": workers, "kind": "oracle",
+            "sample": f"{done} of the {len(items)} {what}, residual + Jacobian, "
+                      f"{workers} processes, at most {seconds:.0f} s each"}
+
+
 def run_c1(args, torch, dev):
     from paper_2011_11880_amd import synth
     from paper_2011_11880_amd.api import Plan
@@ -364,12 +409,18 @@ def run_c2(args, torch, dev, **kw):
             plain64()
     torch.cuda.synchronize()
     ms_p = time_ms(torch, g.replay) / 64
-    return {"grid": "10,000 buses, 12,500 branches", "instances": I,
-            "batched_ms": ms, "batched_evals_per_s": I / (ms * 1e-3),
-            "batched_gbs": nb / (ms * 1e-3) / 1e9,
-            "batched_hbm_frac": nb / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS,
-            "plain_us_per_eval": ms_p * 1e3, "plain_evals_per_s": 1e3 / ms_p,
-            "batched_over_plain": (I / ms) / (1.0 / ms_p), "schedule": bp.schedule}
+    res = {"grid": "10,000 buses, 12,500 branches", "instances": I,
+           "batched_ms": ms, "batched_evals_per_s": I / (ms * 1e-3),
+           "batched_gbs": nb / (ms * 1e-3) / 1e9,
+           "batched_hbm_frac": nb / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS,
+           "plain_us_per_eval": ms_p * 1e3, "plain_evals_per_s": 1e3 / ms_p,
+           "batched_over_plain": (I / ms) / (1.0 / ms_p), "schedule": bp.schedule}
+    if not getattr(args, "no_cpu", False):
+        log("[bench] c2 CPU oracle over instances")
+        items = [(ls[k] if k < 512 else None, ps[k] if k < 512 else None, int(out[k]), Y[k])
+                 for k in range(I)]
+        res["cpu_oracle"] = cpu_baseline_parallel(net, items, 8.0, "instances")
+    return res
 
 
 def run_c3(args, torch, dev, **kw):
@@ -385,9 +436,15 @@ def run_c3(args, torch, dev, **kw):
     best = mp.autotune(x, F, J, reps=5)
     ms = time_ms(torch, lambda: mp.eval(x, F, J))
     nb = per_eval_bytes(mp.n, mp.nnz) + statics_bytes(mp.info)
-    return {"grids": 256, "buses": int(sum(n.n_bus for n in nets)), "n": mp.n, "nnz": mp.nnz,
-            "ms": ms, "grid_evals_per_s": 256 / (ms * 1e-3), "gbs": nb / (ms * 1e-3) / 1e9,
-            "hbm_frac": nb / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS, "autotuned_schedule": best}
+    res = {"grids": 256, "buses": int(sum(n.n_bus for n in nets)), "n": mp.n, "nnz": mp.nnz,
+           "ms": ms, "grid_evals_per_s": 256 / (ms * 1e-3), "gbs": nb / (ms * 1e-3) / 1e9,
+           "hbm_frac": nb / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS, "autotuned_schedule": best}
+    if not getattr(args, "no_cpu", False):
+        log("[bench] c3 CPU oracle over grids")
+        off = np.cumsum([0] + [n.n_var for n in nets])
+        items = [(n, xs[off[g]:off[g + 1]]) for g, n in enumerate(nets)]
+        res["cpu_oracle"] = cpu_baseline_parallel(None, items, 8.0, "grids")
+    return res
 
 
 def run_c4(args, torch, dev, net70k=None, plain_us=None, **kw):
