@@ -76,7 +76,7 @@ struct DevPlan {
     int32_t *order_nat = nullptr, *order_bfs = nullptr;
     // adjoint work lists (single-instance and multi-grid plans)
     int4 *adj_tiles = nullptr;
-    int32_t *adj_src = nullptr, *adj_br = nullptr, *adj_ld = nullptr;
+    int32_t *adj_src = nullptr, *adj_own = nullptr, *adj_left = nullptr;
     // Newton scratch (allocated at setup for single-instance plans)
     double *nw_F = nullptr, *nw_J = nullptr, *nw_dx = nullptr;
 };
@@ -651,34 +651,90 @@ __global__ void __launch_bounds__(256) k_newton_update(int64_t n, double *__rest
 // adjoint (vector-Jacobian products)
 // ---------------------------------------------------------------------------
 
-// Entries (or branches) per adjoint work tile and cotangent group of the
-// second phase (gathers of a group are issued together).
+// Cotangent group of the second phase (gathers of a group are issued
+// together) and branches per wavefront of the separate branch pass.
 constexpr int kVjpGroup = 8;
-// Branches (or loads) per wavefront of the parameter adjoint.
 constexpr int kVjpTile = 16;
+// Entries per first-phase pass of the row walk (the adjoint tile size).
+constexpr int kVjpChunk = kAdjTileEntries;
 
-// State part of the adjoint, gx = J(x)^T W, one wavefront per (tile of whole
-// admittance rows, 64-cotangent chunk).  Column a of J collects, for every
-// entry (a, c) of row a, the entry's share of the diagonal sums of rows P_a
-// and Q_a and the off-diagonal values J[P_c, .a], J[Q_c, .a] of the
-// transpose-partner entry (c, a).  Phase 1 (lane = entry) evaluates these
-// eight state-only coefficients once per entry into LDS; phase 2 (lane =
-// cotangent) walks the entries in row order, folding them against the W rows
-// of P_a, Q_a, P_c, Q_c, and writes column a when its row ends.  Rows are
-// taken in breadth-first order (tiles over `src`, the entry indices in that
-// order) and each XCD runs a contiguous range of tiles, so the partner rows
-// of W that neighbouring buses share are read once per XCD.
+// Partials of a branch's four terminal injections P_f, Q_f, P_t, Q_t with
+// respect to r, x, line charging b, tap and phase shift (per degree), from
+// the pi-model with series g + jb = 1/(r + jx):
+//   dg/dr = db/dx = (x^2 - r^2)/D^2, dg/dx = -2rx/D^2, db/dr = 2rx/D^2
+//   (D = r^2 + x^2), chained through the flows' g and b partials; the charging
+//   enters Q only; the tap partials follow from the 1/t^2 and 1/t factors;
+//   a phase shift acts as -theta_f.  d[4 p + f] = dFlow_f / dParam_p.
+__device__ __forceinline__ void branch_partials(double r, double xx, double bc, double tap,
+                                                double sh, double thf, double vf, double tht,
+                                                double vt, double d[20]) {
+    const double Dd = r * r + xx * xx;
+    const double D2 = Dd * Dd;
+    const double g = r / Dd;
+    const double b = -xx / Dd;
+    const double delta = thf - tht - sh * (M_PI / 180.0);
+    double S, Cc;
+    sincos(delta, &S, &Cc);
+    const double u = vf * vt / tap;
+    const double t2 = tap * tap;
+    const double A1 = u * (g * Cc + b * S), B1 = u * (g * S - b * Cc);
+    const double A2 = u * (g * Cc - b * S), B2 = u * (g * S + b * Cc);
+    const double vf2 = vf * vf, vt2 = vt * vt;
+    // flow partials w.r.t. series g and b: [Pf, Qf, Pt, Qt]
+    const double dg[4] = {vf2 / t2 - u * Cc, -(u * S), vt2 - u * Cc, u * S};
+    const double db[4] = {-(u * S), -(vf2 / t2) + u * Cc, u * S, -vt2 + u * Cc};
+    const double dg_dr = (xx * xx - r * r) / D2, dg_dx = -(2.0 * r * xx) / D2;
+    const double db_dr = (2.0 * r * xx) / D2, db_dx = (xx * xx - r * r) / D2;
+    const double deg = -(M_PI / 180.0);
+#pragma unroll
+    for (int f = 0; f < 4; ++f) {
+        d[f] = dg[f] * dg_dr + db[f] * db_dr;
+        d[4 + f] = dg[f] * dg_dx + db[f] * db_dx;
+    }
+    d[8] = 0.0;
+    d[9] = -(vf2 / (2.0 * t2));
+    d[10] = 0.0;
+    d[11] = -(vt2 / 2.0);
+    d[12] = -(2.0 * vf2 * g) / (t2 * tap) + A1 / tap;
+    d[13] = (2.0 * vf2 * (b + 0.5 * bc)) / (t2 * tap) + B1 / tap;
+    d[14] = A2 / tap;
+    d[15] = -(B2 / tap);
+    d[16] = deg * B1;
+    d[17] = deg * (-A1);
+    d[18] = deg * B2;
+    d[19] = deg * A2;
+}
+
+// The adjoint, gx = J(x)^T W (WGX) and gparam = (dF/dparams)^T W (WGP), one
+// wavefront per (tile of whole admittance rows, 64-cotangent chunk).
+// Column a of J collects, for every entry (a, c) of row a, the entry's share
+// of the diagonal sums of rows P_a and Q_a and the off-diagonal values
+// J[P_c, .a], J[Q_c, .a] of the transpose-partner entry (c, a).  Phase 1
+// (lane = entry) evaluates these eight state-only coefficients once per
+// entry into LDS, and the 20 partials of the branch the entry carries (the
+// branch from a to c); phase 2 (lane = cotangent) walks the entries in row
+// order, folding the coefficients against the W rows of P_a, Q_a, P_c, Q_c,
+// and writes column a when its row ends.  The same four W rows give the
+// carried branch's five gradient rows (its partials dotted with them), and
+// each load's two rows are the W rows of its bus (dF_p/dP_load =
+// dF_q/dQ_load = 1), written when the bus's row opens.  Rows are taken in
+// breadth-first order (tiles over `src`, the entry indices in that order)
+// and each XCD runs a contiguous range of tiles.
+template <bool WGX, bool WGP>
 __global__ void __launch_bounds__(256)
-k_vjp_state(const int4 *__restrict__ tiles, int ntiles, int n_kchunks,
-            const int32_t *__restrict__ order, const int32_t *__restrict__ src,
-            const GridDev *__restrict__ grids, const int2 *__restrict__ bus2,
-            const int32_t *__restrict__ ycol, const int32_t *__restrict__ ytr,
-            const double *__restrict__ yG, const double *__restrict__ yB,
-            const int4 *__restrict__ gen4, const double *__restrict__ x,
-            const double *__restrict__ W, int K, double *__restrict__ gx) {
-    __shared__ double sc[4][8][64];
-    __shared__ int sp[4][64];
-    __shared__ int sb[4][64];
+k_vjp(const int4 *__restrict__ tiles, int ntiles, int n_kchunks, const int32_t *__restrict__ order,
+      const int32_t *__restrict__ src, const int32_t *__restrict__ own,
+      const GridDev *__restrict__ grids, const int2 *__restrict__ bus2,
+      const int32_t *__restrict__ ycol, const int32_t *__restrict__ ytr,
+      const double *__restrict__ yG, const double *__restrict__ yB,
+      const int4 *__restrict__ gen4, const int32_t *__restrict__ ldptr,
+      const int32_t *__restrict__ ldlist, const double *__restrict__ P, int B, int NL,
+      const double *__restrict__ x, const double *__restrict__ W, int K,
+      double *__restrict__ gx, double *__restrict__ gp) {
+    constexpr int CH = kVjpChunk;
+    __shared__ double sc[4][8][CH];
+    __shared__ double sd[4][WGP ? 20 : 1][CH];
+    __shared__ int si[4][6][CH];
     const int lane = threadIdx.x & 63;
     const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     const int wid = xcd_logical_block(blockIdx.x, gridDim.x) * 4 + wv;
@@ -689,9 +745,15 @@ k_vjp_state(const int4 *__restrict__ tiles, int ntiles, int n_kchunks,
     const bool kvalid = k < K;
     const size_t kk = size_t(kvalid ? k : K - 1);
     const size_t SK = size_t(K);
-    double(*C)[64] = sc[wv];
-    int *PC = sp[wv];
-    int *PB = sb[wv];
+    const int64_t B64 = B;
+    double(*C)[CH] = sc[wv];
+    double(*D)[CH] = sd[wv];
+    int *PC = si[wv][0];   // partner column, -1 on the diagonal
+    int *PB = si[wv][1];   // bus of the entry's row
+    int *OB = si[wv][2];   // carried branch or -1
+    int *LF = si[wv][3];   // first load of the row's bus or -1 (row-start entries)
+    int *LS = si[wv][4];   // position of that load in ldlist
+    int *LN = si[wv][5];   // loads at the bus
     const int4 td = tiles[t];
     const int e0 = td.x, e1 = td.y, p0 = td.z;
     const GridDev gd = grids[td.w];
@@ -724,8 +786,8 @@ k_vjp_state(const int4 *__restrict__ tiles, int ntiles, int n_kchunks,
             st(&gx[size_t(gd.xoff + gd.N + ia) * SK + k], gv);
         }
     };
-    for (int c0 = e0; c0 < e1; c0 += 64) {
-        const int nvalid = min(64, e1 - c0);
+    for (int c0 = e0; c0 < e1; c0 += CH) {
+        const int nvalid = min(CH, e1 - c0);
         // ---- phase 1: one entry per lane
         uint64_t smask;
         {
@@ -739,21 +801,24 @@ k_vjp_state(const int4 *__restrict__ tiles, int ntiles, int n_kchunks,
             const int b = valid ? order[p0 + r] : 0;   // bus of the entry's row
             const int ia = b - gd.bus_off;
             double cf[8] = {0, 0, 0, 0, 0, 0, 0, 0};
-            int partner = -1;
+            double d[20];
+#pragma unroll
+            for (int q = 0; q < 20; ++q) d[q] = 0.0;
+            int partner = -1, ob = -1, lf = -1, ls = 0, ln = 0;
             if (valid) {
                 const double tha = xt[ia], va = xv[ia];
-                const double G = yG[e], B = yB[e];
+                const double G = yG[e], Bc = yB[e];
                 if (ic == ia) {
                     cf[2] = 2.0 * va * G;      // dP_a/dV_a (diagonal term)
-                    cf[3] = -(2.0 * va * B);   // dQ_a/dV_a
+                    cf[3] = -(2.0 * va * Bc);  // dQ_a/dV_a
                 } else {
                     const double thc = xt[ic], vc = xv[ic];
                     const int et = ytr[e];
                     const double Gp = yG[et], Bp = yB[et];
                     double s, co;
                     sincos(tha - thc, &s, &co);
-                    const double t1 = fma(G, co, B * s);
-                    const double t2 = fma(G, s, -(B * co));
+                    const double t1 = fma(G, co, Bc * s);
+                    const double t2 = fma(G, s, -(Bc * co));
                     const double t1p = fma(Gp, co, -(Bp * s));
                     const double t2p = -fma(Gp, s, Bp * co);
                     const double vv = va * vc;
@@ -766,12 +831,33 @@ k_vjp_state(const int4 *__restrict__ tiles, int ntiles, int n_kchunks,
                     cf[6] = vc * t1p;     // dP_c/dV_a
                     cf[7] = vc * t2p;     // dQ_c/dV_a
                     partner = ic;
+                    if (WGP) {
+                        ob = own[c0 + lane];
+                        if (ob >= 0)
+                            branch_partials(P[ob], P[B64 + ob], P[2 * B64 + ob], P[3 * B64 + ob],
+                                            P[4 * B64 + ob], tha, va, thc, vc, d);
+                    }
+                }
+                if (WGP && start) {
+                    ls = ldptr[b];
+                    ln = ldptr[b + 1] - ls;
+                    lf = ln > 0 ? ldlist[ls] : -1;
                 }
             }
+            if (lane < CH) {
 #pragma unroll
-            for (int q = 0; q < 8; ++q) C[q][lane] = cf[q];
-            PC[lane] = partner;
-            PB[lane] = b;
+                for (int q = 0; q < 8; ++q) C[q][lane] = cf[q];
+                if constexpr (WGP) {
+#pragma unroll
+                    for (int q = 0; q < 20; ++q) D[q][lane] = d[q];
+                }
+                PC[lane] = partner;
+                PB[lane] = b;
+                OB[lane] = ob;
+                LF[lane] = lf;
+                LS[lane] = ls;
+                LN[lane] = ln;
+            }
         }
         wave_sync();
         // ---- phase 2: one cotangent per lane, entries in order; the W rows
@@ -797,7 +883,7 @@ k_vjp_state(const int4 *__restrict__ tiles, int ntiles, int n_kchunks,
                 const int q = q0 + u;
                 if (q >= nvalid) break;
                 if ((smask >> q) & 1ull) {   // a row starts here
-                    if (row_bus >= 0) flush(row_bus);
+                    if (WGX && row_bus >= 0) flush(row_bus);
                     row_bus = PB[q];
                     ++rows_seen;
                     const int ia = row_bus - gd.bus_off;
@@ -805,45 +891,61 @@ k_vjp_state(const int4 *__restrict__ tiles, int ntiles, int n_kchunks,
                     wQa = W[size_t(gd.xoff + gd.N + ia) * SK + kk];
                     accT = 0.0;
                     accV = 0.0;
+                    if (WGP && kvalid) {
+                        const int lf = LF[q];
+                        if (lf >= 0) {
+                            st(&gp[size_t(5 * B64 + lf) * SK + k], wPa);
+                            st(&gp[size_t(5 * B64 + NL + lf) * SK + k], wQa);
+                            for (int j = LS[q] + 1; j < LS[q] + LN[q]; ++j) {
+                                const int l = ldlist[j];
+                                st(&gp[size_t(5 * B64 + l) * SK + k], wPa);
+                                st(&gp[size_t(5 * B64 + NL + l) * SK + k], wQa);
+                            }
+                        }
+                    }
                 }
-                accT = accT + C[0][q] * wPa + C[1][q] * wQa + C[4][q] * wPc[u] + C[5][q] * wQc[u];
-                accV = accV + C[2][q] * wPa + C[3][q] * wQa + C[6][q] * wPc[u] + C[7][q] * wQc[u];
+                if (WGX) {
+                    accT = accT + C[0][q] * wPa + C[1][q] * wQa + C[4][q] * wPc[u] +
+                           C[5][q] * wQc[u];
+                    accV = accV + C[2][q] * wPa + C[3][q] * wQa + C[6][q] * wPc[u] +
+                           C[7][q] * wQc[u];
+                }
+                if constexpr (WGP) {
+                    const int ob = OB[q];
+                    if (ob >= 0 && kvalid) {
+#pragma unroll
+                        for (int pr = 0; pr < 5; ++pr) {
+                            const double v = D[4 * pr][q] * wPa + D[4 * pr + 1][q] * wQa +
+                                             D[4 * pr + 2][q] * wPc[u] + D[4 * pr + 3][q] * wQc[u];
+                            st(&gp[size_t(pr * B64 + ob) * SK + k], v);
+                        }
+                    }
+                }
             }
         }
         wave_sync();
     }
-    if (row_bus >= 0) flush(row_bus);
+    if (WGX && row_bus >= 0) flush(row_bus);
 }
 
-// Parameter part of the adjoint.  Phase 1 (lane = branch): the partials of
-// the branch's four terminal injections P_f, Q_f, P_t, Q_t with respect to
-// r, x, line charging b, tap and phase shift (per degree), from the pi-model
-// with series g + jb = 1/(r + jx):
-//   dg/dr = db/dx = (x^2 - r^2)/D^2, dg/dx = -2rx/D^2, db/dr = 2rx/D^2
-//   (D = r^2 + x^2), chained through the flows' g and b partials; the charging
-//   enters Q only; the tap partials follow from the 1/t^2 and 1/t factors;
-//   a phase shift acts as -theta_f.  Phase 2 (lane = cotangent): each
-//   gradient row is the four partials dotted with the W rows of the branch's
-//   bus equations.  Out-of-service branches get zero rows.  Load rows are
-//   copies of the W rows of their bus (dF_p/dP_load = dF_q/dQ_load = 1).
-//   Branches and loads are taken in the breadth-first order of their bus
-//   (`bsort`, `lsort`) with a contiguous range per XCD, so each XCD reads the
-//   W rows of one region of the grid.
+// Parameter gradients of the branches no admittance entry carries: a second
+// branch joining the same pair of buses in the same direction, and
+// out-of-service branches (zero rows).  Phase 1 (lane = branch in `list`):
+// the partials; phase 2 (lane = cotangent): each gradient row is the four
+// partials dotted with the W rows of the branch's bus equations.
 __global__ void __launch_bounds__(256)
-k_vjp_params(int B, int NL, int n_btiles, int n_ltiles, int n_kchunks,
-             const int32_t *__restrict__ bsort, const int32_t *__restrict__ lsort,
-             const int32_t *__restrict__ br_f, const int32_t *__restrict__ br_t,
-             const int32_t *__restrict__ br_on, const int2 *__restrict__ busx,
-             const int32_t *__restrict__ load_bus, const double *__restrict__ P,
-             const double *__restrict__ x, const double *__restrict__ W, int K,
-             double *__restrict__ gp) {
+k_vjp_branches(int B, int nlist, int n_tiles, int n_kchunks, const int32_t *__restrict__ list,
+               const int32_t *__restrict__ br_f, const int32_t *__restrict__ br_t,
+               const int32_t *__restrict__ br_on, const int2 *__restrict__ busx,
+               const double *__restrict__ P, const double *__restrict__ x,
+               const double *__restrict__ W, int K, double *__restrict__ gp) {
     __shared__ double sd[4][20][kVjpTile];
     __shared__ int4 sr[4][kVjpTile];
     __shared__ int se[4][kVjpTile];
     const int lane = threadIdx.x & 63;
     const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
-    const int wid = xcd_logical_block(blockIdx.x, gridDim.x) * 4 + wv;
-    if (wid >= (n_btiles + n_ltiles) * n_kchunks) return;
+    const int wid = blockIdx.x * 4 + wv;
+    if (wid >= n_tiles * n_kchunks) return;
     const int t = wid / n_kchunks;
     const int kc = wid - t * n_kchunks;
     const int k = kc * 64 + lane;
@@ -851,40 +953,13 @@ k_vjp_params(int B, int NL, int n_btiles, int n_ltiles, int n_kchunks,
     const size_t kk = size_t(kvalid ? k : K - 1);
     const size_t SK = size_t(K);
     const int64_t B64 = B;
-    if (t >= n_btiles) {   // loads
-        const int l0 = (t - n_btiles) * kVjpTile;
-        const int nl = min(kVjpTile, NL - l0);
-        for (int q0 = 0; q0 < nl; q0 += kVjpGroup) {
-            double wp[kVjpGroup], wq[kVjpGroup];
-            int ls[kVjpGroup];
-#pragma unroll
-            for (int u = 0; u < kVjpGroup; ++u) {
-                ls[u] = 0;
-                if (q0 + u < nl) {
-                    ls[u] = lsort[l0 + q0 + u];
-                    const int2 bx = busx[load_bus[ls[u]]];
-                    wp[u] = W[size_t(bx.x) * SK + kk];
-                    wq[u] = W[size_t(bx.y) * SK + kk];
-                }
-            }
-#pragma unroll
-            for (int u = 0; u < kVjpGroup; ++u) {
-                const int l = ls[u];
-                if (q0 + u < nl && kvalid) {
-                    st(&gp[size_t(5 * B64 + l) * SK + k], wp[u]);
-                    st(&gp[size_t(5 * B64 + NL + l) * SK + k], wq[u]);
-                }
-            }
-        }
-        return;
-    }
     double(*D)[kVjpTile] = sd[wv];
     int4 *R = sr[wv];
     int *RE = se[wv];
     const int e0 = t * kVjpTile;
-    const int nb = min(kVjpTile, B - e0);
+    const int nb = min(kVjpTile, nlist - e0);
     {   // phase 1
-        const int e = lane < nb ? bsort[e0 + lane] : 0;
+        const int e = lane < nb ? list[e0 + lane] : 0;
         double d[20];
 #pragma unroll
         for (int q = 0; q < 20; ++q) d[q] = 0.0;
@@ -892,42 +967,8 @@ k_vjp_params(int B, int NL, int n_btiles, int n_ltiles, int n_kchunks,
         if (lane < nb && br_on[e]) {
             const int2 xf = busx[br_f[e]], xt = busx[br_t[e]];
             rows = make_int4(xf.x, xf.y, xt.x, xt.y);
-            const double r = P[e], xx = P[B64 + e], bc = P[2 * B64 + e];
-            const double tap = P[3 * B64 + e], sh = P[4 * B64 + e];
-            const double thf = x[xf.x], vf = x[xf.y], tht = x[xt.x], vt = x[xt.y];
-            const double Dd = r * r + xx * xx;
-            const double D2 = Dd * Dd;
-            const double g = r / Dd;
-            const double b = -xx / Dd;
-            const double delta = thf - tht - sh * (M_PI / 180.0);
-            double S, Cc;
-            sincos(delta, &S, &Cc);
-            const double u = vf * vt / tap;
-            const double t2 = tap * tap;
-            const double A1 = u * (g * Cc + b * S), B1 = u * (g * S - b * Cc);
-            const double A2 = u * (g * Cc - b * S), B2 = u * (g * S + b * Cc);
-            const double vf2 = vf * vf, vt2 = vt * vt;
-            // flow partials w.r.t. series g and b: [Pf, Qf, Pt, Qt]
-            const double dg[4] = {vf2 / t2 - u * Cc, -(u * S), vt2 - u * Cc, u * S};
-            const double db[4] = {-(u * S), -(vf2 / t2) + u * Cc, u * S, -vt2 + u * Cc};
-            const double dg_dr = (xx * xx - r * r) / D2, dg_dx = -(2.0 * r * xx) / D2;
-            const double db_dr = (2.0 * r * xx) / D2, db_dx = (xx * xx - r * r) / D2;
-            const double deg = -(M_PI / 180.0);
-#pragma unroll
-            for (int f = 0; f < 4; ++f) {
-                d[f] = dg[f] * dg_dr + db[f] * db_dr;
-                d[4 + f] = dg[f] * dg_dx + db[f] * db_dx;
-            }
-            d[9] = -(vf2 / (2.0 * t2));
-            d[11] = -(vt2 / 2.0);
-            d[12] = -(2.0 * vf2 * g) / (t2 * tap) + A1 / tap;
-            d[13] = (2.0 * vf2 * (b + 0.5 * bc)) / (t2 * tap) + B1 / tap;
-            d[14] = A2 / tap;
-            d[15] = -(B2 / tap);
-            d[16] = deg * B1;
-            d[17] = deg * (-A1);
-            d[18] = deg * B2;
-            d[19] = deg * A2;
+            branch_partials(P[e], P[B64 + e], P[2 * B64 + e], P[3 * B64 + e], P[4 * B64 + e],
+                            x[xf.x], x[xf.y], x[xt.x], x[xt.y], d);
         }
         if (lane < kVjpTile) {
 #pragma unroll
@@ -1114,8 +1155,8 @@ int dev_create(HostPlan &hp, DevPlan **out) {
         if (!rc) rc = dupload(dp, &dp->order_bfs, hp.order_bfs);
         if (!rc) rc = dupload(dp, &dp->adj_tiles, hp.adj_tiles);
         if (!rc) rc = dupload(dp, &dp->adj_src, hp.adj_src);
-        if (!rc) rc = dupload(dp, &dp->adj_br, hp.adj_br);
-        if (!rc) rc = dupload(dp, &dp->adj_ld, hp.adj_ld);
+        if (!rc) rc = dupload(dp, &dp->adj_own, hp.adj_own);
+        if (!rc) rc = dupload(dp, &dp->adj_left, hp.adj_left);
         if (!rc) rc = dalloc(dp, &dp->nw_F, size_t(hp.n));
         if (!rc) rc = dalloc(dp, &dp->nw_J, size_t(hp.nnz));
         if (!rc) rc = dalloc(dp, &dp->nw_dx, size_t(hp.n));
@@ -1358,24 +1399,31 @@ int dev_vjp(HostPlan &hp, DevPlan *dp, const double *x, const double *W, int32_t
     if (!g.ok) return fail(PF_EDEVICE, "cannot select device %d", dp->device);
     hipStream_t st = static_cast<hipStream_t>(stream);
     const int n_kchunks = (K + 63) / 64;
-    if (gx && hp.n_adj_tiles() > 0) {
+    if (hp.n_adj_tiles() > 0) {
         const int64_t waves = int64_t(hp.n_adj_tiles()) * n_kchunks;
-        hipLaunchKernelGGL(k_vjp_state, dim3(unsigned((waves + 3) / 4)), dim3(256), 0, st,
-                           dp->adj_tiles, hp.n_adj_tiles(), n_kchunks, dp->order_bfs,
-                           dp->adj_src, dp->grids, dp->bus2, dp->ycol, dp->ytr, dp->yG, dp->yB,
-                           dp->gen4, x, W, int(K), gx);
+#define LAUNCH(WGX, WGP)                                                                        \
+    hipLaunchKernelGGL((k_vjp<WGX, WGP>), dim3(unsigned((waves + 3) / 4)), dim3(256), 0, st,     \
+                       dp->adj_tiles, hp.n_adj_tiles(), n_kchunks, dp->order_bfs, dp->adj_src,   \
+                       dp->adj_own, dp->grids, dp->bus2, dp->ycol, dp->ytr, dp->yG, dp->yB,      \
+                       dp->gen4, dp->ldptr, dp->ldlist, dp->params, hp.Bt, hp.NLt, x, W, int(K), \
+                       gx, gp)
+        if (gx && gp)
+            LAUNCH(true, true);
+        else if (gx)
+            LAUNCH(true, false);
+        else
+            LAUNCH(false, true);
+#undef LAUNCH
         HIP_TRY(hipGetLastError());
     }
-    if (gp) {
-        const int nbt = (hp.Bt + kVjpTile - 1) / kVjpTile, nlt = (hp.NLt + kVjpTile - 1) / kVjpTile;
-        const int64_t waves = int64_t(nbt + nlt) * n_kchunks;
-        if (waves > 0) {
-            hipLaunchKernelGGL(k_vjp_params, dim3(unsigned((waves + 3) / 4)), dim3(256), 0, st,
-                               hp.Bt, hp.NLt, nbt, nlt, n_kchunks, dp->adj_br, dp->adj_ld,
-                               dp->br_f, dp->br_t, dp->br_on,
-                               dp->busx, dp->load_bus, dp->params, x, W, int(K), gp);
-            HIP_TRY(hipGetLastError());
-        }
+    const int nleft = int(hp.adj_left.size());
+    if (gp && nleft > 0) {
+        const int nt = (nleft + kVjpTile - 1) / kVjpTile;
+        const int64_t waves = int64_t(nt) * n_kchunks;
+        hipLaunchKernelGGL(k_vjp_branches, dim3(unsigned((waves + 3) / 4)), dim3(256), 0, st,
+                           hp.Bt, nleft, nt, n_kchunks, dp->adj_left, dp->br_f, dp->br_t,
+                           dp->br_on, dp->busx, dp->params, x, W, int(K), gp);
+        HIP_TRY(hipGetLastError());
     }
     return PF_OK;
 }

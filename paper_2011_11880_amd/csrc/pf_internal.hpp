@@ -121,8 +121,13 @@ struct HostPlan {
     std::vector<int32_t> adj_src;      // n_y: entry index, rows in order_bfs order
     std::vector<int32_t> adj_tiles;    // n * 4: e0, e1 (positions in adj_src),
                                        //   position of the first row in order_bfs, grid
-    std::vector<int32_t> adj_br;       // Bt: branches by breadth-first position of br_f
-    std::vector<int32_t> adj_ld;       // NLt: loads by breadth-first position of their bus
+    // parameter gradients: each in-service branch belongs to the entry
+    // (from bus, to bus) of its from bus's row, which evaluates it next to
+    // that entry; adj_own holds that branch per position of adj_src (or -1).
+    // A second branch on the same entry and out-of-service branches go to
+    // adj_left, evaluated by a separate pass.
+    std::vector<int32_t> adj_own;      // n_y
+    std::vector<int32_t> adj_left;
 
     int64_t n_params() const { return 5LL * Bt + 2LL * NLt; }
     int32_t n_tiles() const { return int32_t(tiles.size() / 8); }

@@ -435,9 +435,8 @@ int build_host_plan(const pf_network *nets, int32_t n_grids, HostPlan &hp) {
 
 // Adjoint work lists.  Each grid's buses fill positions [bus_off, bus_off +
 // N) of order_bfs, so tiles of whole rows taken along that order (at most
-// kAdjTileEntries entries unless one row is longer) never cross grids.
-// Branches and loads follow the breadth-first position of their bus
-// (stable, so ties keep input order).
+// kAdjTileEntries entries unless one row is longer) never cross grids.  Each
+// in-service branch is assigned to the position of its (from, to) entry.
 void build_adjoint_order(HostPlan &hp) {
     hp.adj_src.clear();
     hp.adj_tiles.clear();
@@ -464,17 +463,26 @@ void build_adjoint_order(HostPlan &hp) {
             hp.adj_tiles.push_back(g);
         }
     }
-    std::vector<int32_t> pos(size_t(hp.Nt));
-    for (int32_t q = 0; q < hp.Nt; ++q) pos[size_t(hp.order_bfs[q])] = q;
-    hp.adj_br.resize(size_t(hp.Bt));
-    std::iota(hp.adj_br.begin(), hp.adj_br.end(), 0);
-    std::stable_sort(hp.adj_br.begin(), hp.adj_br.end(),
-                     [&](int32_t a, int32_t b) { return pos[hp.br_f[a]] < pos[hp.br_f[b]]; });
-    hp.adj_ld.resize(size_t(hp.NLt));
-    std::iota(hp.adj_ld.begin(), hp.adj_ld.end(), 0);
-    std::stable_sort(hp.adj_ld.begin(), hp.adj_ld.end(), [&](int32_t a, int32_t b) {
-        return pos[hp.load_bus[a]] < pos[hp.load_bus[b]];
-    });
+    std::vector<int32_t> at(size_t(hp.n_y));
+    for (size_t q = 0; q < hp.adj_src.size(); ++q) at[size_t(hp.adj_src[q])] = int32_t(q);
+    hp.adj_own.assign(size_t(hp.n_y), -1);
+    hp.adj_left.clear();
+    for (const GridInfo &gi : hp.grids) {
+        for (int32_t e = gi.br_off; e < gi.br_off + gi.NB; ++e) {
+            if (!hp.br_on[e]) {
+                hp.adj_left.push_back(e);
+                continue;
+            }
+            const int32_t f = hp.br_f[e], tl = hp.br_t[e] - gi.bus_off;
+            int32_t q = hp.yptr[f];
+            while (q < hp.yptr[f + 1] && (hp.ycol[q] & kColMask) != tl) ++q;
+            int32_t *own = q < hp.yptr[f + 1] ? &hp.adj_own[size_t(at[size_t(q)])] : nullptr;
+            if (own && *own < 0)
+                *own = e;
+            else
+                hp.adj_left.push_back(e);
+        }
+    }
 }
 
 int attach_batch(const pf_batch_spec *spec, HostPlan &hp) {
