@@ -720,8 +720,11 @@ __device__ __forceinline__ void branch_partials(double r, double xx, double bc, 
 // dF_q/dQ_load = 1), written when the bus's row opens.  Rows are taken in
 // breadth-first order (tiles over `src`, the entry indices in that order)
 // and each XCD runs a contiguous range of tiles.
+// Five wavefronts per SIMD (at most 96 registers; a few spill in phase 1)
+// outrun four without spills: each wavefront's walk is a chain of dependent
+// loads, so more of them in flight is what helps.
 template <bool WGX, bool WGP>
-__global__ void __launch_bounds__(256)
+__global__ void __launch_bounds__(256, 5)
 k_vjp(const int4 *__restrict__ tiles, int ntiles, int n_kchunks, const int32_t *__restrict__ order,
       const int32_t *__restrict__ src, const int32_t *__restrict__ own,
       const GridDev *__restrict__ grids, const int2 *__restrict__ bus2,
@@ -788,7 +791,9 @@ k_vjp(const int4 *__restrict__ tiles, int ntiles, int n_kchunks, const int32_t *
     };
     for (int c0 = e0; c0 < e1; c0 += CH) {
         const int nvalid = min(CH, e1 - c0);
-        // ---- phase 1: one entry per lane
+        // ---- phase 1: one entry per lane; the entry's coefficients go to
+        // LDS before its branch's partials are formed, so the two sets are
+        // never live together
         uint64_t smask;
         {
             const bool valid = lane < nvalid;
@@ -801,18 +806,18 @@ k_vjp(const int4 *__restrict__ tiles, int ntiles, int n_kchunks, const int32_t *
             const int b = valid ? order[p0 + r] : 0;   // bus of the entry's row
             const int ia = b - gd.bus_off;
             double cf[8] = {0, 0, 0, 0, 0, 0, 0, 0};
-            double d[20];
-#pragma unroll
-            for (int q = 0; q < 20; ++q) d[q] = 0.0;
-            int partner = -1, ob = -1, lf = -1, ls = 0, ln = 0;
+            int partner = -1;
+            double tha = 0.0, va = 0.0, thc = 0.0, vc = 0.0;
             if (valid) {
-                const double tha = xt[ia], va = xv[ia];
+                tha = xt[ia];
+                va = xv[ia];
                 const double G = yG[e], Bc = yB[e];
                 if (ic == ia) {
                     cf[2] = 2.0 * va * G;      // dP_a/dV_a (diagonal term)
                     cf[3] = -(2.0 * va * Bc);  // dQ_a/dV_a
                 } else {
-                    const double thc = xt[ic], vc = xv[ic];
+                    thc = xt[ic];
+                    vc = xv[ic];
                     const int et = ytr[e];
                     const double Gp = yG[et], Bp = yB[et];
                     double s, co;
@@ -831,32 +836,40 @@ k_vjp(const int4 *__restrict__ tiles, int ntiles, int n_kchunks, const int32_t *
                     cf[6] = vc * t1p;     // dP_c/dV_a
                     cf[7] = vc * t2p;     // dQ_c/dV_a
                     partner = ic;
-                    if (WGP) {
-                        ob = own[c0 + lane];
-                        if (ob >= 0)
-                            branch_partials(P[ob], P[B64 + ob], P[2 * B64 + ob], P[3 * B64 + ob],
-                                            P[4 * B64 + ob], tha, va, thc, vc, d);
-                    }
-                }
-                if (WGP && start) {
-                    ls = ldptr[b];
-                    ln = ldptr[b + 1] - ls;
-                    lf = ln > 0 ? ldlist[ls] : -1;
                 }
             }
             if (lane < CH) {
 #pragma unroll
                 for (int q = 0; q < 8; ++q) C[q][lane] = cf[q];
-                if constexpr (WGP) {
-#pragma unroll
-                    for (int q = 0; q < 20; ++q) D[q][lane] = d[q];
-                }
                 PC[lane] = partner;
                 PB[lane] = b;
-                OB[lane] = ob;
-                LF[lane] = lf;
-                LS[lane] = ls;
-                LN[lane] = ln;
+            }
+            if constexpr (WGP) {
+                double d[20];
+#pragma unroll
+                for (int q = 0; q < 20; ++q) d[q] = 0.0;
+                int ob = -1, lf = -1, ls = 0, ln = 0;
+                if (valid) {
+                    if (partner >= 0) {
+                        ob = own[c0 + lane];
+                        if (ob >= 0)
+                            branch_partials(P[ob], P[B64 + ob], P[2 * B64 + ob], P[3 * B64 + ob],
+                                            P[4 * B64 + ob], tha, va, thc, vc, d);
+                    }
+                    if (start) {
+                        ls = ldptr[b];
+                        ln = ldptr[b + 1] - ls;
+                        lf = ln > 0 ? ldlist[ls] : -1;
+                    }
+                }
+                if (lane < CH) {
+#pragma unroll
+                    for (int q = 0; q < 20; ++q) D[q][lane] = d[q];
+                    OB[lane] = ob;
+                    LF[lane] = lf;
+                    LS[lane] = ls;
+                    LN[lane] = ln;
+                }
             }
         }
         wave_sync();
