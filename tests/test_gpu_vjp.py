@@ -66,6 +66,49 @@ def test_vjp_vs_oracle(ora, cuda, k):
     _check_vjp(ora, p, net, y, Wn, cuda, f"k{k}", params_too=(k <= 65))
 
 
+def test_vjp_several_loads_per_bus(ora, cuda):
+    """Buses with two and three loads (also at PV and slack buses), reversed
+    and same-direction parallel branches and an out-of-service branch: every
+    gradient row is written (outputs start as NaN) and matches the oracle."""
+    from paper_2011_11880_amd.api import Plan
+    net = _net()
+    rng = np.random.default_rng(21)
+    extra = np.concatenate([net.load_bus[:6], net.load_bus[:3], net.pv_bus[:2],
+                            net.slack_bus[:1]]).astype(np.int32)
+    net = net.copy()
+    net.load_bus = np.concatenate([net.load_bus, extra]).astype(np.int32)
+    net.load_p = np.concatenate([net.load_p, rng.uniform(0, 1, extra.size)])
+    net.load_q = np.concatenate([net.load_q, rng.uniform(-0.2, 0.3, extra.size)])
+    p = Plan(net)
+    y = synth.random_states(net, seed=22)
+    K = 3
+    Wn = rng.standard_normal((net.n_var, K))
+    x = torch.from_numpy(y).to(cuda)
+    W = torch.from_numpy(np.ascontiguousarray(Wn)).to(cuda)
+    gx = torch.full((p.n, K), float("nan"), dtype=torch.float64, device=cuda)
+    gp = torch.full((p.n_params, K), float("nan"), dtype=torch.float64, device=cuda)
+    p.vjp(x, W, gx, gp)
+    gp_only = torch.full_like(gp, float("nan"))
+    p.vjp(x, W, None, gp_only, want_gx=False)
+    gx_only = torch.full_like(gx, float("nan"))
+    p.vjp(x, W, gx_only, None, want_gparam=False)
+    torch.cuda.synchronize()
+    gx, gp = gx.cpu().numpy(), gp.cpu().numpy()
+    assert not np.isnan(gx).any() and not np.isnan(gp).any()
+    assert np.array_equal(gp, gp_only.cpu().numpy())
+    assert np.array_equal(gx, gx_only.cpu().numpy())
+    J, A = ora.jacobian(net, y)
+    B, L = net.n_branch, net.n_load
+    for k in range(K):
+        go, gpo = ora.vjp(net, y, Wn[:, k])
+        check_close(gx[:, k], go, A.T @ np.abs(Wn[:, k]), f"gx[{k}]")
+        sc = ora.vjp_params_scale(net, y, Wn[:, k])
+        for q, name in enumerate(PNAMES):
+            check_close(gp[q * B:(q + 1) * B, k], gpo[name], sc[name], f"{name}[{k}]")
+        np.testing.assert_array_equal(gp[5 * B:5 * B + L, k], gpo["load_p"])
+        np.testing.assert_array_equal(gp[5 * B + L:, k], gpo["load_q"])
+
+
 def test_vjp_hub_rows_and_schedules(ora, cuda):
     from paper_2011_11880_amd.api import Plan
     import test_gpu_eval as E
