@@ -13,8 +13,12 @@
 //       t_rk <- t_rk / t_kk;   t_rj <- t_rj - t_rk t_kj  for every j > k of row k;
 // rows are grouped into levels (a row only needs rows of earlier levels) and
 // each level is one launch; a wave keeps its row in LDS for all instances of
-// its chunk.  Solves: forward over the same levels, backward over levels of
-// U, then the update x[pivQ[k]] -= z[k].
+// its chunk.  A row's work is one stream of items, each reading one value of
+// T: a step's divide (by t_kk) followed by its updates (by t_kj).  The
+// values of a group of items are loaded together across step boundaries,
+// so a row waits on memory once per group rather than once per step.
+// Solves: forward over the same levels, backward over levels of U, then the
+// update x[pivQ[k]] -= z[k].
 #include <algorithm>
 #include <chrono>
 #include <cmath>
@@ -49,9 +53,9 @@ struct pf_batch_lu {
     int32_t *tci = nullptr;   // nnzT
     int32_t *tsrc = nullptr;  // nnzT: Jacobian slot of each T entry, -1 for fill
     int32_t *tdiag = nullptr; // n
-    int4 *step = nullptr;     // per L entry: {local index in row, diag position of k, update begin, end}
-    int32_t *step_ptr = nullptr;  // n + 1: steps of each row
-    int2 *upd = nullptr;      // {local index in row r, T position of (k, j)}
+    int32_t *item_ptr = nullptr;  // n + 1: items of each row
+    int2 *item = nullptr;     // {-(local index of t_rk) - 1, T position of t_kk} opens a step;
+                              // {local index of t_rj, T position of t_kj} is an update
     int32_t *frows = nullptr, *brows = nullptr;  // rows in level order
     int32_t *pivP = nullptr, *pivQ = nullptr;
     // device work arrays, instance-fastest with row pitch ld
@@ -65,7 +69,13 @@ struct pf_batch_lu {
 namespace {
 
 constexpr int kNormRowBlocks = 512;  // row blocks of the per-instance norm
-constexpr int kG = 8;               // loads issued together in the inner loops
+constexpr int kG = 8;               // loads issued together in the solves and row loads
+constexpr int kItems = 32;          // factorisation items whose loads are issued together
+// The index arrays (tci, tsrc, item) and T carry padding past their ends so
+// that a group's reads need no bounds test: the loads of a group are then
+// issued back to back, and only the use of an entry is guarded.  Padding
+// entries point at T row 0, Jacobian slot -1 (none) and column 0.
+constexpr int kPad = kItems;
 
 struct BGuard {
     int prev = -1;
@@ -96,7 +106,7 @@ void release(pf_batch_lu *b) {
     (void)hipGetDevice(&prev);
     (void)hipSetDevice(b->device);
     for (void *p : {(void *)b->trp, (void *)b->tci, (void *)b->tsrc, (void *)b->tdiag,
-                    (void *)b->step, (void *)b->step_ptr, (void *)b->upd, (void *)b->frows,
+                    (void *)b->item_ptr, (void *)b->item, (void *)b->frows,
                     (void *)b->brows, (void *)b->pivP, (void *)b->pivQ, (void *)b->T,
                     (void *)b->F, (void *)b->J, (void *)b->Y, (void *)b->part, (void *)b->norm,
                     (void *)b->active})
@@ -129,8 +139,7 @@ int lanes_for(int maxr, size_t lds_limit) {
 __global__ void __launch_bounds__(64) k_blu_factor(
     const int32_t *__restrict__ rows, int n_chunks, int W, int n_inst, int SI,
     const int32_t *__restrict__ trp, const int32_t *__restrict__ tsrc,
-    const int32_t *__restrict__ tdiag, const int32_t *__restrict__ step_ptr,
-    const int4 *__restrict__ step, const int2 *__restrict__ upd,
+    const int32_t *__restrict__ item_ptr, const int2 *__restrict__ item,
     const double *__restrict__ J, double *__restrict__ T) {
     extern __shared__ double Lrow[];
     const int lane = threadIdx.x;
@@ -141,37 +150,39 @@ __global__ void __launch_bounds__(64) k_blu_factor(
     if (live) {
         // the row's Jacobian values, kG loads in flight at a time
         for (int q0 = 0; q0 < R; q0 += kG) {
+            int sl[kG];
             double v[kG];
 #pragma unroll
-            for (int q = 0; q < kG; ++q) {
-                const int s = q0 + q < R ? tsrc[r0 + q0 + q] : -1;
-                v[q] = s >= 0 ? J[size_t(s) * SI + inst] : 0.0;
-            }
+            for (int q = 0; q < kG; ++q) sl[q] = tsrc[r0 + q0 + q];
+#pragma unroll
+            for (int q = 0; q < kG; ++q) v[q] = J[size_t(max(sl[q], 0)) * SI + inst];
 #pragma unroll
             for (int q = 0; q < kG; ++q)
-                if (q0 + q < R) Lrow[(q0 + q) * W + lane] = v[q];
+                if (q0 + q < R) Lrow[(q0 + q) * W + lane] = sl[q] >= 0 ? v[q] : 0.0;
         }
-        const int s0 = step_ptr[r], s1 = step_ptr[r + 1];
-        for (int st = s0; st < s1; ++st) {
-            const int4 sp = step[st];
-            const double lik = Lrow[sp.x * W + lane] / T[size_t(sp.y) * SI + inst];
-            Lrow[sp.x * W + lane] = lik;
-            // updates in groups: the group's loads of row k are issued before
-            // its read-modify-writes of the LDS row (one wait per group); the
-            // order of the updates, and so every result, is unchanged
-            for (int u0 = sp.z; u0 < sp.w; u0 += kG) {
-                double t[kG];
-                int px[kG];
+        // the row's items in groups: a group's loads are issued before its
+        // divides and read-modify-writes of the LDS row, which follow the
+        // stream's order, so every result is that of the plain loop
+        const int i0 = item_ptr[r], i1 = item_ptr[r + 1];
+        double lik = 0.0;
+        for (int g0 = i0; g0 < i1; g0 += kItems) {
+            double t[kItems];
+            int2 it[kItems];
 #pragma unroll
-                for (int q = 0; q < kG; ++q) {
-                    const bool in = u0 + q < sp.w;
-                    const int2 p = in ? upd[u0 + q] : make_int2(0, 0);
-                    px[q] = in ? p.x : -1;
-                    t[q] = in ? T[size_t(p.y) * SI + inst] : 0.0;
+            for (int q = 0; q < kItems; ++q) it[q] = item[g0 + q];
+#pragma unroll
+            for (int q = 0; q < kItems; ++q) t[q] = T[size_t(it[q].y) * SI + inst];
+#pragma unroll
+            for (int q = 0; q < kItems; ++q) {
+                if (g0 + q < i1) {
+                    if (it[q].x < 0) {   // a step opens: t_rk <- t_rk / t_kk
+                        const int xk = -it[q].x - 1;
+                        lik = Lrow[xk * W + lane] / t[q];
+                        Lrow[xk * W + lane] = lik;
+                    } else {
+                        Lrow[it[q].x * W + lane] = fma(-lik, t[q], Lrow[it[q].x * W + lane]);
+                    }
                 }
-#pragma unroll
-                for (int q = 0; q < kG; ++q)
-                    if (px[q] >= 0) Lrow[px[q] * W + lane] = fma(-lik, t[q], Lrow[px[q] * W + lane]);
             }
         }
         for (int q = 0; q < R; ++q) T[size_t(r0 + q) * SI + inst] = Lrow[q * W + lane];
@@ -191,12 +202,14 @@ __global__ void __launch_bounds__(64) k_blu_fwd(
     double s = F[size_t(pivP[r]) * SI + inst];
     const int e1 = tdiag[r];   // the strictly lower part ends at the diagonal
     for (int e0 = trp[r]; e0 < e1; e0 += kG) {
+        int c[kG];
         double t[kG], y[kG];
 #pragma unroll
+        for (int q = 0; q < kG; ++q) c[q] = tci[e0 + q];
+#pragma unroll
         for (int q = 0; q < kG; ++q) {
-            const bool in = e0 + q < e1;
-            t[q] = in ? T[size_t(e0 + q) * SI + inst] : 0.0;
-            y[q] = in ? Y[size_t(tci[e0 + q]) * SI + inst] : 0.0;
+            t[q] = T[size_t(e0 + q) * SI + inst];
+            y[q] = Y[size_t(c[q]) * SI + inst];
         }
 #pragma unroll
         for (int q = 0; q < kG; ++q)
@@ -217,12 +230,14 @@ __global__ void __launch_bounds__(64) k_blu_bwd(
     double s = Y[size_t(r) * SI + inst];
     const int e1 = trp[r + 1];
     for (int e0 = tdiag[r] + 1; e0 < e1; e0 += kG) {
+        int c[kG];
         double t[kG], y[kG];
 #pragma unroll
+        for (int q = 0; q < kG; ++q) c[q] = tci[e0 + q];
+#pragma unroll
         for (int q = 0; q < kG; ++q) {
-            const bool in = e0 + q < e1;
-            t[q] = in ? T[size_t(e0 + q) * SI + inst] : 0.0;
-            y[q] = in ? Y[size_t(tci[e0 + q]) * SI + inst] : 0.0;
+            t[q] = T[size_t(e0 + q) * SI + inst];
+            y[q] = Y[size_t(c[q]) * SI + inst];
         }
 #pragma unroll
         for (int q = 0; q < kG; ++q)
@@ -297,7 +312,7 @@ __global__ void __launch_bounds__(256) k_blu_norm_fold(int nb, int n_inst, int S
 int build(pf_batch_lu *b, const HostPlan &hp, int64_t nnzT, const int32_t *trp,
           const int32_t *tci, const int32_t *pivP, const int32_t *pivQ, size_t lds_limit) {
     const int n = int(hp.n);
-    std::vector<int32_t> tdiag(size_t(n), -1), tsrc(size_t(nnzT), -1);
+    std::vector<int32_t> tdiag(size_t(n), -1), tsrc(size_t(nnzT) + kPad, -1);
     // Jacobian slot of each T entry: entry (r, c) of P M Q is (pivP[r], pivQ[c]) of M
     for (int r = 0; r < n; ++r) {
         const int32_t mr = pivP[r];
@@ -320,10 +335,9 @@ int build(pf_batch_lu *b, const HostPlan &hp, int64_t nnzT, const int32_t *trp,
             if (!hit[size_t(s)])
                 return fail(PF_EINVAL, "T does not hold every Jacobian entry (slot %lld)", (long long)s);
     }
-    // elimination steps and updates; T must be closed under elimination
-    std::vector<int4> step;
-    std::vector<int32_t> step_ptr(size_t(n) + 1, 0);
-    std::vector<int2> upd;
+    // elimination items; T must be closed under elimination
+    std::vector<int32_t> item_ptr(size_t(n) + 1, 0);
+    std::vector<int2> item;
     std::vector<int32_t> flev(size_t(n), 0);
     for (int r = 0; r < n; ++r) {
         const int32_t r0 = trp[r], r1 = trp[r + 1];
@@ -331,19 +345,18 @@ int build(pf_batch_lu *b, const HostPlan &hp, int64_t nnzT, const int32_t *trp,
         for (int32_t e = r0; e < r1 && tci[e] < r; ++e) {
             const int k = tci[e];
             lev = std::max(lev, flev[size_t(k)] + 1);
-            const int32_t ub = int32_t(upd.size());
+            item.push_back(make_int2(-(e - r0) - 1, tdiag[size_t(k)]));
             for (int32_t f = tdiag[size_t(k)] + 1; f < trp[k + 1]; ++f) {
                 const int32_t j = tci[f];
                 const int32_t *p = std::lower_bound(tci + r0, tci + r1, j);
                 if (p == tci + r1 || *p != j)
                     return fail(PF_EINVAL, "T is not closed under elimination (row %d, column %d)", r, j);
-                upd.push_back(make_int2(int32_t(p - (tci + r0)), f));
+                item.push_back(make_int2(int32_t(p - (tci + r0)), f));
             }
-            step.push_back(make_int4(e - r0, tdiag[size_t(k)], ub, int32_t(upd.size())));
+            if (item.size() > size_t(INT32_MAX)) return fail(PF_EINVAL, "elimination too large");
         }
         flev[size_t(r)] = lev;
-        step_ptr[size_t(r) + 1] = int32_t(step.size());
-        if (upd.size() > size_t(INT32_MAX)) return fail(PF_EINVAL, "elimination too large");
+        item_ptr[size_t(r) + 1] = int32_t(item.size());
     }
     // backward levels over U
     std::vector<int32_t> blev(size_t(n), 0);
@@ -383,12 +396,14 @@ int build(pf_batch_lu *b, const HostPlan &hp, int64_t nnzT, const int32_t *trp,
     b->blev_w.assign(b->blev_ptr.size() - 1, 64);
     int rc = PF_OK;
     if (!rc) rc = balloc(&b->trp, trp, size_t(n) + 1);
-    if (!rc) rc = balloc(&b->tci, tci, size_t(nnzT));
+    std::vector<int32_t> tci_pad(tci, tci + nnzT);
+    tci_pad.resize(size_t(nnzT) + kPad, 0);
+    item.resize(item.size() + kPad, make_int2(0, 0));
+    if (!rc) rc = balloc(&b->tci, tci_pad.data(), tci_pad.size());
     if (!rc) rc = balloc(&b->tsrc, tsrc.data(), tsrc.size());
     if (!rc) rc = balloc(&b->tdiag, tdiag.data(), tdiag.size());
-    if (!rc) rc = balloc(&b->step, step.data(), step.size());
-    if (!rc) rc = balloc(&b->step_ptr, step_ptr.data(), step_ptr.size());
-    if (!rc) rc = balloc(&b->upd, upd.data(), upd.size());
+    if (!rc) rc = balloc(&b->item_ptr, item_ptr.data(), item_ptr.size());
+    if (!rc) rc = balloc(&b->item, item.data(), item.size());
     if (!rc) rc = balloc(&b->frows, frows.data(), frows.size());
     if (!rc) rc = balloc(&b->brows, brows.data(), brows.size());
     if (!rc) rc = balloc(&b->pivP, pivP, size_t(n));
@@ -404,8 +419,8 @@ int factor_levels(pf_batch_lu *b, const double *J, hipStream_t st) {
         const int nc = (I + W - 1) / W;
         const size_t shm = size_t(b->flev_maxr[l]) * size_t(W) * sizeof(double);
         hipLaunchKernelGGL(k_blu_factor, dim3(unsigned(int64_t(nr) * nc)), dim3(64), shm, st,
-                           b->frows + b->flev_ptr[l], nc, W, I, SI, b->trp, b->tsrc, b->tdiag,
-                           b->step_ptr, b->step, b->upd, J, b->T);
+                           b->frows + b->flev_ptr[l], nc, W, I, SI, b->trp, b->tsrc,
+                           b->item_ptr, b->item, J, b->T);
     }
     BL_HIP(hipGetLastError());
     return PF_OK;
@@ -483,7 +498,7 @@ int pf_batch_lu_create(pf_plan *plan, int64_t nnzT, const int32_t *T_rowptr,
     }
     const size_t SI = size_t(hp.ld);
     b->part_rows = int((n + kNormRowBlocks - 1) / kNormRowBlocks);
-    if (!rc) rc = balloc<double>(&b->T, nullptr, size_t(nnzT) * SI);
+    if (!rc) rc = balloc<double>(&b->T, nullptr, (size_t(nnzT) + kPad) * SI);
     if (!rc) rc = balloc<double>(&b->F, nullptr, size_t(n) * SI);
     if (!rc) rc = balloc<double>(&b->J, nullptr, size_t(hp.nnz) * SI);
     if (!rc) rc = balloc<double>(&b->Y, nullptr, size_t(n) * SI);
