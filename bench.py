@@ -581,6 +581,22 @@ def run_newton(args, torch, dev, **kw):
         reps.append(p.newton_device(x, lu))
     rep = min(reps, key=lambda r: r["t_total_s"])
     err = float(np.max(np.abs(x.cpu().numpy() - ystar)))
+    # the same Newton on this library's own factorisation (the batched LU
+    # with the plan as its one instance)
+    log("[bench] newton: device Newton on the library's own factorisation")
+    x = torch.from_numpy(y0).to(dev)
+    t0 = time.perf_counter()
+    olu = p.batch_lu(x)
+    t_olu = time.perf_counter() - t0
+    p.newton_batch(x, olu, tol=1e-10, max_iter=12)  # warm-up
+    oreps = []
+    for _ in range(3):
+        x = torch.from_numpy(y0).to(dev)
+        oreps.append(p.newton_batch(x, olu, tol=1e-10, max_iter=12))
+    orep = min(oreps, key=lambda r: r["t_total_s"])
+    oerr = float(np.max(np.abs(x.cpu().numpy() - ystar)))
+    oit = orep["iterations"]
+    olu.close()
     log("[bench] newton: host-solve Newton")
     xh = torch.from_numpy(y0).to(dev)
     reph = p.newton(xh)
@@ -614,6 +630,11 @@ def run_newton(args, torch, dev, **kw):
                        "total_ms": rep["t_total_s"] * 1e3,
                        "eval_ms_per_iter": rep["t_eval_s"] * 1e3 / (it + 1),
                        "solve_ms_per_iter": rep["t_solve_s"] * 1e3 / max(it, 1)},
+            "device_own_lu": {"iterations": oit, "converged": orep["n_converged"] == 1,
+                              "max_error_vs_solution": oerr, "nnz_lu": orep["nnz_lu"],
+                              "host_lu_s": t_olu, "total_ms": orep["t_total_s"] * 1e3,
+                              "eval_ms_per_iter": orep["t_eval_s"] * 1e3 / (oit + 1),
+                              "solve_ms_per_iter": orep["t_solve_s"] * 1e3 / max(oit, 1)},
             "host_solve": {"iterations": ith, "converged": reph["converged"],
                            "total_ms": reph["t_total_s"] * 1e3,
                            "eval_ms_per_iter": reph["t_eval_s"] * 1e3 / (ith + 1),

@@ -510,8 +510,10 @@ void pf_fdlf_destroy(pf_fdlf *fd);
  * instance: each is factorised on the device along T without pivoting again
  * (a zero pivot gives non-finite values for that instance only).
  *
- * pf_batch_lu_create: batched plan in the row layout; host arrays read
- *   during the call; the object keeps a pointer to the plan (destroy it
+ * pf_batch_lu_create: batched plan in the row layout, or a single-instance
+ *   or multi-grid plan (one instance: its x, F and Jval are the row layout
+ *   with pitch 1, and the same calls give a device-resident Newton whose
+ *   factorisation is this library's own); host arrays read during the call; the object keeps a pointer to the plan (destroy it
  *   first) and owns its device buffers (T values for every instance: nnzT x
  *   the plan's row pitch doubles, plus F, J and work rows).  Rows of T
  *   longer than the device's LDS allows for 16 instances give PF_EINVAL.
@@ -520,7 +522,8 @@ void pf_fdlf_destroy(pf_fdlf *fd);
  * pf_batch_lu_solve: after a factorisation, Xout[., i] = J_i^-1 B[., i] for
  *   every instance (device [n][pitch], must not alias).  Asynchronous.
  * pf_newton_batch: X (device [n][pitch]) updated in place; per iteration one
- *   batched evaluation (pf_eval_batch's kernel), per-instance ||F||_inf (the
+ *   evaluation (pf_eval_batch's kernel, or pf_eval's for a plan of one
+ *   instance), per-instance ||F||_inf (the
  *   norms are copied to the host), the factorisation and solves, and
  *   x <- x - dx for the instances still above tol; an instance that reaches
  *   tol is not stepped again.  inst_iters / inst_norm (host [n_inst],

@@ -556,14 +556,20 @@ class Plan:
 
     # batched Newton ---------------------------------------------------------
     def batch_lu(self, X, inst=0, permc_spec=None):
-        """A BatchLU for this batched plan: pattern and pivots from one host LU
-        of instance ``inst``'s Jacobian at the batched state X."""
+        """A BatchLU for this plan: pattern and pivots from one host LU of
+        instance ``inst``'s Jacobian at the batched state X.  A single-instance
+        or multi-grid plan is one instance (X of shape (n,)); its newton_batch
+        is then a device-resident Newton on this library's own factorisation."""
         return BatchLU(self, X, inst=inst, permc_spec=permc_spec)
 
+    def _lu_shape(self, rows):
+        return self.batch_shape(rows) if self.info["kind"] == "batch" else (rows,)
+
     def newton_batch(self, X, lu=None, tol=1e-10, max_iter=10):
-        """Newton power flow for every instance of this batched plan at once
-        (pf_newton_batch).  X (batch_shape(n)) is updated in place.  Returns a
-        dict report with per-instance step counts and last norms."""
+        """Newton power flow for every instance of this plan at once
+        (pf_newton_batch).  X (batch_shape(n), or (n,) for a plan of one
+        instance) is updated in place.  Returns a dict report with
+        per-instance step counts and last norms."""
         if lu is None:
             lu = BatchLU(self, X)
         I = self.n_inst
@@ -573,7 +579,7 @@ class Plan:
         rep = capi.pf_newton_report()
         import math
         rc = capi.lib().pf_newton_batch(self._h, lu._h,
-                                        _ptr(X, math.prod(self.batch_shape(self.n)), "X"),
+                                        _ptr(X, math.prod(self._lu_shape(self.n)), "X"),
                                         ctypes.byref(opts), its.ctypes.data_as(capi._pi32),
                                         nrm.ctypes.data_as(capi._pd), ctypes.byref(rep),
                                         _stream(self._dev(X)))
@@ -707,9 +713,9 @@ class DeviceSparseLU:
 
 
 class BatchLU:
-    """Batched factorisation (pf_batch_lu_*) of every instance of a batched
-    plan along the pattern and pivots of one host LU of one instance's
-    Jacobian."""
+    """Batched factorisation (pf_batch_lu_*) of every instance of a plan
+    along the pattern and pivots of one host LU of one instance's Jacobian
+    (a single-instance or multi-grid plan is one instance)."""
 
     def __init__(self, plan, X, inst=0, permc_spec=None):
         import weakref
@@ -717,8 +723,14 @@ class BatchLU:
             raise ValueError("the batched factorisation needs the row layout")
         self.plan = plan
         self._h = None
-        _, J = plan.eval_batch(X, want_F=False)
-        Jh = plan.from_batch(J)[inst]
+        if plan.info["kind"] == "batch":
+            _, J = plan.eval_batch(X, want_F=False)
+            Jh = plan.from_batch(J)[inst]
+        else:
+            if inst != 0:
+                raise ValueError("a single-instance plan has instance 0 only")
+            _, J = plan.eval(X, want_F=False)
+            Jh = J.cpu().numpy()
         rp, ci = plan.pattern()
         trp, tci, _, pivP, pivQ = host_lu(rp, ci, Jh, plan.n, permc_spec,
                                           row_order=plan.jacobian_row_order())
@@ -736,7 +748,7 @@ class BatchLU:
         """Factorise every instance from the batched Jacobian J."""
         import math
         p = self.plan
-        check(capi.lib().pf_batch_lu_factor(self._h, _ptr(J, math.prod(p.batch_shape(p.nnz)), "J"),
+        check(capi.lib().pf_batch_lu_factor(self._h, _ptr(J, math.prod(p._lu_shape(p.nnz)), "J"),
                                             _stream(J.device)))
 
     def solve(self, B, out=None):
@@ -745,7 +757,7 @@ class BatchLU:
 
         import torch
         p = self.plan
-        sh = p.batch_shape(p.n)
+        sh = p._lu_shape(p.n)
         if out is None:
             out = torch.empty(sh, dtype=torch.float64, device=B.device)
         check(capi.lib().pf_batch_lu_solve(self._h, _ptr(B, math.prod(sh), "B"),

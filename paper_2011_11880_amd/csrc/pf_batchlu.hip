@@ -389,7 +389,10 @@ int build(pf_batch_lu *b, const HostPlan &hp, int64_t nnzT, const int32_t *trp,
             maxr = std::max(maxr, trp[r + 1] - trp[r]);
         }
         b->flev_maxr[l] = maxr;
-        b->flev_w[l] = lanes_for(maxr, lds_limit);
+        // no more lanes than the instances need (16, 32 or 64), at most what
+        // the LDS allows for the level's longest row
+        const int wneed = b->n_inst <= 16 ? 16 : b->n_inst <= 32 ? 32 : 64;
+        b->flev_w[l] = std::min(lanes_for(maxr, lds_limit), wneed);
         if (!b->flev_w[l])
             return fail(PF_EINVAL, "a row of T has %d entries: too long for the batched factorisation", maxr);
     }
@@ -457,7 +460,9 @@ int pf_batch_lu_create(pf_plan *plan, int64_t nnzT, const int32_t *T_rowptr,
     *out = nullptr;
     if (!plan) return fail(PF_EINVAL, "plan is NULL");
     const HostPlan &hp = plan->host;
-    if (hp.kind != KIND_BATCH) return fail(PF_EINVAL, "pf_batch_lu_create needs a batched plan");
+    // single-instance and multi-grid plans are one instance of row pitch 1
+    if (hp.kind != KIND_BATCH && (hp.n_inst != 1 || hp.ld != 1))
+        return fail(PF_EINVAL, "unexpected instance layout of a single-instance plan");
     if (hp.panels) return fail(PF_EINVAL, "the batched factorisation needs the row layout");
     if (!T_rowptr || !T_colidx || !pivP || !pivQ) return fail(PF_EINVAL, "NULL argument");
     const int64_t n = hp.n;
@@ -567,7 +572,8 @@ int pf_newton_batch(pf_plan *plan, pf_batch_lu *b, double *X, const pf_newton_op
     int n_conv = 0;
     for (;; ++it) {
         (void)hipEventRecord(ev[0], st);
-        rc = dev_eval_batch(hp, plan->dev, X, b->F, b->J, st);
+        rc = hp.kind == KIND_BATCH ? dev_eval_batch(hp, plan->dev, X, b->F, b->J, st)
+                                   : dev_eval_single(hp, plan->dev, X, b->F, b->J, st);
         if (rc) break;
         (void)hipEventRecord(ev[1], st);
         hipLaunchKernelGGL(k_blu_norm_part, dim3(unsigned((I + 255) / 256), kNormRowBlocks),

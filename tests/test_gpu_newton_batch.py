@@ -143,3 +143,69 @@ def test_newton_batch_failure_paths(ora, cuda):
     assert np.all(np.isfinite(np.delete(rep["inst_norm"], 2)))
     q.close()
     assert lu_q._h is None
+
+
+@pytest.mark.parametrize("which", ["tiny", "10k"])
+def test_one_instance_plan_solves_match_host(ora, cuda, which):
+    """A single-instance plan is one instance of the batched factorisation:
+    factorise and solve at a random state, against a host solve of the
+    oracle's J and F."""
+    from paper_2011_11880_amd.api import Plan
+    net = synth.tiny_grid(9) if which == "tiny" else synth.grid_10k()
+    p = Plan(net)
+    y = synth.random_states(net, seed=41)
+    x = torch.from_numpy(y).to(cuda)
+    lu = p.batch_lu(x)
+    F, J = p.eval(x)
+    lu.factor(J)
+    d = lu.solve(F)
+    torch.cuda.synchronize()
+    assert tuple(d.shape) == (p.n,)
+    d = d.cpu().numpy()
+    Jo, _ = ora.jacobian(net, y)
+    Fo, _ = ora.residual(net, y)
+    ref = spla.spsolve(Jo.tocsc(), Fo)
+    np.testing.assert_allclose(d, ref, rtol=0, atol=1e-7 * np.max(np.abs(ref)))
+
+
+@pytest.mark.parametrize("which", ["tiny", "10k", "70k"])
+def test_one_instance_newton_matches_oracle(ora, cuda, which):
+    """Device-resident Newton of a single-instance plan on the library's own
+    factorisation: the oracle's step count and end state (200 and 10k
+    buses), convergence to the manufactured solution at 70k."""
+    from paper_2011_11880_amd.api import Plan
+    import test_gpu_newton_device as D
+    if which == "tiny":
+        net, ystar, y0 = D._manufactured(ora, synth.tiny_grid(7), 7)
+    else:
+        net0 = synth.grid_10k() if which == "10k" else synth.grid_70k()
+        net, ystar, y0 = D._manufactured(ora, net0, 3, ang=0.03, pert=(1e-4, 2.5e-4))
+    p = Plan(net)
+    x = torch.from_numpy(y0).to(cuda)
+    rep = p.newton_batch(x, tol=1e-10, max_iter=12)
+    assert rep["n_converged"] == 1 and rep["inst_norm"][0] < 1e-10
+    xh = x.cpu().numpy()
+    if which != "70k":
+        y, norms, _ = ora.newton(net, y0, tol=1e-10, max_iter=12)
+        assert norms[-1] < 1e-10
+        assert abs(rep["iterations"] - (len(norms) - 1)) <= 1
+        np.testing.assert_allclose(xh, y, rtol=0, atol=1e-9)
+    np.testing.assert_allclose(xh, ystar, rtol=0, atol=1e-6)
+
+
+def test_one_instance_multi_grid_newton(ora, cuda):
+    """Two grids in one multi-grid plan, solved together as one instance."""
+    from paper_2011_11880_amd.api import Plan
+    import test_gpu_newton_device as D
+    cases = [D._manufactured(ora, synth.tiny_grid(s, n_bus=60 + 40 * s, n_branch=85 + 55 * s,
+                                                  n_pv=8), 30 + s) for s in range(2)]
+    nets = [c[0] for c in cases]
+    mp = Plan.multi(nets)
+    x = torch.from_numpy(np.concatenate([c[2] for c in cases])).to(cuda)
+    rep = mp.newton_batch(x, tol=1e-10, max_iter=12)
+    assert rep["n_converged"] == 1
+    xh = x.cpu().numpy()
+    for g, (net, ystar, y0) in enumerate(cases):
+        y, norms, _ = ora.newton(net, y0, tol=1e-10, max_iter=12)
+        assert norms[-1] < 1e-10
+        np.testing.assert_allclose(xh[mp.x_off[g]:mp.x_off[g + 1]], y, rtol=0, atol=1e-9)

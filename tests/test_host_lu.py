@@ -196,8 +196,9 @@ def test_batch_lu_create_checks(ora):
                                   pivQ.ctypes.data_as(capi._pi32), ctypes.byref(h))
         return rc, L.pf_last_error().decode()
 
+    # a single-instance plan is accepted (one instance); host-only plans are not
     rc, msg = create(single)
-    assert rc == capi.PF_EINVAL and "batched" in msg
+    assert rc == capi.PF_EINVAL and "host-only" in msg
     bad = pivP.copy()
     bad[0] = bad[1]
     rc, msg = create(batch, bad)
