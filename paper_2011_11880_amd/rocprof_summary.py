@@ -3,6 +3,10 @@
   python -m paper_2011_11880_amd.rocprof_summary stats RUN_results.db [--match NAME]
       per-kernel dispatch count and duration statistics (microseconds)
 
+  python -m paper_2011_11880_amd.rocprof_summary counters RUN_results.db --match NAME
+      per-dispatch average of every counter collected for kernels whose name
+      contains NAME (SQ counters are sums over the device)
+
   python -m paper_2011_11880_amd.rocprof_summary traffic \
         --fetch F.db --write W.db --copy-fetch CF.db --copy-write CW.db \
         --kernel NAME --copy-bytes BYTES --units U --out FILE.json
@@ -49,6 +53,19 @@ def counter_per_dispatch(db, counter, match):
     return sum(vals) / len(vals), len(vals)
 
 
+def counters(db, match):
+    c = sqlite3.connect(db)
+    rows = c.execute("select kernel_name, dispatch_id, counter_name, sum(value) from "
+                     "counters_collection group by kernel_name, dispatch_id, counter_name").fetchall()
+    agg = {}
+    for name, _, counter, v in rows:
+        if match in name:
+            agg.setdefault(counter, []).append(v)
+    if not agg:
+        raise SystemExit(f"no counters for kernels matching {match!r} in {db}")
+    return {k: (sum(v) / len(v), len(v)) for k, v in sorted(agg.items())}
+
+
 def traffic(a):
     from .build import kernel_source_hash
     kib = 1024.0
@@ -80,6 +97,9 @@ def main(argv=None):
     s = sub.add_parser("stats")
     s.add_argument("db")
     s.add_argument("--match")
+    cn = sub.add_parser("counters")
+    cn.add_argument("db")
+    cn.add_argument("--match", required=True)
     t = sub.add_parser("traffic")
     for k in ("fetch", "write", "copy_fetch", "copy_write", "kernel", "out"):
         t.add_argument("--" + k.replace("_", "-"), required=True)
@@ -87,6 +107,10 @@ def main(argv=None):
     t.add_argument("--copy-bytes", type=int, required=True)
     t.add_argument("--units", type=int, required=True)
     a = ap.parse_args(argv)
+    if a.cmd == "counters":
+        for k, (avg, nd) in counters(a.db, a.match).items():
+            print(f"{k:34s} {avg:20.1f}  ({nd} dispatches)")
+        return
     if a.cmd == "stats":
         rows = kernel_stats(a.db, a.match)
         print(f"{'calls':>7} {'avg_us':>11} {'median_us':>11} {'min_us':>11} {'max_us':>11}  kernel")
