@@ -611,7 +611,8 @@ def run_newton(args, torch, dev, **kw):
     log("[bench] newton: with reactive limits")
     pq = Plan(net, device=0, q_limits=True)
     lim = {}
-    for name, on_dev in (("device", True), ("host_solve", False)):
+    for name, on_dev in (("device", True), ("device_rocsolver", "rocsolver"),
+                         ("host_solve", False)):
         pq.set_gen_modes(np.zeros(NPV, np.int32))
         x = torch.from_numpy(y0).to(dev)
         torch.cuda.synchronize()

@@ -478,18 +478,28 @@ class Plan:
 
     def newton_qlim(self, x, q_min, q_max, device=False, tol=1e-10, max_iter=10,
                     max_outer=10, switch_tol=1e-9):
-        """Newton power flow with reactive limits: solve (host or device
-        solve), check the limits, and solve again from the last state until
-        no unit switches.  After a switch a held row's nonzero moves from
-        the V column to the Q_g column, so the device path takes a fresh
-        host LU (new pivots) for the next solve.  ``x`` is updated in place."""
+        """Newton power flow with reactive limits: solve, check the limits,
+        and solve again from the last state until no unit switches.
+        ``device``: False solves on the host; True runs every step on the
+        device with this library's factorisation (the plan as one instance);
+        "rocsolver" with rocSOLVER's re-factorisation.  After a switch a held
+        row's nonzero moves from the V column to the Q_g column, so a device
+        path takes a fresh host LU (new pivots) for the next solve.  ``x`` is
+        updated in place."""
+        if device not in (False, True, "rocsolver"):
+            raise ValueError("device must be False, True or 'rocsolver'")
         rounds = []
         lu = None
         for outer in range(1, max_outer + 1):
-            if device:
+            if device == "rocsolver":
                 if lu is None:
                     lu = DeviceLU(self, x)
                 rep = self.newton_device(x, lu, tol=tol, max_iter=max_iter)
+            elif device:
+                if lu is None:
+                    lu = BatchLU(self, x)
+                rep = self.newton_batch(x, lu, tol=tol, max_iter=max_iter)
+                rep["converged"] = rep["n_converged"] == 1
             else:
                 rep = self.newton(x, tol=tol, max_iter=max_iter)
             rounds.append(rep)

@@ -159,7 +159,7 @@ def _limits_case(ora, net0, seed, ang, pert, lo_idx, hi_idx, margin):
     return net, y0, qmin, qmax
 
 
-@pytest.mark.parametrize("device", [False, True])
+@pytest.mark.parametrize("device", [False, True, "rocsolver"])
 def test_newton_with_limits_matches_oracle(ora, cuda, device):
     from paper_2011_11880_amd.api import Plan
     net, y0, qmin, qmax = _limits_case(ora, synth.tiny_grid(11), 11, 0.3, (0.02, 0.05),
@@ -175,7 +175,8 @@ def test_newton_with_limits_matches_oracle(ora, cuda, device):
     np.testing.assert_allclose(x.cpu().numpy(), y_o, rtol=0, atol=1e-9)
 
 
-def test_newton_with_limits_10k_device(ora, cuda):
+@pytest.mark.parametrize("device", [True, "rocsolver"])
+def test_newton_with_limits_10k_device(ora, cuda, device):
     """10k grid: ten units above their upper limit at the solution, by
     0.002.  Larger shifts of held outputs make Newton wander on the
     synthetic grid's weak corridors. The plain switching rule can also
@@ -193,7 +194,7 @@ def test_newton_with_limits_10k_device(ora, cuda):
     assert ok_o and m_o.sum() >= 10
     p = Plan(net, q_limits=True)
     x = torch.from_numpy(y0).to(cuda)
-    rep = p.newton_qlim(x, qmin, qmax, device=True)
+    rep = p.newton_qlim(x, qmin, qmax, device=device)
     assert rep["converged"] and rep["outer"] == outer_o
     m, qt = p.gen_modes()
     assert np.array_equal(m, m_o) and np.array_equal(qt, qt_o)
