@@ -807,7 +807,7 @@ def main():
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
     args = ap.parse_args()
     if args.gpus != 1:
-        print(f"bench.py: this build evaluates on one GPU only; --gpus {args.gpus} is not "
+        print(f"bench.py: the evaluation runs on one GPU only; --gpus {args.gpus} is not "
               "supported (batches would shard by instance with no communication)",
               file=sys.stderr)
         sys.exit(2)

@@ -6,7 +6,7 @@ namespace pf {
 struct DevPlan {};
 int dev_create(HostPlan &, DevPlan **out) {
     *out = nullptr;
-    return fail(PF_EDEVICE, "no device in this build");
+    return fail(PF_EDEVICE, "no device in the host-only binary");
 }
 void dev_destroy(DevPlan *dp) { delete dp; }
 int dev_upload_tiles(HostPlan &, DevPlan *) { return PF_OK; }

@@ -1,0 +1,60 @@
+"""Host-side checks of the benchmark script and the profile summary tool
+(CPU only): the one-GPU guard, the multi-process oracle baseline over
+independent instances, and per-dispatch counter averages."""
+
+import os
+import sqlite3
+import subprocess
+import sys
+
+import numpy as np
+
+from paper_2011_11880_amd import synth
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def test_more_than_one_gpu_is_refused():
+    r = subprocess.run([sys.executable, os.path.join(ROOT, "bench.py"), "--gpus", "2"],
+                       capture_output=True, text=True, timeout=120, cwd=ROOT)
+    assert r.returncode == 2
+    assert "one GPU" in r.stderr
+
+
+def test_parallel_oracle_baseline_counts_every_instance():
+    sys.path.insert(0, ROOT)
+    import bench
+    net = synth.tiny_grid(3)
+    I = 6
+    ls = np.exp(0.1 * np.random.default_rng(1).normal(size=(I, net.n_load)))
+    ps = np.ones((I, net.n_pv))
+    out = np.full(I, -1, np.int32)
+    out[3:] = synth.contingencies(net, 3, seed=2)
+    Y = synth.random_states(net, I, seed=3)
+    items = [(ls[k] if k < 3 else None, ps[k] if k < 3 else None, int(out[k]), Y[k])
+             for k in range(I)]
+    r = bench.cpu_baseline_parallel(net, items, 30.0, "instances")
+    assert r["kind"] == "oracle" and r["unit"] == "evals/s" and r["value"] > 0
+    assert 1 <= r["cores"] <= min(16, I)
+    assert r["sample"].startswith(f"{I} of the {I} instances")
+    # one grid and state per item, no base network
+    r = bench.cpu_baseline_parallel(None, [(net, Y[0]), (net, Y[1])], 30.0, "grids")
+    assert r["sample"].startswith("2 of the 2 grids")
+
+
+def test_counter_summary_averages_per_dispatch(tmp_path):
+    from paper_2011_11880_amd import rocprof_summary as R
+    db = tmp_path / "run_results.db"
+    c = sqlite3.connect(db)
+    c.execute("create table counters_collection (kernel_name text, dispatch_id int, "
+              "counter_name text, value real)")
+    rows = [("k_a(int)", 1, "FETCH_SIZE", 10.0), ("k_a(int)", 1, "FETCH_SIZE", 6.0),
+            ("k_a(int)", 2, "FETCH_SIZE", 20.0), ("k_b(int)", 3, "FETCH_SIZE", 99.0),
+            ("k_a(int)", 1, "SQ_WAVES", 4.0), ("k_a(int)", 2, "SQ_WAVES", 8.0)]
+    c.executemany("insert into counters_collection values (?, ?, ?, ?)", rows)
+    c.commit()
+    c.close()
+    out = R.counters(str(db), "k_a")
+    # per dispatch, values of one counter are summed (over the device's units)
+    assert out["FETCH_SIZE"] == ((16.0 + 20.0) / 2, 2)
+    assert out["SQ_WAVES"] == (6.0, 2)

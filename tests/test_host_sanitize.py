@@ -20,7 +20,7 @@ def test_host_code_under_asan_ubsan(tmp_path):
            "-fsanitize=address,undefined", "-fno-sanitize-recover=undefined",
            "-I", os.path.join(ROOT, "include"), "-I", CSRC,
            os.path.join(CSRC, "pf_setup.cpp"), os.path.join(CSRC, "pf_api.cpp"),
-           os.path.join(HERE, "stub_device.cpp"), os.path.join(HERE, "driver.cpp"),
+           os.path.join(HERE, "stub_device.cpp"), os.path.join(HERE, "sanitize_main.cpp"),
            "-o", exe]
     subprocess.check_call(cmd)
     env = dict(os.environ, ASAN_OPTIONS="detect_leaks=1:abort_on_error=1",
