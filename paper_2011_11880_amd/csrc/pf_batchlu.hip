@@ -48,6 +48,7 @@ struct pf_batch_lu {
     std::vector<int32_t> flev_ptr, blev_ptr;  // levels -> rows (offsets into the row lists)
     std::vector<int32_t> flev_w, blev_w;      // lanes used per wave (64, 32 or 16) per level
     std::vector<int32_t> flev_maxr;           // longest row per factor level
+    std::vector<int32_t> flev_maxi;           // most items of a row per factor level
     // device structure
     int32_t *trp = nullptr;   // n + 1
     int32_t *tci = nullptr;   // nnzT
@@ -64,6 +65,7 @@ struct pf_batch_lu {
     int32_t *active = nullptr;
     double *norm_host = nullptr;              // pinned [ld]
     int part_rows = 0;
+    size_t lds_limit = 0;     // dynamic LDS a block may use
 };
 
 namespace {
@@ -187,6 +189,66 @@ __global__ void __launch_bounds__(64) k_blu_factor(
         }
         for (int q = 0; q < R; ++q) T[size_t(r0 + q) * SI + inst] = Lrow[q * W + lane];
     }
+}
+
+__device__ __forceinline__ void wave_sync() {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+// One instance (row pitch 1): a wavefront per row, its lanes spread over the
+// row.  The row and the values its items read (final entries of rows of
+// earlier levels) are loaded into LDS by all lanes at once; the steps then
+// run in order, each step's divide on the wave-uniform value and its updates
+// over the lanes.  A step's updates change distinct entries of the row, so
+// every result equals that of the one-lane loop of k_blu_factor.
+__global__ void __launch_bounds__(64) k_blu_factor1(
+    const int32_t *__restrict__ rows, const int32_t *__restrict__ trp,
+    const int32_t *__restrict__ tsrc, const int32_t *__restrict__ item_ptr,
+    const int2 *__restrict__ item, const double *__restrict__ J, double *__restrict__ T) {
+    extern __shared__ double sm[];
+    const int lane = threadIdx.x;
+    const int r = rows[blockIdx.x];
+    const int r0 = trp[r], R = trp[r + 1] - r0;
+    const int i0 = item_ptr[r], NI = item_ptr[r + 1] - i0;
+    double *Lrow = sm;
+    double *tv = sm + R;
+    int *ix = reinterpret_cast<int *>(tv + NI);
+    for (int q = lane; q < R; q += 64) {
+        const int s = tsrc[r0 + q];
+        Lrow[q] = s >= 0 ? J[s] : 0.0;
+    }
+    for (int q = lane; q < NI; q += 64) {
+        const int2 it = item[i0 + q];
+        ix[q] = it.x;
+        tv[q] = T[it.y];
+    }
+    wave_sync();
+    int q = 0;
+    while (q < NI) {
+        // item q opens a step: t_rk <- t_rk / t_kk
+        const int xk = -ix[q] - 1;
+        const double lik = Lrow[xk] / tv[q];
+        wave_sync();
+        if (lane == 0) Lrow[xk] = lik;
+        // its updates run up to the next opening item
+        int next = NI;
+        for (int u0 = q + 1; u0 < NI; u0 += 64) {
+            const int uq = u0 + lane;
+            const bool stop = uq >= NI || ix[uq] < 0;
+            const uint64_t m = __ballot(stop);
+            const int lim = m ? __ffsll((unsigned long long)m) - 1 : 64;
+            if (lane < lim) Lrow[ix[uq]] = fma(-lik, tv[uq], Lrow[ix[uq]]);
+            if (m) {
+                next = u0 + lim;
+                break;
+            }
+        }
+        wave_sync();
+        q = next;
+    }
+    for (int q2 = lane; q2 < R; q2 += 64) T[r0 + q2] = Lrow[q2];
 }
 
 // forward: Y[r] = F[pivP[r]] - sum_{k < r} t_rk Y[k]
@@ -382,11 +444,13 @@ int build(pf_batch_lu *b, const HostPlan &hp, int64_t nnzT, const int32_t *trp,
     const size_t nfl = b->flev_ptr.size() - 1;
     b->flev_w.assign(nfl, 64);
     b->flev_maxr.assign(nfl, 0);
+    b->flev_maxi.assign(nfl, 0);
     for (size_t l = 0; l < nfl; ++l) {
         int maxr = 0;
         for (int32_t q = b->flev_ptr[l]; q < b->flev_ptr[l + 1]; ++q) {
             const int r = frows[size_t(q)];
             maxr = std::max(maxr, trp[r + 1] - trp[r]);
+            b->flev_maxi[l] = std::max(b->flev_maxi[l], item_ptr[size_t(r) + 1] - item_ptr[size_t(r)]);
         }
         b->flev_maxr[l] = maxr;
         // no more lanes than the instances need (16, 32 or 64), at most what
@@ -418,6 +482,16 @@ int factor_levels(pf_batch_lu *b, const double *J, hipStream_t st) {
     const int I = b->n_inst, SI = b->ld;
     for (size_t l = 0; l + 1 < b->flev_ptr.size(); ++l) {
         const int nr = b->flev_ptr[l + 1] - b->flev_ptr[l];
+        if (I == 1 && SI == 1) {   // one instance: lanes spread over the row
+            const size_t shm1 = size_t(b->flev_maxr[l] + b->flev_maxi[l]) * sizeof(double) +
+                                size_t(b->flev_maxi[l]) * sizeof(int32_t);
+            if (shm1 <= b->lds_limit) {
+                hipLaunchKernelGGL(k_blu_factor1, dim3(unsigned(nr)), dim3(64), shm1, st,
+                                   b->frows + b->flev_ptr[l], b->trp, b->tsrc, b->item_ptr,
+                                   b->item, J, b->T);
+                continue;
+            }
+        }
         const int W = b->flev_w[l];
         const int nc = (I + W - 1) / W;
         const size_t shm = size_t(b->flev_maxr[l]) * size_t(W) * sizeof(double);
@@ -487,6 +561,8 @@ int pf_batch_lu_create(pf_plan *plan, int64_t nnzT, const int32_t *T_rowptr,
     // rows of the factorisation live in dynamic LDS, up to the device's limit
     (void)hipFuncSetAttribute(reinterpret_cast<const void *>(&k_blu_factor),
                               hipFuncAttributeMaxDynamicSharedMemorySize, lds);
+    (void)hipFuncSetAttribute(reinterpret_cast<const void *>(&k_blu_factor1),
+                              hipFuncAttributeMaxDynamicSharedMemorySize, lds);
     pf_batch_lu *b = new (std::nothrow) pf_batch_lu();
     if (!b) return fail(PF_ENOMEM, "host allocation failed");
     b->plan = plan;
@@ -495,6 +571,7 @@ int pf_batch_lu_create(pf_plan *plan, int64_t nnzT, const int32_t *T_rowptr,
     b->nnzT = int(nnzT);
     b->n_inst = hp.n_inst;
     b->ld = hp.ld;
+    b->lds_limit = size_t(lds);
     int rc;
     try {
         rc = build(b, hp, nnzT, T_rowptr, T_colidx, pivP, pivQ, size_t(lds));
