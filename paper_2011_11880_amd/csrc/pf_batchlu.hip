@@ -308,6 +308,40 @@ __global__ void __launch_bounds__(64) k_blu_bwd(
     Y[size_t(r) * SI + inst] = s / T[size_t(tdiag[r]) * SI + inst];
 }
 
+// One instance: a wavefront per row, its lanes over the row's entries; the
+// lanes' partial sums are combined by a fixed butterfly, so results are
+// deterministic (their rounding differs from the one-lane loop's).
+__device__ __forceinline__ double wave_sum(double p) {
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) p += __shfl_xor(p, off);
+    return p;
+}
+
+__global__ void __launch_bounds__(64) k_blu_fwd1(
+    const int32_t *__restrict__ rows, const int32_t *__restrict__ trp,
+    const int32_t *__restrict__ tci, const int32_t *__restrict__ tdiag,
+    const int32_t *__restrict__ pivP, const double *__restrict__ T,
+    const double *__restrict__ F, double *__restrict__ Y) {
+    const int lane = threadIdx.x;
+    const int r = rows[blockIdx.x];
+    double p = 0.0;
+    for (int e = trp[r] + lane; e < tdiag[r]; e += 64) p = fma(T[e], Y[tci[e]], p);
+    p = wave_sum(p);
+    if (lane == 0) Y[r] = F[pivP[r]] - p;
+}
+
+__global__ void __launch_bounds__(64) k_blu_bwd1(
+    const int32_t *__restrict__ rows, const int32_t *__restrict__ trp,
+    const int32_t *__restrict__ tci, const int32_t *__restrict__ tdiag,
+    const double *__restrict__ T, double *__restrict__ Y) {
+    const int lane = threadIdx.x;
+    const int r = rows[blockIdx.x];
+    double p = 0.0;
+    for (int e = tdiag[r] + 1 + lane; e < trp[r + 1]; e += 64) p = fma(T[e], Y[tci[e]], p);
+    p = wave_sum(p);
+    if (lane == 0) Y[r] = (Y[r] - p) / T[tdiag[r]];
+}
+
 // x[pivQ[k]] -= z[k] for active instances (subtract = 1), or x[pivQ[k]] = z[k]
 // (subtract = 0); one block per (row k, 256 instances)
 __global__ void __launch_bounds__(256) k_blu_step(int n, int n_inst, int SI, int inst_blocks,
@@ -506,6 +540,21 @@ int factor_levels(pf_batch_lu *b, const double *J, hipStream_t st) {
 int solve_levels(pf_batch_lu *b, const double *Fin, double *Y, hipStream_t st) {
     const int I = b->n_inst, SI = b->ld;
     const int nc = (I + 63) / 64;
+    if (I == 1 && SI == 1) {   // one instance: lanes over each row's entries
+        for (size_t l = 0; l + 1 < b->flev_ptr.size(); ++l) {
+            const int nr = b->flev_ptr[l + 1] - b->flev_ptr[l];
+            hipLaunchKernelGGL(k_blu_fwd1, dim3(unsigned(nr)), dim3(64), 0, st,
+                               b->frows + b->flev_ptr[l], b->trp, b->tci, b->tdiag, b->pivP,
+                               b->T, Fin, Y);
+        }
+        for (size_t l = 0; l + 1 < b->blev_ptr.size(); ++l) {
+            const int nr = b->blev_ptr[l + 1] - b->blev_ptr[l];
+            hipLaunchKernelGGL(k_blu_bwd1, dim3(unsigned(nr)), dim3(64), 0, st,
+                               b->brows + b->blev_ptr[l], b->trp, b->tci, b->tdiag, b->T, Y);
+        }
+        BL_HIP(hipGetLastError());
+        return PF_OK;
+    }
     for (size_t l = 0; l + 1 < b->flev_ptr.size(); ++l) {
         const int nr = b->flev_ptr[l + 1] - b->flev_ptr[l];
         hipLaunchKernelGGL(k_blu_fwd, dim3(unsigned(int64_t(nr) * nc)), dim3(64), 0, st,
