@@ -433,7 +433,7 @@ int pf_newton_device(pf_plan *plan, pf_refact *rf, double *x,
 void pf_refact_destroy(pf_refact *rf);
 
 /*
- * Fast decoupled power flow, XB variant (the conclusion names it as another
+ * Fast decoupled power flow, XB variant (Section V names it as another
  * method that reuses the same equation evaluation).  Constant matrices,
  * built from the network given at setup (single-grid plans):
  *   B'  over the buses without a slack: per in-service branch the weight

@@ -296,9 +296,11 @@ def q_limit_switch(net, y, mode, qt, qmin, qmax, tol=1e-9):
 
 
 def newton_qlim(net, y0, qmin, qmax, tol=1e-10, max_iter=10, max_outer=10):
-    """Newton power flow with reactive limits: solve, check the limits,
-    switch, and solve again from the last state until no generator
-    switches.  Returns (y, mode, qt, outer rounds, converged)."""
+    """Newton power flow with reactive limits (Section II-A: the extended
+    formulation serves before and after a PV generator becomes a PQ
+    injection): solve, check the limits, switch, and solve again from the
+    last state until no generator switches.  Returns (y, mode, qt, outer
+    rounds, converged)."""
     y = np.array(y0, dtype=np.float64)
     mode = np.zeros(net.n_pv, np.int32)
     qt = np.zeros(net.n_pv)
@@ -314,8 +316,8 @@ def newton_qlim(net, y0, qmin, qmax, tol=1e-10, max_iter=10, max_outer=10):
 
 def fdlf_matrices(net):
     """Constant matrices of the fast decoupled method, XB variant (the
-    method the paper's conclusion names as another user of the same
-    residual evaluation).  B' (angle step) over the buses without a slack:
+    method Section V names as another user of the same residual
+    evaluation).  B' (angle step) over the buses without a slack:
     per in-service branch the weight 1/x only (resistance, taps, shifts and
     charging left out), so B' is the weighted Laplacian of the network with
     the slack rows and columns removed.  B'' (voltage step) over the buses

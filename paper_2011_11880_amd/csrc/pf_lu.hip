@@ -437,7 +437,7 @@ int pf_newton_device(pf_plan *plan, pf_refact *rf, double *x, const pf_newton_op
 }  // extern "C"
 
 // ===========================================================================
-// Fast decoupled power flow, XB variant (the conclusion names the method as
+// Fast decoupled power flow, XB variant (Section V names the method as
 // another user of the same residual evaluation).  The constant matrices
 // B' (angle step, over the buses without a slack) and B'' (voltage step, over
 // the buses without a voltage controller) are built here from the network
