@@ -209,3 +209,28 @@ def test_one_instance_multi_grid_newton(ora, cuda):
         y, norms, _ = ora.newton(net, y0, tol=1e-10, max_iter=12)
         assert norms[-1] < 1e-10
         np.testing.assert_allclose(xh[mp.x_off[g]:mp.x_off[g + 1]], y, rtol=0, atol=1e-9)
+
+
+def test_one_instance_failure_paths(ora, cuda):
+    """A single-instance plan's Newton on its own factorisation: a
+    factorisation of another plan is refused, a start that does not converge
+    in the allowed steps reports it without error, and a NaN state gives a
+    NaN norm."""
+    from paper_2011_11880_amd.api import Plan
+    from paper_2011_11880_amd.capi import PF_EINVAL, PFError
+    net = synth.tiny_grid(12)
+    p, q = Plan(net), Plan(net)
+    y = synth.random_states(net, seed=5)
+    x = torch.from_numpy(y).to(cuda)
+    lu_q = q.batch_lu(x)
+    with pytest.raises(PFError) as ei:
+        p.newton_batch(x, lu_q)
+    assert ei.value.code == PF_EINVAL
+    rep = q.newton_batch(x, lu_q, max_iter=1)
+    assert rep["n_converged"] == 0 and rep["iterations"] == 1
+    y[3] = np.nan
+    x = torch.from_numpy(y).to(cuda)
+    rep = q.newton_batch(x, lu_q, max_iter=1)
+    assert np.isnan(rep["inst_norm"][0]) and np.isnan(rep["norms"][0])
+    q.close()
+    assert lu_q._h is None

@@ -268,3 +268,16 @@ def test_refact_rejects_pattern_without_fill(ora):
     assert rc == capi.PF_EINVAL and "fill" in msg
     rc, msg, _ = _create(plan, M.data, trp, tci, tv, pivP, pivQ)
     assert rc == capi.PF_EINVAL and "host-only" in msg
+
+
+def test_batch_lu_binding_refusals():
+    """The binding refuses, before any device work, a panel-layout plan and
+    an instance other than 0 of a single-instance plan."""
+    from paper_2011_11880_amd.api import BatchLU
+    net = synth.tiny_grid(4)
+    panels = Plan(net, host_only=True, batch=dict(n_inst=3, layout="panels"))
+    with pytest.raises(ValueError, match="row layout"):
+        BatchLU(panels, None)
+    single = Plan(net, host_only=True)
+    with pytest.raises(ValueError, match="instance 0"):
+        BatchLU(single, None, inst=1)
