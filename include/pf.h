@@ -384,6 +384,10 @@ int pf_q_limit_check(pf_plan *plan, const double *x, const double *q_min,
  * T = (L - I) + U and the row and column orders; rocSOLVER's sparse
  * re-factorisation (csrrf) then factorises every later Jacobian of the plan
  * on the device along that pattern, without pivoting again, and solves there.
+ * (pf_batch_lu_create and pf_newton_batch below give the same Newton on this
+ * library's own factorisation, with the plan as one instance; they are faster
+ * on sparse factors, and rocSOLVER remains for factors whose rows are too
+ * long for them.)
  *
  * pf_refact_create: host inputs, read during the call only.
  *   Jval_host  [nnz]   the values of M in pf_pattern order
