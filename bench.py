@@ -177,6 +177,20 @@ def cpu_baseline_parallel(base, items, seconds, what):
                       f"{workers} processes, at most {seconds:.0f} s each"}
 
 
+def cpu_baseline_solve(run, what):
+    """The CPU oracle's own solver loop (plain-C evaluation, scipy's sparse
+    LU) timed once on the same case, one core.  ``run(O)`` returns the
+    number of iterations and the final largest mismatch."""
+    from oracle import oracle as O
+    O.build()
+    t0 = time.perf_counter()
+    its, final = run(O)
+    dt = time.perf_counter() - t0
+    return {"total_ms": dt * 1e3, "iterations": int(its), "final_mismatch": float(final),
+            "cores": 1,
+            "kind": "oracle", "sample": what}
+
+
 def run_c1(args, torch, dev):
     from paper_2011_11880_amd import synth
     from paper_2011_11880_amd.api import Plan
@@ -419,7 +433,7 @@ def run_c2(args, torch, dev, **kw):
         log("[bench] c2 CPU oracle over instances")
         items = [(ls[k] if k < 512 else None, ps[k] if k < 512 else None, int(out[k]), Y[k])
                  for k in range(I)]
-        res["cpu_oracle"] = cpu_baseline_parallel(net, items, 8.0, "instances")
+        res["cpu_baseline"] = cpu_baseline_parallel(net, items, 8.0, "instances")
     return res
 
 
@@ -443,7 +457,7 @@ def run_c3(args, torch, dev, **kw):
         log("[bench] c3 CPU oracle over grids")
         off = np.cumsum([0] + [n.n_var for n in nets])
         items = [(n, xs[off[g]:off[g + 1]]) for g, n in enumerate(nets)]
-        res["cpu_oracle"] = cpu_baseline_parallel(None, items, 8.0, "grids")
+        res["cpu_baseline"] = cpu_baseline_parallel(None, items, 8.0, "grids")
     return res
 
 
@@ -545,7 +559,17 @@ def run_fdlf(args, torch, dev, **kw):
     p.newton_device(xn, lu)
     xn = torch.from_numpy(y0).to(dev)
     rn = p.newton_device(xn, lu)
+    cpu = None
+    if not getattr(args, "no_cpu", False):
+        log("[bench] fdlf: the oracle's fast decoupled method on the same case")
+
+        def ora_fdlf(O):
+            _, norms, iters = O.fdlf(net, y0, tol=1e-10, max_iter=60)
+            return len(iters) - 1, norms[-1]
+        cpu = cpu_baseline_solve(ora_fdlf, "the oracle's fast decoupled method (plain-C "
+                                 "residuals, scipy LUs of B' and B'' once) on the same case")
     return {"grid": "70,000 buses, 175,000 branches (meshed), R/X 0.05..0.3",
+            "cpu_baseline": cpu,
             "n": p.n, "nnz_bp": int(Bp.nnz), "nnz_bpp": int(Bpp.nnz),
             "setup_s": r0["t_setup_s"],
             "fdlf": {"iterations": it, "converged": r["converged"], "final_norm": r["norms"][-1],
@@ -624,7 +648,17 @@ def run_newton(args, torch, dev, **kw):
                      "iterations": [rr["iterations"] for rr in r["rounds"]],
                      "total_ms": (t1 - t0) * 1e3}
     pq.close()
+    cpu = None
+    if not getattr(args, "no_cpu", False):
+        log("[bench] newton: the oracle's Newton on the same case")
+
+        def ora_newton(O):
+            _, norms, _ = O.newton(net, y0, tol=1e-10, max_iter=12)
+            return len(norms) - 1, norms[-1]
+        cpu = cpu_baseline_solve(ora_newton, "the oracle's Newton (plain-C evaluation, "
+                                 "scipy SuperLU each iteration) on the same case")
     return {"grid": "70,000 buses, 88,207 branches, zero loads on empty buses",
+            "cpu_baseline": cpu,
             "n": p.n, "nnz": p.nnz, "nnz_lu": lu.nnzT, "host_lu_s": t_lu,
             "device": {"iterations": it, "converged": rep["converged"],
                        "final_norm": rep["norms"][-1], "max_error_vs_solution": err,
@@ -760,6 +794,23 @@ def run_newton_batch(args, torch, dev, **kw):
     per_inst_ms = float(np.mean(t_one)) * 1e3
     per_own_ms = float(np.mean(t_own)) * 1e3
     best_ms = min(per_inst_ms, per_own_ms)
+    cpu = None
+    if not getattr(args, "no_cpu", False):
+        log("[bench] newton batch: the oracle's Newton on the sampled outages")
+        from oracle import oracle as O
+        O.build()
+        t_ora, it_ora = [], []
+        for i in sample:
+            v = net.without_branch(int(out[i]))
+            t0 = time.perf_counter()
+            _, norms, _ = O.newton(v, ystar, tol=1e-10, max_iter=12)
+            t_ora.append(time.perf_counter() - t0)
+            it_ora.append(len(norms) - 1)
+        cpu = {"mean_ms_per_instance": float(np.mean(t_ora)) * 1e3,
+               "extrapolated_total_ms": float(np.mean(t_ora)) * 1e3 * I,
+               "mean_iterations": float(np.mean(it_ora)), "cores": 1, "kind": "oracle",
+               "sample": f"the oracle's Newton (plain-C evaluation, scipy SuperLU each "
+                         f"iteration) on the same {len(sample)} outages"}
     return {"grid": "10,000 buses, 12,500 branches; base case solved, 1024 N-1 outages",
             "instances": I, "nnz_lu": r["nnz_lu"], "host_lu_s": t_lu,
             "batched": {"iterations": it, "n_converged": r["n_converged"],
@@ -776,6 +827,7 @@ def run_newton_batch(args, torch, dev, **kw):
                                              "mean_iterations": float(np.mean(it_own)),
                                              "mean_ms_per_instance": per_own_ms,
                                              "extrapolated_total_ms": per_own_ms * I},
+            "cpu_baseline": cpu,
             "speedup": best_ms * I / (r["t_total_s"] * 1e3),
             "speedup_vs_rocsolver_one_by_one": per_inst_ms * I / (r["t_total_s"] * 1e3)}
 
