@@ -1,6 +1,7 @@
 """Host-side checks of the benchmark script and the profile summary tool
 (CPU only): the one-GPU guard, the multi-process oracle baseline over
-independent instances, and per-dispatch counter averages."""
+independent instances, the one-core oracle solver baseline, and per-dispatch
+counter averages."""
 
 import os
 import sqlite3
@@ -58,3 +59,21 @@ def test_counter_summary_averages_per_dispatch(tmp_path):
     # per dispatch, values of one counter are summed (over the device's units)
     assert out["FETCH_SIZE"] == ((16.0 + 20.0) / 2, 2)
     assert out["SQ_WAVES"] == (6.0, 2)
+
+
+def test_solver_baseline_reports_the_oracle_loop():
+    sys.path.insert(0, ROOT)
+    import bench
+    net = synth.tiny_grid(3)
+    y0 = synth.random_states(net, seed=4)
+    calls = []
+
+    def run(O):
+        calls.append(O)
+        _, norms, _ = O.newton(net, y0, tol=1e-10, max_iter=3)
+        return len(norms) - 1, norms[-1]
+    r = bench.cpu_baseline_solve(run, "oracle Newton on the tiny grid")
+    assert len(calls) == 1 and calls[0].__name__ == "oracle.oracle"
+    assert r["kind"] == "oracle" and r["cores"] == 1 and r["total_ms"] > 0
+    assert 0 <= r["iterations"] <= 3 and np.isfinite(r["final_mismatch"])
+    assert r["sample"] == "oracle Newton on the tiny grid"
