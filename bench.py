@@ -427,6 +427,8 @@ def run_c2(args, torch, dev, **kw):
            "batched_ms": ms, "batched_evals_per_s": I / (ms * 1e-3),
            "batched_gbs": nb / (ms * 1e-3) / 1e9,
            "batched_hbm_frac": nb / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS,
+           "batched_bytes_per_launch": nb,
+           "batched_traffic": measured_traffic("k_eval_batch_10k_x1024_traffic.json", I),
            "plain_us_per_eval": ms_p * 1e3, "plain_evals_per_s": 1e3 / ms_p,
            "batched_over_plain": (I / ms) / (1.0 / ms_p), "schedule": bp.schedule}
     if not getattr(args, "no_cpu", False):
@@ -452,7 +454,9 @@ def run_c3(args, torch, dev, **kw):
     nb = per_eval_bytes(mp.n, mp.nnz) + statics_bytes(mp.info)
     res = {"grids": 256, "buses": int(sum(n.n_bus for n in nets)), "n": mp.n, "nnz": mp.nnz,
            "ms": ms, "grid_evals_per_s": 256 / (ms * 1e-3), "gbs": nb / (ms * 1e-3) / 1e9,
-           "hbm_frac": nb / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS, "autotuned_schedule": best}
+           "hbm_frac": nb / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS, "bytes_per_launch": nb,
+           "traffic": measured_traffic("k_eval_single_256_uneven_grids_traffic.json", 1),
+           "autotuned_schedule": best}
     if not getattr(args, "no_cpu", False):
         log("[bench] c3 CPU oracle over grids")
         off = np.cumsum([0] + [n.n_var for n in nets])

@@ -9,10 +9,12 @@
 
   python -m paper_2011_11880_amd.rocprof_summary traffic \
         --fetch F.db --write W.db --copy-fetch CF.db --copy-write CW.db \
-        --kernel NAME --copy-bytes BYTES --units U --out FILE.json
+        --kernel NAME --copy-bytes BYTES --units U --out FILE.json [--last N]
       HBM bytes per dispatch of a kernel from FETCH_SIZE / WRITE_SIZE runs,
       each scaled by what the same counter reads for a plain copy kernel of
-      known size (copy_bytes read and copy_bytes written per dispatch)
+      known size (copy_bytes read and copy_bytes written per dispatch);
+      --last N averages only the kernel's last N dispatches (the timed
+      launches of a run that autotunes first)
 """
 
 from __future__ import annotations
@@ -42,12 +44,15 @@ def kernel_stats(db, match=None):
     return out
 
 
-def counter_per_dispatch(db, counter, match):
+def counter_per_dispatch(db, counter, match, last=None):
     c = sqlite3.connect(db)
     rows = c.execute("select kernel_name, dispatch_id, sum(value) from counters_collection "
                      "where counter_name = ? group by kernel_name, dispatch_id",
                      (counter,)).fetchall()
-    vals = [v for name, _, v in rows if match in name]
+    rows = sorted((d, v) for name, d, v in rows if match in name)
+    if last:
+        rows = rows[-last:]
+    vals = [v for _, v in rows]
     if not vals:
         raise SystemExit(f"no {counter} rows for kernels matching {match!r} in {db}")
     return sum(vals) / len(vals), len(vals)
@@ -69,8 +74,8 @@ def counters(db, match):
 def traffic(a):
     from .build import kernel_source_hash
     kib = 1024.0
-    f_k, nf = counter_per_dispatch(a.fetch, "FETCH_SIZE", a.kernel)
-    w_k, nw = counter_per_dispatch(a.write, "WRITE_SIZE", a.kernel)
+    f_k, nf = counter_per_dispatch(a.fetch, "FETCH_SIZE", a.kernel, a.last)
+    w_k, nw = counter_per_dispatch(a.write, "WRITE_SIZE", a.kernel, a.last)
     f_c, _ = counter_per_dispatch(a.copy_fetch, "FETCH_SIZE", a.copy_kernel)
     w_c, _ = counter_per_dispatch(a.copy_write, "WRITE_SIZE", a.copy_kernel)
     sf = a.copy_bytes / (f_c * kib)
@@ -106,6 +111,7 @@ def main(argv=None):
     t.add_argument("--copy-kernel", default="copyBuffer")
     t.add_argument("--copy-bytes", type=int, required=True)
     t.add_argument("--units", type=int, required=True)
+    t.add_argument("--last", type=int, default=None)
     a = ap.parse_args(argv)
     if a.cmd == "counters":
         for k, (avg, nd) in counters(a.db, a.match).items():

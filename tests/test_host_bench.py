@@ -77,3 +77,20 @@ def test_solver_baseline_reports_the_oracle_loop():
     assert r["kind"] == "oracle" and r["cores"] == 1 and r["total_ms"] > 0
     assert 0 <= r["iterations"] <= 3 and np.isfinite(r["final_mismatch"])
     assert r["sample"] == "oracle Newton on the tiny grid"
+
+
+def test_traffic_counter_takes_the_last_dispatches(tmp_path):
+    from paper_2011_11880_amd import rocprof_summary as R
+    db = tmp_path / "run_results.db"
+    c = sqlite3.connect(db)
+    c.execute("create table counters_collection (kernel_name text, dispatch_id int, "
+              "counter_name text, value real)")
+    # an autotuning phase (dispatches 1-3) before two timed launches (7, 9)
+    rows = [("k_a(int)", d, "WRITE_SIZE", v) for d, v in
+            ((1, 50.0), (2, 70.0), (3, 90.0), (7, 10.0), (9, 4.0), (9, 8.0))]
+    rows.append(("k_b(int)", 8, "WRITE_SIZE", 1000.0))
+    c.executemany("insert into counters_collection values (?, ?, ?, ?)", rows)
+    c.commit()
+    c.close()
+    assert R.counter_per_dispatch(str(db), "WRITE_SIZE", "k_a", last=2) == (11.0, 2)
+    assert R.counter_per_dispatch(str(db), "WRITE_SIZE", "k_a") == ((50 + 70 + 90 + 10 + 12) / 5, 5)
