@@ -497,6 +497,126 @@ k_eval_batch(int N, int I, int LD, int panel, int64_t rows_x, int64_t rows_j, in
         // masked lanes read a valid duplicate address so loads need no
         // masking (a panel is always 64 columns wide)
         const size_t kk = panel ? kq : size_t(valid ? k : I - 1);
+        constexpr int EU = 4;
+        if constexpr (!SCEN && !OUTG) {
+            // Without an overlay, every vector load of a row (own state,
+            // generator variables, the first EU partners) is issued before the
+            // row's first store. A wavefront's loads complete in order behind
+            // its earlier stores, so a load issued after a store also waits for
+            // that store's write. The overlay walk below instead fetches the
+            // next row's header and state one row ahead: it keeps fewer
+            // registers live there, and measured faster for it.
+            for (int qq = q0; qq < q1; ++qq) {
+                const int b = order[qq];
+                const int4 bi = bus4[b];
+                const int2 b2 = bus2[b];
+                const int L = bi.y - bi.x;
+                const double thi = Xc[size_t(b) * SI + kk];
+                const double vi = Xc[size_t(N + b) * SI + kk];
+                int4 g4 = make_int4(0, 0, 0, 0);
+                double2 gs = make_double2(0.0, 0.0);
+                double qg = 0.0, ps = 0.0;
+                if (b2.y >= 0) {
+                    g4 = gen4[b2.y];
+                    gs = gen2[b2.y];
+                    qg = Xc[size_t(g4.x) * SI + kk];
+                    if (g4.z >= 0) ps = Xc[size_t(g4.z) * SI + kk];
+                }
+                // entry arrays carry kEntryPad trailing entries, so the first
+                // group's coefficients are read unconditionally
+                int jj[EU];
+                double GG[EU], BB[EU], thj[EU], vj[EU];
+#pragma unroll
+                for (int u = 0; u < EU; ++u) {
+                    jj[u] = ycol[bi.x + u] & kColMask;
+                    GG[u] = yG[bi.x + u];
+                    BB[u] = yB[bi.x + u];
+                }
+#pragma unroll
+                for (int u = 0; u < EU; ++u) {
+                    if (u < L) {
+                        thj[u] = Xc[size_t(jj[u]) * SI + kk];
+                        vj[u] = Xc[size_t(N + jj[u]) * SI + kk];
+                    }
+                }
+                double a[6] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
+                auto entry = [&](int p, int j, double G, double Bv, double tj, double vjj) {
+                    const bool diag = (j == b);
+                    double c[6], o[4];
+                    entry_eval(diag, G, Bv, thi, vi, tj, vjj, c, o);
+                    if (WJ && !diag && valid) {
+                        st(&Jc[size_t(bi.z + p) * SI + kq], o[0]);
+                        st(&Jc[size_t(bi.z + L + p) * SI + kq], o[1]);
+                        st(&Jc[size_t(bi.w + p) * SI + kq], o[2]);
+                        st(&Jc[size_t(bi.w + L + p) * SI + kq], o[3]);
+                    }
+#pragma unroll
+                    for (int q = 0; q < 6; ++q) a[q] += c[q];
+                };
+#pragma unroll
+                for (int u = 0; u < EU; ++u) {
+                    if (u >= L) break;
+                    entry(u, jj[u], GG[u], BB[u], thj[u], vj[u]);
+                }
+                // a longer row continues in groups of EU
+                for (int e0 = bi.x + EU; e0 < bi.y; e0 += EU) {
+                    int j2[EU];
+                    double G2[EU], B2[EU], t2[EU], v2[EU];
+#pragma unroll
+                    for (int u = 0; u < EU; ++u) {
+                        j2[u] = ycol[e0 + u] & kColMask;
+                        G2[u] = yG[e0 + u];
+                        B2[u] = yB[e0 + u];
+                    }
+#pragma unroll
+                    for (int u = 0; u < EU; ++u) {
+                        if (e0 + u < bi.y) {
+                            t2[u] = Xc[size_t(j2[u]) * SI + kk];
+                            v2[u] = Xc[size_t(N + j2[u]) * SI + kk];
+                        }
+                    }
+#pragma unroll
+                    for (int u = 0; u < EU; ++u) {
+                        if (e0 + u >= bi.y) break;
+                        entry(e0 + u - bi.x, j2[u], G2[u], B2[u], t2[u], v2[u]);
+                    }
+                }
+                if (!valid) continue;
+                const double2 sp = spec[b];
+                double fp = a[0] + sp.x;
+                double fq = a[1] + sp.y;
+                if (b2.y >= 0) {
+                    const bool held = g4.z == kGenHeld;
+                    fq = fq - qg;
+                    if (WF) st(&Fc[size_t(g4.x) * SI + kq], held ? qg - gs.x : vi - gs.x);
+                    if (WJ) {
+                        st(&Jc[size_t(bi.w + 2 * L) * SI + kq], -1.0);
+                        st(&Jc[size_t(g4.y) * SI + kq], held ? 0.0 : 1.0);
+                        if (g4.z <= kGenVoltageSlot)
+                            st(&Jc[size_t(g4.y + 1) * SI + kq], held ? 1.0 : 0.0);
+                    }
+                    if (g4.z >= 0) {
+                        fp = fp - ps;
+                        if (WF) st(&Fc[size_t(g4.z) * SI + kq], thi - gs.y);
+                        if (WJ) {
+                            st(&Jc[size_t(bi.z + 2 * L) * SI + kq], -1.0);
+                            st(&Jc[size_t(g4.w) * SI + kq], 1.0);
+                        }
+                    }
+                }
+                if (WF) {
+                    st(&Fc[size_t(b) * SI + kq], fp);
+                    st(&Fc[size_t(N + b) * SI + kq], fq);
+                }
+                if (WJ) {
+                    st(&Jc[size_t(bi.z + b2.x) * SI + kq], a[2]);
+                    st(&Jc[size_t(bi.z + L + b2.x) * SI + kq], a[3]);
+                    st(&Jc[size_t(bi.w + b2.x) * SI + kq], a[4]);
+                    st(&Jc[size_t(bi.w + L + b2.x) * SI + kq], a[5]);
+                }
+            }
+            continue;
+        }
         // the next bus's row header and own state are fetched one bus ahead
         int b_nx = order[q0];
         int4 bi_nx = bus4[b_nx];
@@ -529,7 +649,6 @@ k_eval_batch(int N, int I, int LD, int panel, int64_t rows_x, int64_t rows_j, in
             double a[6] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
             // entries in groups of EU: all gathers of a group are issued
             // before any of its arithmetic, so they are in flight together
-            constexpr int EU = 4;
             for (int e0 = bi.x; e0 < bi.y; e0 += EU) {
                 int jj[EU];
                 double GG[EU], BB[EU], thj[EU], vj[EU];
