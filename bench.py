@@ -114,6 +114,20 @@ def measured_traffic(name, launch_units):
     return d.get("hbm_bytes_per_launch")
 
 
+def host_cpu():
+    """The host the CPU baselines ran on: usable cores and the processor model."""
+    model = None
+    try:
+        with open("/proc/cpuinfo") as fh:
+            for line in fh:
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    return {"usable_cores": len(os.sched_getaffinity(0)), "cpus": os.cpu_count(), "model": model}
+
+
 def cpu_baseline(net, states, seconds=12.0, max_states=200):
     """The CPU oracle (plain C + scipy triplet assembly) on a bounded sample."""
     from oracle import oracle as O
@@ -129,7 +143,8 @@ def cpu_baseline(net, states, seconds=12.0, max_states=200):
     dt = time.perf_counter() - t0
     return {"value": n_done / dt, "unit": "evals/s", "cores": 1, "kind": "oracle",
             "sample": f"{n_done} of the {len(states)} states, residual + Jacobian "
-                      f"(triplets summed into CSR), {dt:.1f} s"}
+                      f"(triplets summed into CSR), {dt:.1f} s",
+            "host": host_cpu()}
 
 
 def _oracle_share(task):
@@ -174,7 +189,8 @@ def cpu_baseline_parallel(base, items, seconds, what):
     rate = sum(r[0] / r[1] for r in res if r[1] > 0)
     return {"value": rate, "unit": "evals/s", "cores": workers, "kind": "oracle",
             "sample": f"{done} of the {len(items)} {what}, residual + Jacobian, "
-                      f"{workers} processes, at most {seconds:.0f} s each"}
+                      f"{workers} processes, at most {seconds:.0f} s each",
+            "host": host_cpu()}
 
 
 def cpu_baseline_solve(run, what):

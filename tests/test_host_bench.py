@@ -94,3 +94,11 @@ def test_traffic_counter_takes_the_last_dispatches(tmp_path):
     c.close()
     assert R.counter_per_dispatch(str(db), "WRITE_SIZE", "k_a", last=2) == (11.0, 2)
     assert R.counter_per_dispatch(str(db), "WRITE_SIZE", "k_a") == ((50 + 70 + 90 + 10 + 12) / 5, 5)
+
+
+def test_host_cpu_record():
+    sys.path.insert(0, ROOT)
+    import bench
+    h = bench.host_cpu()
+    assert 1 <= h["usable_cores"] <= h["cpus"]
+    assert h["model"] is None or isinstance(h["model"], str)
