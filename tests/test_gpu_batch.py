@@ -1,8 +1,9 @@
 """GPU parity of the batched kernel (pf_eval_batch): random states as
 instances (bit-identical to the single-instance kernel), load/PV scenario
 overlays and N-1 outages (against the oracle on the modified network),
-ragged instance counts, schedule invariance, graph replay, and the
-10,000-bus x 1024-instance batch on sampled instances."""
+ragged instance counts, residual-only and Jacobian-only launches, schedule
+invariance, graph replay, and the 10,000-bus x 1024-instance batch on
+sampled instances."""
 
 import numpy as np
 import pytest
@@ -87,6 +88,36 @@ def test_scenarios_and_outages_vs_oracle(ora, cuda):
         Jo, Ao = ora.jacobian(nk, Y[k])
         check_close(Fb[:, k], Fo, So, f"inst {k} F")
         check_jacobian(rp, ci, Jb[:, k], Jo, Ao, f"inst {k} J")
+
+
+@pytest.mark.parametrize("overlay", [False, True])
+def test_residual_only_and_jacobian_only_equal_fused(cuda, overlay):
+    """The residual-only and Jacobian-only launches write exactly what the
+    fused launch writes, without an overlay and with scenarios and outages,
+    on a grid whose longest admittance rows need more than one group of
+    four entries."""
+    Plan = _Plan()
+    net = _net()
+    pairs = {(min(f, t), max(f, t)) for f, t in zip(net.br_from, net.br_to)}
+    deg = np.bincount(np.array([b for p in pairs for b in p]), minlength=net.n_bus)
+    assert deg.max() + 1 > 4
+    I = 70
+    spec = dict(n_inst=I)
+    if overlay:
+        ls, ps = synth.batch_scenarios(net, I, seed=8)
+        out = np.full(I, -1, np.int32)
+        out[35:] = synth.non_bridge_branches(net)[:I - 35]
+        spec.update(load_scale=ls, pv_scale=ps, outage=out)
+    bp = Plan(net, batch=spec)
+    Y = synth.random_states(net, I, seed=9)
+    X = torch.from_numpy(bp.to_batch(Y)).to(cuda)
+    F0, J0 = bp.eval_batch(X)
+    F1, none_j = bp.eval_batch(X, want_J=False)
+    none_f, J1 = bp.eval_batch(X, want_F=False)
+    torch.cuda.synchronize()
+    assert none_j is None and none_f is None
+    assert np.array_equal(bp.from_batch(F1), bp.from_batch(F0))
+    assert np.array_equal(bp.from_batch(J1), bp.from_batch(J0))
 
 
 def test_outage_slots_are_exact_zero(cuda):
