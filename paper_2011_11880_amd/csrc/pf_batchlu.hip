@@ -49,6 +49,11 @@ struct pf_batch_lu {
     std::vector<int32_t> flev_w, blev_w;      // lanes used per wave (64, 32 or 16) per level
     std::vector<int32_t> flev_maxr;           // longest row per factor level
     std::vector<int32_t> flev_maxi;           // most items of a row per factor level
+    // one instance: runs of consecutive small levels done by one block, as
+    // {first level, end level, waves, LDS bytes per wave} (factorisation) and
+    // {first level, end level, waves} (forward, backward solves)
+    std::vector<int32_t> fchain_factor, fchain_fwd, bchain;
+    int32_t *flev_ptr_d = nullptr, *blev_ptr_d = nullptr;
     // device structure
     int32_t *trp = nullptr;   // n + 1
     int32_t *tci = nullptr;   // nnzT
@@ -111,7 +116,7 @@ void release(pf_batch_lu *b) {
                     (void *)b->item_ptr, (void *)b->item, (void *)b->frows,
                     (void *)b->brows, (void *)b->pivP, (void *)b->pivQ, (void *)b->T,
                     (void *)b->F, (void *)b->J, (void *)b->Y, (void *)b->part, (void *)b->norm,
-                    (void *)b->active})
+                    (void *)b->active, (void *)b->flev_ptr_d, (void *)b->blev_ptr_d})
         if (p) (void)hipFree(p);
     if (b->norm_host) (void)hipHostFree(b->norm_host);
     if (prev >= 0) (void)hipSetDevice(prev);
@@ -203,13 +208,12 @@ __device__ __forceinline__ void wave_sync() {
 // run in order, each step's divide on the wave-uniform value and its updates
 // over the lanes.  A step's updates change distinct entries of the row, so
 // every result equals that of the one-lane loop of k_blu_factor.
-__global__ void __launch_bounds__(64) k_blu_factor1(
-    const int32_t *__restrict__ rows, const int32_t *__restrict__ trp,
-    const int32_t *__restrict__ tsrc, const int32_t *__restrict__ item_ptr,
-    const int2 *__restrict__ item, const double *__restrict__ J, double *__restrict__ T) {
-    extern __shared__ double sm[];
-    const int lane = threadIdx.x;
-    const int r = rows[blockIdx.x];
+__device__ __forceinline__ void factor_row1(int r, int lane, const int32_t *__restrict__ trp,
+                                            const int32_t *__restrict__ tsrc,
+                                            const int32_t *__restrict__ item_ptr,
+                                            const int2 *__restrict__ item,
+                                            const double *__restrict__ J, double *__restrict__ T,
+                                            double *sm) {
     const int r0 = trp[r], R = trp[r + 1] - r0;
     const int i0 = item_ptr[r], NI = item_ptr[r + 1] - i0;
     double *Lrow = sm;
@@ -249,6 +253,38 @@ __global__ void __launch_bounds__(64) k_blu_factor1(
         q = next;
     }
     for (int q2 = lane; q2 < R; q2 += 64) T[r0 + q2] = Lrow[q2];
+}
+
+__global__ void __launch_bounds__(64) k_blu_factor1(
+    const int32_t *__restrict__ rows, const int32_t *__restrict__ trp,
+    const int32_t *__restrict__ tsrc, const int32_t *__restrict__ item_ptr,
+    const int2 *__restrict__ item, const double *__restrict__ J, double *__restrict__ T) {
+    extern __shared__ double sm[];
+    factor_row1(rows[blockIdx.x], threadIdx.x, trp, tsrc, item_ptr, item, J, T, sm);
+}
+
+// Levels with this many rows or fewer, when consecutive, run in one block:
+// wavefront w takes row w of each level, and a block barrier separates the
+// levels (a row reads only rows of earlier levels, whose writes the barrier
+// makes visible to the block).  This saves a launch per level where the
+// levels are small.
+constexpr int kChainRows = 16;
+
+__global__ void __launch_bounds__(64 * kChainRows) k_blu_factor1_chain(
+    int l0, int l1, const int32_t *__restrict__ lev_ptr, const int32_t *__restrict__ rows,
+    int stride, const int32_t *__restrict__ trp, const int32_t *__restrict__ tsrc,
+    const int32_t *__restrict__ item_ptr, const int2 *__restrict__ item,
+    const double *__restrict__ J, double *__restrict__ T) {
+    extern __shared__ double sm[];
+    const int lane = threadIdx.x & 63;
+    const int wv = threadIdx.x >> 6;
+    for (int l = l0; l < l1; ++l) {
+        const int q0 = lev_ptr[l];
+        if (wv < lev_ptr[l + 1] - q0)
+            factor_row1(rows[q0 + wv], lane, trp, tsrc, item_ptr, item, J, T,
+                        sm + size_t(wv) * size_t(stride));
+        __syncthreads();
+    }
 }
 
 // forward: Y[r] = F[pivP[r]] - sum_{k < r} t_rk Y[k]
@@ -317,29 +353,70 @@ __device__ __forceinline__ double wave_sum(double p) {
     return p;
 }
 
-__global__ void __launch_bounds__(64) k_blu_fwd1(
-    const int32_t *__restrict__ rows, const int32_t *__restrict__ trp,
-    const int32_t *__restrict__ tci, const int32_t *__restrict__ tdiag,
-    const int32_t *__restrict__ pivP, const double *__restrict__ T,
-    const double *__restrict__ F, double *__restrict__ Y) {
-    const int lane = threadIdx.x;
-    const int r = rows[blockIdx.x];
+__device__ __forceinline__ void fwd_row1(int r, int lane, const int32_t *__restrict__ trp,
+                                         const int32_t *__restrict__ tci,
+                                         const int32_t *__restrict__ tdiag,
+                                         const int32_t *__restrict__ pivP,
+                                         const double *__restrict__ T,
+                                         const double *__restrict__ F, double *__restrict__ Y) {
     double p = 0.0;
     for (int e = trp[r] + lane; e < tdiag[r]; e += 64) p = fma(T[e], Y[tci[e]], p);
     p = wave_sum(p);
     if (lane == 0) Y[r] = F[pivP[r]] - p;
 }
 
-__global__ void __launch_bounds__(64) k_blu_bwd1(
-    const int32_t *__restrict__ rows, const int32_t *__restrict__ trp,
-    const int32_t *__restrict__ tci, const int32_t *__restrict__ tdiag,
-    const double *__restrict__ T, double *__restrict__ Y) {
-    const int lane = threadIdx.x;
-    const int r = rows[blockIdx.x];
+__device__ __forceinline__ void bwd_row1(int r, int lane, const int32_t *__restrict__ trp,
+                                         const int32_t *__restrict__ tci,
+                                         const int32_t *__restrict__ tdiag,
+                                         const double *__restrict__ T, double *__restrict__ Y) {
     double p = 0.0;
     for (int e = tdiag[r] + 1 + lane; e < trp[r + 1]; e += 64) p = fma(T[e], Y[tci[e]], p);
     p = wave_sum(p);
     if (lane == 0) Y[r] = (Y[r] - p) / T[tdiag[r]];
+}
+
+__global__ void __launch_bounds__(64) k_blu_fwd1(
+    const int32_t *__restrict__ rows, const int32_t *__restrict__ trp,
+    const int32_t *__restrict__ tci, const int32_t *__restrict__ tdiag,
+    const int32_t *__restrict__ pivP, const double *__restrict__ T,
+    const double *__restrict__ F, double *__restrict__ Y) {
+    fwd_row1(rows[blockIdx.x], threadIdx.x, trp, tci, tdiag, pivP, T, F, Y);
+}
+
+__global__ void __launch_bounds__(64) k_blu_bwd1(
+    const int32_t *__restrict__ rows, const int32_t *__restrict__ trp,
+    const int32_t *__restrict__ tci, const int32_t *__restrict__ tdiag,
+    const double *__restrict__ T, double *__restrict__ Y) {
+    bwd_row1(rows[blockIdx.x], threadIdx.x, trp, tci, tdiag, T, Y);
+}
+
+// Runs of small consecutive solve levels in one block (as for the
+// factorisation): wavefront w takes row w of each level.
+__global__ void __launch_bounds__(64 * kChainRows) k_blu_fwd1_chain(
+    int l0, int l1, const int32_t *__restrict__ lev_ptr, const int32_t *__restrict__ rows,
+    const int32_t *__restrict__ trp, const int32_t *__restrict__ tci,
+    const int32_t *__restrict__ tdiag, const int32_t *__restrict__ pivP,
+    const double *__restrict__ T, const double *__restrict__ F, double *__restrict__ Y) {
+    const int lane = threadIdx.x & 63;
+    const int wv = threadIdx.x >> 6;
+    for (int l = l0; l < l1; ++l) {
+        const int q0 = lev_ptr[l];
+        if (wv < lev_ptr[l + 1] - q0) fwd_row1(rows[q0 + wv], lane, trp, tci, tdiag, pivP, T, F, Y);
+        __syncthreads();
+    }
+}
+
+__global__ void __launch_bounds__(64 * kChainRows) k_blu_bwd1_chain(
+    int l0, int l1, const int32_t *__restrict__ lev_ptr, const int32_t *__restrict__ rows,
+    const int32_t *__restrict__ trp, const int32_t *__restrict__ tci,
+    const int32_t *__restrict__ tdiag, const double *__restrict__ T, double *__restrict__ Y) {
+    const int lane = threadIdx.x & 63;
+    const int wv = threadIdx.x >> 6;
+    for (int l = l0; l < l1; ++l) {
+        const int q0 = lev_ptr[l];
+        if (wv < lev_ptr[l + 1] - q0) bwd_row1(rows[q0 + wv], lane, trp, tci, tdiag, T, Y);
+        __syncthreads();
+    }
 }
 
 // x[pivQ[k]] -= z[k] for active instances (subtract = 1), or x[pivQ[k]] = z[k]
@@ -495,6 +572,52 @@ int build(pf_batch_lu *b, const HostPlan &hp, int64_t nnzT, const int32_t *trp,
             return fail(PF_EINVAL, "a row of T has %d entries: too long for the batched factorisation", maxr);
     }
     b->blev_w.assign(b->blev_ptr.size() - 1, 64);
+    if (b->n_inst == 1 && b->ld == 1) {
+        auto nrows = [](const std::vector<int32_t> &ptr, size_t l) { return ptr[l + 1] - ptr[l]; };
+        // LDS of a factorisation level's row, in doubles per wavefront
+        auto lds_of = [&](size_t l) {
+            const size_t bytes = size_t(b->flev_maxr[l] + b->flev_maxi[l]) * sizeof(double) +
+                                 size_t(b->flev_maxi[l]) * sizeof(int32_t);
+            return (bytes + sizeof(double) - 1) / sizeof(double);
+        };
+        // factorisation: runs of small levels whose rows fit the block's LDS together
+        for (size_t l = 0; l < nfl;) {
+            size_t e = l;
+            int w = 0;
+            size_t stride = 0;
+            while (e < nfl && nrows(b->flev_ptr, e) <= kChainRows) {
+                const int w2 = std::max(w, nrows(b->flev_ptr, e));
+                const size_t s2 = std::max(stride, lds_of(e));
+                if (size_t(w2) * s2 * sizeof(double) > lds_limit) break;
+                w = w2;
+                stride = s2;
+                ++e;
+            }
+            if (e - l >= 2) {
+                b->fchain_factor.insert(b->fchain_factor.end(),
+                                        {int32_t(l), int32_t(e), int32_t(w), int32_t(stride)});
+                l = e;
+            } else {
+                l = std::max(e, l + 1);
+            }
+        }
+        auto solve_runs = [&](const std::vector<int32_t> &ptr, std::vector<int32_t> &out) {
+            const size_t nl = ptr.size() - 1;
+            for (size_t l = 0; l < nl;) {
+                size_t e = l;
+                int w = 0;
+                while (e < nl && nrows(ptr, e) <= kChainRows) w = std::max(w, nrows(ptr, e++));
+                if (e - l >= 2) {
+                    out.insert(out.end(), {int32_t(l), int32_t(e), int32_t(w)});
+                    l = e;
+                } else {
+                    l = std::max(e, l + 1);
+                }
+            }
+        };
+        solve_runs(b->flev_ptr, b->fchain_fwd);
+        solve_runs(b->blev_ptr, b->bchain);
+    }
     int rc = PF_OK;
     if (!rc) rc = balloc(&b->trp, trp, size_t(n) + 1);
     std::vector<int32_t> tci_pad(tci, tci + nnzT);
@@ -507,6 +630,8 @@ int build(pf_batch_lu *b, const HostPlan &hp, int64_t nnzT, const int32_t *trp,
     if (!rc) rc = balloc(&b->item, item.data(), item.size());
     if (!rc) rc = balloc(&b->frows, frows.data(), frows.size());
     if (!rc) rc = balloc(&b->brows, brows.data(), brows.size());
+    if (!rc) rc = balloc(&b->flev_ptr_d, b->flev_ptr.data(), b->flev_ptr.size());
+    if (!rc) rc = balloc(&b->blev_ptr_d, b->blev_ptr.data(), b->blev_ptr.size());
     if (!rc) rc = balloc(&b->pivP, pivP, size_t(n));
     if (!rc) rc = balloc(&b->pivQ, pivQ, size_t(n));
     return rc;
@@ -514,9 +639,22 @@ int build(pf_batch_lu *b, const HostPlan &hp, int64_t nnzT, const int32_t *trp,
 
 int factor_levels(pf_batch_lu *b, const double *J, hipStream_t st) {
     const int I = b->n_inst, SI = b->ld;
+    const bool one = I == 1 && SI == 1;
+    size_t ci = 0;   // next run of small levels
     for (size_t l = 0; l + 1 < b->flev_ptr.size(); ++l) {
         const int nr = b->flev_ptr[l + 1] - b->flev_ptr[l];
-        if (I == 1 && SI == 1) {   // one instance: lanes spread over the row
+        if (one && ci < b->fchain_factor.size() && size_t(b->fchain_factor[ci]) == l) {
+            const int l1 = b->fchain_factor[ci + 1], w = b->fchain_factor[ci + 2];
+            const int stride = b->fchain_factor[ci + 3];
+            hipLaunchKernelGGL(k_blu_factor1_chain, dim3(1), dim3(unsigned(64 * w)),
+                               size_t(w) * size_t(stride) * sizeof(double), st, int(l), l1,
+                               b->flev_ptr_d, b->frows, stride, b->trp, b->tsrc, b->item_ptr,
+                               b->item, J, b->T);
+            l = size_t(l1) - 1;
+            ci += 4;
+            continue;
+        }
+        if (one) {   // one instance: lanes spread over the row
             const size_t shm1 = size_t(b->flev_maxr[l] + b->flev_maxi[l]) * sizeof(double) +
                                 size_t(b->flev_maxi[l]) * sizeof(int32_t);
             if (shm1 <= b->lds_limit) {
@@ -541,13 +679,33 @@ int solve_levels(pf_batch_lu *b, const double *Fin, double *Y, hipStream_t st) {
     const int I = b->n_inst, SI = b->ld;
     const int nc = (I + 63) / 64;
     if (I == 1 && SI == 1) {   // one instance: lanes over each row's entries
+        size_t ci = 0;   // next run of small levels
         for (size_t l = 0; l + 1 < b->flev_ptr.size(); ++l) {
+            if (ci < b->fchain_fwd.size() && size_t(b->fchain_fwd[ci]) == l) {
+                const int l1 = b->fchain_fwd[ci + 1], w = b->fchain_fwd[ci + 2];
+                hipLaunchKernelGGL(k_blu_fwd1_chain, dim3(1), dim3(unsigned(64 * w)), 0, st,
+                                   int(l), l1, b->flev_ptr_d, b->frows, b->trp, b->tci, b->tdiag,
+                                   b->pivP, b->T, Fin, Y);
+                l = size_t(l1) - 1;
+                ci += 3;
+                continue;
+            }
             const int nr = b->flev_ptr[l + 1] - b->flev_ptr[l];
             hipLaunchKernelGGL(k_blu_fwd1, dim3(unsigned(nr)), dim3(64), 0, st,
                                b->frows + b->flev_ptr[l], b->trp, b->tci, b->tdiag, b->pivP,
                                b->T, Fin, Y);
         }
+        ci = 0;
         for (size_t l = 0; l + 1 < b->blev_ptr.size(); ++l) {
+            if (ci < b->bchain.size() && size_t(b->bchain[ci]) == l) {
+                const int l1 = b->bchain[ci + 1], w = b->bchain[ci + 2];
+                hipLaunchKernelGGL(k_blu_bwd1_chain, dim3(1), dim3(unsigned(64 * w)), 0, st,
+                                   int(l), l1, b->blev_ptr_d, b->brows, b->trp, b->tci, b->tdiag,
+                                   b->T, Y);
+                l = size_t(l1) - 1;
+                ci += 3;
+                continue;
+            }
             const int nr = b->blev_ptr[l + 1] - b->blev_ptr[l];
             hipLaunchKernelGGL(k_blu_bwd1, dim3(unsigned(nr)), dim3(64), 0, st,
                                b->brows + b->blev_ptr[l], b->trp, b->tci, b->tdiag, b->T, Y);
@@ -611,6 +769,8 @@ int pf_batch_lu_create(pf_plan *plan, int64_t nnzT, const int32_t *T_rowptr,
     (void)hipFuncSetAttribute(reinterpret_cast<const void *>(&k_blu_factor),
                               hipFuncAttributeMaxDynamicSharedMemorySize, lds);
     (void)hipFuncSetAttribute(reinterpret_cast<const void *>(&k_blu_factor1),
+                              hipFuncAttributeMaxDynamicSharedMemorySize, lds);
+    (void)hipFuncSetAttribute(reinterpret_cast<const void *>(&k_blu_factor1_chain),
                               hipFuncAttributeMaxDynamicSharedMemorySize, lds);
     pf_batch_lu *b = new (std::nothrow) pf_batch_lu();
     if (!b) return fail(PF_ENOMEM, "host allocation failed");
