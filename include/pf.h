@@ -458,9 +458,13 @@ int pf_fdlf_matrices(const pf_plan *plan, int64_t *nnz_bp, int32_t *bp_rowptr,
 /*
  * A constant sparse factorisation on the device: the n x n CSR matrix M and
  * one host LU of it (P M Q = L U in the form pf_refact_create takes), all
- * host arrays read during the call.  device < 0: the current device.
- * pf_lu_solve solves M y = b in place (b: device [n]) on the stream; calls
- * on one object must not overlap.  Errors as pf_refact_create.
+ * host arrays read during the call.  The factor values T_val are used as
+ * given (M is only checked against them); the rows of T are grouped into
+ * elimination levels at creation.  device < 0: the current device.
+ * pf_lu_solve solves M y = b in place (b: device [n]) on the stream with
+ * level-scheduled forward and backward solves of this library (runs of small
+ * consecutive levels in one block); calls on one object must not overlap.
+ * Errors as pf_refact_create.
  */
 typedef struct pf_lu pf_lu;
 

@@ -30,6 +30,7 @@
 #include <hip/hip_runtime.h>
 
 #include "pf_internal.hpp"
+#include "pf_trisolve.hpp"
 
 #define BL_HIP(expr)                                                               \
     do {                                                                           \
@@ -52,7 +53,8 @@ struct pf_batch_lu {
     // one instance: runs of consecutive small levels done by one block, as
     // {first level, end level, waves, LDS bytes per wave} (factorisation) and
     // {first level, end level, waves} (forward, backward solves)
-    std::vector<int32_t> fchain_factor, fchain_fwd, bchain;
+    std::vector<int32_t> fchain_factor;
+    TriLevels tri;   // one instance: levels and runs of the solves
     int32_t *flev_ptr_d = nullptr, *blev_ptr_d = nullptr;
     // device structure
     int32_t *trp = nullptr;   // n + 1
@@ -263,14 +265,12 @@ __global__ void __launch_bounds__(64) k_blu_factor1(
     factor_row1(rows[blockIdx.x], threadIdx.x, trp, tsrc, item_ptr, item, J, T, sm);
 }
 
-// Levels with this many rows or fewer, when consecutive, run in one block:
+// Levels of at most kTriChainRows rows, when consecutive, run in one block:
 // wavefront w takes row w of each level, and a block barrier separates the
 // levels (a row reads only rows of earlier levels, whose writes the barrier
 // makes visible to the block).  This saves a launch per level where the
 // levels are small.
-constexpr int kChainRows = 16;
-
-__global__ void __launch_bounds__(64 * kChainRows) k_blu_factor1_chain(
+__global__ void __launch_bounds__(64 * kTriChainRows) k_blu_factor1_chain(
     int l0, int l1, const int32_t *__restrict__ lev_ptr, const int32_t *__restrict__ rows,
     int stride, const int32_t *__restrict__ trp, const int32_t *__restrict__ tsrc,
     const int32_t *__restrict__ item_ptr, const int2 *__restrict__ item,
@@ -344,80 +344,6 @@ __global__ void __launch_bounds__(64) k_blu_bwd(
     Y[size_t(r) * SI + inst] = s / T[size_t(tdiag[r]) * SI + inst];
 }
 
-// One instance: a wavefront per row, its lanes over the row's entries; the
-// lanes' partial sums are combined by a fixed butterfly, so results are
-// deterministic (their rounding differs from the one-lane loop's).
-__device__ __forceinline__ double wave_sum(double p) {
-#pragma unroll
-    for (int off = 32; off > 0; off >>= 1) p += __shfl_xor(p, off);
-    return p;
-}
-
-__device__ __forceinline__ void fwd_row1(int r, int lane, const int32_t *__restrict__ trp,
-                                         const int32_t *__restrict__ tci,
-                                         const int32_t *__restrict__ tdiag,
-                                         const int32_t *__restrict__ pivP,
-                                         const double *__restrict__ T,
-                                         const double *__restrict__ F, double *__restrict__ Y) {
-    double p = 0.0;
-    for (int e = trp[r] + lane; e < tdiag[r]; e += 64) p = fma(T[e], Y[tci[e]], p);
-    p = wave_sum(p);
-    if (lane == 0) Y[r] = F[pivP[r]] - p;
-}
-
-__device__ __forceinline__ void bwd_row1(int r, int lane, const int32_t *__restrict__ trp,
-                                         const int32_t *__restrict__ tci,
-                                         const int32_t *__restrict__ tdiag,
-                                         const double *__restrict__ T, double *__restrict__ Y) {
-    double p = 0.0;
-    for (int e = tdiag[r] + 1 + lane; e < trp[r + 1]; e += 64) p = fma(T[e], Y[tci[e]], p);
-    p = wave_sum(p);
-    if (lane == 0) Y[r] = (Y[r] - p) / T[tdiag[r]];
-}
-
-__global__ void __launch_bounds__(64) k_blu_fwd1(
-    const int32_t *__restrict__ rows, const int32_t *__restrict__ trp,
-    const int32_t *__restrict__ tci, const int32_t *__restrict__ tdiag,
-    const int32_t *__restrict__ pivP, const double *__restrict__ T,
-    const double *__restrict__ F, double *__restrict__ Y) {
-    fwd_row1(rows[blockIdx.x], threadIdx.x, trp, tci, tdiag, pivP, T, F, Y);
-}
-
-__global__ void __launch_bounds__(64) k_blu_bwd1(
-    const int32_t *__restrict__ rows, const int32_t *__restrict__ trp,
-    const int32_t *__restrict__ tci, const int32_t *__restrict__ tdiag,
-    const double *__restrict__ T, double *__restrict__ Y) {
-    bwd_row1(rows[blockIdx.x], threadIdx.x, trp, tci, tdiag, T, Y);
-}
-
-// Runs of small consecutive solve levels in one block (as for the
-// factorisation): wavefront w takes row w of each level.
-__global__ void __launch_bounds__(64 * kChainRows) k_blu_fwd1_chain(
-    int l0, int l1, const int32_t *__restrict__ lev_ptr, const int32_t *__restrict__ rows,
-    const int32_t *__restrict__ trp, const int32_t *__restrict__ tci,
-    const int32_t *__restrict__ tdiag, const int32_t *__restrict__ pivP,
-    const double *__restrict__ T, const double *__restrict__ F, double *__restrict__ Y) {
-    const int lane = threadIdx.x & 63;
-    const int wv = threadIdx.x >> 6;
-    for (int l = l0; l < l1; ++l) {
-        const int q0 = lev_ptr[l];
-        if (wv < lev_ptr[l + 1] - q0) fwd_row1(rows[q0 + wv], lane, trp, tci, tdiag, pivP, T, F, Y);
-        __syncthreads();
-    }
-}
-
-__global__ void __launch_bounds__(64 * kChainRows) k_blu_bwd1_chain(
-    int l0, int l1, const int32_t *__restrict__ lev_ptr, const int32_t *__restrict__ rows,
-    const int32_t *__restrict__ trp, const int32_t *__restrict__ tci,
-    const int32_t *__restrict__ tdiag, const double *__restrict__ T, double *__restrict__ Y) {
-    const int lane = threadIdx.x & 63;
-    const int wv = threadIdx.x >> 6;
-    for (int l = l0; l < l1; ++l) {
-        const int q0 = lev_ptr[l];
-        if (wv < lev_ptr[l + 1] - q0) bwd_row1(rows[q0 + wv], lane, trp, tci, tdiag, T, Y);
-        __syncthreads();
-    }
-}
 
 // x[pivQ[k]] -= z[k] for active instances (subtract = 1), or x[pivQ[k]] = z[k]
 // (subtract = 0); one block per (row k, 256 instances)
@@ -585,7 +511,7 @@ int build(pf_batch_lu *b, const HostPlan &hp, int64_t nnzT, const int32_t *trp,
             size_t e = l;
             int w = 0;
             size_t stride = 0;
-            while (e < nfl && nrows(b->flev_ptr, e) <= kChainRows) {
+            while (e < nfl && nrows(b->flev_ptr, e) <= kTriChainRows) {
                 const int w2 = std::max(w, nrows(b->flev_ptr, e));
                 const size_t s2 = std::max(stride, lds_of(e));
                 if (size_t(w2) * s2 * sizeof(double) > lds_limit) break;
@@ -601,22 +527,10 @@ int build(pf_batch_lu *b, const HostPlan &hp, int64_t nnzT, const int32_t *trp,
                 l = std::max(e, l + 1);
             }
         }
-        auto solve_runs = [&](const std::vector<int32_t> &ptr, std::vector<int32_t> &out) {
-            const size_t nl = ptr.size() - 1;
-            for (size_t l = 0; l < nl;) {
-                size_t e = l;
-                int w = 0;
-                while (e < nl && nrows(ptr, e) <= kChainRows) w = std::max(w, nrows(ptr, e++));
-                if (e - l >= 2) {
-                    out.insert(out.end(), {int32_t(l), int32_t(e), int32_t(w)});
-                    l = e;
-                } else {
-                    l = std::max(e, l + 1);
-                }
-            }
-        };
-        solve_runs(b->flev_ptr, b->fchain_fwd);
-        solve_runs(b->blev_ptr, b->bchain);
+        b->tri.flev_ptr = b->flev_ptr;
+        b->tri.blev_ptr = b->blev_ptr;
+        tri_chains(b->tri.flev_ptr, b->tri.fchain);
+        tri_chains(b->tri.blev_ptr, b->tri.bchain);
     }
     int rc = PF_OK;
     if (!rc) rc = balloc(&b->trp, trp, size_t(n) + 1);
@@ -679,37 +593,9 @@ int solve_levels(pf_batch_lu *b, const double *Fin, double *Y, hipStream_t st) {
     const int I = b->n_inst, SI = b->ld;
     const int nc = (I + 63) / 64;
     if (I == 1 && SI == 1) {   // one instance: lanes over each row's entries
-        size_t ci = 0;   // next run of small levels
-        for (size_t l = 0; l + 1 < b->flev_ptr.size(); ++l) {
-            if (ci < b->fchain_fwd.size() && size_t(b->fchain_fwd[ci]) == l) {
-                const int l1 = b->fchain_fwd[ci + 1], w = b->fchain_fwd[ci + 2];
-                hipLaunchKernelGGL(k_blu_fwd1_chain, dim3(1), dim3(unsigned(64 * w)), 0, st,
-                                   int(l), l1, b->flev_ptr_d, b->frows, b->trp, b->tci, b->tdiag,
-                                   b->pivP, b->T, Fin, Y);
-                l = size_t(l1) - 1;
-                ci += 3;
-                continue;
-            }
-            const int nr = b->flev_ptr[l + 1] - b->flev_ptr[l];
-            hipLaunchKernelGGL(k_blu_fwd1, dim3(unsigned(nr)), dim3(64), 0, st,
-                               b->frows + b->flev_ptr[l], b->trp, b->tci, b->tdiag, b->pivP,
-                               b->T, Fin, Y);
-        }
-        ci = 0;
-        for (size_t l = 0; l + 1 < b->blev_ptr.size(); ++l) {
-            if (ci < b->bchain.size() && size_t(b->bchain[ci]) == l) {
-                const int l1 = b->bchain[ci + 1], w = b->bchain[ci + 2];
-                hipLaunchKernelGGL(k_blu_bwd1_chain, dim3(1), dim3(unsigned(64 * w)), 0, st,
-                                   int(l), l1, b->blev_ptr_d, b->brows, b->trp, b->tci, b->tdiag,
-                                   b->T, Y);
-                l = size_t(l1) - 1;
-                ci += 3;
-                continue;
-            }
-            const int nr = b->blev_ptr[l + 1] - b->blev_ptr[l];
-            hipLaunchKernelGGL(k_blu_bwd1, dim3(unsigned(nr)), dim3(64), 0, st,
-                               b->brows + b->blev_ptr[l], b->trp, b->tci, b->tdiag, b->T, Y);
-        }
+        const TriDev d{b->flev_ptr_d, b->blev_ptr_d, b->frows, b->brows,
+                       b->trp,        b->tci,        b->tdiag, b->pivP, b->T};
+        tri_solve(b->tri, d, Fin, Y, st);
         BL_HIP(hipGetLastError());
         return PF_OK;
     }

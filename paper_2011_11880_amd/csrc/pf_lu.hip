@@ -26,6 +26,7 @@
 #include <rocsolver/rocsolver.h>
 
 #include "pf_internal.hpp"
+#include "pf_trisolve.hpp"
 
 #define LU_HIP(expr)                                                               \
     do {                                                                           \
@@ -451,12 +452,12 @@ int pf_newton_device(pf_plan *plan, pf_refact *rf, double *x, const pf_newton_op
 
 struct pf_lu {
     int device = 0;
-    int n = 0, nnzM = 0, nnzT = 0;
-    int *ptrM = nullptr, *indM = nullptr, *ptrT = nullptr, *indT = nullptr;
-    double *valM = nullptr, *valT = nullptr;
+    int n = 0, nnzT = 0;
+    int *ptrT = nullptr, *indT = nullptr, *tdiag = nullptr;
+    double *valT = nullptr, *Y = nullptr;
     int *pivP = nullptr, *pivQ = nullptr;
-    rocblas_handle handle = nullptr;
-    rocsolver_rfinfo info = nullptr;
+    int *frows = nullptr, *brows = nullptr, *flev_ptr = nullptr, *blev_ptr = nullptr;
+    TriLevels tri;   // host copy of the level structure
 };
 
 struct pf_fdlf {
@@ -553,14 +554,12 @@ int build_fd(const HostPlan &hp, FdMats &m) {
 
 void release_lu(pf_lu *lu) {
     if (!lu) return;
-    const RfApi &api = rf_api();
     int prev = -1;
     (void)hipGetDevice(&prev);
     (void)hipSetDevice(lu->device);
-    if (lu->info && api.ok) (void)api.destroy_rfinfo(lu->info);
-    if (lu->handle && api.ok) (void)api.destroy_handle(lu->handle);
-    for (void *p : {(void *)lu->ptrM, (void *)lu->indM, (void *)lu->valM, (void *)lu->ptrT,
-                    (void *)lu->indT, (void *)lu->valT, (void *)lu->pivP, (void *)lu->pivQ})
+    for (void *p : {(void *)lu->ptrT, (void *)lu->indT, (void *)lu->tdiag, (void *)lu->valT,
+                    (void *)lu->Y, (void *)lu->pivP, (void *)lu->pivQ, (void *)lu->frows,
+                    (void *)lu->brows, (void *)lu->flev_ptr, (void *)lu->blev_ptr})
         if (p) (void)hipFree(p);
     if (prev >= 0) (void)hipSetDevice(prev);
     delete lu;
@@ -591,50 +590,52 @@ const char *check_csr(int n, int64_t nnz, const int32_t *rp, const int32_t *ci) 
     return nullptr;
 }
 
-int create_lu(int device, int n, int64_t nnz, const int32_t *rowptr, const int32_t *colidx,
-              const double *val, int64_t nnzT, const int32_t *T_rowptr, const int32_t *T_colidx,
+// The factors are the host LU's own: T's values are uploaded as given and
+// every solve runs this library's level-scheduled kernels along them (the
+// matrix M itself is only checked).
+int create_lu(int device, int n, const int32_t *T_rowptr, const int32_t *T_colidx,
               const double *T_val, const int32_t *pivP, const int32_t *pivQ, pf_lu *lu) {
-    const RfApi &api = rf_api();
-    if (!api.ok) return fail(PF_EDEVICE, "%s", api.why);
     Guard g(device);
     if (!g.ok) return fail(PF_EDEVICE, "cannot select device %d", device);
     lu->device = device;
     lu->n = n;
-    lu->nnzM = int(nnz);
-    lu->nnzT = int(nnzT);
+    lu->nnzT = T_rowptr[n];
+    try {
+        tri_levels(n, T_rowptr, T_colidx, lu->tri);
+    } catch (const std::bad_alloc &) {
+        return fail(PF_ENOMEM, "host allocation failed");
+    }
+    const TriLevels &t = lu->tri;
     int rc = PF_OK;
-    if (!rc) rc = alloc_copy(&lu->ptrM, rowptr, size_t(n) + 1);
-    if (!rc) rc = alloc_copy(&lu->indM, colidx, size_t(nnz));
-    if (!rc) rc = alloc_copy(&lu->valM, val, size_t(nnz));
     if (!rc) rc = alloc_copy(&lu->ptrT, T_rowptr, size_t(n) + 1);
-    if (!rc) rc = alloc_copy(&lu->indT, T_colidx, size_t(nnzT));
-    if (!rc) rc = alloc_copy(&lu->valT, T_val, size_t(nnzT));
+    if (!rc) rc = alloc_copy(&lu->indT, T_colidx, size_t(lu->nnzT));
+    if (!rc) rc = alloc_copy(&lu->valT, T_val, size_t(lu->nnzT));
+    if (!rc) rc = alloc_copy(&lu->tdiag, t.tdiag.data(), t.tdiag.size());
     if (!rc) rc = alloc_copy(&lu->pivP, pivP, size_t(n));
     if (!rc) rc = alloc_copy(&lu->pivQ, pivQ, size_t(n));
-    if (rc) return rc;
-    double *b = nullptr;
-    LU_HIP(hipMalloc(&b, size_t(n) * sizeof(double)));
-    LU_HIP(hipMemset(b, 0, size_t(n) * sizeof(double)));
-    rocblas_status s = api.create_handle(&lu->handle);
-    if (s == rocblas_status_success) s = api.create_rfinfo(&lu->info, lu->handle);
-    if (s == rocblas_status_success)
-        s = api.analysis(lu->handle, n, 1, lu->nnzM, lu->ptrM, lu->indM, lu->valM, lu->nnzT,
-                         lu->ptrT, lu->indT, lu->valT, lu->pivP, lu->pivQ, b, n, lu->info);
-    // factor values recomputed on the device along the same pivots
-    if (s == rocblas_status_success)
-        s = api.refactlu(lu->handle, n, lu->nnzM, lu->ptrM, lu->indM, lu->valM, lu->nnzT,
-                         lu->ptrT, lu->indT, lu->valT, lu->pivP, lu->pivQ, lu->info);
-    (void)hipDeviceSynchronize();
-    (void)hipFree(b);
-    if (s != rocblas_status_success) return fail(PF_ESOLVE, "rocSOLVER setup failed: status %d", int(s));
-    return PF_OK;
+    if (!rc) rc = alloc_copy(&lu->frows, t.frows.data(), t.frows.size());
+    if (!rc) rc = alloc_copy(&lu->brows, t.brows.data(), t.brows.size());
+    if (!rc) rc = alloc_copy(&lu->flev_ptr, t.flev_ptr.data(), t.flev_ptr.size());
+    if (!rc) rc = alloc_copy(&lu->blev_ptr, t.blev_ptr.data(), t.blev_ptr.size());
+    if (!rc) rc = alloc_copy(&lu->Y, static_cast<const double *>(nullptr), size_t(n));
+    return rc;
+}
+
+// X[pivQ[k]] = Y[k]
+__global__ void __launch_bounds__(256) k_lu_unpermute(int n, const int32_t *__restrict__ pivQ,
+                                                      const double *__restrict__ Y,
+                                                      double *__restrict__ X) {
+    const int k = blockIdx.x * 256 + threadIdx.x;
+    if (k < n) X[pivQ[k]] = Y[k];
 }
 
 int lu_solve(pf_lu *lu, double *b, hipStream_t st) {
-    const RfApi &api = rf_api();
-    LU_RS(api.set_stream(lu->handle, st));
-    LU_RS(api.solve(lu->handle, lu->n, 1, lu->nnzT, lu->ptrT, lu->indT, lu->valT, lu->pivP,
-                    lu->pivQ, b, lu->n, lu->info));
+    const TriDev d{lu->flev_ptr, lu->blev_ptr, lu->frows, lu->brows, lu->ptrT,
+                   lu->indT,     lu->tdiag,    lu->pivP,  lu->valT};
+    tri_solve(lu->tri, d, b, lu->Y, st);
+    hipLaunchKernelGGL(k_lu_unpermute, dim3(unsigned((lu->n + 255) / 256)), dim3(256), 0, st,
+                       lu->n, lu->pivQ, lu->Y, b);
+    LU_HIP(hipGetLastError());
     return PF_OK;
 }
 
@@ -824,8 +825,7 @@ int pf_lu_create(int32_t device, int64_t n, int64_t nnz, const int32_t *rowptr,
     if (dev < 0 && hipGetDevice(&dev) != hipSuccess) return fail(PF_EDEVICE, "no current device");
     pf_lu *lu = new (std::nothrow) pf_lu();
     if (!lu) return fail(PF_ENOMEM, "host allocation failed");
-    int rc = create_lu(dev, int(n), nnz, rowptr, colidx, val, nnzT, T_rowptr, T_colidx, T_val,
-                       pivP, pivQ, lu);
+    int rc = create_lu(dev, int(n), T_rowptr, T_colidx, T_val, pivP, pivQ, lu);
     if (rc) {
         release_lu(lu);
         return rc;
