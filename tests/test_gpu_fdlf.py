@@ -1,6 +1,8 @@
 """GPU parity of the fast decoupled method: constant device factorisations
-against host solves, and pf_fdlf_solve iterate by iterate against the
-oracle's fast decoupled iteration, on meshed transmission-like grids."""
+against host solves (on the method's matrices and on matrices whose factors
+take the level-scheduled solves to their extreme shapes), and pf_fdlf_solve
+iterate by iterate against the oracle's fast decoupled iteration, on meshed
+transmission-like grids."""
 
 import numpy as np
 import pytest
@@ -43,6 +45,44 @@ def test_device_sparse_lu_solves(ora, cuda):
         assert np.max(np.abs(M @ y - b)) <= 1e-11 * (abs(M).max() * np.max(np.abs(y)) + 1)
         assert np.max(np.abs(y - ref)) <= 1e-9 * np.max(np.abs(ref))
         lu.close()
+
+
+def _lu_structures():
+    """Matrices whose factors give the level-scheduled solves their extreme
+    shapes: one level of n rows (diagonal), n levels of one row each way
+    (bidiagonal chains, one run of small levels), a dense block (long rows)
+    and a random unsymmetric sparse matrix that needs pivoting."""
+    import scipy.sparse as sp
+    rng = np.random.default_rng(11)
+    n = 3000
+    diag = sp.diags(rng.uniform(1.0, 2.0, n)).tocsr()
+    lower = (sp.diags(rng.uniform(2.0, 3.0, n)) + sp.diags(rng.uniform(-1, 1, n - 1), -1)).tocsr()
+    upper = (sp.diags(rng.uniform(2.0, 3.0, n)) + sp.diags(rng.uniform(-1, 1, n - 1), 1)).tocsr()
+    dense = sp.csr_matrix(rng.normal(size=(300, 300)) + 30.0 * np.eye(300))
+    rnd = sp.random(2000, 2000, density=0.003, random_state=5, format="csr")
+    rnd = (rnd + sp.diags(rng.uniform(0.5, 1.0, 2000)) + sp.random(2000, 2000, density=0.001,
+                                                                  random_state=6)).tocsr()
+    one = sp.csr_matrix(np.array([[4.0]]))
+    return {"diagonal": diag, "lower_chain": lower, "upper_chain": upper, "dense_300": dense,
+            "random_2000": rnd, "one_by_one": one}
+
+
+@pytest.mark.parametrize("name", list(_lu_structures()))
+def test_device_sparse_lu_level_structures(cuda, name):
+    from paper_2011_11880_amd.api import DeviceSparseLU
+    M = _lu_structures()[name]
+    lu = DeviceSparseLU(M)
+    b = np.random.default_rng(4).normal(size=M.shape[0])
+    y = torch.from_numpy(b.copy()).to(cuda)
+    lu.solve(y)
+    torch.cuda.synchronize()
+    ref = spla.spsolve(M.tocsc(), b)
+    got = y.cpu().numpy()
+    scale = np.abs(ref).max()
+    assert np.max(np.abs(got - ref)) <= 1e-10 * scale
+    # the residual of the device solution is at rounding level too
+    assert np.max(np.abs(M @ got - b)) <= 1e-10 * np.abs(b).max() * max(1.0, abs(M).max())
+    lu.close()
 
 
 def test_fdlf_iterates_match_oracle(ora, cuda):
