@@ -85,6 +85,10 @@ constexpr int kItems = 32;          // factorisation items whose loads are issue
 // issued back to back, and only the use of an entry is guarded.  Padding
 // entries point at T row 0, Jacobian slot -1 (none) and column 0.
 constexpr int kPad = kItems;
+// Levels whose rows times instances are at most this many run a wavefront
+// per (row, instance) rather than a lane per instance (at 1024 instances:
+// levels of up to 16 rows; 2048 to 16384 measured alike, 65536 slower).
+constexpr int64_t kInstWaves = 16384;
 
 struct BGuard {
     int prev = -1;
@@ -204,18 +208,19 @@ __device__ __forceinline__ void wave_sync() {
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 }
 
-// One instance (row pitch 1): a wavefront per row, its lanes spread over the
-// row.  The row and the values its items read (final entries of rows of
-// earlier levels) are loaded into LDS by all lanes at once; the steps then
-// run in order, each step's divide on the wave-uniform value and its updates
-// over the lanes.  A step's updates change distinct entries of the row, so
-// every result equals that of the one-lane loop of k_blu_factor.
+// One row of one instance (instance inst of rows of pitch SI): a wavefront
+// per row, its lanes spread over the row.  The row and the values its items
+// read (final entries of rows of earlier levels) are loaded into LDS by all
+// lanes at once; the steps then run in order, each step's divide on the
+// wave-uniform value and its updates over the lanes.  A step's updates change
+// distinct entries of the row, so every result equals that of the one-lane
+// loop of k_blu_factor.
 __device__ __forceinline__ void factor_row1(int r, int lane, const int32_t *__restrict__ trp,
                                             const int32_t *__restrict__ tsrc,
                                             const int32_t *__restrict__ item_ptr,
                                             const int2 *__restrict__ item,
                                             const double *__restrict__ J, double *__restrict__ T,
-                                            double *sm) {
+                                            double *sm, size_t SI = 1, int inst = 0) {
     const int r0 = trp[r], R = trp[r + 1] - r0;
     const int i0 = item_ptr[r], NI = item_ptr[r + 1] - i0;
     double *Lrow = sm;
@@ -223,12 +228,12 @@ __device__ __forceinline__ void factor_row1(int r, int lane, const int32_t *__re
     int *ix = reinterpret_cast<int *>(tv + NI);
     for (int q = lane; q < R; q += 64) {
         const int s = tsrc[r0 + q];
-        Lrow[q] = s >= 0 ? J[s] : 0.0;
+        Lrow[q] = s >= 0 ? J[size_t(s) * SI + inst] : 0.0;
     }
     for (int q = lane; q < NI; q += 64) {
         const int2 it = item[i0 + q];
         ix[q] = it.x;
-        tv[q] = T[it.y];
+        tv[q] = T[size_t(it.y) * SI + inst];
     }
     wave_sync();
     int q = 0;
@@ -254,7 +259,20 @@ __device__ __forceinline__ void factor_row1(int r, int lane, const int32_t *__re
         wave_sync();
         q = next;
     }
-    for (int q2 = lane; q2 < R; q2 += 64) T[r0 + q2] = Lrow[q2];
+    for (int q2 = lane; q2 < R; q2 += 64) T[size_t(r0 + q2) * SI + inst] = Lrow[q2];
+}
+
+// Several instances, levels of few rows: a wavefront per (row, instance) as
+// for one instance, instead of one lane per instance walking the row's long
+// chain of items alone.
+__global__ void __launch_bounds__(64) k_blu_factor_inst(
+    const int32_t *__restrict__ rows, int n_inst, int SI, const int32_t *__restrict__ trp,
+    const int32_t *__restrict__ tsrc, const int32_t *__restrict__ item_ptr,
+    const int2 *__restrict__ item, const double *__restrict__ J, double *__restrict__ T) {
+    extern __shared__ double sm[];
+    const int r = rows[blockIdx.x / n_inst];
+    const int inst = blockIdx.x % n_inst;
+    factor_row1(r, threadIdx.x, trp, tsrc, item_ptr, item, J, T, sm, size_t(SI), inst);
 }
 
 __global__ void __launch_bounds__(64) k_blu_factor1(
@@ -578,6 +596,16 @@ int factor_levels(pf_batch_lu *b, const double *J, hipStream_t st) {
                 continue;
             }
         }
+        if (!one && int64_t(nr) * I <= kInstWaves) {
+            const size_t shm1 = size_t(b->flev_maxr[l] + b->flev_maxi[l]) * sizeof(double) +
+                                size_t(b->flev_maxi[l]) * sizeof(int32_t);
+            if (shm1 <= b->lds_limit) {
+                hipLaunchKernelGGL(k_blu_factor_inst, dim3(unsigned(int64_t(nr) * I)), dim3(64), shm1,
+                                   st, b->frows + b->flev_ptr[l], I, SI, b->trp, b->tsrc,
+                                   b->item_ptr, b->item, J, b->T);
+                continue;
+            }
+        }
         const int W = b->flev_w[l];
         const int nc = (I + W - 1) / W;
         const size_t shm = size_t(b->flev_maxr[l]) * size_t(W) * sizeof(double);
@@ -657,6 +685,8 @@ int pf_batch_lu_create(pf_plan *plan, int64_t nnzT, const int32_t *T_rowptr,
     (void)hipFuncSetAttribute(reinterpret_cast<const void *>(&k_blu_factor1),
                               hipFuncAttributeMaxDynamicSharedMemorySize, lds);
     (void)hipFuncSetAttribute(reinterpret_cast<const void *>(&k_blu_factor1_chain),
+                              hipFuncAttributeMaxDynamicSharedMemorySize, lds);
+    (void)hipFuncSetAttribute(reinterpret_cast<const void *>(&k_blu_factor_inst),
                               hipFuncAttributeMaxDynamicSharedMemorySize, lds);
     pf_batch_lu *b = new (std::nothrow) pf_batch_lu();
     if (!b) return fail(PF_ENOMEM, "host allocation failed");
