@@ -311,10 +311,19 @@ void ora_vjp_params(const ora_topo *tp, const ora_data *dd, const double *y,
 }
 
 /*
- * Tolerance scale for ora_vjp_params: the same chain of products with every
- * factor replaced by its absolute value, i.e. the sum of |terms| that the
- * gradient of each parameter adds up.  Used only to bound rounding
- * differences under cancellation; it is not part of the reference values.
+ * Tolerance scale for ora_vjp_params: for each gradient, the sum of the
+ * absolute values of the product terms it is made of, with every difference
+ * or sum of products counted as its separate products (x^2 - r^2 contributes
+ * x^2 + r^2, u (g C + b S) contributes |u g C| + |u b S|, b + b_c/2
+ * contributes |b| + |b_c|/2).  The rounding error of the gradient, evaluated
+ * in any order or grouping of those terms, is bounded by a small multiple of
+ * the machine epsilon times this sum.  It only bounds rounding differences
+ * under cancellation; it is not part of the reference values.
+ *
+ * With sg, sb the scales of dL/dg and dL/db (the flow partials of
+ * Section II-A's pi-model dotted with |w|) and D = r^2 + x^2:
+ *   s_r = (sg (x^2 + r^2) + sb 2|r x|) / D^2   (g_r = dL/dg dg/dr + dL/db db/dr)
+ *   s_x = (sg 2|r x| + sb (x^2 + r^2)) / D^2   (g_x = dL/dg dg/dx + dL/db db/dx)
  */
 void ora_vjp_params_scale(const ora_topo *tp, const ora_data *dd, const double *y,
                           const double *w, double *s_r, double *s_x, double *s_b,
@@ -326,7 +335,7 @@ void ora_vjp_params_scale(const ora_topo *tp, const ora_data *dd, const double *
     for (e = 0; e < tp->n_branch; ++e) {
         int f, t;
         double r, x, bc, tap, phi, D, D2, g, b, delta, C, S, u, t2, vf, vt;
-        double A1, B1, A2, B2, wpf, wqf, wpt, wqt, sg, sb;
+        double aC, aS, ag, ab, A1, B1, A2, B2, wpf, wqf, wpt, wqt, sg, sb;
         s_r[e] = s_x[e] = s_b[e] = s_tap[e] = s_shift[e] = 0.0;
         if (tp->br_status && !tp->br_status[e]) continue;
         f = tp->br_from[e];
@@ -347,24 +356,27 @@ void ora_vjp_params_scale(const ora_topo *tp, const ora_data *dd, const double *
         S = sin(delta);
         u = vf * vt / tap;
         t2 = tap * tap;
-        A1 = fabs(u * (g * C + b * S));
-        B1 = fabs(u * (g * S - b * C));
-        A2 = fabs(u * (g * C - b * S));
-        B2 = fabs(u * (g * S + b * C));
+        aC = fabs(u * C);
+        aS = fabs(u * S);
+        ag = fabs(g);
+        ab = fabs(b);
+        /* |terms| of A1 = u(gC + bS), B1 = u(gS - bC), A2 = u(gC - bS),
+           B2 = u(gS + bC) */
+        A1 = ag * aC + ab * aS;
+        B1 = ag * aS + ab * aC;
+        A2 = A1;
+        B2 = B1;
         wpf = fabs(w[f]);
         wqf = fabs(w[N + f]);
         wpt = fabs(w[t]);
         wqt = fabs(w[N + t]);
-        sg = wpf * (vf * vf / t2 + fabs(u * C)) + wqf * fabs(u * S) +
-             wpt * (vt * vt + fabs(u * C)) + wqt * fabs(u * S);
-        sb = wpf * fabs(u * S) + wqf * (vf * vf / t2 + fabs(u * C)) +
-             wpt * fabs(u * S) + wqt * (vt * vt + fabs(u * C));
-        s_r[e] = sg * fabs(x * x - r * r) / D2 + sb * fabs(2.0 * r * x) / D2 +
-                 (sg + sb) * (x * x + r * r) / D2;
-        s_x[e] = s_r[e];
+        sg = wpf * (vf * vf / t2 + aC) + wqf * aS + wpt * (vt * vt + aC) + wqt * aS;
+        sb = wpf * aS + wqf * (vf * vf / t2 + aC) + wpt * aS + wqt * (vt * vt + aC);
+        s_r[e] = (sg * (x * x + r * r) + sb * fabs(2.0 * r * x)) / D2;
+        s_x[e] = (sg * fabs(2.0 * r * x) + sb * (x * x + r * r)) / D2;
         s_b[e] = wqf * vf * vf / (2.0 * t2) + wqt * vt * vt / 2.0;
-        s_tap[e] = wpf * (2.0 * vf * vf * fabs(g) / (t2 * tap) + A1 / tap) +
-                   wqf * (2.0 * vf * vf * fabs(b + bc / 2.0) / (t2 * tap) + B1 / tap) +
+        s_tap[e] = wpf * (2.0 * vf * vf * ag / (t2 * tap) + A1 / tap) +
+                   wqf * (2.0 * vf * vf * (ab + fabs(bc) / 2.0) / (t2 * tap) + B1 / tap) +
                    wpt * (A2 / tap) + wqt * (B2 / tap);
         s_shift[e] = (wpf * B1 + wqf * A1 + wpt * B2 + wqt * A2) * (ORA_PI / 180.0);
     }

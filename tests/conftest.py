@@ -18,3 +18,18 @@ def ora():
     from oracle import oracle as O
     O.build()
     return O
+
+
+def pytest_terminal_summary(terminalreporter):
+    """Totals of the oracle comparisons: entries compared and entries that
+    passed only through the cancellation fallback."""
+    parity = sys.modules.get("parity")
+    rec = getattr(parity, "RECORD", None)
+    if not rec:
+        return
+    n = sum(r[1] for r in rec)
+    fb = sum(r[2] for r in rec)
+    worst = max(rec, key=lambda r: r[2] / max(r[1], 1))
+    terminalreporter.write_line(
+        f"oracle parity: {len(rec)} comparisons, {n} entries, {fb} through the cancellation "
+        f"fallback; highest share {worst[2]}/{worst[1]} ({worst[0]})")

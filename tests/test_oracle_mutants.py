@@ -57,6 +57,11 @@ MUTANTS = [
      "g_shift[e] = -(wpf * B1 + wqf * (-A1) + wpt * B2 + wqt * A2);"),
     ("vjp load index", "pf_oracle.c", "g_lq[e] = w[N + tp->load_bus[e]];", "g_lq[e] = w[tp->load_bus[e]];"),
     ("held PV row uses V", "ora_core.inc", "FV[k] = Qg[k] - pv_qt[k];", "FV[k] = V[i] - pv_qt[k];"),
+    ("scale s_x = s_r", "pf_oracle.c",
+     "s_x[e] = (sg * fabs(2.0 * r * x) + sb * (x * x + r * r)) / D2;", "s_x[e] = s_r[e];"),
+    ("scale difference counted once", "pf_oracle.c", "s_r[e] = (sg * (x * x + r * r)",
+     "s_r[e] = (sg * fabs(x * x - r * r)"),
+    ("scale tap charging dropped", "pf_oracle.c", "(ab + fabs(bc) / 2.0)", "(ab)"),
     ("J held PV column", "pf_oracle.c", "k = put(rows, cols, vals, k, 2 * N + e, 2 * N + e, 1.0);",
      "k = put(rows, cols, vals, k, 2 * N + e, N + i, 1.0);"),
 ]
@@ -75,6 +80,7 @@ PINS = [
     P.test_sizes_and_pattern,
     P.test_vjp_state_is_transpose_product,
     P.test_vjp_params_complex_step,
+    P.test_vjp_params_scale_is_sum_of_abs_terms,
     Q.test_held_output_equals_pq_injection,
     lambda o: Q.test_jacobian_complex_step_with_held_outputs(o, "tiny"),
 ]

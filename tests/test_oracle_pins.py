@@ -310,6 +310,90 @@ def test_vjp_params_complex_step(ora):
             assert abs(d - gp[name][k]) <= 1e-11 * (1 + abs(d)), (name, k)
 
 
+def _param_gradient_terms(net, yv, w):
+    """Every parameter gradient of w.F written out as its list of signed
+    product terms, per branch, from the pi-model partials (Section II-A's
+    line model with tap t and shift phi on the from side): the flow partials
+    with respect to series g and b, chained through g = r/D, b = -x/D
+    (dg/dr = (x^2 - r^2)/D^2, db/dr = 2rx/D^2, dg/dx = -2rx/D^2,
+    db/dx = (x^2 - r^2)/D^2), the charging partials of the Q flows, the tap
+    partials of the 1/t^2 and 1/t factors and the shift acting as -theta_f.
+    Returns {name: array [n_terms, B]}."""
+    N = net.n_bus
+    f, t = net.br_from, net.br_to
+    r, x, bc, tap = net.br_r, net.br_x, net.br_b, net.br_tap
+    phi = np.deg2rad(net.br_shift_deg)
+    D = r * r + x * x
+    g, b = r / D, -x / D
+    vf, vt = yv[N + f], yv[N + t]
+    d = yv[f] - yv[t] - phi
+    C, S = np.cos(d), np.sin(d)
+    u = vf * vt / tap
+    t2 = tap * tap
+    wpf, wqf, wpt, wqt = w[f], w[N + f], w[t], w[N + t]
+    tg = [wpf * vf * vf / t2, -wpf * u * C, -wqf * u * S, wpt * vt * vt, -wpt * u * C, wqt * u * S]
+    tb = [-wpf * u * S, -wqf * vf * vf / t2, wqf * u * C, wpt * u * S, -wqt * vt * vt, wqt * u * C]
+    dgdr = [x * x / D ** 2, -r * r / D ** 2]
+    dbdr = [2 * r * x / D ** 2]
+    dgdx = [-2 * r * x / D ** 2]
+    dbdx = [x * x / D ** 2, -r * r / D ** 2]
+    terms = {
+        "br_r": [a * c for a in tg for c in dgdr] + [a * c for a in tb for c in dbdr],
+        "br_x": [a * c for a in tg for c in dgdx] + [a * c for a in tb for c in dbdx],
+        "br_b": [-wqf * vf * vf / (2 * t2), -wqt * vt * vt / 2],
+        "br_tap": [-wpf * 2 * vf * vf * g / (t2 * tap), wpf * u * g * C / tap, wpf * u * b * S / tap,
+                   wqf * 2 * vf * vf * b / (t2 * tap), wqf * vf * vf * bc / (t2 * tap),
+                   wqf * u * g * S / tap, -wqf * u * b * C / tap,
+                   wpt * u * g * C / tap, -wpt * u * b * S / tap,
+                   -wqt * u * g * S / tap, -wqt * u * b * C / tap],
+        "br_shift_deg": [k * np.pi / 180 for k in
+                         (-wpf * u * g * S, wpf * u * b * C, wqf * u * g * C, wqf * u * b * S,
+                          -wpt * u * g * S, -wpt * u * b * C, -wqt * u * g * C, wqt * u * b * S)],
+    }
+    off = net.br_status == 0
+    out = {}
+    for k, v in terms.items():
+        a = np.array(v)
+        a[:, off] = 0.0
+        out[k] = a
+    return out
+
+
+def test_vjp_params_scale_is_sum_of_abs_terms(ora):
+    """The tolerance scale of the parameter gradients is the sum of |terms|
+    of each gradient: the explicit term lists add up to the oracle's
+    gradients (which the complex-step pin fixes), and their absolute values
+    add up to ora_vjp_params_scale, branch by branch, on the two-bus hand
+    circuits and on a grid with transformers, parallel and out-of-service
+    branches."""
+    nets = []
+    with open(os.path.join(GOLD, "two_bus.json")) as fh:
+        for case in json.load(fh)["cases"]:
+            br, st = case["branch"], case["state"]
+            two = synth.Network(
+                n_bus=2, br_from=[0], br_to=[1], br_r=[br["r"]], br_x=[br["x"]],
+                br_b=[br["b"]], br_tap=[br["tap"]], br_shift_deg=[br["shift_deg"]],
+                br_status=[1], load_bus=[1], load_p=[0.5], load_q=[0.1], pv_bus=[],
+                pv_p=[], pv_v=[], slack_bus=[0], slack_v=[st["vf"]],
+                slack_theta=[st["thf"]], shunt_bus=[], shunt_g=[], shunt_b=[])
+            # y = [theta_0, theta_1, V_0, V_1, Q_g, P_s]
+            nets.append((two, np.array([st["thf"], st["tht"], st["vf"], st["vt"], 0.2, 0.5])))
+    net = _net_with_everything(seed=5)
+    net.br_status[int(synth.non_bridge_branches(net)[1])] = 0
+    nets.append((net, synth.random_states(net, seed=31)))
+    rng = np.random.default_rng(33)
+    for net, yv in nets:
+        for _ in range(3):
+            w = rng.standard_normal(yv.size)
+            _, gp = ora.vjp(net, yv, w)
+            sc = ora.vjp_params_scale(net, yv, w)
+            terms = _param_gradient_terms(net, yv, w)
+            for name, tl in terms.items():
+                s_abs = np.abs(tl).sum(axis=0)
+                assert np.all(np.abs(tl.sum(axis=0) - gp[name]) <= 1e-13 * s_abs + 1e-300), name
+                assert np.all(np.abs(sc[name] - s_abs) <= 1e-13 * s_abs), name
+
+
 def test_vjp_outaged_branch_has_zero_gradient(ora):
     net = _net_with_everything()
     e = int(synth.non_bridge_branches(net)[0])
