@@ -73,7 +73,7 @@ def _load(path):
     L.ora_jacobian_size.argtypes = [ctypes.POINTER(_Topo)]
     L.ora_jacobian_size.restype = ctypes.c_long
     L.ora_jacobian.argtypes = [ctypes.POINTER(_Topo), ctypes.POINTER(_Data),
-                               _pd, _pi, _pi, _pd]
+                               _pd, _pi, _pi, _pd, _pd]
     L.ora_jacobian.restype = ctypes.c_long
     L.ora_vjp_params.argtypes = [ctypes.POINTER(_Topo), ctypes.POINTER(_Data),
                                  _pd, _pd] + [_pd] * 7
@@ -188,25 +188,31 @@ def branch_flows(r, x, bc, tap, shift_deg, vf, vt, thf, tht):
     return out
 
 
-def jacobian_coo(net, y, data=None, modes=None):
+def jacobian_coo(net, y, data=None, modes=None, scales=False):
+    """Jacobian triplets (rows, cols, values) model by model; with
+    ``scales`` also each triplet's sum of |products| (a tolerance scale)."""
     b = _Bound(net, data, modes)
     y = np.ascontiguousarray(y, dtype=np.float64)
     m = lib().ora_jacobian_size(ctypes.byref(b.topo))
     rows = np.empty(m, np.int32)
     cols = np.empty(m, np.int32)
     vals = np.empty(m)
+    sc = np.empty(m)
     k = lib().ora_jacobian(ctypes.byref(b.topo), ctypes.byref(b.data), _dp(y),
-                           _ip(rows), _ip(cols), _dp(vals))
+                           _ip(rows), _ip(cols), _dp(vals), _dp(sc))
+    if scales:
+        return rows[:k], cols[:k], vals[:k], sc[:k]
     return rows[:k], cols[:k], vals[:k]
 
 
 def jacobian(net, y, data=None, modes=None):
-    """(J, |J|-scale) as scipy CSR: triplets summed into a sparse matrix; the
-    second matrix sums the absolute triplet values (used for tolerances)."""
+    """(J, scale) as scipy CSR: triplets summed into a sparse matrix; the
+    second matrix sums the triplets' sums of |products| (used for
+    tolerances: a bound on the rounding of either side's sum)."""
     n = n_var(net)
-    r, c, v = jacobian_coo(net, y, data, modes)
+    r, c, v, m = jacobian_coo(net, y, data, modes, scales=True)
     J = sp.csr_matrix((v, (r, c)), shape=(n, n))
-    A = sp.csr_matrix((np.abs(v), (r, c)), shape=(n, n))
+    A = sp.csr_matrix((m, (r, c)), shape=(n, n))
     J.sort_indices()
     A.sort_indices()
     return J, A
@@ -215,11 +221,19 @@ def jacobian(net, y, data=None, modes=None):
 def vjp(net, y, w, data=None, modes=None):
     """(g_state, g_params) for the loss w.F: g_state = J^T w with the explicit
     Jacobian; g_params is a dict keyed by parameter name."""
-    b = _Bound(net, data)
-    y = np.ascontiguousarray(y, dtype=np.float64)
     w = np.ascontiguousarray(w, dtype=np.float64)
     J, _ = jacobian(net, y, data, modes)
     gx = J.T @ w
+    return gx, vjp_params(net, y, w, data)
+
+
+def vjp_params(net, y, w, data=None):
+    """The parameter half of vjp(): gradients of w.F with respect to every
+    branch's r, x, b, tap and shift (per degree) and every load's P and Q,
+    from the pi-model partials."""
+    b = _Bound(net, data)
+    y = np.ascontiguousarray(y, dtype=np.float64)
+    w = np.ascontiguousarray(w, dtype=np.float64)
     B, L = net.n_branch, net.n_load
     out = {k: np.empty(B) for k in ("br_r", "br_x", "br_b", "br_tap", "br_shift_deg")}
     out["load_p"] = np.empty(L)
@@ -228,7 +242,7 @@ def vjp(net, y, w, data=None, modes=None):
                          _dp(out["br_r"]), _dp(out["br_x"]), _dp(out["br_b"]),
                          _dp(out["br_tap"]), _dp(out["br_shift_deg"]),
                          _dp(out["load_p"]), _dp(out["load_q"]))
-    return gx, out
+    return out
 
 
 def vjp_params_scale(net, y, w, data=None):

@@ -18,7 +18,8 @@
  *   ora_residual      F(y) and, per row, the sum of |terms| (for tolerances)
  *   ora_residual_cs   F(y) in complex arithmetic (complex-step derivatives)
  *   ora_branch_flows  one branch's four terminal injections
- *   ora_jacobian      dF/dy as COO triplets, model by model
+ *   ora_jacobian      dF/dy as COO triplets, model by model, with each
+ *                     triplet's sum of |products| (for tolerances)
  *   ora_vjp_params    gradient of w.F with respect to branch and load data
  *   ora_vjp_params_scale  sum of |terms| behind each of those gradients
  */
@@ -46,18 +47,54 @@ typedef struct {
     const double *pv_qtarget;   /* per PV generator; read where pv_mode is 1 */
 } ora_data;
 
+/*
+ * Rounding scale of a branch's four terminal injections: for each flow, the
+ * sum of the absolute values of the products it is made of (with the
+ * charging half split from the series susceptance).  A flow is itself a
+ * difference of nearly equal products when the angle across the branch is
+ * small, so |flow| alone would understate the rounding of either side's sum.
+ */
+static void branch_flow_scales(double r, double x, double bc, double tap,
+                               double shift_deg, double vf, double vt,
+                               double thf, double tht, double out[4])
+{
+    const double d = r * r + x * x;
+    const double g = r / d, b = -x / d;
+    const double delta = thf - tht - shift_deg * (ORA_PI / 180.0);
+    const double c = cos(delta), s = sin(delta);
+    const double u = vf * vt / tap, t2 = tap * tap;
+    const double ugc = fabs(u * g * c), ubs = fabs(u * b * s);
+    const double ugs = fabs(u * g * s), ubc = fabs(u * b * c);
+    out[0] = fabs(vf * vf * g / t2) + ugc + ubs;
+    out[1] = fabs(vf * vf * b / t2) + fabs(vf * vf * bc / (2.0 * t2)) + ugs + ubc;
+    out[2] = fabs(vt * vt * g) + ugc + ubs;
+    out[3] = fabs(vt * vt * b) + fabs(vt * vt * bc / 2.0) + ugs + ubc;
+}
+
 /* ---- real instantiation ---- */
 #define ORA_T double
 #define ORA_SIN sin
 #define ORA_COS cos
 #define ORA_NAME(x) x##_d
 #define ORA_ACC(S, i, v) do { if (S) (S)[i] += fabs(v); } while (0)
+#define ORA_ACC_FLOWS(S, N, f, t, r, x, bc, tap, sh, vf, vt, thf, tht)         \
+    do {                                                                       \
+        if (S) {                                                               \
+            double m_[4];                                                      \
+            branch_flow_scales(r, x, bc, tap, sh, vf, vt, thf, tht, m_);       \
+            (S)[f] += m_[0];                                                   \
+            (S)[(N) + (f)] += m_[1];                                           \
+            (S)[t] += m_[2];                                                   \
+            (S)[(N) + (t)] += m_[3];                                           \
+        }                                                                      \
+    } while (0)
 #include "ora_core.inc"
 #undef ORA_T
 #undef ORA_SIN
 #undef ORA_COS
 #undef ORA_NAME
 #undef ORA_ACC
+#undef ORA_ACC_FLOWS
 
 /* ---- complex instantiation (complex-step differentiation) ---- */
 #define ORA_T double complex
@@ -65,12 +102,14 @@ typedef struct {
 #define ORA_COS ccos
 #define ORA_NAME(x) x##_z
 #define ORA_ACC(S, i, v) do { (void)(S); } while (0)
+#define ORA_ACC_FLOWS(S, N, f, t, r, x, bc, tap, sh, vf, vt, thf, tht) do { (void)(S); } while (0)
 #include "ora_core.inc"
 #undef ORA_T
 #undef ORA_SIN
 #undef ORA_COS
 #undef ORA_NAME
 #undef ORA_ACC
+#undef ORA_ACC_FLOWS
 
 void ora_residual(const ora_topo *tp, const ora_data *d, const double *y,
                   double *F, double *S)
@@ -109,12 +148,15 @@ void ora_branch_flows(double r, double x, double bc, double tap,
     branch_flows_d(r, x, bc, tap, shift_deg, vf, vt, thf, tht, out);
 }
 
-static long put(int *rows, int *cols, double *vals, long k, int r, int c,
-                double v)
+/* Store one triplet and, when asked for, its rounding scale m (the sum of
+ * the absolute values of the products the value is made of). */
+static long put(int *rows, int *cols, double *vals, double *scales, long k,
+                int r, int c, double v, double m)
 {
     rows[k] = r;
     cols[k] = c;
     vals[k] = v;
+    if (scales) scales[k] = m;
     return k + 1;
 }
 
@@ -144,36 +186,37 @@ long ora_jacobian_size(const ora_topo *tp)
  * (the divisions by V are carried out as products with the other voltage).
  */
 long ora_jacobian(const ora_topo *tp, const ora_data *dd, const double *y,
-                  int *rows, int *cols, double *vals)
+                  int *rows, int *cols, double *vals, double *scales)
 {
     const int N = tp->n_bus, NPV = tp->n_pv, NS = tp->n_slack;
     const int NG = NPV + NS;
     const double *th = y, *V = y + N;
     long k = 0;
     int e, i;
+#define PUT(r, c, v, m) (k = put(rows, cols, vals, scales, k, (r), (c), (v), (m)))
     /* PQ loads: constant power, no state dependence. */
     /* PV generators */
     for (e = 0; e < NPV; ++e) {
         i = tp->pv_bus[e];
-        k = put(rows, cols, vals, k, N + i, 2 * N + e, -1.0);     /* dFq/dQg */
+        PUT(N + i, 2 * N + e, -1.0, 1.0);                 /* dFq/dQg */
         if (tp->pv_mode && tp->pv_mode[e])
-            k = put(rows, cols, vals, k, 2 * N + e, 2 * N + e, 1.0);  /* d(Qg - Qt)/dQg */
+            PUT(2 * N + e, 2 * N + e, 1.0, 1.0);          /* d(Qg - Qt)/dQg */
         else
-            k = put(rows, cols, vals, k, 2 * N + e, N + i, 1.0);      /* dFV/dV */
+            PUT(2 * N + e, N + i, 1.0, 1.0);              /* dFV/dV */
     }
     /* Slack generators */
     for (e = 0; e < NS; ++e) {
         i = tp->slack_bus[e];
-        k = put(rows, cols, vals, k, i, 2 * N + NG + e, -1.0);        /* dFp/dPs */
-        k = put(rows, cols, vals, k, N + i, 2 * N + NPV + e, -1.0);   /* dFq/dQg */
-        k = put(rows, cols, vals, k, 2 * N + NPV + e, N + i, 1.0);    /* dFV/dV */
-        k = put(rows, cols, vals, k, 2 * N + NG + e, i, 1.0);         /* dFth/dth */
+        PUT(i, 2 * N + NG + e, -1.0, 1.0);                /* dFp/dPs */
+        PUT(N + i, 2 * N + NPV + e, -1.0, 1.0);           /* dFq/dQg */
+        PUT(2 * N + NPV + e, N + i, 1.0, 1.0);            /* dFV/dV */
+        PUT(2 * N + NG + e, i, 1.0, 1.0);                 /* dFth/dth */
     }
     /* Lines and transformers */
     for (e = 0; e < tp->n_branch; ++e) {
         int f, t;
         double r, x, bc, tap, phi, d, g, b, delta, C, S, u, t2;
-        double A1, B1, A2, B2, vf, vt;
+        double A1, B1, A2, B2, vf, vt, mA, mB, af, at;
         if (tp->br_status && !tp->br_status[e]) continue;
         f = tp->br_from[e];
         t = tp->br_to[e];
@@ -196,35 +239,45 @@ long ora_jacobian(const ora_topo *tp, const ora_data *dd, const double *y,
         B1 = u * (g * S - b * C);
         A2 = u * (g * C - b * S);
         B2 = u * (g * S + b * C);
+        /* scales: A1, A2 are made of u g C and u b S; B1, B2 of u g S and
+           u b C; the V partials of the same products over V_f or V_t */
+        mA = fabs(u * g * C) + fabs(u * b * S);
+        mB = fabs(u * g * S) + fabs(u * b * C);
+        af = vf / tap;
+        at = vt / tap;
         /* theta columns */
-        k = put(rows, cols, vals, k, f, f, B1);
-        k = put(rows, cols, vals, k, f, t, -B1);
-        k = put(rows, cols, vals, k, N + f, f, -A1);
-        k = put(rows, cols, vals, k, N + f, t, A1);
-        k = put(rows, cols, vals, k, t, f, B2);
-        k = put(rows, cols, vals, k, t, t, -B2);
-        k = put(rows, cols, vals, k, N + t, f, A2);
-        k = put(rows, cols, vals, k, N + t, t, -A2);
+        PUT(f, f, B1, mB);
+        PUT(f, t, -B1, mB);
+        PUT(N + f, f, -A1, mA);
+        PUT(N + f, t, A1, mA);
+        PUT(t, f, B2, mB);
+        PUT(t, t, -B2, mB);
+        PUT(N + t, f, A2, mA);
+        PUT(N + t, t, -A2, mA);
         /* V columns */
-        k = put(rows, cols, vals, k, f, N + f,
-                2.0 * vf * g / t2 - (vt / tap) * (g * C + b * S));
-        k = put(rows, cols, vals, k, f, N + t, -(vf / tap) * (g * C + b * S));
-        k = put(rows, cols, vals, k, N + f, N + f,
-                -2.0 * vf * (b + bc / 2.0) / t2 - (vt / tap) * (g * S - b * C));
-        k = put(rows, cols, vals, k, N + f, N + t, -(vf / tap) * (g * S - b * C));
-        k = put(rows, cols, vals, k, t, N + f, -(vt / tap) * (g * C - b * S));
-        k = put(rows, cols, vals, k, t, N + t,
-                2.0 * vt * g - (vf / tap) * (g * C - b * S));
-        k = put(rows, cols, vals, k, N + t, N + f, (vt / tap) * (g * S + b * C));
-        k = put(rows, cols, vals, k, N + t, N + t,
-                -2.0 * vt * (b + bc / 2.0) + (vf / tap) * (g * S + b * C));
+        PUT(f, N + f, 2.0 * vf * g / t2 - (vt / tap) * (g * C + b * S),
+            fabs(2.0 * vf * g / t2) + fabs(at * g * C) + fabs(at * b * S));
+        PUT(f, N + t, -(vf / tap) * (g * C + b * S), fabs(af * g * C) + fabs(af * b * S));
+        PUT(N + f, N + f, -2.0 * vf * (b + bc / 2.0) / t2 - (vt / tap) * (g * S - b * C),
+            fabs(2.0 * vf * b / t2) + fabs(vf * bc / t2) + fabs(at * g * S) + fabs(at * b * C));
+        PUT(N + f, N + t, -(vf / tap) * (g * S - b * C), fabs(af * g * S) + fabs(af * b * C));
+        PUT(t, N + f, -(vt / tap) * (g * C - b * S), fabs(at * g * C) + fabs(at * b * S));
+        PUT(t, N + t, 2.0 * vt * g - (vf / tap) * (g * C - b * S),
+            fabs(2.0 * vt * g) + fabs(af * g * C) + fabs(af * b * S));
+        PUT(N + t, N + f, (vt / tap) * (g * S + b * C), fabs(at * g * S) + fabs(at * b * C));
+        PUT(N + t, N + t, -2.0 * vt * (b + bc / 2.0) + (vf / tap) * (g * S + b * C),
+            fabs(2.0 * vt * b) + fabs(vt * bc) + fabs(af * g * S) + fabs(af * b * C));
     }
     /* Shunts */
     for (e = 0; e < tp->n_shunt; ++e) {
+        double vg, vb;
         i = tp->shunt_bus[e];
-        k = put(rows, cols, vals, k, i, N + i, 2.0 * dd->shunt_g[e] * V[i]);
-        k = put(rows, cols, vals, k, N + i, N + i, -2.0 * dd->shunt_b[e] * V[i]);
+        vg = 2.0 * dd->shunt_g[e] * V[i];
+        vb = -2.0 * dd->shunt_b[e] * V[i];
+        PUT(i, N + i, vg, fabs(vg));
+        PUT(N + i, N + i, vb, fabs(vb));
     }
+#undef PUT
     return k;
 }
 

@@ -38,18 +38,17 @@ MUTANTS = [
     ("load Q uses P", "ora_core.inc", "Fq[i] += load_q[k];", "Fq[i] += load_p[k];"),
     ("PV Q_g index", "ora_core.inc", "Fq[i] -= Qg[k];", "Fq[i] -= Qg[NPV - 1 - k];"),
     ("to-bus row gets from flow", "ora_core.inc", "Fp[t] += fl[2];", "Fp[t] += fl[0];"),
-    ("J dPf/dth_t sign", "pf_oracle.c", "k = put(rows, cols, vals, k, f, t, -B1);",
-     "k = put(rows, cols, vals, k, f, t, B1);"),
-    ("J dQf/dV_t column", "pf_oracle.c",
-     "k = put(rows, cols, vals, k, N + f, N + t, -(vf / tap) * (g * S - b * C));",
-     "k = put(rows, cols, vals, k, N + f, t, -(vf / tap) * (g * S - b * C));"),
-    ("J dPt/dV_t factor 2 dropped", "pf_oracle.c", "2.0 * vt * g - (vf / tap) * (g * C - b * S));",
-     "vt * g - (vf / tap) * (g * C - b * S));"),
-    ("J transposed dQt/dth", "pf_oracle.c", "k = put(rows, cols, vals, k, N + t, f, A2);",
-     "k = put(rows, cols, vals, k, f, N + t, A2);"),
-    ("J shunt Q sign", "pf_oracle.c", "-2.0 * dd->shunt_b[e] * V[i]);", "2.0 * dd->shunt_b[e] * V[i]);"),
-    ("J slack theta row", "pf_oracle.c", "k = put(rows, cols, vals, k, 2 * N + NG + e, i, 1.0);",
-     "k = put(rows, cols, vals, k, 2 * N + NG + e, N + i, 1.0);"),
+    ("J dPf/dth_t sign", "pf_oracle.c", "PUT(f, t, -B1, mB);", "PUT(f, t, B1, mB);"),
+    ("J dQf/dV_t column", "pf_oracle.c", "PUT(N + f, N + t, -(vf / tap) * (g * S - b * C),",
+     "PUT(N + f, t, -(vf / tap) * (g * S - b * C),"),
+    ("J dPt/dV_t factor 2 dropped", "pf_oracle.c",
+     "PUT(t, N + t, 2.0 * vt * g - (vf / tap) * (g * C - b * S),",
+     "PUT(t, N + t, vt * g - (vf / tap) * (g * C - b * S),"),
+    ("J transposed dQt/dth", "pf_oracle.c", "PUT(N + t, f, A2, mA);", "PUT(f, N + t, A2, mA);"),
+    ("J shunt Q sign", "pf_oracle.c", "vb = -2.0 * dd->shunt_b[e] * V[i];",
+     "vb = 2.0 * dd->shunt_b[e] * V[i];"),
+    ("J slack theta row", "pf_oracle.c", "PUT(2 * N + NG + e, i, 1.0, 1.0);",
+     "PUT(2 * N + NG + e, N + i, 1.0, 1.0);"),
     ("vjp dg/dx sign", "pf_oracle.c", "dg_dx = -2.0 * r * x / D2;", "dg_dx = 2.0 * r * x / D2;"),
     ("vjp tap term", "pf_oracle.c", "wpt * (A2 / tap) + wqt * (-B2 / tap);",
      "wpt * (A2 / tap) + wqt * (B2 / tap);"),
@@ -62,8 +61,22 @@ MUTANTS = [
     ("scale difference counted once", "pf_oracle.c", "s_r[e] = (sg * (x * x + r * r)",
      "s_r[e] = (sg * fabs(x * x - r * r)"),
     ("scale tap charging dropped", "pf_oracle.c", "(ab + fabs(bc) / 2.0)", "(ab)"),
-    ("J held PV column", "pf_oracle.c", "k = put(rows, cols, vals, k, 2 * N + e, 2 * N + e, 1.0);",
-     "k = put(rows, cols, vals, k, 2 * N + e, N + i, 1.0);"),
+    ("J held PV column", "pf_oracle.c", "PUT(2 * N + e, 2 * N + e, 1.0, 1.0);",
+     "PUT(2 * N + e, N + i, 1.0, 1.0);"),
+    ("flow scale drops u b S", "pf_oracle.c", "out[0] = fabs(vf * vf * g / t2) + ugc + ubs;",
+     "out[0] = fabs(vf * vf * g / t2) + ugc;"),
+    ("flow scale charging dropped", "pf_oracle.c",
+     "out[3] = fabs(vt * vt * b) + fabs(vt * vt * bc / 2.0) + ugs + ubc;",
+     "out[3] = fabs(vt * vt * b) + ugs + ubc;"),
+    ("flow scale to-side uses V_f", "pf_oracle.c", "out[2] = fabs(vt * vt * g) + ugc + ubs;",
+     "out[2] = fabs(vf * vf * g) + ugc + ubs;"),
+    ("J scale of B1 taken as |B1|", "pf_oracle.c", "mB = fabs(u * g * S) + fabs(u * b * C);",
+     "mB = fabs(u * (g * S - b * C));"),
+    ("J scale dQf/dV_f charging dropped", "pf_oracle.c",
+     "fabs(2.0 * vf * b / t2) + fabs(vf * bc / t2) + fabs(at * g * S)",
+     "fabs(2.0 * vf * b / t2) + fabs(at * g * S)"),
+    ("J scale shunt dropped", "pf_oracle.c", "PUT(i, N + i, vg, fabs(vg));",
+     "PUT(i, N + i, vg, 0.0);"),
 ]
 
 PINS = [
@@ -81,6 +94,8 @@ PINS = [
     P.test_vjp_state_is_transpose_product,
     P.test_vjp_params_complex_step,
     P.test_vjp_params_scale_is_sum_of_abs_terms,
+    P.test_residual_scale_is_sum_of_abs_products,
+    P.test_jacobian_scale_is_sum_of_abs_products,
     Q.test_held_output_equals_pq_injection,
     lambda o: Q.test_jacobian_complex_step_with_held_outputs(o, "tiny"),
 ]

@@ -394,6 +394,182 @@ def test_vjp_params_scale_is_sum_of_abs_terms(ora):
                 assert np.all(np.abs(sc[name] - s_abs) <= 1e-13 * s_abs), name
 
 
+def _flow_products(net, yv):
+    """The signed products each in-service branch's four terminal injections
+    are made of (the pi-model of Section II-A: series g + jb = 1/(r + jx),
+    charging bc/2 per end, ideal transformer t e^{j phi} on the from side):
+    P_f = Vf^2 g/t^2 - u g C - u b S, Q_f = -Vf^2 b/t^2 - Vf^2 bc/(2t^2)
+    - u g S + u b C, P_t = Vt^2 g - u g C + u b S, Q_t = -Vt^2 b - Vt^2 bc/2
+    + u g S + u b C, with u = Vf Vt / t and C, S of th_f - th_t - phi.
+    Returns (from rows, to rows, [P_f, Q_f, P_t, Q_t] term arrays
+    [n_terms, B_on])."""
+    N = net.n_bus
+    on = net.br_status != 0
+    f, t = net.br_from[on], net.br_to[on]
+    r, x, bc, tap = net.br_r[on], net.br_x[on], net.br_b[on], net.br_tap[on]
+    phi = np.deg2rad(net.br_shift_deg[on])
+    D = r * r + x * x
+    g, b = r / D, -x / D
+    vf, vt = yv[N + f], yv[N + t]
+    d = yv[f] - yv[t] - phi
+    C, S = np.cos(d), np.sin(d)
+    u = vf * vt / tap
+    t2 = tap * tap
+    z = np.zeros_like(u)
+    pf = [vf * vf * g / t2, -u * g * C, -u * b * S, z]
+    qf = [-vf * vf * b / t2, -vf * vf * bc / (2 * t2), -u * g * S, u * b * C]
+    pt = [vt * vt * g, -u * g * C, u * b * S, z]
+    qt = [-vt * vt * b, -vt * vt * bc / 2, u * g * S, u * b * C]
+    return f, t, [np.array(a) for a in (pf, qf, pt, qt)]
+
+
+def _residual_products(net, yv):
+    """Every row of F written out as its list of signed products, per model:
+    loads, PV and slack generators, branch flows and shunts; returns
+    (rows, terms) with one entry per product."""
+    N, NPV = net.n_bus, net.n_pv
+    NG = NPV + net.n_slack
+    V = yv[N:2 * N]
+    Qg, Ps = yv[2 * N:2 * N + NG], yv[2 * N + NG:]
+    rows, terms = [], []
+
+    def add(r, v):
+        rows.append(np.atleast_1d(np.asarray(r, np.int64)))
+        terms.append(np.atleast_1d(np.asarray(v, float)))
+    add(net.load_bus, net.load_p)
+    add(N + net.load_bus, net.load_q)
+    add(net.pv_bus, -net.pv_p)
+    add(N + net.pv_bus, -Qg[:NPV])
+    add(2 * N + np.arange(NPV), V[net.pv_bus])
+    add(2 * N + np.arange(NPV), -net.pv_v)
+    add(net.slack_bus, -Ps)
+    add(N + net.slack_bus, -Qg[NPV:])
+    add(2 * N + NPV + np.arange(net.n_slack), V[net.slack_bus])
+    add(2 * N + NPV + np.arange(net.n_slack), -net.slack_v)
+    add(2 * N + NG + np.arange(net.n_slack), yv[net.slack_bus])
+    add(2 * N + NG + np.arange(net.n_slack), -net.slack_theta)
+    f, t, (pf, qf, pt, qt) = _flow_products(net, yv)
+    for row, tl in ((f, pf), (N + f, qf), (t, pt), (N + t, qt)):
+        for term in tl:
+            add(row, term)
+    add(net.shunt_bus, net.shunt_g * V[net.shunt_bus] ** 2)
+    add(N + net.shunt_bus, -net.shunt_b * V[net.shunt_bus] ** 2)
+    return np.concatenate(rows), np.concatenate(terms)
+
+
+def _scale_cases():
+    """Two-bus hand circuits of the golden file and a grid with
+    transformers, shunts, parallel and out-of-service branches."""
+    cases = []
+    with open(os.path.join(GOLD, "two_bus.json")) as fh:
+        for case in json.load(fh)["cases"]:
+            br, st = case["branch"], case["state"]
+            two = synth.Network(
+                n_bus=2, br_from=[0], br_to=[1], br_r=[br["r"]], br_x=[br["x"]],
+                br_b=[br["b"]], br_tap=[br["tap"]], br_shift_deg=[br["shift_deg"]],
+                br_status=[1], load_bus=[1], load_p=[0.5], load_q=[0.1], pv_bus=[],
+                pv_p=[], pv_v=[], slack_bus=[0], slack_v=[st["vf"]],
+                slack_theta=[st["thf"]], shunt_bus=[1], shunt_g=[0.01], shunt_b=[0.2])
+            cases.append((two, np.array([st["thf"], st["tht"], st["vf"], st["vt"], 0.2, 0.5])))
+    net = _net_with_everything(seed=5)
+    net.br_status[int(synth.non_bridge_branches(net)[1])] = 0
+    cases.append((net, synth.random_states(net, seed=31)))
+    return cases
+
+
+def test_residual_scale_is_sum_of_abs_products(ora):
+    """The residual's tolerance scale S is, row by row, the sum of the
+    absolute values of the products the row is made of: the explicit
+    product lists add up to F (which the other pins fix) and their absolute
+    values to S.  A branch flow counts as its products, not as one term."""
+    for net, yv in _scale_cases():
+        F, S = ora.residual(net, yv)
+        rows, terms = _residual_products(net, yv)
+        n = F.size
+        tot = np.bincount(rows, weights=terms, minlength=n)
+        mag = np.bincount(rows, weights=np.abs(terms), minlength=n)
+        assert np.all(np.abs(tot - F) <= 1e-13 * mag + 1e-300)
+        assert np.all(np.abs(S - mag) <= 1e-13 * mag + 1e-300)
+        # a flow at a small angle is a difference of nearly equal products
+        assert np.max(mag / (np.abs(F) + 1e-300)) > 10
+
+
+def _jacobian_products(net, yv):
+    """Every Jacobian triplet of the branch and device models written out as
+    its signed products (the partials of the flows of _flow_products with
+    respect to th_f, th_t, V_f, V_t, and the constant and shunt entries);
+    returns (rows, cols, terms), one entry per product."""
+    N, NPV = net.n_bus, net.n_pv
+    NG = NPV + net.n_slack
+    V = yv[N:2 * N]
+    on = net.br_status != 0
+    f, t = net.br_from[on], net.br_to[on]
+    r, x, bc, tap = net.br_r[on], net.br_x[on], net.br_b[on], net.br_tap[on]
+    phi = np.deg2rad(net.br_shift_deg[on])
+    D = r * r + x * x
+    g, b = r / D, -x / D
+    vf, vt = yv[N + f], yv[N + t]
+    d = yv[f] - yv[t] - phi
+    C, S = np.cos(d), np.sin(d)
+    u = vf * vt / tap
+    t2 = tap * tap
+    af, at = vf / tap, vt / tap
+    rows, cols, terms = [], [], []
+
+    def add(rr, cc, *tl):
+        for term in tl:
+            rows.append(np.atleast_1d(np.asarray(rr, np.int64)))
+            cols.append(np.atleast_1d(np.asarray(cc, np.int64)))
+            terms.append(np.atleast_1d(np.asarray(term, float)))
+    one = np.ones(NPV)
+    add(N + net.pv_bus, 2 * N + np.arange(NPV), -one)
+    add(2 * N + np.arange(NPV), N + net.pv_bus, one)
+    ones = np.ones(net.n_slack)
+    add(net.slack_bus, 2 * N + NG + np.arange(net.n_slack), -ones)
+    add(N + net.slack_bus, 2 * N + NPV + np.arange(net.n_slack), -ones)
+    add(2 * N + NPV + np.arange(net.n_slack), N + net.slack_bus, ones)
+    add(2 * N + NG + np.arange(net.n_slack), net.slack_bus, ones)
+    B1, A1 = (u * g * S, -u * b * C), (u * g * C, u * b * S)
+    B2, A2 = (u * g * S, u * b * C), (u * g * C, -u * b * S)
+    neg = lambda tl: tuple(-a for a in tl)   # noqa: E731
+    add(f, f, *B1)
+    add(f, t, *neg(B1))
+    add(N + f, f, *neg(A1))
+    add(N + f, t, *A1)
+    add(t, f, *B2)
+    add(t, t, *neg(B2))
+    add(N + t, f, *A2)
+    add(N + t, t, *neg(A2))
+    add(f, N + f, 2 * vf * g / t2, -at * g * C, -at * b * S)
+    add(f, N + t, -af * g * C, -af * b * S)
+    add(N + f, N + f, -2 * vf * b / t2, -vf * bc / t2, -at * g * S, at * b * C)
+    add(N + f, N + t, -af * g * S, af * b * C)
+    add(t, N + f, -at * g * C, at * b * S)
+    add(t, N + t, 2 * vt * g, -af * g * C, af * b * S)
+    add(N + t, N + f, at * g * S, at * b * C)
+    add(N + t, N + t, -2 * vt * b, -vt * bc, af * g * S, af * b * C)
+    add(net.shunt_bus, N + net.shunt_bus, 2 * net.shunt_g * V[net.shunt_bus])
+    add(N + net.shunt_bus, N + net.shunt_bus, -2 * net.shunt_b * V[net.shunt_bus])
+    return np.concatenate(rows), np.concatenate(cols), np.concatenate(terms)
+
+
+def test_jacobian_scale_is_sum_of_abs_products(ora):
+    """The Jacobian's tolerance scale is, entry by entry, the sum of the
+    absolute values of the products behind it: the explicit product lists
+    of the pi-model partials add up to J (which the complex-step pin fixes)
+    and their absolute values to the oracle's scale matrix."""
+    for net, yv in _scale_cases():
+        J, A = ora.jacobian(net, yv)
+        r, c, terms = _jacobian_products(net, yv)
+        n = J.shape[0]
+        T = sp.csr_matrix((terms, (r, c)), shape=(n, n)).toarray()
+        M = sp.csr_matrix((np.abs(terms), (r, c)), shape=(n, n)).toarray()
+        Jd, Ad = J.toarray(), A.toarray()
+        assert np.all(np.abs(T - Jd) <= 1e-13 * M + 1e-300)
+        assert np.all(np.abs(Ad - M) <= 1e-13 * M + 1e-300)
+        assert np.array_equal(Ad != 0, M != 0)
+
+
 def test_vjp_outaged_branch_has_zero_gradient(ora):
     net = _net_with_everything()
     e = int(synth.non_bridge_branches(net)[0])
