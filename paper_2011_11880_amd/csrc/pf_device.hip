@@ -532,9 +532,13 @@ k_eval_batch(int N, int I, int LD, int panel, int64_t rows_x, int64_t rows_j, in
                     GG[u] = yG[bi.x + u];
                     BB[u] = yB[bi.x + u];
                 }
+                // the diagonal entry needs no partner state: its loads
+                // would only repeat the bus's own
 #pragma unroll
                 for (int u = 0; u < EU; ++u) {
-                    if (u < L) {
+                    thj[u] = thi;
+                    vj[u] = vi;
+                    if (u < L && u != b2.x) {
                         thj[u] = Xc[size_t(jj[u]) * SI + kk];
                         vj[u] = Xc[size_t(N + jj[u]) * SI + kk];
                     }
@@ -570,7 +574,9 @@ k_eval_batch(int N, int I, int LD, int panel, int64_t rows_x, int64_t rows_j, in
                     }
 #pragma unroll
                     for (int u = 0; u < EU; ++u) {
-                        if (e0 + u < bi.y) {
+                        t2[u] = thi;
+                        v2[u] = vi;
+                        if (e0 + u < bi.y && j2[u] != b) {
                             t2[u] = Xc[size_t(j2[u]) * SI + kk];
                             v2[u] = Xc[size_t(N + j2[u]) * SI + kk];
                         }
@@ -662,7 +668,9 @@ k_eval_batch(int N, int I, int LD, int panel, int64_t rows_x, int64_t rows_j, in
                 }
 #pragma unroll
                 for (int u = 0; u < EU; ++u) {
-                    if (e0 + u < bi.y) {
+                    thj[u] = thi;
+                    vj[u] = vi;
+                    if (e0 + u < bi.y && jj[u] != b) {
                         thj[u] = Xc[size_t(jj[u]) * SI + kk];
                         vj[u] = Xc[size_t(N + jj[u]) * SI + kk];
                     }
