@@ -288,6 +288,9 @@ int pf_eval_batch(pf_plan *plan, const double *X, double *F, double *Jval,
  * (n_params doubles; concatenated in grid order for multi-grid plans) and
  * rebuild every derived coefficient on the device.  The pattern is fixed:
  * r = x = 0 or tap <= 0 are not checked here and yield non-finite values.
+ * The fast decoupled matrices (pf_fdlf_matrices, pf_fdlf_create) are built
+ * on the host; the first such call after pf_set_params waits for the device
+ * and copies the new parameters back before building them.
  */
 int pf_set_params(pf_plan *plan, const double *params, void *stream);
 
@@ -307,13 +310,30 @@ int pf_get_schedule(const pf_plan *plan, pf_schedule *sched);
 int pf_set_schedule(pf_plan *plan, const pf_schedule *sched);
 
 /*
- * Autotuner: times every candidate schedule of the plan's kernel on the
- * given buffers (single: x, F, Jval as pf_eval; batched: as pf_eval_batch),
- * keeps the fastest and returns it in *best (nullable).  reps >= 1 timed
- * launches per candidate (median).  Synchronises the stream.
+ * Autotuner: coordinate descent over the plan kernel's schedules (tile
+ * size, work-item size, bus order, instance-chunk grouping, waves per
+ * block, grid size, XCD mapping), each candidate timed on the given buffers
+ * (single: x, F, Jval as pf_eval; batched: as pf_eval_batch) as the median
+ * of reps >= 1 launches; a candidate must be 1.5% faster than the best so
+ * far to replace it.  The winner becomes the plan's schedule and is
+ * returned in *best (nullable).  Synchronises the stream.  Every schedule
+ * gives bit-identical outputs.
+ *
+ * Tune cache: with cache_path non-NULL and non-empty, the text file there
+ * is searched first for a line keyed by the GPU (architecture, compute
+ * units), the kernel source the library was built from and the plan's
+ * shape (kind, sizes, grids, instances, pitch, layout, overlays, outputs
+ * asked for).  On a hit that schedule is applied without timing anything
+ * and *hit (nullable) is set to 1; on a miss the search runs and appends its
+ * result to the file (PF_EINVAL if the file cannot be written).
+ * pf_autotune is pf_autotune_cached with the path taken from the
+ * environment variable PF_TUNE_CACHE (unset or empty: no cache).
  */
 int pf_autotune(pf_plan *plan, const double *x, double *F, double *Jval,
                 int32_t reps, void *stream, pf_schedule *best);
+int pf_autotune_cached(pf_plan *plan, const double *x, double *F, double *Jval,
+                       int32_t reps, void *stream, const char *cache_path,
+                       pf_schedule *best, int32_t *hit);
 
 /*
  * Newton power flow (tasks 1-4, Section I): full steps
@@ -322,7 +342,8 @@ int pf_autotune(pf_plan *plan, const double *x, double *F, double *Jval,
  * F to host and calls solve(user, n, rowptr, colidx, Jval_host, rhs_host,
  * dx_host), which must fill dx and return 0 (non-zero -> PF_ESOLVE).
  * x: device [n], updated in place.  Runs on the default stream and
- * synchronises.  report (nullable) receives iteration counts, per-iteration
+ * synchronises; work queued on other (non-blocking) streams that writes x
+ * must be complete before the call.  report (nullable) receives iteration counts, per-iteration
  * norms (up to 64) and times.  Returns PF_ENOCONV if max_iter is reached.
  */
 typedef int (*pf_linsolve_fn)(void *user, int64_t n, const int32_t *rowptr,

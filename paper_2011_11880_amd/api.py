@@ -8,6 +8,7 @@ must be contiguous float64 CUDA tensors of the documented shapes.
 from __future__ import annotations
 
 import ctypes
+import os
 
 import numpy as np
 
@@ -378,8 +379,13 @@ class Plan:
                                 _ptr(gparam, self.n_params * k, "gparam"), _stream(dev)))
         return gx, gparam
 
-    def autotune(self, x, F=None, J=None, reps=5):
-        """Time every candidate schedule on these buffers and keep the fastest."""
+    def autotune(self, x, F=None, J=None, reps=5, cache=None):
+        """Time every candidate schedule on these buffers and keep the fastest
+        (pf_autotune).  ``cache``: path of a tune-cache file
+        (pf_autotune_cached; a hit applies the stored schedule without
+        timing, a miss appends the result); None leaves the choice to the
+        PF_TUNE_CACHE environment variable.  ``self.tune_hit`` records
+        whether the schedule came from the cache."""
         dev = self._dev(x)
         best = capi.pf_schedule()
         if self.info["kind"] == "batch":
@@ -390,8 +396,12 @@ class Plan:
             Js = _ptr(J, math.prod(sj), "J")
         else:
             xs, Fs, Js = _ptr(x, self.n, "x"), _ptr(F, self.n, "F"), _ptr(J, self.nnz, "J")
-        check(capi.lib().pf_autotune(self._h, xs, Fs, Js, int(reps), _stream(dev),
-                                     ctypes.byref(best)))
+        hit = ctypes.c_int32(0)
+        path = os.environ.get("PF_TUNE_CACHE", "") if cache is None else os.fspath(cache)
+        check(capi.lib().pf_autotune_cached(self._h, xs, Fs, Js, int(reps), _stream(dev),
+                                            path.encode() if path else None,
+                                            ctypes.byref(best), ctypes.byref(hit)))
+        self.tune_hit = bool(hit.value)
         self._load_info()
         return best.as_dict()
 
@@ -432,6 +442,10 @@ class Plan:
 
         opts = capi.pf_newton_opts(tol=float(tol), max_iter=int(max_iter))
         rep = capi.pf_newton_report()
+        # pf_newton works on the null stream; whatever the caller's stream
+        # still has to write into x must land first
+        import torch
+        torch.cuda.current_stream(self._dev(x)).synchronize()
         rc = capi.lib().pf_newton(self._h, _ptr(x, n, "x"), ctypes.byref(opts), cb, None,
                                   ctypes.byref(rep))
         if rc not in (capi.PF_OK, capi.PF_ENOCONV):

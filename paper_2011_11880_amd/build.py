@@ -52,9 +52,11 @@ def build(verbose: bool = False) -> str:
         o = os.path.join(BUILD_DIR, s + ".o")
         _run(["g++", *HOST_FLAGS, *inc, "-c", os.path.join(CSRC, s), "-o", o])
         objs.append(o)
+    # the tune cache keys schedules by the kernel source they were timed on
+    tag = [f'-DPF_KERNEL_SHA="{kernel_source_hash()}"']
     for s in DEVICE_SRCS:
         o = os.path.join(BUILD_DIR, s + ".o")
-        out = _run([HIPCC, *HIP_FLAGS, *inc, "-c", os.path.join(CSRC, s), "-o", o])
+        out = _run([HIPCC, *HIP_FLAGS, *tag, *inc, "-c", os.path.join(CSRC, s), "-o", o])
         if verbose and out.strip():
             print(out)
         objs.append(o)

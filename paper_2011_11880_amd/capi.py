@@ -108,6 +108,8 @@ SIGNATURES = {
     "pf_get_schedule": (ctypes.c_int, [_P, ctypes.POINTER(pf_schedule)]),
     "pf_set_schedule": (ctypes.c_int, [_P, ctypes.POINTER(pf_schedule)]),
     "pf_autotune": (ctypes.c_int, [_P, _vp, _vp, _vp, _i32, _vp, ctypes.POINTER(pf_schedule)]),
+    "pf_autotune_cached": (ctypes.c_int, [_P, _vp, _vp, _vp, _i32, _vp, ctypes.c_char_p,
+                                          ctypes.POINTER(pf_schedule), _pi32]),
     "pf_newton": (ctypes.c_int, [_P, _vp, ctypes.POINTER(pf_newton_opts), pf_linsolve_fn, _vp,
                                  ctypes.POINTER(pf_newton_report)]),
     "pf_set_gen_modes": (ctypes.c_int, [_P, _pi32, _pd]),

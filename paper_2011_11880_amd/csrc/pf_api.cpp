@@ -1,6 +1,7 @@
 // C ABI of libpf (declared in include/pf.h): argument checks and dispatch to
 // the host setup and the device layer.  No computation of the hot path
 // happens here.
+#include <cstdlib>
 #include <cstring>
 #include <new>
 
@@ -225,7 +226,9 @@ int pf_set_params(pf_plan *plan, const double *params, void *stream) {
     if (!plan) return fail(PF_EINVAL, "plan is NULL");
     if (plan->host.host_only || !plan->dev) return fail(PF_EINVAL, "plan is host-only");
     if (!params && plan->host.n_params() > 0) return fail(PF_EINVAL, "params is NULL");
-    return dev_set_params(plan->host, plan->dev, params, stream);
+    const int rc = dev_set_params(plan->host, plan->dev, params, stream);
+    if (!rc) plan->host.params_stale = true;
+    return rc;
 }
 
 int pf_vjp(pf_plan *plan, const double *x, const double *W, int32_t k, double *gx,
@@ -261,14 +264,21 @@ int pf_set_schedule(pf_plan *plan, const pf_schedule *sched) {
     return PF_OK;
 }
 
-int pf_autotune(pf_plan *plan, const double *x, double *F, double *Jval, int32_t reps,
-                void *stream, pf_schedule *best) {
+int pf_autotune_cached(pf_plan *plan, const double *x, double *F, double *Jval, int32_t reps,
+                       void *stream, const char *cache_path, pf_schedule *best, int32_t *hit) {
     clear_error();
+    if (hit) *hit = 0;
     if (!plan) return fail(PF_EINVAL, "plan is NULL");
     if (plan->host.host_only || !plan->dev) return fail(PF_EINVAL, "plan is host-only");
     if (!x || (!F && !Jval)) return fail(PF_EINVAL, "need x and at least one output");
     if (reps < 1) return fail(PF_EINVAL, "reps must be >= 1");
-    return dev_autotune(plan->host, plan->dev, x, F, Jval, reps, stream, best);
+    return dev_autotune(plan->host, plan->dev, x, F, Jval, reps, stream, cache_path, best, hit);
+}
+
+int pf_autotune(pf_plan *plan, const double *x, double *F, double *Jval, int32_t reps,
+                void *stream, pf_schedule *best) {
+    return pf_autotune_cached(plan, x, F, Jval, reps, stream, std::getenv("PF_TUNE_CACHE"), best,
+                              nullptr);
 }
 
 int pf_newton(pf_plan *plan, double *x, const pf_newton_opts *opts, pf_linsolve_fn solve,

@@ -23,6 +23,9 @@
 #include <algorithm>
 #include <chrono>
 #include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <string>
 #include <vector>
 
 #include "pf_internal.hpp"
@@ -35,6 +38,10 @@ namespace pf {
         if (e_ != hipSuccess)                                                      \
             return fail(PF_EDEVICE, "%s failed: %s", #expr, hipGetErrorString(e_)); \
     } while (0)
+
+// Relative margin by which a candidate schedule must beat the best so far in
+// the autotuner's search.
+constexpr float kTuneMargin = 0.015f;
 
 // Trailing padding of the admittance-entry arrays (>= the batched kernel's
 // entry group size minus one).
@@ -1325,6 +1332,19 @@ int dev_set_params(HostPlan &hp, DevPlan *dp, const double *params_dev, void *st
     return build_coeffs(hp, dp, st);
 }
 
+// Host copy of the parameters after pf_set_params (read by the host-side
+// builders of the fast decoupled matrices): waits for the device, then copies.
+int dev_fetch_params(HostPlan &hp, DevPlan *dp) {
+    DeviceGuard g(dp->device);
+    if (!g.ok) return fail(PF_EDEVICE, "cannot select device %d", dp->device);
+    const size_t np = size_t(hp.n_params());
+    HIP_TRY(hipDeviceSynchronize());
+    if (np) HIP_TRY(hipMemcpy(hp.params.data(), dp->params, np * sizeof(double),
+                              hipMemcpyDeviceToHost));
+    hp.params_stale = false;
+    return PF_OK;
+}
+
 static void wave_grid(int64_t units, const pf_schedule &s, int &blocks, int &units_per_wave) {
     const int wpb = s.waves_per_block;
     if (units <= 0) {
@@ -1502,37 +1522,37 @@ int dev_newton(HostPlan &hp, DevPlan *dp, double *x, const pf_newton_opts *opts,
 
 
 // Median time (ms) of `reps` launches of the plan's kernel under its
-// current schedule, each bracketed by its own pair of events.
+// current schedule, each bracketed by its own pair of events (released on
+// every path).
 static int time_schedule(HostPlan &hp, DevPlan *dp, const double *x, double *F, double *J,
                          int reps, hipStream_t st, float &ms_out) {
-    std::vector<hipEvent_t> ev(2 * size_t(reps));
-    for (auto &e : ev) HIP_TRY(hipEventCreate(&e));
-    int rc = PF_OK;
+    std::vector<hipEvent_t> ev(2 * size_t(reps), nullptr);
     auto launch = [&]() {
         return hp.kind == KIND_BATCH ? dev_eval_batch(hp, dp, x, F, J, st)
                                      : dev_eval_single(hp, dp, x, F, J, st);
     };
-    rc = launch();  // warm-up
-    for (int r = 0; r < reps && !rc; ++r) {
-        HIP_TRY(hipEventRecord(ev[2 * r], st));
-        rc = launch();
-        HIP_TRY(hipEventRecord(ev[2 * r + 1], st));
-    }
-    if (!rc) HIP_TRY(hipStreamSynchronize(st));
-    std::vector<float> t(reps, 0.f);
-    for (int r = 0; r < reps && !rc; ++r)
-        HIP_TRY(hipEventElapsedTime(&t[r], ev[2 * r], ev[2 * r + 1]));
-    for (auto &e : ev) (void)hipEventDestroy(e);
-    if (rc) return rc;
-    std::sort(t.begin(), t.end());
-    ms_out = t[reps / 2];
-    return PF_OK;
+    auto run = [&]() -> int {
+        for (auto &e : ev) HIP_TRY(hipEventCreate(&e));
+        int rc = launch();  // warm-up
+        for (int r = 0; r < reps && !rc; ++r) {
+            HIP_TRY(hipEventRecord(ev[2 * r], st));
+            rc = launch();
+            if (!rc) HIP_TRY(hipEventRecord(ev[2 * r + 1], st));
+        }
+        if (rc) return rc;
+        HIP_TRY(hipStreamSynchronize(st));
+        std::vector<float> t(size_t(reps), 0.f);
+        for (int r = 0; r < reps; ++r) HIP_TRY(hipEventElapsedTime(&t[r], ev[2 * r], ev[2 * r + 1]));
+        std::sort(t.begin(), t.end());
+        ms_out = t[size_t(reps) / 2];
+        return PF_OK;
+    };
+    const int rc = run();
+    for (auto &e : ev)
+        if (e) (void)hipEventDestroy(e);
+    return rc;
 }
 
-// Coordinate descent over the schedule space: starting from the current
-// schedule, each parameter in turn is set to the fastest of its candidate
-// values while the others stay fixed; two sweeps.  Every candidate gives
-// bit-identical results, so only time decides.
 int dev_vjp(HostPlan &hp, DevPlan *dp, const double *x, const double *W, int32_t K, double *gx,
             double *gp, void *stream) {
     DeviceGuard g(dp->device);
@@ -1568,8 +1588,14 @@ int dev_vjp(HostPlan &hp, DevPlan *dp, const double *x, const double *W, int32_t
     return PF_OK;
 }
 
-int dev_autotune(HostPlan &hp, DevPlan *dp, const double *x, double *F, double *J, int32_t reps,
-                 void *stream, pf_schedule *best_out) {
+// Coordinate descent over the schedule space: starting from the current
+// schedule, each parameter in turn is set to the fastest of its candidate
+// values while the others stay fixed; two sweeps.  A candidate replaces the
+// best so far only when it is faster by more than kTuneMargin, so that
+// timing noise between near-equal schedules does not decide.  Every candidate gives
+// bit-identical results, so only time decides.
+static int autotune_search(HostPlan &hp, DevPlan *dp, const double *x, double *F, double *J,
+                           int32_t reps, void *stream, pf_schedule *best_out, float *best_ms_out) {
     DeviceGuard g(dp->device);
     if (!g.ok) return fail(PF_EDEVICE, "cannot select device %d", dp->device);
     hipStream_t st = static_cast<hipStream_t>(stream);
@@ -1613,7 +1639,7 @@ int dev_autotune(HostPlan &hp, DevPlan *dp, const double *x, double *F, double *
                 rc = apply(cand);
                 if (!rc) rc = time_schedule(hp, dp, x, F, J, reps, st, ms);
                 if (rc) break;
-                if (ms < best_ms) {
+                if (ms < best_ms * (1.0f - kTuneMargin)) {
                     best_ms = ms;
                     best = cand;
                 }
@@ -1624,6 +1650,117 @@ int dev_autotune(HostPlan &hp, DevPlan *dp, const double *x, double *F, double *
     const int rc2 = apply(best);
     if (!rc) rc = rc2;
     if (!rc && best_out) *best_out = best;
+    if (!rc && best_ms_out) *best_ms_out = best_ms;
+    return rc;
+}
+
+// ---------------------------------------------------------------------------
+// tune cache: one text line per tuned plan shape,
+//   <key> tile_entries waves_per_block grid_blocks batch_buses batch_order
+//         xcd_remap batch_group <ms>
+// The key names the GPU (architecture, compute units), the kernel source the
+// library was built from, and everything about the plan that the kernel's
+// work depends on; the last line with a matching key wins.
+// ---------------------------------------------------------------------------
+
+#ifndef PF_KERNEL_SHA
+#define PF_KERNEL_SHA "unversioned"
+#endif
+
+static int tune_key(const HostPlan &hp, const DevPlan *dp, bool wf, bool wj, std::string &key) {
+    hipDeviceProp_t prop;
+    HIP_TRY(hipGetDeviceProperties(&prop, dp->device));
+    // FNV-1a over the grids' bus and entry counts (multi-grid plans)
+    uint64_t h = 1469598103934665603ull;
+    auto mix = [&](int64_t v) {
+        for (int b = 0; b < 8; ++b) {
+            h ^= uint64_t((v >> (8 * b)) & 0xff);
+            h *= 1099511628211ull;
+        }
+    };
+    for (const GridInfo &g : hp.grids) {
+        mix(g.N);
+        mix(g.n_y);
+        mix(g.NG);
+    }
+    char buf[512];
+    std::snprintf(buf, sizeof buf,
+                  "arch=%s;cus=%d;src=%s;kind=%d;grids=%zu;gh=%016llx;n=%lld;nnz=%lld;inst=%d;"
+                  "ld=%d;panels=%d;scen=%d;outg=%d;out=%d%d",
+                  prop.gcnArchName, prop.multiProcessorCount, PF_KERNEL_SHA, hp.kind,
+                  hp.grids.size(), (unsigned long long)h, (long long)hp.n, (long long)hp.nnz,
+                  hp.n_inst, hp.ld, hp.panels,
+                  int(!hp.load_scale_t.empty() || !hp.pv_scale_t.empty()),
+                  int(!hp.outage.empty()), int(wf), int(wj));
+    key = buf;
+    return PF_OK;
+}
+
+static bool cache_lookup(const char *path, const std::string &key, pf_schedule &out) {
+    FILE *f = std::fopen(path, "r");
+    if (!f) return false;
+    bool found = false;
+    std::vector<char> line(4096);
+    while (std::fgets(line.data(), int(line.size()), f)) {
+        const size_t len = std::strlen(line.data());
+        if (len <= key.size() || std::strncmp(line.data(), key.c_str(), key.size()) != 0 ||
+            line[key.size()] != ' ')
+            continue;
+        pf_schedule s{};
+        if (std::sscanf(line.data() + key.size(), "%d %d %d %d %d %d %d", &s.tile_entries,
+                        &s.waves_per_block, &s.grid_blocks, &s.batch_buses, &s.batch_order,
+                        &s.xcd_remap, &s.batch_group) == 7) {
+            out = s;
+            found = true;
+        }
+    }
+    std::fclose(f);
+    return found;
+}
+
+static int cache_append(const char *path, const std::string &key, const pf_schedule &s,
+                        float ms) {
+    FILE *f = std::fopen(path, "a");
+    if (!f) return fail(PF_EINVAL, "cannot open tune cache %s for appending", path);
+    std::fprintf(f, "%s %d %d %d %d %d %d %d %.6f\n", key.c_str(), s.tile_entries,
+                 s.waves_per_block, s.grid_blocks, s.batch_buses, s.batch_order, s.xcd_remap,
+                 s.batch_group, double(ms));
+    const bool bad = std::fclose(f) != 0;
+    return bad ? fail(PF_EINVAL, "cannot write tune cache %s", path) : PF_OK;
+}
+
+int dev_autotune(HostPlan &hp, DevPlan *dp, const double *x, double *F, double *J, int32_t reps,
+                 void *stream, const char *cache, pf_schedule *best_out, int32_t *hit) {
+    DeviceGuard g(dp->device);
+    if (!g.ok) return fail(PF_EDEVICE, "cannot select device %d", dp->device);
+    if (hit) *hit = 0;
+    std::string key;
+    if (cache && cache[0]) {
+        int rc = tune_key(hp, dp, F != nullptr, J != nullptr, key);
+        if (rc) return rc;
+        pf_schedule s{};
+        if (cache_lookup(cache, key, s)) {
+            pf_schedule n{};
+            rc = normalise_schedule(hp, &s, n);
+            if (rc) return rc;
+            const bool retile = n.tile_entries != hp.sched.tile_entries;
+            hp.sched = n;
+            if (retile) {
+                build_tiles(hp);
+                rc = dev_upload_tiles(hp, dp);
+                if (rc) return rc;
+            }
+            if (best_out) *best_out = n;
+            if (hit) *hit = 1;
+            return PF_OK;
+        }
+    }
+    pf_schedule best{};
+    float ms = 0.f;
+    int rc = autotune_search(hp, dp, x, F, J, reps, stream, &best, &ms);
+    if (rc) return rc;
+    if (best_out) *best_out = best;
+    if (!key.empty()) rc = cache_append(cache, key, best, ms);
     return rc;
 }
 

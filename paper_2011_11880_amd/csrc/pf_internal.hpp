@@ -99,6 +99,8 @@ struct HostPlan {
     std::vector<int32_t> br_f, br_t;   // global bus ids
     std::vector<int32_t> br_on;        // 1 in service
     std::vector<double> params;        // [r][x][b][tap][shift_deg][load_p][load_q]
+    bool params_stale = false;         // device copy replaced by pf_set_params since the
+                                       // host copy was last refreshed
     std::vector<double> pv_p;          // NPVt
     std::vector<double> shunt_g, shunt_b;
     std::vector<int32_t> load_bus;     // global bus id
@@ -147,6 +149,7 @@ int dev_create(HostPlan &hp, DevPlan **out);
 void dev_destroy(DevPlan *dp);
 int dev_upload_tiles(HostPlan &hp, DevPlan *dp);
 int dev_set_params(HostPlan &hp, DevPlan *dp, const double *params_dev, void *stream);
+int dev_fetch_params(HostPlan &hp, DevPlan *dp);
 int dev_upload_gens(const HostPlan &hp, DevPlan *dp);
 int dev_eval_single(HostPlan &hp, DevPlan *dp, const double *x, double *F,
                     double *J, void *stream);
@@ -157,7 +160,8 @@ int dev_vjp(HostPlan &hp, DevPlan *dp, const double *x, const double *W,
 int dev_newton(HostPlan &hp, DevPlan *dp, double *x, const pf_newton_opts *opts,
                pf_linsolve_fn solve, void *user, pf_newton_report *rep);
 int dev_autotune(HostPlan &hp, DevPlan *dp, const double *x, double *F,
-                 double *J, int32_t reps, void *stream, pf_schedule *best);
+                 double *J, int32_t reps, void *stream, const char *cache,
+                 pf_schedule *best, int32_t *hit);
 
 }  // namespace pf
 

@@ -773,6 +773,14 @@ int pf_lu_symbolic(int64_t n, const int32_t *rowptr, const int32_t *colidx, cons
     return PF_OK;
 }
 
+// The matrices are built on the host from the plan's parameters; after
+// pf_set_params the host copy is refreshed from the device first.
+static int fresh_params(const pf_plan *plan) {
+    if (!plan->host.params_stale || !plan->dev) return PF_OK;
+    pf_plan *p = const_cast<pf_plan *>(plan);
+    return dev_fetch_params(p->host, p->dev);
+}
+
 int pf_fdlf_matrices(const pf_plan *plan, int64_t *nnz_bp, int32_t *bp_rowptr,
                      int32_t *bp_colidx, double *bp_val, int32_t *bp_bus, int64_t *nnz_bpp,
                      int32_t *bpp_rowptr, int32_t *bpp_colidx, double *bpp_val,
@@ -780,7 +788,8 @@ int pf_fdlf_matrices(const pf_plan *plan, int64_t *nnz_bp, int32_t *bp_rowptr,
     clear_error();
     if (!plan) return fail(PF_EINVAL, "plan is NULL");
     FdMats m;
-    int rc;
+    int rc = fresh_params(plan);
+    if (rc) return rc;
     try {
         rc = build_fd(plan->host, m);
     } catch (const std::bad_alloc &) {
@@ -852,7 +861,8 @@ int pf_fdlf_create(pf_plan *plan, pf_lu *bp, pf_lu *bpp, pf_fdlf **out) {
     const HostPlan &hp = plan->host;
     if (hp.host_only || !plan->dev) return fail(PF_EINVAL, "plan is host-only");
     FdMats m;
-    int rc = build_fd(hp, m);
+    int rc = fresh_params(plan);
+    if (!rc) rc = build_fd(hp, m);
     if (rc) return rc;
     const int np = int(m.bus_p.size()), nq = int(m.bus_q.size());
     if ((np > 0) != (bp != nullptr) || (nq > 0) != (bpp != nullptr))

@@ -26,7 +26,8 @@ int dev_newton(HostPlan &, DevPlan *, double *, const pf_newton_opts *, pf_linso
     return PF_EDEVICE;
 }
 int dev_autotune(HostPlan &, DevPlan *, const double *, double *, double *, int32_t, void *,
-                 pf_schedule *) {
+                 const char *, pf_schedule *, int32_t *) {
     return PF_EDEVICE;
 }
+int dev_fetch_params(HostPlan &, DevPlan *) { return PF_EDEVICE; }
 }  // namespace pf

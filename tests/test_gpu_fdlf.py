@@ -144,3 +144,28 @@ def test_fdlf_failure_paths(ora, cuda):
         p.fdlf(x)
     assert ei.value.code == PF_EINVAL
     p.close()
+
+
+def test_matrices_follow_set_params(ora, cuda):
+    """B' and B'' built after pf_set_params use the new r, x, b and tap:
+    equal to the oracle's matrices of the network with those values."""
+    from paper_2011_11880_amd.api import Plan, params_vector
+    net = synth.grid_meshed(300, 3)
+    p = Plan(net)
+    p.fdlf_matrices()   # built once from the setup values
+    rng = np.random.default_rng(5)
+    B = net.n_branch
+    new = net.copy()
+    new.br_r = net.br_r * rng.uniform(0.5, 1.5, B)
+    new.br_x = net.br_x * rng.uniform(0.5, 1.5, B)
+    new.br_b = net.br_b * rng.uniform(0.5, 1.5, B)
+    new.br_tap = np.where(net.br_tap != 1.0, net.br_tap * 1.01, 1.0)
+    s = torch.cuda.Stream()
+    with torch.cuda.stream(s):
+        p.set_params(torch.from_numpy(params_vector(new)).to(cuda))
+    Bp, Bpp, bus_p, bus_q = p.fdlf_matrices()
+    Op, Opp, rp, rq = ora.fdlf_matrices(new)
+    assert np.array_equal(bus_p, rp) and np.array_equal(bus_q, rq)
+    for A, Bm in ((Bp, Op), (Bpp, Opp)):
+        assert np.array_equal(A.indptr, Bm.indptr) and np.array_equal(A.indices, Bm.indices)
+        np.testing.assert_allclose(A.data, Bm.data, rtol=1e-15, atol=0)
