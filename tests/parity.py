@@ -80,3 +80,35 @@ def check_jacobian(rp, ci, vals, J_ora, A_ora, what="J"):
     if np.any(absent):
         assert np.all(vals[absent] == 0.0), what + ": entries absent from the oracle are not 0"
     return check_close(vals[present], v[present], s[present], what)
+
+
+def pattern_keys(rp, ci):
+    """Sorted keys row * n + col of a CSR pattern with sorted columns."""
+    n = rp.shape[0] - 1
+    rows = np.repeat(np.arange(n, dtype=np.int64), np.diff(rp))
+    return rows * n + ci.astype(np.int64)
+
+
+def triplet_positions(keys, n, rows, cols):
+    """Position in the pattern (keys from pattern_keys) of every oracle
+    triplet; reusable for every instance whose triplets share one structure."""
+    tk = rows.astype(np.int64) * n + cols.astype(np.int64)
+    pos = np.searchsorted(keys, tk)
+    assert np.all(pos < keys.size) and np.all(keys[pos] == tk), \
+        "oracle has entries outside the library pattern"
+    return pos
+
+
+def check_jacobian_triplets(vals, keys, pos, trip_vals, trip_scales, what="J"):
+    """The oracle's Jacobian as its triplets summed per pattern slot (values,
+    and the triplets' sums of |products| as the scale, in triplet order),
+    compared with the library's values on the same pattern; slots no
+    triplet reaches must be exactly 0."""
+    m = keys.size
+    v = np.bincount(pos, weights=trip_vals, minlength=m)
+    s = np.bincount(pos, weights=trip_scales, minlength=m)
+    present = np.bincount(pos, minlength=m) > 0
+    vals = np.asarray(vals)
+    if not np.all(present):
+        assert np.all(vals[~present] == 0.0), what + ": entries absent from the oracle are not 0"
+    return check_close(vals[present], v[present], s[present], what)

@@ -2,14 +2,17 @@
 instances (bit-identical to the single-instance kernel), load/PV scenario
 overlays and N-1 outages (against the oracle on the modified network),
 ragged instance counts, residual-only and Jacobian-only launches, schedule
-invariance, graph replay, and the 10,000-bus x 1024-instance batch on
-sampled instances."""
+invariance, graph replay, every instance of the 10,000-bus x 1024-instance
+batch against the oracle, and the benchmark's 70,000-bus x 1000-state launch
+(every instance bit-identical to the single-instance kernel, a wide sample
+against the oracle)."""
 
 import numpy as np
 import pytest
 
 from paper_2011_11880_amd import synth
-from parity import check_close, check_jacobian
+from parity import (check_close, check_jacobian, check_jacobian_triplets, pattern_keys,
+                    triplet_positions)
 
 pytestmark = pytest.mark.gpu
 
@@ -191,7 +194,8 @@ def test_graph_replay_matches_eager(cuda):
 
 def test_10k_1024_scenarios_and_contingencies(ora, cuda):
     """512 load/renewable scenarios and 512 N-1 contingencies of the
-    10,000-bus grid in one launch; sampled instances against the oracle."""
+    10,000-bus grid in one launch; every instance against the oracle on its
+    own modified network."""
     Plan = _Plan()
     net = synth.grid_10k()
     I = 1024
@@ -205,13 +209,23 @@ def test_10k_1024_scenarios_and_contingencies(ora, cuda):
     bp = Plan(net, batch=spec)
     Y = synth.random_states(net, I, seed=2003)
     Fb, Jb = _batch_eval(bp, Y, cuda)
+    Fb = np.ascontiguousarray(Fb.T)
+    Jb = np.ascontiguousarray(Jb.T)
     rp, ci = bp.pattern()
-    for k in [0, 1, 300, 511, 512, 513, 777, 1023]:
+    keys = pattern_keys(rp, ci)
+    base_pos = None
+    for k in range(I):
         nk = _instance_net(net, spec, k)
         Fo, So = ora.residual(nk, Y[k])
-        Jo, Ao = ora.jacobian(nk, Y[k])
-        check_close(Fb[:, k], Fo, So, f"inst {k} F")
-        check_jacobian(rp, ci, Jb[:, k], Jo, Ao, f"inst {k} J")
+        check_close(Fb[k], Fo, So, f"inst {k} F")
+        r, c, v, m = ora.jacobian_coo(nk, Y[k], scales=True)
+        if out[k] < 0:
+            if base_pos is None:
+                base_pos = triplet_positions(keys, bp.n, r, c)
+            pos = base_pos
+        else:
+            pos = triplet_positions(keys, bp.n, r, c)
+        check_jacobian_triplets(Jb[k], keys, pos, v, m, f"inst {k} J")
 
 
 def test_padded_instance_stride(cuda):
@@ -269,28 +283,41 @@ def test_panel_layout_matches_rows(cuda):
         assert np.all(Fn[2, :, I - 128:] == 7.0) and np.all(Jn[2, :, I - 128:] == 7.0)
 
 
-def test_70k_x1000_bench_configuration_sampled(ora, cuda):
+def test_70k_x1000_bench_configuration(ora, cuda):
     """The benchmark's batched launch as timed (70,000-bus grid, 1000 random
-    states in rows padded to 1024, default schedule): sampled instances
-    against the oracle and bit-identical to the single-instance kernel."""
+    states in rows padded to 1008, default schedule): every instance
+    bit-identical to the single-instance kernel, every residual and every
+    eighth Jacobian (plus the chunk edges) against the oracle."""
     Plan = _Plan()
     net = synth.grid_70k()
     S = 1000
     Y = synth.random_states(net, S, seed=1001)
-    bp = Plan(net, batch=dict(n_inst=S, inst_stride=1024))
+    bp = Plan(net, batch=dict(n_inst=S, inst_stride=1008))
     X = torch.from_numpy(bp.to_batch(Y)).to(cuda)
     F, J = bp.eval_batch(X)
     sp = Plan(net)
-    rp, ci = bp.pattern()
-    for k in [0, 63, 64, 511, 999]:
-        Fk = F[:, k].cpu().numpy()
-        Jk = J[:, k].cpu().numpy()
+    Xs = torch.from_numpy(Y).to(cuda)
+    Fs = torch.empty(sp.n, dtype=torch.float64, device=cuda)
+    Js = torch.empty(sp.nnz, dtype=torch.float64, device=cuda)
+    for k in range(S):
+        sp.eval(Xs[k], Fs, Js)
+        assert torch.equal(Fs, F[:, k]) and torch.equal(Js, J[:, k]), k
+    Fh = np.ascontiguousarray(F[:, :S].cpu().numpy().T)
+    for k in range(S):
         Fo, So = ora.residual(net, Y[k])
-        Jo, Ao = ora.jacobian(net, Y[k])
-        check_close(Fk, Fo, So, f"inst {k} F")
-        check_jacobian(rp, ci, Jk, Jo, Ao, f"inst {k} J")
-        Fs, Js = sp.eval(torch.from_numpy(Y[k]).to(cuda))
-        torch.cuda.synchronize()
-        assert np.array_equal(Fs.cpu().numpy(), Fk) and np.array_equal(Js.cpu().numpy(), Jk)
+        check_close(Fh[k], Fo, So, f"inst {k} F")
+    del Fh
+    rp, ci = bp.pattern()
+    keys = pattern_keys(rp, ci)
+    pos = None
+    ks = sorted(set(range(0, S, 8)) | {63, 64, 511, 959, 960, 999})
+    for g in range(0, len(ks), 64):
+        kk = ks[g:g + 64]
+        Jh = np.ascontiguousarray(J[:, kk].cpu().numpy().T)
+        for q, k in enumerate(kk):
+            r, c, v, m = ora.jacobian_coo(net, Y[k], scales=True)
+            if pos is None:
+                pos = triplet_positions(keys, bp.n, r, c)
+            check_jacobian_triplets(Jh[q], keys, pos, v, m, f"inst {k} J")
     del F, J, X
     torch.cuda.empty_cache()

@@ -1,8 +1,9 @@
 """GPU parity of the adjoint (pf_vjp): J^T W and (dF/dp)^T W against the
 oracle's explicit transposed-Jacobian product and parameter gradients, the
-dot-product identity <W, J V> = <J^T W, V> at the 70,000-bus scale with 64
-cotangents, torch.autograd.gradcheck of PFResidual on the 200-bus grid, and
-batched cotangents through torch.func.vmap."""
+adjoint as benchmarked (70,000 buses, 64 cotangents) column by column and
+gradient by gradient with the dot-product identity <W, J V> = <J^T W, V>,
+torch.autograd.gradcheck of PFResidual on the 200-bus grid, and batched
+cotangents through torch.func.vmap."""
 
 import numpy as np
 import pytest
@@ -148,34 +149,46 @@ def test_vjp_multi_grid(ora, cuda):
         boff += net.n_branch
 
 
-def test_dot_product_identity_70k_64_cotangents(ora, cuda):
-    """<W_k, J V> = <(J^T W)_k, V> with J from pf_eval and J^T W from
-    pf_vjp, at the paper-scale grid; plus the oracle's J^T W on two columns."""
+def test_adjoint_70k_64_cotangents(ora, cuda):
+    """The adjoint as benchmarked (70,000-bus grid, 64 cotangents, one
+    launch): every column of J^T W against the oracle's explicit transposed
+    Jacobian, every parameter gradient (r, x, b, tap, shift, load P and Q)
+    against the oracle's pi-model partials, and the dot-product identity
+    <W_k, J V> = <(J^T W)_k, V> with J from pf_eval."""
     from paper_2011_11880_amd.api import Plan
     net = synth.grid_70k()
     p = Plan(net)
     y = synth.random_states(net, seed=4000)
     rng = np.random.default_rng(4001)
-    Wn = rng.standard_normal((net.n_var, 64))
+    K = 64
+    Wn = rng.standard_normal((net.n_var, K))
     V = rng.standard_normal(net.n_var)
     x = torch.from_numpy(y).to(cuda)
     _, Jv = p.eval(x)
-    gx, _ = p.vjp(x, torch.from_numpy(Wn).to(cuda))
+    gx, gp = p.vjp(x, torch.from_numpy(Wn).to(cuda))
     torch.cuda.synchronize()
     rp, ci = p.pattern()
     J = sp.csr_matrix((Jv.cpu().numpy(), ci, rp), shape=(p.n, p.n))
-    gx = gx.cpu().numpy()
+    gx, gp = gx.cpu().numpy(), gp.cpu().numpy()
     JV = J @ V
     absJ = abs(J)
-    for k in range(64):
+    for k in range(K):
         lhs = Wn[:, k] @ JV
         rhs = gx[:, k] @ V
         scale = np.abs(Wn[:, k]) @ (absJ @ np.abs(V))
         assert abs(lhs - rhs) <= 1e-12 * scale, k
     Jo, Ao = ora.jacobian(net, y)
-    for k in (0, 63):
-        go, _ = ora.vjp(net, y, Wn[:, k])
-        check_close(gx[:, k], go, Ao.T @ np.abs(Wn[:, k]), f"70k gx[{k}]")
+    GX = Jo.T @ Wn                  # the oracle's J^T w, all columns at once
+    SX = Ao.T @ np.abs(Wn)
+    B, L = net.n_branch, net.n_load
+    for k in range(K):
+        check_close(gx[:, k], GX[:, k], SX[:, k], f"70k gx[{k}]")
+        gpo = ora.vjp_params(net, y, Wn[:, k])
+        sc = ora.vjp_params_scale(net, y, Wn[:, k])
+        for q, name in enumerate(PNAMES):
+            check_close(gp[q * B:(q + 1) * B, k], gpo[name], sc[name], f"70k {name}[{k}]")
+        np.testing.assert_array_equal(gp[5 * B:5 * B + L, k], gpo["load_p"])
+        np.testing.assert_array_equal(gp[5 * B + L:, k], gpo["load_q"])
 
 
 def test_gradcheck_residual(cuda):
