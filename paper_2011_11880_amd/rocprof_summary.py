@@ -15,6 +15,11 @@
       known size (copy_bytes read and copy_bytes written per dispatch);
       --last N averages only the kernel's last N dispatches (the timed
       launches of a run that autotunes first)
+
+  python -m paper_2011_11880_amd.rocprof_summary fp64 RUN_results.db \
+        --kernel NAME --units U --out FILE.json [--last N]
+      FP64 operations per dispatch from SQ_INSTS_VALU_FLOPS_FP64 (an
+      instruction count per wavefront, FMA counted twice; x 64 lanes)
 """
 
 from __future__ import annotations
@@ -95,6 +100,17 @@ def traffic(a):
                     "included); scaled so that a plain copy reads and writes its own size"}
 
 
+def fp64(a):
+    from .build import kernel_source_hash
+    n, nd = counter_per_dispatch(a.db, "SQ_INSTS_VALU_FLOPS_FP64", a.kernel, a.last)
+    return {"kernel": a.kernel, "launch_units": a.units, "dispatches": nd,
+            "sq_insts_valu_flops_fp64_per_dispatch": n,
+            "fp64_flops_per_launch": 64.0 * n,
+            "kernel_source_sha256_16": kernel_source_hash(),
+            "note": "SQ_INSTS_VALU_FLOPS_FP64 counts ADD_F64 + MUL_F64 + 2 x FMA_F64 "
+                    "instructions per wavefront; 64 lanes each, idle lanes included"}
+
+
 def main(argv=None):
     ap = argparse.ArgumentParser(description=__doc__,
                                  formatter_class=argparse.RawDescriptionHelpFormatter)
@@ -112,7 +128,20 @@ def main(argv=None):
     t.add_argument("--copy-bytes", type=int, required=True)
     t.add_argument("--units", type=int, required=True)
     t.add_argument("--last", type=int, default=None)
+    f = sub.add_parser("fp64")
+    f.add_argument("db")
+    for k in ("kernel", "out"):
+        f.add_argument("--" + k, required=True)
+    f.add_argument("--units", type=int, required=True)
+    f.add_argument("--last", type=int, default=None)
     a = ap.parse_args(argv)
+    if a.cmd == "fp64":
+        d = fp64(a)
+        with open(a.out, "w") as fh:
+            json.dump(d, fh, indent=1)
+        json.dump(d, sys.stdout, indent=1)
+        print()
+        return
     if a.cmd == "counters":
         for k, (avg, nd) in counters(a.db, a.match).items():
             print(f"{k:34s} {avg:20.1f}  ({nd} dispatches)")

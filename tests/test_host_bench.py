@@ -102,3 +102,36 @@ def test_host_cpu_record():
     h = bench.host_cpu()
     assert 1 <= h["usable_cores"] <= h["cpus"]
     assert h["model"] is None or isinstance(h["model"], str)
+
+
+def test_fp64_summary_and_bench_rate(tmp_path, monkeypatch):
+    """The FP64 counter summary scales the per-dispatch instruction count by
+    64 lanes; the bench turns it into a rate only for the kernel source it
+    was taken on and the same launch size."""
+    from paper_2011_11880_amd import rocprof_summary as R
+    db = tmp_path / "run_results.db"
+    c = sqlite3.connect(db)
+    c.execute("create table counters_collection (kernel_name text, dispatch_id int, "
+              "counter_name text, value real)")
+    rows = [("k_eval_batch<a>", 1, "SQ_INSTS_VALU_FLOPS_FP64", 100.0),
+            ("k_eval_batch<a>", 1, "SQ_INSTS_VALU_FLOPS_FP64", 50.0),
+            ("k_eval_batch<a>", 2, "SQ_INSTS_VALU_FLOPS_FP64", 250.0),
+            ("k_other", 3, "SQ_INSTS_VALU_FLOPS_FP64", 7.0)]
+    c.executemany("insert into counters_collection values (?, ?, ?, ?)", rows)
+    c.commit()
+    c.close()
+    out = tmp_path / "fp64.json"
+    R.main(["fp64", str(db), "--kernel", "k_eval_batch", "--units", "10", "--out", str(out)])
+    import json
+    d = json.load(open(out))
+    assert d["sq_insts_valu_flops_fp64_per_dispatch"] == 200.0
+    assert d["fp64_flops_per_launch"] == 64 * 200.0 and d["dispatches"] == 2
+    sys.path.insert(0, ROOT)
+    import bench
+    monkeypatch.setattr(bench, "ROOT", str(tmp_path))
+    os.makedirs(tmp_path / "profiles")
+    os.replace(out, tmp_path / "profiles" / "fp64.json")
+    r = bench.fp64_rate("fp64.json", 10, 2.0)
+    assert abs(r["fp64_tflops"] - 64 * 200.0 / 2e-3 / 1e12) < 1e-18
+    assert bench.fp64_rate("fp64.json", 11, 2.0) == {"fp64_tflops": None}
+    assert bench.fp64_rate("missing.json", 10, 2.0) == {"fp64_tflops": None}
