@@ -505,6 +505,20 @@ int pf_lu_create(int32_t device, int64_t n, int64_t nnz, const int32_t *rowptr,
                  const double *T_val, const int32_t *pivP, const int32_t *pivQ,
                  pf_lu **out);
 int pf_lu_solve(pf_lu *lu, double *b, void *stream);
+
+/*
+ * For callers that cannot allocate device memory while they run (code under
+ * HIP graph capture, serving loops, harnesses that forbid hipMalloc): the
+ * solve of pf_lu_solve, bit for bit, with its permuted working vector (n
+ * doubles) in a static device array of the library instead of the object's
+ * buffer.  The array holds 1,048,576 doubles (8 MiB) on every device the
+ * library runs on, until the process ends; n above that -> PF_EINVAL.  The
+ * call allocates nothing (the array's address is looked up once per
+ * device).  Every call on one device shares the array and leaves it holding
+ * its last working vector: calls that overlap on one device (other streams,
+ * graphs replayed concurrently) race.  Errors as pf_lu_solve.
+ */
+int pf_lu_solve_noalloc(pf_lu *lu, double *b, void *stream);
 void pf_lu_destroy(pf_lu *lu);
 
 /*

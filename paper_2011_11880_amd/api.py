@@ -719,9 +719,12 @@ class DeviceSparseLU:
             pivQ.ctypes.data_as(capi._pi32), ctypes.byref(h)))
         self._h = h
 
-    def solve(self, b):
-        """Solve M y = b in place (b: device [n]); returns b."""
-        check(capi.lib().pf_lu_solve(self._h, _ptr(b, self.n, "b"), _stream(b.device)))
+    def solve(self, b, noalloc=False):
+        """Solve M y = b in place (b: device [n]); returns b.  ``noalloc``:
+        pf_lu_solve_noalloc, the working vector in the library's static
+        device array."""
+        fn = capi.lib().pf_lu_solve_noalloc if noalloc else capi.lib().pf_lu_solve
+        check(fn(self._h, _ptr(b, self.n, "b"), _stream(b.device)))
         return b
 
     def close(self):

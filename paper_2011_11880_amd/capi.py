@@ -127,6 +127,7 @@ SIGNATURES = {
     "pf_lu_create": (ctypes.c_int, [_i32, _i64, _i64, _pi32, _pi32, _pd, _i64, _pi32, _pi32,
                                     _pd, _pi32, _pi32, ctypes.POINTER(_vp)]),
     "pf_lu_solve": (ctypes.c_int, [_vp, _vp, _vp]),
+    "pf_lu_solve_noalloc": (ctypes.c_int, [_vp, _vp, _vp]),
     "pf_lu_destroy": (None, [_vp]),
     "pf_fdlf_create": (ctypes.c_int, [_P, _vp, _vp, ctypes.POINTER(_vp)]),
     "pf_fdlf_solve": (ctypes.c_int, [_vp, _vp, ctypes.POINTER(pf_newton_opts),

@@ -629,13 +629,47 @@ __global__ void __launch_bounds__(256) k_lu_unpermute(int n, const int32_t *__re
     if (k < n) X[pivQ[k]] = Y[k];
 }
 
-int lu_solve(pf_lu *lu, double *b, hipStream_t st) {
+// Solve with the permuted working vector Y (n doubles, written in full by
+// the forward solve before anything reads it).
+int lu_solve_in(pf_lu *lu, double *b, double *Y, hipStream_t st) {
     const TriDev d{lu->flev_ptr, lu->blev_ptr, lu->frows, lu->brows, lu->ptrT,
                    lu->indT,     lu->tdiag,    lu->pivP,  lu->valT};
-    tri_solve(lu->tri, d, b, lu->Y, st);
+    tri_solve(lu->tri, d, b, Y, st);
     hipLaunchKernelGGL(k_lu_unpermute, dim3(unsigned((lu->n + 255) / 256)), dim3(256), 0, st,
-                       lu->n, lu->pivQ, lu->Y, b);
+                       lu->n, lu->pivQ, Y, b);
     LU_HIP(hipGetLastError());
+    return PF_OK;
+}
+
+int lu_solve(pf_lu *lu, double *b, hipStream_t st) { return lu_solve_in(lu, b, lu->Y, st); }
+
+// ---------------------------------------------------------------------------
+// Working vector of pf_lu_solve_noalloc: a static device array, one copy per
+// device, held until the process ends.  Host code reaches it only through the
+// address hipGetSymbolAddress returns on each device (the array's name is a
+// host-side stand-in there).
+// ---------------------------------------------------------------------------
+constexpr int64_t kStaticScratchDoubles = int64_t(1) << 20;   // 8 MiB
+static __device__ __align__(256) double scratch[kStaticScratchDoubles];
+constexpr int kMaxScratchDevices = 64;
+
+// The array's address on `device`, which must be current; looked up once per
+// device.
+int static_scratch(int device, double **out) {
+    static std::mutex mu;
+    static double *addr[kMaxScratchDevices] = {};
+    if (device < 0 || device >= kMaxScratchDevices)
+        return fail(PF_EINVAL, "device %d is out of range for the static scratch", device);
+    std::lock_guard<std::mutex> lock(mu);
+    if (!addr[device]) {
+        void *p = nullptr;
+        const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess || !p)
+            return fail(PF_EDEVICE, "hipGetSymbolAddress(scratch) on device %d: %s", device,
+                        hipGetErrorString(e));
+        addr[device] = static_cast<double *>(p);
+    }
+    *out = addr[device];
     return PF_OK;
 }
 
@@ -849,6 +883,20 @@ int pf_lu_solve(pf_lu *lu, double *b, void *stream) {
     Guard g(lu->device);
     if (!g.ok) return fail(PF_EDEVICE, "cannot select device %d", lu->device);
     return lu_solve(lu, b, static_cast<hipStream_t>(stream));
+}
+
+int pf_lu_solve_noalloc(pf_lu *lu, double *b, void *stream) {
+    clear_error();
+    if (!lu || !b) return fail(PF_EINVAL, "NULL argument");
+    if (int64_t(lu->n) > kStaticScratchDoubles)
+        return fail(PF_EINVAL, "n = %d exceeds the static scratch of %lld doubles", lu->n,
+                    (long long)kStaticScratchDoubles);
+    Guard g(lu->device);
+    if (!g.ok) return fail(PF_EDEVICE, "cannot select device %d", lu->device);
+    double *Y = nullptr;
+    const int rc = static_scratch(lu->device, &Y);
+    if (rc) return rc;
+    return lu_solve_in(lu, b, Y, static_cast<hipStream_t>(stream));
 }
 
 void pf_lu_destroy(pf_lu *lu) { release_lu(lu); }
