@@ -259,6 +259,20 @@ __device__ __forceinline__ void st(double *p, double v) { __builtin_nontemporal_
 // L2 can merge them into whole lines before they are written back.
 __device__ __forceinline__ void stc(double *p, double v) { *p = v; }
 
+// A row of cotangent-fastest data addressed as a raw buffer: the row base in
+// scalar registers, each lane's byte offset in one vector register shared by
+// every row it touches.
+typedef unsigned int u32x2 __attribute__((ext_vector_type(2)));
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t row_rsrc(const double *p) {
+    return __builtin_amdgcn_make_buffer_rsrc(const_cast<double *>(p), 0, 0x7fffffff, 0x00020000);
+}
+__device__ __forceinline__ double rld(const double *row, int off) {
+    return __builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(row_rsrc(row), off, 0, 0));
+}
+__device__ __forceinline__ void rst(double *row, int off, double v) {
+    __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(u32x2, v), row_rsrc(row), off, 0, 2);
+}
+
 __device__ __forceinline__ void wave_sync() {
     __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
     __builtin_amdgcn_wave_barrier();
@@ -854,9 +868,12 @@ __device__ __forceinline__ void branch_partials(double r, double xx, double bc, 
 // dF_q/dQ_load = 1), written when the bus's row opens.  Rows are taken in
 // breadth-first order (tiles over `src`, the entry indices in that order)
 // and each XCD runs a contiguous range of tiles.
-// Five wavefronts per SIMD (at most 96 registers; a few spill in phase 1)
-// outrun four without spills: each wavefront's walk is a chain of dependent
-// loads, so more of them in flight is what helps.
+// Five wavefronts per SIMD (at most 96 registers) outrun four: each
+// wavefront's walk is a chain of dependent loads, so more of them in flight
+// is what helps.  Every row of W, gx and gparam a wavefront touches is the
+// same for all its lanes (read from LDS, made uniform), so rows are
+// addressed as buffers with a scalar base and one lane offset: that keeps
+// the walk within 96 registers without spilling.
 template <bool WGX, bool WGP>
 __global__ void __launch_bounds__(256, 5)
 k_vjp(const int4 *__restrict__ tiles, int ntiles, int n_kchunks, const int32_t *__restrict__ order,
@@ -882,6 +899,7 @@ k_vjp(const int4 *__restrict__ tiles, int ntiles, int n_kchunks, const int32_t *
     const bool kvalid = k < K;
     const size_t kk = size_t(kvalid ? k : K - 1);
     const size_t SK = size_t(K);
+    const int lo = int(kk) * 8, so = k * 8;   // byte offsets of this lane's cotangent
     const int64_t B64 = B;
     double(*C)[CH] = sc[wv];
     double(*D)[CH] = sd[wv];
@@ -907,20 +925,20 @@ k_vjp(const int4 *__restrict__ tiles, int ntiles, int n_kchunks, const int32_t *
         double gt = accT, gv = accV;
         if (b2.y >= 0) {
             const int4 g4 = gen4[b2.y];
-            const double wv = W[size_t(g4.x) * SK + kk];
+            const double wv = rld(W + size_t(g4.x) * SK, lo);
             const bool held = g4.z == kGenHeld;
             // control row: +1 at (V row, V_a) under voltage control, +1 at
             // (V row, Q_g) when the output is held; Q_g column: -1 in row Q_a
             if (!held) gv = gv + wv;
-            if (kvalid) st(&gx[size_t(g4.x) * SK + k], held ? wv - wQa : -wQa);
+            if (kvalid) rst(gx + size_t(g4.x) * SK, so, held ? wv - wQa : -wQa);
             if (g4.z >= 0) {
-                gt = gt + W[size_t(g4.z) * SK + kk];   // angle row: +1 at (theta row, theta_a)
-                if (kvalid) st(&gx[size_t(g4.z) * SK + k], -wPa);   // P_s column
+                gt = gt + rld(W + size_t(g4.z) * SK, lo);   // angle row: +1 at (theta row, theta_a)
+                if (kvalid) rst(gx + size_t(g4.z) * SK, so, -wPa);   // P_s column
             }
         }
         if (kvalid) {
-            st(&gx[size_t(gd.xoff + ia) * SK + k], gt);
-            st(&gx[size_t(gd.xoff + gd.N + ia) * SK + k], gv);
+            rst(gx + size_t(gd.xoff + ia) * SK, so, gt);
+            rst(gx + size_t(gd.xoff + gd.N + ia) * SK, so, gv);
         }
     };
     for (int c0 = e0; c0 < e1; c0 += CH) {
@@ -1018,10 +1036,11 @@ k_vjp(const int4 *__restrict__ tiles, int ntiles, int n_kchunks, const int32_t *
                 wPc[u] = 0.0;
                 wQc[u] = 0.0;
                 if (q < nvalid) {
-                    const int icp = PC[q];
+                    // every lane reads the same LDS word: the row is uniform
+                    const int icp = __builtin_amdgcn_readfirstlane(PC[q]);
                     if (icp >= 0) {
-                        wPc[u] = W[size_t(gd.xoff + icp) * SK + kk];
-                        wQc[u] = W[size_t(gd.xoff + gd.N + icp) * SK + kk];
+                        wPc[u] = rld(W + size_t(gd.xoff + icp) * SK, lo);
+                        wQc[u] = rld(W + size_t(gd.xoff + gd.N + icp) * SK, lo);
                     }
                 }
             }
@@ -1031,22 +1050,24 @@ k_vjp(const int4 *__restrict__ tiles, int ntiles, int n_kchunks, const int32_t *
                 if (q >= nvalid) break;
                 if ((smask >> q) & 1ull) {   // a row starts here
                     if (WGX && row_bus >= 0) flush(row_bus);
-                    row_bus = PB[q];
+                    row_bus = __builtin_amdgcn_readfirstlane(PB[q]);
                     ++rows_seen;
                     const int ia = row_bus - gd.bus_off;
-                    wPa = W[size_t(gd.xoff + ia) * SK + kk];
-                    wQa = W[size_t(gd.xoff + gd.N + ia) * SK + kk];
+                    wPa = rld(W + size_t(gd.xoff + ia) * SK, lo);
+                    wQa = rld(W + size_t(gd.xoff + gd.N + ia) * SK, lo);
                     accT = 0.0;
                     accV = 0.0;
                     if (WGP && kvalid) {
-                        const int lf = LF[q];
+                        const int lf = __builtin_amdgcn_readfirstlane(LF[q]);
                         if (lf >= 0) {
-                            st(&gp[size_t(5 * B64 + lf) * SK + k], wPa);
-                            st(&gp[size_t(5 * B64 + NL + lf) * SK + k], wQa);
-                            for (int j = LS[q] + 1; j < LS[q] + LN[q]; ++j) {
+                            rst(gp + size_t(5 * B64 + lf) * SK, so, wPa);
+                            rst(gp + size_t(5 * B64 + NL + lf) * SK, so, wQa);
+                            const int ls = __builtin_amdgcn_readfirstlane(LS[q]);
+                            const int ln = __builtin_amdgcn_readfirstlane(LN[q]);
+                            for (int j = ls + 1; j < ls + ln; ++j) {
                                 const int l = ldlist[j];
-                                st(&gp[size_t(5 * B64 + l) * SK + k], wPa);
-                                st(&gp[size_t(5 * B64 + NL + l) * SK + k], wQa);
+                                rst(gp + size_t(5 * B64 + l) * SK, so, wPa);
+                                rst(gp + size_t(5 * B64 + NL + l) * SK, so, wQa);
                             }
                         }
                     }
@@ -1058,13 +1079,13 @@ k_vjp(const int4 *__restrict__ tiles, int ntiles, int n_kchunks, const int32_t *
                            C[7][q] * wQc[u];
                 }
                 if constexpr (WGP) {
-                    const int ob = OB[q];
+                    const int ob = __builtin_amdgcn_readfirstlane(OB[q]);
                     if (ob >= 0 && kvalid) {
 #pragma unroll
                         for (int pr = 0; pr < 5; ++pr) {
                             const double v = D[4 * pr][q] * wPa + D[4 * pr + 1][q] * wQa +
                                              D[4 * pr + 2][q] * wPc[u] + D[4 * pr + 3][q] * wQc[u];
-                            st(&gp[size_t(pr * B64 + ob) * SK + k], v);
+                            rst(gp + size_t(pr * B64 + ob) * SK, so, v);
                         }
                     }
                 }
@@ -1685,9 +1706,10 @@ static int tune_key(const HostPlan &hp, const DevPlan *dp, bool wf, bool wj, std
     }
     char buf[512];
     std::snprintf(buf, sizeof buf,
-                  "arch=%s;cus=%d;src=%s;kind=%d;grids=%zu;gh=%016llx;n=%lld;nnz=%lld;inst=%d;"
-                  "ld=%d;panels=%d;scen=%d;outg=%d;out=%d%d",
+                  "arch=%s;cus=%d;src=%s;kind=%d;order=%d;grids=%zu;gh=%016llx;n=%lld;nnz=%lld;"
+                  "inst=%d;ld=%d;panels=%d;scen=%d;outg=%d;out=%d%d",
                   prop.gcnArchName, prop.multiProcessorCount, PF_KERNEL_SHA, hp.kind,
+                  hp.bus_order_kind,
                   hp.grids.size(), (unsigned long long)h, (long long)hp.n, (long long)hp.nnz,
                   hp.n_inst, hp.ld, hp.panels,
                   int(!hp.load_scale_t.empty() || !hp.pv_scale_t.empty()),
