@@ -146,12 +146,28 @@ typedef struct pf_schedule {
  *              (the row then has two slots, V then Q_g; nnz grows by the
  *              number of PV units), so that pf_set_gen_modes can hold the
  *              generator at a reactive target without changing the pattern
+ *   bus_order  PF_ORDER_INPUT (0): the plan keeps the network's bus numbers.
+ *              PF_ORDER_LOCALITY (1): the plan numbers each grid's buses
+ *              breadth-first over its in-service branches (from bus 0, then
+ *              from the lowest-numbered bus not yet reached), so that
+ *              neighbouring buses sit close together in every bus-indexed
+ *              array: the single-instance kernel's state gathers then share
+ *              cache lines (Section II-D's point about contiguous data).
+ *              Every bus-indexed array the library takes or returns (the
+ *              angle and voltage blocks of x and F, the rows and columns of
+ *              the pattern, bus lists) is then in the plan's order;
+ *              pf_bus_order gives the map.  Branch, load and generator
+ *              numbering (and so the parameter vector and the generator
+ *              blocks of x and F) are unchanged.
  */
+#define PF_ORDER_INPUT 0
+#define PF_ORDER_LOCALITY 1
 typedef struct pf_setup_opts {
     int32_t host_only;
     int32_t device;
     pf_schedule sched;
     int32_t q_limits;
+    int32_t bus_order;
 } pf_setup_opts;
 
 typedef struct pf_plan pf_plan;
@@ -244,6 +260,13 @@ int pf_info_ex(const pf_plan *plan, pf_info_t *info);
  * multi-grid plan: x_off and j_off each receive n_grids + 1 entries. */
 int pf_info_multi(const pf_plan *plan, int64_t *x_off, int64_t *j_off);
 
+/* Host copy of the plan's bus order: order[k] (host [total buses]) is the
+ * input bus (numbered within its grid) that plan bus k of that grid stands
+ * for; the identity unless the plan was set up with PF_ORDER_LOCALITY.  For
+ * a state y in input numbering, the plan's x has x[k] = y[order[k]] and
+ * x[N + k] = y[N + order[k]] per grid, the generator entries unchanged. */
+int pf_bus_order(const pf_plan *plan, int32_t *order);
+
 /* Host copy of the fixed CSR pattern: rowptr[n + 1], colidx[nnz]. */
 int pf_pattern(const pf_plan *plan, int32_t *rowptr, int32_t *colidx);
 
@@ -322,8 +345,8 @@ int pf_set_schedule(pf_plan *plan, const pf_schedule *sched);
  * Tune cache: with cache_path non-NULL and non-empty, the text file there
  * is searched first for a line keyed by the GPU (architecture, compute
  * units), the kernel source the library was built from and the plan's
- * shape (kind, sizes, grids, instances, pitch, layout, overlays, outputs
- * asked for).  On a hit that schedule is applied without timing anything
+ * shape (kind, bus order, sizes, grids, instances, pitch, layout, overlays,
+ * outputs asked for).  On a hit that schedule is applied without timing anything
  * and *hit (nullable) is set to 1; on a miss the search runs and appends its
  * result to the file (PF_EINVAL if the file cannot be written).
  * pf_autotune is pf_autotune_cached with the path taken from the

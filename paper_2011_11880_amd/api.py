@@ -116,10 +116,14 @@ def host_lu(rowptr, colidx, values, n, permc_spec=None, row_order=None):
     return trp, tci, tv, pivP, pivQ
 
 
-def _opts(host_only=False, device=None, schedule=None, q_limits=False):
+_ORDERS = {"input": capi.PF_ORDER_INPUT, "locality": capi.PF_ORDER_LOCALITY}
+
+
+def _opts(host_only=False, device=None, schedule=None, q_limits=False, bus_order="input"):
     o = capi.pf_setup_opts()
     o.host_only = 1 if host_only else 0
     o.q_limits = 1 if q_limits else 0
+    o.bus_order = _ORDERS[bus_order]
     o.device = -1 if device is None else int(device)
     if schedule:
         for k, v in schedule.items():
@@ -156,17 +160,22 @@ class Plan:
     ``Plan(net)``                         single instance
     ``Plan(net, batch=dict(n_inst=..., load_scale=..., pv_scale=..., outage=...))``
     ``Plan.multi([net0, net1, ...])``     block-diagonal multi-grid plan
+
+    ``bus_order="locality"`` renumbers each grid's buses breadth-first at
+    setup; bus-indexed vectors (x, F, the pattern) are then in the plan's
+    order: ``to_plan`` / ``from_plan`` convert states and residuals.
     """
 
     def __init__(self, net=None, *, batch=None, host_only=False, device=None, schedule=None,
-                 q_limits=False, _handle=None):
+                 q_limits=False, bus_order="input", _handle=None, _grid_buses=None):
         self._h = None
         L = capi.lib()
         if _handle is not None:
             self._h = _handle
         else:
             ns = _NetStruct(net)
-            opts = _opts(host_only, device, schedule, q_limits)
+            _grid_buses = [int(net.n_bus)]
+            opts = _opts(host_only, device, schedule, q_limits, bus_order)
             h = capi._P()
             if batch is None:
                 check(L.pf_setup(ctypes.byref(ns.s), ctypes.byref(opts), ctypes.byref(h)))
@@ -201,21 +210,58 @@ class Plan:
             self._h = h
         self._load_info()
         self.device = device
+        self._grid_buses = _grid_buses
+        self._perm = None
 
     @classmethod
-    def multi(cls, nets, *, host_only=False, device=None, schedule=None, q_limits=False):
+    def multi(cls, nets, *, host_only=False, device=None, schedule=None, q_limits=False,
+              bus_order="input"):
         structs = [_NetStruct(n) for n in nets]
         arr = (capi.pf_network * len(structs))(*[s.s for s in structs])
-        opts = _opts(host_only, device, schedule, q_limits)
+        opts = _opts(host_only, device, schedule, q_limits, bus_order)
         h = capi._P()
         check(capi.lib().pf_setup_multi(arr, len(structs), ctypes.byref(opts), ctypes.byref(h)))
-        p = cls(_handle=h, device=device)
+        p = cls(_handle=h, device=device, _grid_buses=[int(n.n_bus) for n in nets])
         xo = np.empty(len(structs) + 1, np.int64)
         jo = np.empty(len(structs) + 1, np.int64)
         check(capi.lib().pf_info_multi(h, xo.ctypes.data_as(capi._pi64),
                                        jo.ctypes.data_as(capi._pi64)))
         p.x_off, p.j_off = xo, jo
         return p
+
+    # bus order --------------------------------------------------------------
+    def bus_order(self):
+        """pf_bus_order: input bus (within its grid) of every plan bus."""
+        order = np.empty(self.info["n_bus"], np.int32)
+        check(capi.lib().pf_bus_order(self._h, order.ctypes.data_as(capi._pi32)))
+        return order
+
+    def state_perm(self):
+        """Index vector p of length n with x_plan = y_input[p] (angle and
+        voltage blocks of each grid permuted, generator entries in place)."""
+        if self._perm is None:
+            order = self.bus_order().astype(np.int64)
+            xo = getattr(self, "x_off", np.array([0, self.n], np.int64))
+            perm = np.arange(self.n, dtype=np.int64)
+            b0 = 0
+            for g, N in enumerate(self._grid_buses or [self.info["n_bus"]]):
+                o = order[b0:b0 + N]
+                perm[xo[g]:xo[g] + N] = xo[g] + o
+                perm[xo[g] + N:xo[g] + 2 * N] = xo[g] + N + o
+                b0 += N
+            self._perm = perm
+        return self._perm
+
+    def to_plan(self, y):
+        """State(s) or residual(s) in input numbering (last axis n) -> plan order."""
+        return np.ascontiguousarray(np.asarray(y)[..., self.state_perm()])
+
+    def from_plan(self, x):
+        """Plan order (last axis n) -> input numbering."""
+        x = np.asarray(x)
+        out = np.empty_like(x)
+        out[..., self.state_perm()] = x
+        return out
 
     def _load_info(self):
         inf = capi.pf_info_t()

@@ -24,6 +24,9 @@ PF_ENOCONV = -6
 PF_LAYOUT_ROWS = 0
 PF_LAYOUT_PANELS = 1
 
+PF_ORDER_INPUT = 0
+PF_ORDER_LOCALITY = 1
+
 _i32 = ctypes.c_int32
 _i64 = ctypes.c_int64
 _d = ctypes.c_double
@@ -58,7 +61,7 @@ class pf_schedule(ctypes.Structure):
 
 class pf_setup_opts(ctypes.Structure):
     _fields_ = [("host_only", _i32), ("device", _i32), ("sched", pf_schedule),
-                ("q_limits", _i32)]
+                ("q_limits", _i32), ("bus_order", _i32)]
 
 
 class pf_batch_spec(ctypes.Structure):
@@ -98,6 +101,7 @@ SIGNATURES = {
     "pf_info_ex": (ctypes.c_int, [_P, ctypes.POINTER(pf_info_t)]),
     "pf_info_multi": (ctypes.c_int, [_P, _pi64, _pi64]),
     "pf_pattern": (ctypes.c_int, [_P, _pi32, _pi32]),
+    "pf_bus_order": (ctypes.c_int, [_P, _pi32]),
     "pf_jacobian_row_order": (ctypes.c_int, [_P, _pi32]),
     "pf_eval_residual": (ctypes.c_int, [_P, _vp, _vp, _vp]),
     "pf_eval_jacobian": (ctypes.c_int, [_P, _vp, _vp, _vp]),

@@ -4,6 +4,7 @@
 #include <cstdlib>
 #include <cstring>
 #include <new>
+#include <vector>
 
 #include "pf_internal.hpp"
 
@@ -14,6 +15,113 @@ const char *last_error();
 using namespace pf;
 
 namespace {
+
+// A network with its buses renumbered for locality: breadth-first over the
+// in-service branches, from bus 0 and then from the lowest-numbered bus not
+// yet reached, so neighbouring buses get nearby numbers and the states a
+// wavefront gathers share cache lines.  order[k] = input bus at position k.
+struct Renumbered {
+    pf_network net{};
+    std::vector<int32_t> order, from, to, load_bus, pv_bus, slack_bus, shunt_bus;
+};
+
+bool in_range(const int32_t *a, int32_t n, int32_t hi) {
+    if (n > 0 && !a) return false;
+    for (int32_t k = 0; k < n; ++k)
+        if (a[k] < 0 || a[k] >= hi) return false;
+    return true;
+}
+
+// False (and no renumbering) for networks whose sizes or bus indices are
+// malformed: build_host_plan then reports the error on the input itself.
+bool renumber(const pf_network &in, Renumbered &r) {
+    const int32_t N = in.n_bus;
+    if (N < 1 || in.n_branch < 0 || in.n_load < 0 || in.n_pv < 0 || in.n_slack < 0 ||
+        in.n_shunt < 0)
+        return false;
+    if (!in_range(in.br_from, in.n_branch, N) || !in_range(in.br_to, in.n_branch, N) ||
+        !in_range(in.load_bus, in.n_load, N) || !in_range(in.pv_bus, in.n_pv, N) ||
+        !in_range(in.slack_bus, in.n_slack, N) || !in_range(in.shunt_bus, in.n_shunt, N))
+        return false;
+    std::vector<int32_t> deg(size_t(N) + 1, 0), adj;
+    auto on = [&](int32_t e) { return !in.br_status || in.br_status[e]; };
+    for (int32_t e = 0; e < in.n_branch; ++e)
+        if (on(e)) {
+            ++deg[size_t(in.br_from[e]) + 1];
+            ++deg[size_t(in.br_to[e]) + 1];
+        }
+    for (int32_t i = 0; i < N; ++i) deg[size_t(i) + 1] += deg[size_t(i)];
+    adj.resize(size_t(deg[size_t(N)]));
+    std::vector<int32_t> fill(deg.begin(), deg.end() - 1);
+    for (int32_t e = 0; e < in.n_branch; ++e)
+        if (on(e)) {
+            adj[size_t(fill[size_t(in.br_from[e])]++)] = in.br_to[e];
+            adj[size_t(fill[size_t(in.br_to[e])]++)] = in.br_from[e];
+        }
+    r.order.clear();
+    r.order.reserve(size_t(N));
+    std::vector<int32_t> pos(size_t(N), -1);
+    for (int32_t s = 0; s < N; ++s) {
+        if (pos[size_t(s)] >= 0) continue;
+        pos[size_t(s)] = int32_t(r.order.size());
+        r.order.push_back(s);
+        for (size_t h = r.order.size() - 1; h < r.order.size(); ++h) {
+            const int32_t b = r.order[h];
+            for (int32_t q = deg[size_t(b)]; q < deg[size_t(b) + 1]; ++q) {
+                const int32_t c = adj[size_t(q)];
+                if (pos[size_t(c)] < 0) {
+                    pos[size_t(c)] = int32_t(r.order.size());
+                    r.order.push_back(c);
+                }
+            }
+        }
+    }
+    auto map = [&](const int32_t *a, int32_t n, std::vector<int32_t> &out) -> const int32_t * {
+        out.resize(size_t(n));
+        for (int32_t k = 0; k < n; ++k) out[size_t(k)] = pos[size_t(a[k])];
+        return out.data();
+    };
+    r.net = in;
+    r.net.br_from = map(in.br_from, in.n_branch, r.from);
+    r.net.br_to = map(in.br_to, in.n_branch, r.to);
+    r.net.load_bus = map(in.load_bus, in.n_load, r.load_bus);
+    r.net.pv_bus = map(in.pv_bus, in.n_pv, r.pv_bus);
+    r.net.slack_bus = map(in.slack_bus, in.n_slack, r.slack_bus);
+    r.net.shunt_bus = map(in.shunt_bus, in.n_shunt, r.shunt_bus);
+    return true;
+}
+
+// The host plan of n_grids networks, each renumbered first when the options
+// ask for the locality order; records the plan's bus order.
+int build_ordered(const pf_network *nets, int32_t n_grids, const pf_setup_opts *opt,
+                  HostPlan &hp) {
+    const int32_t how = opt ? opt->bus_order : PF_ORDER_INPUT;
+    if (how != PF_ORDER_INPUT && how != PF_ORDER_LOCALITY)
+        return fail(PF_EINVAL, "unknown bus_order %d", how);
+    if (how == PF_ORDER_INPUT) {
+        const int rc = build_host_plan(nets, n_grids, hp);
+        if (!rc) {
+            hp.bus_order.clear();
+            for (const GridInfo &g : hp.grids)
+                for (int32_t i = 0; i < g.N; ++i) hp.bus_order.push_back(i);
+        }
+        return rc;
+    }
+    std::vector<Renumbered> rn(static_cast<size_t>(n_grids));
+    std::vector<pf_network> nn(static_cast<size_t>(n_grids));
+    for (int32_t g = 0; g < n_grids; ++g) {
+        if (!renumber(nets[g], rn[size_t(g)])) return build_host_plan(nets, n_grids, hp);
+        nn[size_t(g)] = rn[size_t(g)].net;
+    }
+    const int rc = build_host_plan(nn.data(), n_grids, hp);
+    if (!rc) {
+        hp.bus_order_kind = PF_ORDER_LOCALITY;
+        hp.bus_order.clear();
+        for (const Renumbered &r : rn) hp.bus_order.insert(hp.bus_order.end(), r.order.begin(),
+                                                           r.order.end());
+    }
+    return rc;
+}
 
 int finish_setup(pf_plan *p, const pf_setup_opts *opt, pf_plan **out) {
     int rc = normalise_schedule(p->host, opt ? &opt->sched : nullptr, p->host.sched);
@@ -55,7 +163,7 @@ int pf_setup(const pf_network *net, const pf_setup_opts *opt, pf_plan **out) {
     int rc;
     try {
         p->host.q_slots = (opt && opt->q_limits) ? 1 : 0;
-        rc = build_host_plan(net, 1, p->host);
+        rc = build_ordered(net, 1, opt, p->host);
     } catch (const std::bad_alloc &) {
         rc = fail(PF_ENOMEM, "host allocation failed");
     }
@@ -75,7 +183,7 @@ int pf_setup_batch(const pf_network *net, const pf_batch_spec *spec, const pf_se
     int rc;
     try {
         p->host.q_slots = (opt && opt->q_limits) ? 1 : 0;
-        rc = build_host_plan(net, 1, p->host);
+        rc = build_ordered(net, 1, opt, p->host);
         if (!rc) rc = attach_batch(spec, p->host);
     } catch (const std::bad_alloc &) {
         rc = fail(PF_ENOMEM, "host allocation failed");
@@ -96,7 +204,7 @@ int pf_setup_multi(const pf_network *nets, int32_t n_grids, const pf_setup_opts 
     int rc;
     try {
         p->host.q_slots = (opt && opt->q_limits) ? 1 : 0;
-        rc = build_host_plan(nets, n_grids, p->host);
+        rc = build_ordered(nets, n_grids, opt, p->host);
         p->host.kind = KIND_MULTI;
     } catch (const std::bad_alloc &) {
         rc = fail(PF_ENOMEM, "host allocation failed");
@@ -110,6 +218,14 @@ void pf_destroy(pf_plan *plan) {
     if (!plan) return;
     dev_destroy(plan->dev);
     delete plan;
+}
+
+int pf_bus_order(const pf_plan *plan, int32_t *order) {
+    clear_error();
+    if (!plan || !order) return fail(PF_EINVAL, "NULL argument");
+    const std::vector<int32_t> &o = plan->host.bus_order;
+    if (!o.empty()) std::memcpy(order, o.data(), o.size() * sizeof(int32_t));
+    return PF_OK;
 }
 
 int pf_info(const pf_plan *plan, int64_t *n, int64_t *nnz) {

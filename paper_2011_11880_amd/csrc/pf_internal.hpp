@@ -115,6 +115,10 @@ struct HostPlan {
     std::vector<double> pv_scale_t;    // [NPV][ld] or empty
     std::vector<int32_t> outage;       // [I] or empty
     std::vector<int32_t> order_natural, order_bfs;   // bus processing orders
+    // input bus (grid-local) of every plan bus: the identity unless the
+    // network was renumbered for locality at setup (bus_order_kind 1)
+    std::vector<int32_t> bus_order;
+    int32_t bus_order_kind = 0;
 
     // adjoint work order (single-instance and multi-grid plans): admittance
     // rows taken in breadth-first order, so that a contiguous range of work,

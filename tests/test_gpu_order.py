@@ -1,0 +1,126 @@
+"""Plans set up with the locality bus order (PF_ORDER_LOCALITY): single,
+batched (scenarios and outages), multi-grid and adjoint evaluations against
+the oracle on the input network, through the plan's state permutation."""
+
+import numpy as np
+import pytest
+import scipy.sparse as sp
+
+from paper_2011_11880_amd import synth
+from parity import check_close, check_jacobian
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+
+@pytest.fixture(scope="module")
+def cuda():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    return torch.device("cuda", 0)
+
+
+def _oracle_in_plan_order(ora, net, y, perm):
+    """Oracle F, S, J, scale at y (input numbering), rows and columns taken
+    to the plan's order: F_plan = F[perm], J_plan = J[perm][:, perm]."""
+    Fo, So = ora.residual(net, y)
+    Jo, Ao = ora.jacobian(net, y)
+    Jp = Jo[perm][:, perm].tocsr()
+    Ap = Ao[perm][:, perm].tocsr()
+    Jp.sort_indices()
+    Ap.sort_indices()
+    return Fo[perm], So[perm], Jp, Ap
+
+
+@pytest.mark.parametrize("which", ["tiny", "10k", "70k"])
+def test_single_instance_locality_order(ora, cuda, which):
+    from paper_2011_11880_amd.api import Plan
+    net = {"tiny": lambda: synth.tiny_grid(3, n_shunt=5), "10k": synth.grid_10k,
+           "70k": synth.grid_70k}[which]()
+    p = Plan(net, bus_order="locality")
+    perm = p.state_perm()
+    y = synth.random_states(net, seed=7)
+    F, J = p.eval(torch.from_numpy(p.to_plan(y)).to(cuda))
+    torch.cuda.synchronize()
+    Fo, So, Jo, Ao = _oracle_in_plan_order(ora, net, y, perm)
+    check_close(F.cpu().numpy(), Fo, So, f"{which} F")
+    rp, ci = p.pattern()
+    check_jacobian(rp, ci, J.cpu().numpy(), Jo, Ao, f"{which} J")
+
+
+def test_batched_locality_order(ora, cuda):
+    from paper_2011_11880_amd.api import Plan
+    import test_gpu_batch as TB
+    net = TB._net()
+    I = 70
+    ls, ps = synth.batch_scenarios(net, I, seed=5)
+    out = np.full(I, -1, np.int32)
+    out[35:] = synth.non_bridge_branches(net)[:I - 35]
+    spec = dict(n_inst=I, load_scale=ls, pv_scale=ps, outage=out)
+    bp = Plan(net, batch=spec, bus_order="locality")
+    perm = bp.state_perm()
+    Y = synth.random_states(net, I, seed=6)
+    X = torch.from_numpy(bp.to_batch(bp.to_plan(Y))).to(cuda)
+    F, J = bp.eval_batch(X)
+    torch.cuda.synchronize()
+    Fh, Jh = bp.from_batch(F), bp.from_batch(J)
+    rp, ci = bp.pattern()
+    for k in (0, 1, 34, 35, 36, 69):
+        nk = TB._instance_net(net, spec, k)
+        Fo, So, Jo, Ao = _oracle_in_plan_order(ora, nk, Y[k], perm)
+        check_close(Fh[k], Fo, So, f"inst {k} F")
+        check_jacobian(rp, ci, Jh[k], Jo, Ao, f"inst {k} J")
+
+
+def test_multi_grid_locality_order(ora, cuda):
+    from paper_2011_11880_amd.api import Plan
+    nets = synth.uneven_grids(12, seed=3000)
+    mp = Plan.multi(nets, bus_order="locality")
+    ys = [synth.random_states(n, seed=60 + g) for g, n in enumerate(nets)]
+    y = np.concatenate(ys)
+    F, J = mp.eval(torch.from_numpy(mp.to_plan(y)).to(cuda))
+    torch.cuda.synchronize()
+    F = mp.from_plan(F.cpu().numpy())
+    J = J.cpu().numpy()
+    order = mp.bus_order()
+    b0 = 0
+    for g, net in enumerate(nets):
+        x0, x1 = mp.x_off[g], mp.x_off[g + 1]
+        Fo, So = ora.residual(net, ys[g])
+        check_close(F[x0:x1], Fo, So, f"grid {g} F")
+        single = Plan(net, host_only=True, bus_order="locality")
+        assert np.array_equal(single.bus_order(), order[b0:b0 + net.n_bus])
+        perm = single.state_perm()
+        _, _, Jo, Ao = _oracle_in_plan_order(ora, net, ys[g], perm)
+        rp, ci = single.pattern()
+        check_jacobian(rp, ci, J[mp.j_off[g]:mp.j_off[g + 1]], Jo, Ao, f"grid {g} J")
+        b0 += net.n_bus
+
+
+def test_adjoint_locality_order(ora, cuda):
+    """J^T W in the plan's order is the oracle's J^T W with both the
+    cotangent and the result permuted; parameter gradients keep the
+    branch and load order."""
+    from paper_2011_11880_amd.api import Plan
+    import test_gpu_vjp as V
+    net = V._net()
+    p = Plan(net, bus_order="locality")
+    perm = p.state_perm()
+    y = synth.random_states(net, seed=9)
+    Wn = np.random.default_rng(9).standard_normal((net.n_var, 5))
+    gx, gp = p.vjp(torch.from_numpy(p.to_plan(y)).to(cuda),
+                   torch.from_numpy(np.ascontiguousarray(Wn[perm])).to(cuda))
+    torch.cuda.synchronize()
+    gx, gp = gx.cpu().numpy(), gp.cpu().numpy()
+    Jo, Ao = ora.jacobian(net, y)
+    B, L = net.n_branch, net.n_load
+    for k in range(5):
+        go = Jo.T @ Wn[:, k]
+        check_close(gx[:, k], go[perm], (Ao.T @ np.abs(Wn[:, k]))[perm], f"gx[{k}]")
+        gpo = ora.vjp_params(net, y, Wn[:, k])
+        sc = ora.vjp_params_scale(net, y, Wn[:, k])
+        for q, name in enumerate(V.PNAMES):
+            check_close(gp[q * B:(q + 1) * B, k], gpo[name], sc[name], f"{name}[{k}]")
+        np.testing.assert_array_equal(gp[5 * B:5 * B + L, k], gpo["load_p"])
+        np.testing.assert_array_equal(gp[5 * B + L:, k], gpo["load_q"])
