@@ -432,6 +432,22 @@ def run_c1(args, torch, dev):
         log("[bench] plain floors", res["plain"]["empty_launch_us"], res["plain"]["copy_same_bytes_us"])
         del src, dst, tiny
         del g, Fs, Js, Xs
+        # the same launches on a plan whose buses are numbered breadth-first
+        # at setup (states converted to the plan's order beforehand)
+        pl = Plan(net, device=0, bus_order="locality")
+        Xl = torch.from_numpy(pl.to_plan(Y)).to(dev)
+        Fl = torch.empty((S, n), dtype=torch.float64, device=dev)
+        Jl = torch.empty((S, nnz), dtype=torch.float64, device=dev)
+        best = pl.autotune(Xl[0], Fl[0], Jl[0], reps=20, cache=tune_cache(args))
+        us1, us4 = time_plain_launches(torch, pl, Xl, Fl, Jl, args.steps, args.warmup)
+        res["plain_locality_order"] = {
+            "us_per_eval": us1, "evals_per_s": 1e6 / us1,
+            "gbs": bytes_p / (us1 * 1e-6) / 1e9, "hbm_frac": bytes_p / (us1 * 1e-6) / 1e9 /
+            HBM_PEAK_GBS, "us_per_eval_4_streams": us4,
+            "hbm_frac_4_streams": bytes_p / (us4 * 1e-6) / 1e9 / HBM_PEAK_GBS,
+            "schedule": best, "schedule_from_tune_cache": pl.tune_hit}
+        log("[bench] plain, locality order", json.dumps(res["plain_locality_order"]))
+        del Xl, Fl, Jl
 
     head = res["batched"]
     out = {
@@ -473,6 +489,48 @@ def run_c1(args, torch, dev):
                                      plain_us=res.get("plain", {}).get("us_per_eval"))
             log(f"[bench] {name}", json.dumps(out["others"][name]))
     return out
+
+
+def time_plain_launches(torch, plan, Xs, Fs, Js, steps, warmup):
+    """Microseconds per evaluation of len(Xs) single-instance launches (each
+    state its own output slots) replayed from a captured graph, on one
+    stream and spread round-robin over 4 streams (fork/join)."""
+    S = Xs.shape[0]
+    for s in range(S):
+        plan.eval(Xs[s], Fs[s], Js[s])
+    torch.cuda.synchronize()
+    st = torch.cuda.Stream()
+    st.wait_stream(torch.cuda.current_stream())
+    side = [torch.cuda.Stream() for _ in range(4)]
+    g1 = torch.cuda.CUDAGraph()
+    with torch.cuda.stream(st):
+        with torch.cuda.graph(g1, stream=st):
+            for s in range(S):
+                plan.eval(Xs[s], Fs[s], Js[s])
+    g4 = torch.cuda.CUDAGraph()
+    with torch.cuda.stream(st):
+        with torch.cuda.graph(g4, stream=st):
+            fork = torch.cuda.Event()
+            fork.record(st)
+            for q in side:
+                q.wait_event(fork)
+            for s in range(S):
+                with torch.cuda.stream(side[s % 4]):
+                    plan.eval(Xs[s], Fs[s], Js[s])
+            for q in side:
+                join = torch.cuda.Event()
+                join.record(q)
+                st.wait_event(join)
+    torch.cuda.synchronize()
+    out = []
+    for g in (g1, g4):
+        for _ in range(warmup):
+            g.replay()
+        with Timer(torch) as t:
+            for _ in range(steps):
+                g.replay()
+        out.append(t.ms * 1e3 / (steps * S))
+    return out[0], out[1]
 
 
 def run_c2(args, torch, dev, **kw):
@@ -548,12 +606,21 @@ def run_c3(args, torch, dev, **kw):
     best = mp.autotune(x, F, J, reps=10, cache=tune_cache(args))
     hit = mp.tune_hit
     ms = time_ms(torch, lambda: mp.eval(x, F, J), reps=20)
+    # the same grids numbered breadth-first at setup
+    ml = Plan.multi(nets, device=0, bus_order="locality")
+    xl = torch.from_numpy(ml.to_plan(xs)).to(dev)
+    best_l = ml.autotune(xl, F, J, reps=10, cache=tune_cache(args))
+    ms_l = time_ms(torch, lambda: ml.eval(xl, F, J), reps=20)
+    del ml, xl
     nb = per_eval_bytes(mp.n, mp.nnz) + statics_bytes(mp.info)
     res = {"grids": 256, "buses": int(sum(n.n_bus for n in nets)), "n": mp.n, "nnz": mp.nnz,
            "ms": ms, "grid_evals_per_s": 256 / (ms * 1e-3), "gbs": nb / (ms * 1e-3) / 1e9,
            "hbm_frac": nb / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS, "bytes_per_launch": nb,
            "traffic": measured_traffic("k_eval_single_256_uneven_grids_traffic.json", 1),
-           "autotuned_schedule": best, "schedule_from_tune_cache": hit}
+           "autotuned_schedule": best, "schedule_from_tune_cache": hit,
+           "locality_order": {"ms": ms_l, "grid_evals_per_s": 256 / (ms_l * 1e-3),
+                              "hbm_frac": nb / (ms_l * 1e-3) / 1e9 / HBM_PEAK_GBS,
+                              "autotuned_schedule": best_l}}
     if not getattr(args, "no_cpu", False):
         log("[bench] c3 CPU oracle over grids")
         off = np.cumsum([0] + [n.n_var for n in nets])
