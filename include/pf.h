@@ -117,8 +117,11 @@ typedef struct pf_network {
  *                   from the lowest-numbered bus
  *   xcd_remap       1: give each of the 8 XCDs a contiguous range of work
  *                   items (L2 locality), 2: round-robin (hardware order)
- *   batch_group     batched kernel work order: number of 64-instance chunks
- *                   of a bus processed back to back (1..64).  Work runs over
+ *   batch_group     batched kernel work order: number of instance chunks
+ *                   of a bus processed back to back (1..64); a chunk is 64
+ *                   instances, or 128 where two instances share a lane
+ *                   (plans without overlays whose instance count and pitch
+ *                   are even).  Work runs over
  *                   groups of this many chunks, and inside a group bus by
  *                   bus: 1 = one chunk at a time over all buses (small state
  *                   footprint per bus, good cache reuse between neighbouring

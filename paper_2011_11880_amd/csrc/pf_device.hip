@@ -788,6 +788,172 @@ k_eval_batch(int N, int I, int LD, int panel, int64_t rows_x, int64_t rows_j, in
     }
 }
 
+// Batched fused residual + Jacobian without overlays, two instances per lane:
+// a wavefront covers 128 instances, every state gather and output store is
+// 16 bytes per lane (1 KB per instruction), and each bus's structure, row
+// coefficients and scalar lookups serve twice the data.  For row layouts
+// whose instance count and pitch are even (so every pair is 16-byte
+// aligned).  The walk and its arithmetic are those of k_eval_batch's
+// overlay-free path, per instance, so the outputs are bit-identical.
+typedef double d2 __attribute__((ext_vector_type(2)));
+__device__ __forceinline__ d2 ld2(const double *p) { return *reinterpret_cast<const d2 *>(p); }
+__device__ __forceinline__ void st2(double *p, d2 v) {
+    __builtin_nontemporal_store(v, reinterpret_cast<d2 *>(p));
+}
+template <bool WF, bool WJ>
+__global__ void __launch_bounds__(512)
+k_eval_batch2(int N, int I, int LD, int n_btiles, int n_chunks, int TB, int n_items,
+              int items_per_wave, int remap, int group, const int32_t *__restrict__ order,
+              const int4 *__restrict__ bus4, const int2 *__restrict__ bus2,
+              const double2 *__restrict__ spec, const int32_t *__restrict__ ycol,
+              const double *__restrict__ yG, const double *__restrict__ yB,
+              const int4 *__restrict__ gen4, const double2 *__restrict__ gen2,
+              const double *__restrict__ X, double *__restrict__ F, double *__restrict__ J) {
+    const int lane = threadIdx.x & 63;
+    const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    const int wpb = blockDim.x >> 6;
+    const int lb = remap ? xcd_logical_block(blockIdx.x, gridDim.x) : blockIdx.x;
+    const int lw = lb * wpb + wv;
+    const int w_begin = lw * items_per_wave;
+    const int w_end = min(n_items, w_begin + items_per_wave);
+    const size_t SI = size_t(LD);
+    for (int w = w_begin; w < w_end; ++w) {
+        const int per_group = n_btiles * group;
+        const int sg = w / per_group;
+        const int rem = w - sg * per_group;
+        const int bt = rem / group;
+        const int ch = sg * group + (rem - bt * group);
+        if (ch >= n_chunks) continue;
+        const int k0 = ch * 128 + 2 * lane;
+        const bool valid = k0 < I;
+        const size_t kk = size_t(valid ? k0 : I - 2);
+        const size_t kq = size_t(k0);
+        const int q0 = bt * TB;
+        const int q1 = min(N, q0 + TB);
+        constexpr int EU = 4;
+        for (int qq = q0; qq < q1; ++qq) {
+            const int b = order[qq];
+            const int4 bi = bus4[b];
+            const int2 b2 = bus2[b];
+            const int L = bi.y - bi.x;
+            const d2 thi = ld2(X + size_t(b) * SI + kk);
+            const d2 vi = ld2(X + size_t(N + b) * SI + kk);
+            int4 g4 = make_int4(0, 0, 0, 0);
+            double2 gs = make_double2(0.0, 0.0);
+            d2 qg = {0.0, 0.0}, ps = {0.0, 0.0};
+            if (b2.y >= 0) {
+                g4 = gen4[b2.y];
+                gs = gen2[b2.y];
+                qg = ld2(X + size_t(g4.x) * SI + kk);
+                if (g4.z >= 0) ps = ld2(X + size_t(g4.z) * SI + kk);
+            }
+            int jj[EU];
+            double GG[EU], BB[EU];
+            d2 thj[EU], vj[EU];
+#pragma unroll
+            for (int u = 0; u < EU; ++u) {
+                jj[u] = ycol[bi.x + u] & kColMask;
+                GG[u] = yG[bi.x + u];
+                BB[u] = yB[bi.x + u];
+            }
+#pragma unroll
+            for (int u = 0; u < EU; ++u) {
+                thj[u] = thi;
+                vj[u] = vi;
+                if (u < L && u != b2.x) {
+                    thj[u] = ld2(X + size_t(jj[u]) * SI + kk);
+                    vj[u] = ld2(X + size_t(N + jj[u]) * SI + kk);
+                }
+            }
+            double ax[6] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
+            double ay[6] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
+            auto entry = [&](int p, int j, double G, double Bv, d2 tj, d2 vjj) {
+                const bool diag = (j == b);
+                double cx[6], ox[4], cy[6], oy[4];
+                entry_eval(diag, G, Bv, thi.x, vi.x, tj.x, vjj.x, cx, ox);
+                entry_eval(diag, G, Bv, thi.y, vi.y, tj.y, vjj.y, cy, oy);
+                if (WJ && !diag && valid) {
+                    st2(J + size_t(bi.z + p) * SI + kq, d2{ox[0], oy[0]});
+                    st2(J + size_t(bi.z + L + p) * SI + kq, d2{ox[1], oy[1]});
+                    st2(J + size_t(bi.w + p) * SI + kq, d2{ox[2], oy[2]});
+                    st2(J + size_t(bi.w + L + p) * SI + kq, d2{ox[3], oy[3]});
+                }
+#pragma unroll
+                for (int q = 0; q < 6; ++q) {
+                    ax[q] += cx[q];
+                    ay[q] += cy[q];
+                }
+            };
+#pragma unroll
+            for (int u = 0; u < EU; ++u) {
+                if (u >= L) break;
+                entry(u, jj[u], GG[u], BB[u], thj[u], vj[u]);
+            }
+            for (int e0 = bi.x + EU; e0 < bi.y; e0 += EU) {
+                int j2[EU];
+                double G2[EU], B2[EU];
+                d2 t2[EU], v2[EU];
+#pragma unroll
+                for (int u = 0; u < EU; ++u) {
+                    j2[u] = ycol[e0 + u] & kColMask;
+                    G2[u] = yG[e0 + u];
+                    B2[u] = yB[e0 + u];
+                }
+#pragma unroll
+                for (int u = 0; u < EU; ++u) {
+                    t2[u] = thi;
+                    v2[u] = vi;
+                    if (e0 + u < bi.y && j2[u] != b) {
+                        t2[u] = ld2(X + size_t(j2[u]) * SI + kk);
+                        v2[u] = ld2(X + size_t(N + j2[u]) * SI + kk);
+                    }
+                }
+#pragma unroll
+                for (int u = 0; u < EU; ++u) {
+                    if (e0 + u >= bi.y) break;
+                    entry(e0 + u - bi.x, j2[u], G2[u], B2[u], t2[u], v2[u]);
+                }
+            }
+            if (!valid) continue;
+            const double2 sp = spec[b];
+            d2 fp = {ax[0] + sp.x, ay[0] + sp.x};
+            d2 fq = {ax[1] + sp.y, ay[1] + sp.y};
+            if (b2.y >= 0) {
+                const bool held = g4.z == kGenHeld;
+                fq = fq - qg;
+                if (WF) st2(F + size_t(g4.x) * SI + kq, held ? qg - gs.x : vi - gs.x);
+                if (WJ) {
+                    st2(J + size_t(bi.w + 2 * L) * SI + kq, d2{-1.0, -1.0});
+                    const double cv = held ? 0.0 : 1.0;
+                    st2(J + size_t(g4.y) * SI + kq, d2{cv, cv});
+                    if (g4.z <= kGenVoltageSlot) {
+                        const double cq = held ? 1.0 : 0.0;
+                        st2(J + size_t(g4.y + 1) * SI + kq, d2{cq, cq});
+                    }
+                }
+                if (g4.z >= 0) {
+                    fp = fp - ps;
+                    if (WF) st2(F + size_t(g4.z) * SI + kq, thi - gs.y);
+                    if (WJ) {
+                        st2(J + size_t(bi.z + 2 * L) * SI + kq, d2{-1.0, -1.0});
+                        st2(J + size_t(g4.w) * SI + kq, d2{1.0, 1.0});
+                    }
+                }
+            }
+            if (WF) {
+                st2(F + size_t(b) * SI + kq, fp);
+                st2(F + size_t(N + b) * SI + kq, fq);
+            }
+            if (WJ) {
+                st2(J + size_t(bi.z + b2.x) * SI + kq, d2{ax[2], ay[2]});
+                st2(J + size_t(bi.z + L + b2.x) * SI + kq, d2{ax[3], ay[3]});
+                st2(J + size_t(bi.w + b2.x) * SI + kq, d2{ax[4], ay[4]});
+                st2(J + size_t(bi.w + L + b2.x) * SI + kq, d2{ax[5], ay[5]});
+            }
+        }
+    }
+}
+
 // x <- x - dx (Newton update, task 4).
 __global__ void __launch_bounds__(256) k_newton_update(int64_t n, double *__restrict__ x,
                                                        const double *__restrict__ dx) {
@@ -1426,7 +1592,11 @@ int dev_eval_batch(HostPlan &hp, DevPlan *dp, const double *X, double *F, double
     const int I = hp.n_inst;
     const int TB = s.batch_buses;
     const int n_btiles = (N + TB - 1) / TB;
-    const int n_chunks = (I + 63) / 64;
+    // overlay-free row layouts with an even instance count and pitch take two
+    // instances per lane (chunks of 128)
+    const bool pairs = !dp->lscale && !dp->pscale && !dp->outage && !hp.panels && I % 2 == 0 &&
+                       hp.ld % 2 == 0;
+    const int n_chunks = pairs ? (I + 127) / 128 : (I + 63) / 64;
     const int group = std::min(s.batch_group, n_chunks);
     const int64_t n_items = int64_t(n_btiles) * group * ((n_chunks + group - 1) / group);
     if (n_items > (int64_t(1) << 31) - 1) return fail(PF_EINVAL, "batch work list too long");
@@ -1456,7 +1626,19 @@ int dev_eval_batch(HostPlan &hp, DevPlan *dp, const double *X, double *F, double
         LAUNCH(WF, WJ, false, true);   \
     else                               \
         LAUNCH(WF, WJ, false, false)
-    if (F && J) {
+    if (pairs) {
+#define LAUNCH2(WF, WJ)                                                                           \
+    hipLaunchKernelGGL((k_eval_batch2<WF, WJ>), dim3(blocks), dim3(threads), 0, st, N, I, hp.ld,   \
+                       n_btiles, n_chunks, TB, int(n_items), ipw, remap, group, order, dp->bus4, \
+                       dp->bus2, dp->spec, dp->ycol, dp->yG, dp->yB, dp->gen4, dp->gen2, X, F, J)
+        if (F && J)
+            LAUNCH2(true, true);
+        else if (F)
+            LAUNCH2(true, false);
+        else
+            LAUNCH2(false, true);
+#undef LAUNCH2
+    } else if (F && J) {
         LAUNCH_OV(true, true);
     } else if (F) {
         LAUNCH_OV(true, false);

@@ -123,6 +123,40 @@ def test_residual_only_and_jacobian_only_equal_fused(cuda, overlay):
     assert np.array_equal(bp.from_batch(J1), bp.from_batch(J0))
 
 
+@pytest.mark.parametrize("I,LD", [(70, 72), (70, 71), (69, 70), (130, 130)])
+def test_lane_pairing_paths_equal_single(cuda, I, LD):
+    """Without overlays, even instance counts and pitches take two instances
+    per lane, odd ones one: both bit-identical to the single-instance kernel
+    for every instance, under several schedules (residual-only and
+    Jacobian-only launches included), padding columns untouched."""
+    Plan = _Plan()
+    net = _net()
+    Y = synth.random_states(net, I, seed=I + LD)
+    bp = Plan(net, batch=dict(n_inst=I, inst_stride=LD))
+    Xp = np.full((net.n_var, LD), np.nan)
+    Xp[:, :I] = Y.T
+    X = torch.from_numpy(Xp).to(cuda)
+    sp = Plan(net)
+    ref = [sp.eval(torch.from_numpy(Y[k]).to(cuda)) for k in range(I)]
+    for sched in (None, dict(batch_buses=1, batch_group=1, waves_per_block=1),
+                  dict(batch_buses=7, batch_group=2, grid_blocks=5),
+                  dict(batch_buses=64, batch_order=1, batch_group=64)):
+        if sched:
+            bp.schedule = dict(bp.schedule, **sched)
+        F = torch.full((bp.n, LD), 7.0, dtype=torch.float64, device=cuda)
+        J = torch.full((bp.nnz, LD), 7.0, dtype=torch.float64, device=cuda)
+        bp.eval_batch(X, F, J)
+        F1 = torch.full_like(F, 7.0)
+        J1 = torch.full_like(J, 7.0)
+        bp.eval_batch(X, F1, None, want_J=False)
+        bp.eval_batch(X, None, J1, want_F=False)
+        torch.cuda.synchronize()
+        for k in range(I):
+            assert torch.equal(F[:, k], ref[k][0]) and torch.equal(J[:, k], ref[k][1]), (sched, k)
+        assert torch.equal(F1, F) and torch.equal(J1, J), sched
+        assert torch.all(F[:, I:] == 7.0) and torch.all(J[:, I:] == 7.0), sched
+
+
 def test_outage_slots_are_exact_zero(cuda):
     """Taking out a branch with no parallel partner zeroes its eight
     off-diagonal slots exactly."""
