@@ -14,7 +14,7 @@
       each scaled by what the same counter reads for a plain copy kernel of
       known size (copy_bytes read and copy_bytes written per dispatch);
       --last N averages only the kernel's last N dispatches (the timed
-      launches of a run that autotunes first)
+      launches of a run that autotunes first), --first N its first N
 
   python -m paper_2011_11880_amd.rocprof_summary fp64 RUN_results.db \
         --kernel NAME --units U --out FILE.json [--last N]
@@ -49,12 +49,14 @@ def kernel_stats(db, match=None):
     return out
 
 
-def counter_per_dispatch(db, counter, match, last=None):
+def counter_per_dispatch(db, counter, match, last=None, first=None):
     c = sqlite3.connect(db)
     rows = c.execute("select kernel_name, dispatch_id, sum(value) from counters_collection "
                      "where counter_name = ? group by kernel_name, dispatch_id",
                      (counter,)).fetchall()
     rows = sorted((d, v) for name, d, v in rows if match in name)
+    if first:
+        rows = rows[:first]
     if last:
         rows = rows[-last:]
     vals = [v for _, v in rows]
@@ -79,8 +81,8 @@ def counters(db, match):
 def traffic(a):
     from .build import kernel_source_hash
     kib = 1024.0
-    f_k, nf = counter_per_dispatch(a.fetch, "FETCH_SIZE", a.kernel, a.last)
-    w_k, nw = counter_per_dispatch(a.write, "WRITE_SIZE", a.kernel, a.last)
+    f_k, nf = counter_per_dispatch(a.fetch, "FETCH_SIZE", a.kernel, a.last, a.first)
+    w_k, nw = counter_per_dispatch(a.write, "WRITE_SIZE", a.kernel, a.last, a.first)
     f_c, _ = counter_per_dispatch(a.copy_fetch, "FETCH_SIZE", a.copy_kernel)
     w_c, _ = counter_per_dispatch(a.copy_write, "WRITE_SIZE", a.copy_kernel)
     sf = a.copy_bytes / (f_c * kib)
@@ -128,6 +130,7 @@ def main(argv=None):
     t.add_argument("--copy-bytes", type=int, required=True)
     t.add_argument("--units", type=int, required=True)
     t.add_argument("--last", type=int, default=None)
+    t.add_argument("--first", type=int, default=None)
     f = sub.add_parser("fp64")
     f.add_argument("db")
     for k in ("kernel", "out"):
