@@ -309,6 +309,40 @@ def q_limit_switch(net, y, mode, qt, qmin, qmax, tol=1e-9):
     return mode, qt, switched
 
 
+def newton_qlim_inner(net, y0, qmin, qmax, tol=1e-10, max_iter=20, check_below=1e-3,
+                      switch_tol=1e-9):
+    """Newton power flow with the reactive limits checked during the
+    iterations (Section II-A: the extended formulation allows it, since the
+    same equations serve before and after a PV generator becomes a PQ
+    injection).  At every iterate whose mismatch is below ``check_below`` the
+    switching rule (q_limit_switch) is applied; after a switch the residual
+    is taken again under the new modes before the step.  Converged when
+    ||F||_inf < tol under modes that the check at that iterate left
+    unchanged.  Returns (y, mode, qt, list of ||F||_inf, list of the
+    iterations at which a switch happened, converged)."""
+    y = np.array(y0, dtype=np.float64)
+    mode = np.zeros(net.n_pv, np.int32)
+    qt = np.zeros(net.n_pv)
+    norms, switched_at = [], []
+    for it in range(max_iter + 1):
+        F, _ = residual(net, y, modes=(mode, qt))
+        nf = float(np.max(np.abs(F)))
+        if nf < check_below:
+            mode, qt, ns = q_limit_switch(net, y, mode, qt, qmin, qmax, switch_tol)
+            if ns:
+                switched_at.append(it)
+                F, _ = residual(net, y, modes=(mode, qt))
+                nf = float(np.max(np.abs(F)))
+        norms.append(nf)
+        if nf < tol:
+            return y, mode, qt, norms, switched_at, True
+        if it == max_iter:
+            break
+        J, _ = jacobian(net, y, modes=(mode, qt))
+        y = y - spla.spsolve(J.tocsc(), F)
+    return y, mode, qt, norms, switched_at, False
+
+
 def newton_qlim(net, y0, qmin, qmax, tol=1e-10, max_iter=10, max_outer=10):
     """Newton power flow with reactive limits (Section II-A: the extended
     formulation serves before and after a PV generator becomes a PQ

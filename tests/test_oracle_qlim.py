@@ -149,3 +149,40 @@ def test_newton_with_limits_ends_feasible(ora):
     up = held & (qt == qmax)
     lo = held & (qt == qmin)
     assert np.all(V[up] <= net.pv_v[up] + 1e-9) and np.all(V[lo] >= net.pv_v[lo] - 1e-9)
+
+
+def test_newton_with_limits_checked_in_the_iterations_ends_feasible(ora):
+    """Limits checked at every iterate once the mismatch is below 1e-3 (no
+    outer loop): the end state is feasible in the same sense as the outer
+    loop's (F = 0 under the final modes, free generators inside their
+    limits, held ones at a limit with the voltage on the justifying side),
+    the switches happen inside the iterations, and for this case the final
+    modes and state agree with the outer loop's."""
+    net, ystar = _solution(ora, seed=11)
+    N, NPV = net.n_bus, net.n_pv
+    q = ystar[2 * N:2 * N + NPV]
+    qmin = q - 10.0
+    qmax = q + 10.0
+    qmax[[1, 4, 9, 20]] = q[[1, 4, 9, 20]] - 0.05
+    qmin[[2, 30]] = q[[2, 30]] + 0.05
+    rng = np.random.default_rng(4)
+    y0 = ystar + np.concatenate([rng.normal(0, 0.01, 2 * N), np.zeros(net.n_var - 2 * N)])
+    y, mode, qt, norms, sw, ok = ora.newton_qlim_inner(net, y0, qmin, qmax)
+    assert ok and len(sw) >= 1 and mode.sum() >= 1
+    assert sw[0] > 0 and norms[0] >= 1e-3                # first checked below 1e-3
+    assert sw[-1] < len(norms) - 1                       # the last check switched nothing
+    F, S = ora.residual(net, y, modes=(mode, qt))
+    assert np.max(np.abs(F)) < 1e-10
+    Qg = y[2 * N:2 * N + NPV]
+    V = y[N + net.pv_bus]
+    free = mode == 0
+    assert np.all(Qg[free] <= qmax[free] + 1e-9) and np.all(Qg[free] >= qmin[free] - 1e-9)
+    held = ~free
+    assert np.all((qt[held] == qmax[held]) | (qt[held] == qmin[held]))
+    np.testing.assert_allclose(Qg[held], qt[held], rtol=0, atol=1e-12)
+    up = held & (qt == qmax)
+    lo = held & (qt == qmin)
+    assert np.all(V[up] <= net.pv_v[up] + 1e-9) and np.all(V[lo] >= net.pv_v[lo] - 1e-9)
+    y2, mode2, qt2, _, ok2 = ora.newton_qlim(net, y0, qmin, qmax)
+    assert ok2 and np.array_equal(mode, mode2) and np.array_equal(qt, qt2)
+    np.testing.assert_allclose(y, y2, rtol=0, atol=1e-9)
