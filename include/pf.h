@@ -371,14 +371,35 @@ int pf_autotune_cached(pf_plan *plan, const double *x, double *F, double *Jval,
  * synchronises; work queued on other (non-blocking) streams that writes x
  * must be complete before the call.  report (nullable) receives iteration counts, per-iteration
  * norms (up to 64) and times.  Returns PF_ENOCONV if max_iter is reached.
+ *
+ * Reactive limits inside the iterations (Section II-A: with the extended
+ * formulation the same equations serve before and after a PV generator is
+ * held, so the limits may be checked at any iterate): with q_min and q_max
+ * set (host [n_pv], read during the call; plan set up with q_limits = 1,
+ * not batched), at every iterate x_k whose ||F||_inf is below
+ * q_check_below the switching rule of pf_q_limit_check (tolerance
+ * q_switch_tol) is applied to x_k; after a switch F and J are evaluated
+ * again at x_k under the new modes before the step.  norm[k] is then the
+ * norm under the modes in force after the check, switched[k] the number of
+ * units that changed mode at x_k, and convergence needs ||F||_inf < tol
+ * under modes that the check at that iterate left unchanged.  The modes
+ * stay on the plan (pf_get_gen_modes).  Only pf_newton checks limits
+ * inside its iterations: a switch moves the held row's nonzero from the V
+ * column to the Q_g column, which the fixed pivots of pf_newton_device,
+ * pf_newton_batch and pf_fdlf_solve cannot follow; they return PF_EINVAL
+ * when q_min or q_max is set.
  */
 typedef int (*pf_linsolve_fn)(void *user, int64_t n, const int32_t *rowptr,
                               const int32_t *colidx, const double *Jval_host,
                               const double *rhs_host, double *dx_host);
 
 typedef struct pf_newton_opts {
-    double tol;        /* <= 0: 1e-10 */
-    int32_t max_iter;  /* <= 0: 10 */
+    double tol;            /* <= 0: 1e-10 */
+    int32_t max_iter;      /* <= 0: 10 */
+    const double *q_min;   /* both NULL: no limit checks (pf_newton only) */
+    const double *q_max;
+    double q_check_below;  /* <= 0: 1e-3 */
+    double q_switch_tol;   /* < 0: 1e-9; 0 compares exactly */
 } pf_newton_opts;
 
 typedef struct pf_newton_report {
@@ -388,6 +409,8 @@ typedef struct pf_newton_report {
     double t_eval_s;      /* device evaluation time (residual + Jacobian) */
     double t_solve_s;     /* host solve callback time */
     double t_total_s;
+    int32_t switched[65]; /* units that changed mode at x_k (limit checks) */
+    int32_t n_switches;   /* sum of switched[] */
 } pf_newton_report;
 
 int pf_newton(pf_plan *plan, double *x, const pf_newton_opts *opts,
@@ -416,8 +439,8 @@ int pf_newton(pf_plan *plan, double *x, const pf_newton_opts *opts,
  *   while held at q_min.  The new modes are applied as by pf_set_gen_modes;
  *   *n_switched (nullable) receives the number of changes.  Copies x to the
  *   host on the given stream (after the work queued there) and synchronises
- *   it.  A Newton solve with limits repeats solve -> check until nothing
- *   switches.
+ *   it.  A Newton solve with limits either repeats solve -> check until
+ *   nothing switches, or lets pf_newton check inside its iterations.
  */
 int pf_set_gen_modes(pf_plan *plan, const int32_t *mode, const double *q_target);
 int pf_get_gen_modes(const pf_plan *plan, int32_t *mode, double *q_target);

@@ -451,10 +451,15 @@ class Plan:
         self._load_info()
         return best.as_dict()
 
-    def newton(self, x, solve=None, tol=1e-10, max_iter=10):
+    def newton(self, x, solve=None, tol=1e-10, max_iter=10, q_min=None, q_max=None,
+               check_below=1e-3, switch_tol=1e-9):
         """Newton power flow with a host sparse solve (scipy SuperLU by default).
-        ``x`` (device) is updated in place.  Returns a dict report; raises
-        PFError on failure except non-convergence (report['converged'] False)."""
+        ``x`` (device) is updated in place.  With ``q_min``/``q_max`` (one
+        entry per PV unit) the reactive limits are checked inside the
+        iterations, at every iterate whose mismatch is below ``check_below``
+        (pf_newton's limit checks); the report then lists the units switched
+        at each iterate.  Returns a dict report; raises PFError on failure
+        except non-convergence (report['converged'] False)."""
         import scipy.sparse as sp
         import scipy.sparse.linalg as spla
 
@@ -487,6 +492,16 @@ class Plan:
                 return 2
 
         opts = capi.pf_newton_opts(tol=float(tol), max_iter=int(max_iter))
+        if (q_min is None) != (q_max is None):
+            raise ValueError("q_min and q_max go together")
+        if q_min is not None:
+            lo, hi = _f64(q_min), _f64(q_max)
+            if lo.shape != (self.info["n_pv"],) or hi.shape != lo.shape:
+                raise ValueError("q_min and q_max need one entry per PV unit")
+            opts.q_min = lo.ctypes.data_as(capi._pd)
+            opts.q_max = hi.ctypes.data_as(capi._pd)
+            opts.q_check_below = float(check_below)
+            opts.q_switch_tol = float(switch_tol)
         rep = capi.pf_newton_report()
         # pf_newton works on the null stream; whatever the caller's stream
         # still has to write into x must land first
@@ -499,6 +514,8 @@ class Plan:
         it = int(rep.iterations)
         return {"iterations": it, "converged": bool(rep.converged),
                 "norms": [float(v) for v in rep.norm[:min(it + 1, 65)]],
+                "switched": [int(v) for v in rep.switched[:min(it + 1, 65)]],
+                "n_switches": int(rep.n_switches),
                 "t_eval_s": rep.t_eval_s, "t_solve_s": rep.t_solve_s,
                 "t_total_s": rep.t_total_s, "solver_errors": errors}
 
@@ -537,17 +554,25 @@ class Plan:
         return int(ns.value)
 
     def newton_qlim(self, x, q_min, q_max, device=False, tol=1e-10, max_iter=10,
-                    max_outer=10, switch_tol=1e-9):
+                    max_outer=10, switch_tol=1e-9, inner=False, check_below=1e-3):
         """Newton power flow with reactive limits: solve, check the limits,
         and solve again from the last state until no unit switches.
         ``device``: False solves on the host; True runs every step on the
         device with this library's factorisation (the plan as one instance);
         "rocsolver" with rocSOLVER's re-factorisation.  After a switch a held
         row's nonzero moves from the V column to the Q_g column, so a device
-        path takes a fresh host LU (new pivots) for the next solve.  ``x`` is
-        updated in place."""
+        path takes a fresh host LU (new pivots) for the next solve.
+        ``inner``: one Newton run that checks the limits inside its
+        iterations instead (host solve only; ``max_iter`` bounds the whole
+        run).  ``x`` is updated in place."""
         if device not in (False, True, "rocsolver"):
             raise ValueError("device must be False, True or 'rocsolver'")
+        if inner:
+            if device:
+                raise ValueError("limits are checked inside the iterations with the host solve only")
+            rep = self.newton(x, tol=tol, max_iter=max_iter, q_min=q_min, q_max=q_max,
+                              check_below=check_below, switch_tol=switch_tol)
+            return {"converged": rep["converged"], "outer": 1, "rounds": [rep]}
         rounds = []
         lu = None
         for outer in range(1, max_outer + 1):

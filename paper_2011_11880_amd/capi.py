@@ -78,12 +78,14 @@ class pf_info_t(ctypes.Structure):
 
 
 class pf_newton_opts(ctypes.Structure):
-    _fields_ = [("tol", _d), ("max_iter", _i32)]
+    _fields_ = [("tol", _d), ("max_iter", _i32), ("q_min", _pd), ("q_max", _pd),
+                ("q_check_below", _d), ("q_switch_tol", _d)]
 
 
 class pf_newton_report(ctypes.Structure):
     _fields_ = [("iterations", _i32), ("converged", _i32), ("norm", _d * 65),
-                ("t_eval_s", _d), ("t_solve_s", _d), ("t_total_s", _d)]
+                ("t_eval_s", _d), ("t_solve_s", _d), ("t_total_s", _d),
+                ("switched", _i32 * 65), ("n_switches", _i32)]
 
 
 pf_linsolve_fn = ctypes.CFUNCTYPE(ctypes.c_int, _vp, _i64, _pi32, _pi32, _pd, _pd, _pd)

@@ -404,6 +404,11 @@ int pf_newton(pf_plan *plan, double *x, const pf_newton_opts *opts, pf_linsolve_
     if (rc) return rc;
     if (!x || !solve) return fail(PF_EINVAL, "x or solve is NULL");
     if (opts && opts->max_iter > 64) return fail(PF_EINVAL, "max_iter must be <= 64");
+    if (opts && (opts->q_min || opts->q_max)) {
+        rc = q_limits_valid(plan->host, opts->q_min, opts->q_max,
+                            opts->q_switch_tol >= 0 ? opts->q_switch_tol : 1e-9);
+        if (rc) return rc;
+    }
     return dev_newton(plan->host, plan->dev, x, opts, solve, user, report);
 }
 

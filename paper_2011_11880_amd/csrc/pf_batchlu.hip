@@ -755,6 +755,9 @@ int pf_newton_batch(pf_plan *plan, pf_batch_lu *b, double *X, const pf_newton_op
     if (!plan || !b || !X) return fail(PF_EINVAL, "NULL argument");
     if (b->plan != plan) return fail(PF_EINVAL, "the factorisation belongs to another plan");
     if (opts && opts->max_iter > 64) return fail(PF_EINVAL, "max_iter must be <= 64");
+    if (opts && (opts->q_min || opts->q_max))
+        return fail(PF_EINVAL, "reactive limits are checked inside the iterations by pf_newton only: "
+                    "a switch needs new pivots");
     HostPlan &hp = plan->host;
     BGuard g(b->device);
     if (!g.ok) return fail(PF_EDEVICE, "cannot select device %d", b->device);

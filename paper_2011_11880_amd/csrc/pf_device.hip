@@ -1657,28 +1657,27 @@ int dev_newton(HostPlan &hp, DevPlan *dp, double *x, const pf_newton_opts *opts,
     if (!g.ok) return fail(PF_EDEVICE, "cannot select device %d", dp->device);
     const double tol = (opts && opts->tol > 0) ? opts->tol : 1e-10;
     const int max_iter = (opts && opts->max_iter > 0) ? opts->max_iter : 10;
+    const bool limits = opts && (opts->q_min || opts->q_max);
+    const double check_below = (limits && opts->q_check_below > 0) ? opts->q_check_below : 1e-3;
+    const double switch_tol = (limits && opts->q_switch_tol >= 0) ? opts->q_switch_tol : 1e-9;
     const int64_t n = hp.n, nnz = hp.nnz;
     std::vector<double> Fh(static_cast<size_t>(n)), Jh(static_cast<size_t>(nnz)),
-        dxh(static_cast<size_t>(n));
+        dxh(static_cast<size_t>(n)), xh(limits ? static_cast<size_t>(n) : 0);
     pf_newton_report r{};
     hipEvent_t ev0, ev1;
     HIP_TRY(hipEventCreate(&ev0));
     HIP_TRY(hipEventCreate(&ev1));
-    auto t_start = std::chrono::steady_clock::now();
-    int rc = PF_ENOCONV;
-    for (int it = 0;; ++it) {
+    // F and J at x under the current modes; F to the host and its max norm
+    auto evaluate = [&](double &nf) -> int {
         HIP_TRY(hipEventRecord(ev0, nullptr));
-        int e = dev_eval_single(hp, dp, x, dp->nw_F, dp->nw_J, nullptr);
-        if (e) {
-            rc = e;
-            break;
-        }
+        const int e = dev_eval_single(hp, dp, x, dp->nw_F, dp->nw_J, nullptr);
+        if (e) return e;
         HIP_TRY(hipEventRecord(ev1, nullptr));
         HIP_TRY(hipMemcpy(Fh.data(), dp->nw_F, size_t(n) * sizeof(double), hipMemcpyDeviceToHost));
         float ms = 0.f;
         HIP_TRY(hipEventElapsedTime(&ms, ev0, ev1));
         r.t_eval_s += ms * 1e-3;
-        double nf = 0.0;
+        nf = 0.0;
         for (int64_t q = 0; q < n; ++q) {
             const double v = std::fabs(Fh[q]);
             if (v != v) {  // a NaN anywhere makes the norm NaN
@@ -1687,35 +1686,66 @@ int dev_newton(HostPlan &hp, DevPlan *dp, double *x, const pf_newton_opts *opts,
             }
             if (v > nf) nf = v;
         }
-        if (it < 65) r.norm[it] = nf;
-        if (nf < tol) {
-            r.converged = 1;
-            rc = PF_OK;
-            break;
+        return PF_OK;
+    };
+    auto t_start = std::chrono::steady_clock::now();
+    // the iterations; the events are released on every path below
+    auto iterate = [&]() -> int {
+        int rc = PF_ENOCONV;
+        for (int it = 0;; ++it) {
+            double nf = 0.0;
+            int e = evaluate(nf);
+            if (e) {
+                rc = e;
+                break;
+            }
+            int32_t ns = 0;
+            if (limits && nf < check_below) {
+                HIP_TRY(hipMemcpy(xh.data(), x, size_t(n) * sizeof(double),
+                                  hipMemcpyDeviceToHost));
+                e = q_switch(hp, dp, xh.data(), opts->q_min, opts->q_max, switch_tol, &ns);
+                if (!e && ns) e = evaluate(nf);
+                if (e) {
+                    rc = e;
+                    break;
+                }
+            }
+            if (it < 65) {
+                r.norm[it] = nf;
+                r.switched[it] = ns;
+            }
+            r.n_switches += ns;
+            if (nf < tol && ns == 0) {
+                r.converged = 1;
+                rc = PF_OK;
+                break;
+            }
+            if (it >= max_iter) {
+                rc = fail(PF_ENOCONV, "Newton did not converge in %d iterations (|F| = %g)",
+                          max_iter, nf);
+                break;
+            }
+            HIP_TRY(hipMemcpy(Jh.data(), dp->nw_J, size_t(nnz) * sizeof(double),
+                              hipMemcpyDeviceToHost));
+            auto ts = std::chrono::steady_clock::now();
+            const int sr = solve(user, n, hp.rowptr.data(), hp.colidx.data(), Jh.data(), Fh.data(),
+                                 dxh.data());
+            r.t_solve_s += std::chrono::duration<double>(std::chrono::steady_clock::now() - ts).count();
+            if (sr != 0) {
+                rc = fail(PF_ESOLVE, "linear solve callback returned %d at iteration %d", sr, it);
+                break;
+            }
+            HIP_TRY(hipMemcpy(dp->nw_dx, dxh.data(), size_t(n) * sizeof(double),
+                              hipMemcpyHostToDevice));
+            hipLaunchKernelGGL(k_newton_update, dim3(unsigned((n + 255) / 256)), dim3(256), 0, nullptr,
+                               n, x, dp->nw_dx);
+            HIP_TRY(hipGetLastError());
+            r.iterations = it + 1;
         }
-        if (it >= max_iter) {
-            rc = fail(PF_ENOCONV, "Newton did not converge in %d iterations (|F| = %g)",
-                      max_iter, nf);
-            break;
-        }
-        HIP_TRY(hipMemcpy(Jh.data(), dp->nw_J, size_t(nnz) * sizeof(double),
-                          hipMemcpyDeviceToHost));
-        auto ts = std::chrono::steady_clock::now();
-        const int sr = solve(user, n, hp.rowptr.data(), hp.colidx.data(), Jh.data(), Fh.data(),
-                             dxh.data());
-        r.t_solve_s += std::chrono::duration<double>(std::chrono::steady_clock::now() - ts).count();
-        if (sr != 0) {
-            rc = fail(PF_ESOLVE, "linear solve callback returned %d at iteration %d", sr, it);
-            break;
-        }
-        HIP_TRY(hipMemcpy(dp->nw_dx, dxh.data(), size_t(n) * sizeof(double),
-                          hipMemcpyHostToDevice));
-        hipLaunchKernelGGL(k_newton_update, dim3(unsigned((n + 255) / 256)), dim3(256), 0, nullptr,
-                           n, x, dp->nw_dx);
-        HIP_TRY(hipGetLastError());
-        r.iterations = it + 1;
-    }
-    HIP_TRY(hipDeviceSynchronize());
+        HIP_TRY(hipDeviceSynchronize());
+        return rc;
+    };
+    const int rc = iterate();
     r.t_total_s = std::chrono::duration<double>(std::chrono::steady_clock::now() - t_start).count();
     (void)hipEventDestroy(ev0);
     (void)hipEventDestroy(ev1);

@@ -163,6 +163,11 @@ int dev_vjp(HostPlan &hp, DevPlan *dp, const double *x, const double *W,
             int32_t k, double *gx, double *gp, void *stream);
 int dev_newton(HostPlan &hp, DevPlan *dp, double *x, const pf_newton_opts *opts,
                pf_linsolve_fn solve, void *user, pf_newton_report *rep);
+// Reactive limits (pf_qlim.hip): argument checks, and the switching rule
+// at a host copy of the state (uploads the generator table on a switch).
+int q_limits_valid(const HostPlan &hp, const double *q_min, const double *q_max, double tol);
+int q_switch(HostPlan &hp, DevPlan *dp, const double *xh, const double *q_min,
+             const double *q_max, double tol, int32_t *n_switched);
 int dev_autotune(HostPlan &hp, DevPlan *dp, const double *x, double *F,
                  double *J, int32_t reps, void *stream, const char *cache,
                  pf_schedule *best, int32_t *hit);

@@ -366,6 +366,9 @@ int pf_newton_device(pf_plan *plan, pf_refact *rf, double *x, const pf_newton_op
     if (rf->plan != plan) return fail(PF_EINVAL, "the refactorisation belongs to another plan");
     if (!x) return fail(PF_EINVAL, "x is NULL");
     if (opts && opts->max_iter > 64) return fail(PF_EINVAL, "max_iter must be <= 64");
+    if (opts && (opts->q_min || opts->q_max))
+        return fail(PF_EINVAL, "reactive limits are checked inside the iterations by pf_newton only: "
+                    "a switch needs new pivots");
     HostPlan &hp = plan->host;
     Guard g(rf->device);
     if (!g.ok) return fail(PF_EDEVICE, "cannot select device %d", rf->device);
@@ -969,6 +972,9 @@ int pf_fdlf_solve(pf_fdlf *fd, double *x, const pf_newton_opts *opts, pf_newton_
     clear_error();
     if (!fd || !x) return fail(PF_EINVAL, "NULL argument");
     if (opts && opts->max_iter > 64) return fail(PF_EINVAL, "max_iter must be <= 64");
+    if (opts && (opts->q_min || opts->q_max))
+        return fail(PF_EINVAL, "reactive limits are checked inside the iterations by pf_newton only: "
+                    "a switch needs new pivots");
     HostPlan &hp = fd->plan->host;
     for (int32_t k = 0; k < hp.NPVt; ++k)
         if (!hp.pv_mode.empty() && hp.pv_mode[size_t(k)])

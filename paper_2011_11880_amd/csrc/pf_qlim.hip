@@ -4,7 +4,8 @@
 // V - V_set to Q_g - Q_target.  Plans set up with q_limits carry both slots
 // in that row; the mode lives in the generator table the kernels already
 // read (see kGenHeld).  This file holds the host side: setting modes and
-// one check of the limits against a state.
+// the switching rule, used by one check against a state and by the Newton
+// loop that checks the limits inside its iterations.
 #include <cmath>
 #include <vector>
 
@@ -24,80 +25,41 @@ int need_slots(const pf_plan *plan) {
 }
 
 // Write the modes into the generator table (host) and upload it.
-int apply(pf_plan *plan) {
-    HostPlan &hp = plan->host;
+int apply(HostPlan &hp, DevPlan *dp) {
     for (int32_t k = 0; k < hp.NPVt; ++k) {
         const size_t g = size_t(hp.pv_gen[size_t(k)]);
         const bool held = hp.pv_mode[size_t(k)] != 0;
         hp.gen4[4 * g + 2] = held ? kGenHeld : kGenVoltageSlot;
         hp.gen2[2 * g] = held ? hp.pv_qt[size_t(k)] : hp.pv_vset[size_t(k)];
     }
-    if (hp.host_only || !plan->dev) return PF_OK;
-    return dev_upload_gens(hp, plan->dev);
+    if (hp.host_only || !dp) return PF_OK;
+    return dev_upload_gens(hp, dp);
 }
 
 }  // namespace
 
-extern "C" {
+namespace pf {
 
-int pf_set_gen_modes(pf_plan *plan, const int32_t *mode, const double *q_target) {
-    clear_error();
-    int rc = need_slots(plan);
-    if (rc) return rc;
-    HostPlan &hp = plan->host;
-    const size_t NPV = size_t(hp.NPVt);
-    if (NPV && !mode) return fail(PF_EINVAL, "mode is NULL");
-    for (size_t k = 0; k < NPV; ++k) {
-        if (mode[k] != 0 && mode[k] != 1) return fail(PF_EINVAL, "mode[%zu] must be 0 or 1", k);
-        if (mode[k] == 1) {
-            if (!q_target) return fail(PF_EINVAL, "q_target is NULL but mode[%zu] is 1", k);
-            if (!std::isfinite(q_target[k]))
-                return fail(PF_EINVAL, "q_target[%zu] is not finite", k);
-        }
-    }
-    for (size_t k = 0; k < NPV; ++k) {
-        hp.pv_mode[k] = mode[k];
-        hp.pv_qt[k] = mode[k] ? q_target[k] : 0.0;
-    }
-    return apply(plan);
-}
-
-int pf_get_gen_modes(const pf_plan *plan, int32_t *mode, double *q_target) {
-    clear_error();
-    if (!plan) return fail(PF_EINVAL, "plan is NULL");
-    const HostPlan &hp = plan->host;
-    for (size_t k = 0; k < size_t(hp.NPVt); ++k) {
-        if (mode) mode[k] = hp.pv_mode.empty() ? 0 : hp.pv_mode[k];
-        if (q_target) q_target[k] = hp.pv_qt.empty() ? 0.0 : hp.pv_qt[k];
-    }
+int q_limits_valid(const HostPlan &hp, const double *q_min, const double *q_max, double tol) {
+    if (!hp.q_slots)
+        return fail(PF_EINVAL, "the plan was set up without q_limits (no Q_g slot in PV rows)");
+    if (hp.kind == KIND_BATCH) return fail(PF_EINVAL, "reactive-limit checks need a non-batched plan");
+    if (hp.NPVt && (!q_min || !q_max)) return fail(PF_EINVAL, "q_min or q_max is NULL");
+    if (!(tol >= 0.0)) return fail(PF_EINVAL, "the switching tolerance must be >= 0");
+    for (size_t k = 0; k < size_t(hp.NPVt); ++k)
+        if (!(q_min[k] <= q_max[k])) return fail(PF_EINVAL, "q_min[%zu] > q_max[%zu]", k, k);
     return PF_OK;
 }
 
-int pf_q_limit_check(pf_plan *plan, const double *x, const double *q_min, const double *q_max,
-                     double tol, int32_t *n_switched, void *stream) {
-    clear_error();
-    int rc = need_slots(plan);
-    if (rc) return rc;
-    HostPlan &hp = plan->host;
-    if (hp.host_only || !plan->dev) return fail(PF_EINVAL, "plan is host-only");
-    if (hp.kind == KIND_BATCH) return fail(PF_EINVAL, "pf_q_limit_check needs a non-batched plan");
-    if (!x || (hp.NPVt && (!q_min || !q_max))) return fail(PF_EINVAL, "NULL argument");
-    if (!(tol >= 0.0)) return fail(PF_EINVAL, "tol must be >= 0");
-    const size_t NPV = size_t(hp.NPVt);
-    for (size_t k = 0; k < NPV; ++k)
-        if (!(q_min[k] <= q_max[k])) return fail(PF_EINVAL, "q_min[%zu] > q_max[%zu]", k, k);
-    std::vector<double> xh(size_t(hp.n));
-    int prev = -1;
-    if (hipGetDevice(&prev) != hipSuccess) return fail(PF_EDEVICE, "hipGetDevice failed");
-    if (prev != hp.device && hipSetDevice(hp.device) != hipSuccess)
-        return fail(PF_EDEVICE, "cannot select device %d", hp.device);
-    hipStream_t st = static_cast<hipStream_t>(stream);
-    hipError_t e = hipMemcpyAsync(xh.data(), x, xh.size() * sizeof(double), hipMemcpyDeviceToHost, st);
-    if (e == hipSuccess) e = hipStreamSynchronize(st);
-    if (prev != hp.device) (void)hipSetDevice(prev);
-    if (e != hipSuccess) return fail(PF_EDEVICE, "copy of x failed: %s", hipGetErrorString(e));
+// The switching rule at the state xh (host copy): a unit under voltage
+// control whose Q_g leaves [q_min - tol, q_max + tol] is held at the limit
+// it crossed; a held unit returns to voltage control when its bus voltage
+// has moved past V_set on the side that the limit no longer justifies
+// (above V_set while held at q_max, below it while held at q_min).
+int q_switch(HostPlan &hp, DevPlan *dp, const double *xh, const double *q_min,
+             const double *q_max, double tol, int32_t *n_switched) {
     int32_t switched = 0;
-    for (size_t k = 0; k < NPV; ++k) {
+    for (size_t k = 0; k < size_t(hp.NPVt); ++k) {
         const size_t g = size_t(hp.pv_gen[k]);
         const double qg = xh[size_t(hp.gen4[4 * g])];
         // the unit's bus: its V variable is the only V column of its row,
@@ -123,7 +85,68 @@ int pf_q_limit_check(pf_plan *plan, const double *x, const double *q_min, const 
         }
     }
     if (n_switched) *n_switched = switched;
-    return switched ? apply(plan) : PF_OK;
+    return switched ? apply(hp, dp) : PF_OK;
+}
+
+}  // namespace pf
+
+extern "C" {
+
+int pf_set_gen_modes(pf_plan *plan, const int32_t *mode, const double *q_target) {
+    clear_error();
+    int rc = need_slots(plan);
+    if (rc) return rc;
+    HostPlan &hp = plan->host;
+    const size_t NPV = size_t(hp.NPVt);
+    if (NPV && !mode) return fail(PF_EINVAL, "mode is NULL");
+    for (size_t k = 0; k < NPV; ++k) {
+        if (mode[k] != 0 && mode[k] != 1) return fail(PF_EINVAL, "mode[%zu] must be 0 or 1", k);
+        if (mode[k] == 1) {
+            if (!q_target) return fail(PF_EINVAL, "q_target is NULL but mode[%zu] is 1", k);
+            if (!std::isfinite(q_target[k]))
+                return fail(PF_EINVAL, "q_target[%zu] is not finite", k);
+        }
+    }
+    for (size_t k = 0; k < NPV; ++k) {
+        hp.pv_mode[k] = mode[k];
+        hp.pv_qt[k] = mode[k] ? q_target[k] : 0.0;
+    }
+    return apply(plan->host, plan->dev);
+}
+
+int pf_get_gen_modes(const pf_plan *plan, int32_t *mode, double *q_target) {
+    clear_error();
+    if (!plan) return fail(PF_EINVAL, "plan is NULL");
+    const HostPlan &hp = plan->host;
+    for (size_t k = 0; k < size_t(hp.NPVt); ++k) {
+        if (mode) mode[k] = hp.pv_mode.empty() ? 0 : hp.pv_mode[k];
+        if (q_target) q_target[k] = hp.pv_qt.empty() ? 0.0 : hp.pv_qt[k];
+    }
+    return PF_OK;
+}
+
+int pf_q_limit_check(pf_plan *plan, const double *x, const double *q_min, const double *q_max,
+                     double tol, int32_t *n_switched, void *stream) {
+    clear_error();
+    int rc = need_slots(plan);
+    if (rc) return rc;
+    HostPlan &hp = plan->host;
+    if (hp.host_only || !plan->dev) return fail(PF_EINVAL, "plan is host-only");
+    if (hp.kind == KIND_BATCH) return fail(PF_EINVAL, "pf_q_limit_check needs a non-batched plan");
+    if (!x) return fail(PF_EINVAL, "NULL argument");
+    rc = q_limits_valid(hp, q_min, q_max, tol);
+    if (rc) return rc;
+    std::vector<double> xh(size_t(hp.n));
+    int prev = -1;
+    if (hipGetDevice(&prev) != hipSuccess) return fail(PF_EDEVICE, "hipGetDevice failed");
+    if (prev != hp.device && hipSetDevice(hp.device) != hipSuccess)
+        return fail(PF_EDEVICE, "cannot select device %d", hp.device);
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    hipError_t e = hipMemcpyAsync(xh.data(), x, xh.size() * sizeof(double), hipMemcpyDeviceToHost, st);
+    if (e == hipSuccess) e = hipStreamSynchronize(st);
+    if (prev != hp.device) (void)hipSetDevice(prev);
+    if (e != hipSuccess) return fail(PF_EDEVICE, "copy of x failed: %s", hipGetErrorString(e));
+    return q_switch(hp, plan->dev, xh.data(), q_min, q_max, tol, n_switched);
 }
 
 }  // extern "C"

@@ -30,4 +30,5 @@ int dev_autotune(HostPlan &, DevPlan *, const double *, double *, double *, int3
     return PF_EDEVICE;
 }
 int dev_fetch_params(HostPlan &, DevPlan *) { return PF_EDEVICE; }
+int q_limits_valid(const HostPlan &, const double *, const double *, double) { return PF_EDEVICE; }
 }  // namespace pf

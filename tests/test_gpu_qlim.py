@@ -199,3 +199,90 @@ def test_newton_with_limits_10k_device(ora, cuda, device):
     m, qt = p.gen_modes()
     assert np.array_equal(m, m_o) and np.array_equal(qt, qt_o)
     np.testing.assert_allclose(x.cpu().numpy(), y_o, rtol=0, atol=1e-8)
+
+
+def _inner_case(which):
+    """(network, seed, angle scale, perturbation, units pushed above their
+    lower limit, units pushed below their upper limit, margin, state
+    tolerance); on the 10k grid ten upper limits only, as in the outer-loop
+    test above."""
+    if which == "tiny":
+        return synth.tiny_grid(11), 11, 0.3, (0.02, 0.05), [2, 30], [1, 4, 9, 20], 0.05, 1e-9
+    net0 = synth.grid_10k()
+    hi = np.random.default_rng(16).choice(net0.n_pv, 10, replace=False)
+    return net0, 3, 0.03, (1e-4, 2.5e-4), [], hi, 0.002, 1e-8
+
+
+@pytest.mark.parametrize("which", ["tiny", "10k"])
+def test_newton_with_limits_checked_in_the_iterations(ora, cuda, which):
+    """pf_newton with q_min/q_max: the limits are checked at every iterate
+    whose mismatch is below 1e-3, inside one Newton run.  The iterations at
+    which units switch, the final modes and targets, the iteration count and
+    the end state equal the oracle's in-iteration Newton; the norms agree
+    wherever they are above rounding."""
+    from paper_2011_11880_amd.api import Plan
+    net0, seed, ang, pert, lo, hi, margin, atol = _inner_case(which)
+    net, y0, qmin, qmax = _limits_case(ora, net0, seed, ang, pert, lo, hi, margin)
+    y_o, m_o, qt_o, norms_o, sw_o, ok_o = ora.newton_qlim_inner(net, y0, qmin, qmax)
+    assert ok_o and len(sw_o) >= 1
+    p = Plan(net, q_limits=True)
+    x = torch.from_numpy(y0).to(cuda)
+    rep = p.newton(x, q_min=qmin, q_max=qmax, max_iter=20)
+    assert rep["converged"]
+    assert [k for k, s in enumerate(rep["switched"]) if s] == sw_o
+    assert rep["n_switches"] == sum(rep["switched"]) == int(m_o.sum())
+    assert rep["iterations"] == len(norms_o) - 1
+    m, qt = p.gen_modes()
+    assert np.array_equal(m, m_o) and np.array_equal(qt, qt_o)
+    np.testing.assert_allclose(x.cpu().numpy(), y_o, rtol=0, atol=atol)
+    big = np.array(norms_o) > 1e-8
+    np.testing.assert_allclose(np.array(rep["norms"])[big], np.array(norms_o)[big], rtol=1e-6)
+    # the same run through newton_qlim(inner=True), from the same start
+    p.set_gen_modes(np.zeros(net.n_pv, np.int32))
+    x2 = torch.from_numpy(y0).to(cuda)
+    r2 = p.newton_qlim(x2, qmin, qmax, inner=True, max_iter=20)
+    assert r2["converged"] and r2["rounds"][0]["switched"] == rep["switched"]
+    assert torch.equal(x, x2)
+
+
+def test_limit_checks_rejected_where_pivots_are_fixed(cuda):
+    """Limit fields are refused by the solvers whose pivots are fixed
+    (device Newton, batched Newton, fast decoupled) and by pf_newton on a
+    plan without Q_g slots or with q_min > q_max."""
+    import ctypes
+    from paper_2011_11880_amd import capi
+    from paper_2011_11880_amd.api import Plan, BatchLU
+    from paper_2011_11880_amd.capi import PFError
+    net = synth.tiny_grid(11)
+    y = synth.random_states(net, seed=1)
+    y[:net.n_bus] *= 0.1
+    lo = np.full(net.n_pv, -1.0)
+    hi = np.full(net.n_pv, 1.0)
+    x = torch.from_numpy(y).to(cuda)
+    with pytest.raises(PFError, match="q_limits"):
+        Plan(net).newton(x.clone(), q_min=lo, q_max=hi)
+    p = Plan(net, q_limits=True)
+    with pytest.raises(PFError, match="q_min"):
+        p.newton(x.clone(), q_min=hi, q_max=lo)
+    with pytest.raises(ValueError):
+        p.newton(x.clone(), q_min=lo)
+    opts = capi.pf_newton_opts(tol=1e-10, max_iter=5)
+    opts.q_min = lo.ctypes.data_as(capi._pd)
+    opts.q_max = hi.ctypes.data_as(capi._pd)
+    rep = capi.pf_newton_report()
+    L = capi.lib()
+    xd = x.clone()
+    lu = BatchLU(p, xd)
+    rc = L.pf_newton_batch(p._h, lu._h, ctypes.c_void_p(xd.data_ptr()), ctypes.byref(opts),
+                           None, None, ctypes.byref(rep), None)
+    assert rc == capi.PF_EINVAL and b"pf_newton only" in L.pf_last_error()
+    lu.close()
+    dl = p.device_lu(xd)
+    rc = L.pf_newton_device(p._h, dl._h, ctypes.c_void_p(xd.data_ptr()), ctypes.byref(opts),
+                            ctypes.byref(rep), None)
+    assert rc == capi.PF_EINVAL and b"pf_newton only" in L.pf_last_error()
+    dl.close()
+    p.fdlf(xd, max_iter=1)   # creates the fast decoupled object
+    rc = L.pf_fdlf_solve(p._fd[0], ctypes.c_void_p(xd.data_ptr()), ctypes.byref(opts),
+                         ctypes.byref(rep), None)
+    assert rc == capi.PF_EINVAL and b"pf_newton only" in L.pf_last_error()

@@ -106,3 +106,15 @@ def test_row_order_follows_modes(ora):
     import scipy.sparse as sp
     Jp = sp.csr_matrix((v, ci, rp), shape=(p.n, p.n))
     assert np.all(Jp[R].diagonal() != 0)
+
+
+def test_newton_limit_arguments_checked_before_any_call():
+    net = synth.tiny_grid(4)
+    p = Plan(net, host_only=True, q_limits=True)
+    lo = np.full(net.n_pv, -1.0)
+    with pytest.raises(ValueError, match="together"):
+        p.newton(None, q_min=lo)
+    with pytest.raises(ValueError, match="one entry per PV unit"):
+        p.newton(None, q_min=lo[:-1], q_max=lo[:-1] + 2)
+    with pytest.raises(ValueError, match="host solve only"):
+        p.newton_qlim(None, lo, lo + 2, device=True, inner=True)
