@@ -66,14 +66,28 @@ def build(verbose: bool = False) -> str:
     return LIB
 
 
+# Where the kernel-relevant text of each hashed source ends: the host-side
+# drivers at the end of pf_device.hip, and the host plan and declarations of
+# pf_internal.hpp (the constants and the grid record before it are read by
+# the kernels).
+_HASH_CUTS = (("pf_device.hip", "// Host-side drivers:"),
+              ("pf_internal.hpp", "struct HostPlan {"))
+
+
 def kernel_source_hash() -> str:
-    """Short hash of the device sources (ties counter summaries to the
-    kernel they were taken on)."""
+    """Short hash of the evaluation and adjoint kernels' source and their
+    launch code (ties tune-cache entries and counter summaries to the kernel
+    they were taken on).  Host-only code below the cut lines is left out, so
+    changing it keeps cached schedules and summaries valid."""
     import hashlib
     h = hashlib.sha256()
-    for f in ("pf_device.hip", "pf_internal.hpp"):
+    for f, cut in _HASH_CUTS:
         with open(os.path.join(CSRC, f), "rb") as fh:
-            h.update(fh.read())
+            text = fh.read()
+        at = text.find(cut.encode())
+        if at < 0:
+            raise RuntimeError(f"{f}: cut line {cut!r} not found")
+        h.update(text[:at])
     return h.hexdigest()[:16]
 
 

@@ -1651,6 +1651,48 @@ int dev_eval_batch(HostPlan &hp, DevPlan *dp, const double *X, double *F, double
     return PF_OK;
 }
 
+int dev_vjp(HostPlan &hp, DevPlan *dp, const double *x, const double *W, int32_t K, double *gx,
+            double *gp, void *stream) {
+    DeviceGuard g(dp->device);
+    if (!g.ok) return fail(PF_EDEVICE, "cannot select device %d", dp->device);
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    const int n_kchunks = (K + 63) / 64;
+    if (hp.n_adj_tiles() > 0) {
+        const int64_t waves = int64_t(hp.n_adj_tiles()) * n_kchunks;
+#define LAUNCH(WGX, WGP)                                                                        \
+    hipLaunchKernelGGL((k_vjp<WGX, WGP>), dim3(unsigned((waves + 3) / 4)), dim3(256), 0, st,     \
+                       dp->adj_tiles, hp.n_adj_tiles(), n_kchunks, dp->order_bfs, dp->adj_src,   \
+                       dp->adj_own, dp->grids, dp->bus2, dp->ycol, dp->ytr, dp->yG, dp->yB,      \
+                       dp->gen4, dp->ldptr, dp->ldlist, dp->params, hp.Bt, hp.NLt, x, W, int(K), \
+                       gx, gp)
+        if (gx && gp)
+            LAUNCH(true, true);
+        else if (gx)
+            LAUNCH(true, false);
+        else
+            LAUNCH(false, true);
+#undef LAUNCH
+        HIP_TRY(hipGetLastError());
+    }
+    const int nleft = int(hp.adj_left.size());
+    if (gp && nleft > 0) {
+        const int nt = (nleft + kVjpTile - 1) / kVjpTile;
+        const int64_t waves = int64_t(nt) * n_kchunks;
+        hipLaunchKernelGGL(k_vjp_branches, dim3(unsigned((waves + 3) / 4)), dim3(256), 0, st,
+                           hp.Bt, nleft, nt, n_kchunks, dp->adj_left, dp->br_f, dp->br_t,
+                           dp->br_on, dp->busx, dp->params, x, W, int(K), gp);
+        HIP_TRY(hipGetLastError());
+    }
+    return PF_OK;
+}
+
+// ---------------------------------------------------------------------------
+// Host-side drivers: the Newton loop with a host solve, and the schedule
+// search with its cache.  They launch the kernels above and change none of
+// them; the kernel source identity carried in tune-cache keys and counter
+// summaries covers the code above this line only.
+// ---------------------------------------------------------------------------
+
 int dev_newton(HostPlan &hp, DevPlan *dp, double *x, const pf_newton_opts *opts,
                pf_linsolve_fn solve, void *user, pf_newton_report *rep) {
     DeviceGuard g(dp->device);
@@ -1784,41 +1826,6 @@ static int time_schedule(HostPlan &hp, DevPlan *dp, const double *x, double *F, 
     for (auto &e : ev)
         if (e) (void)hipEventDestroy(e);
     return rc;
-}
-
-int dev_vjp(HostPlan &hp, DevPlan *dp, const double *x, const double *W, int32_t K, double *gx,
-            double *gp, void *stream) {
-    DeviceGuard g(dp->device);
-    if (!g.ok) return fail(PF_EDEVICE, "cannot select device %d", dp->device);
-    hipStream_t st = static_cast<hipStream_t>(stream);
-    const int n_kchunks = (K + 63) / 64;
-    if (hp.n_adj_tiles() > 0) {
-        const int64_t waves = int64_t(hp.n_adj_tiles()) * n_kchunks;
-#define LAUNCH(WGX, WGP)                                                                        \
-    hipLaunchKernelGGL((k_vjp<WGX, WGP>), dim3(unsigned((waves + 3) / 4)), dim3(256), 0, st,     \
-                       dp->adj_tiles, hp.n_adj_tiles(), n_kchunks, dp->order_bfs, dp->adj_src,   \
-                       dp->adj_own, dp->grids, dp->bus2, dp->ycol, dp->ytr, dp->yG, dp->yB,      \
-                       dp->gen4, dp->ldptr, dp->ldlist, dp->params, hp.Bt, hp.NLt, x, W, int(K), \
-                       gx, gp)
-        if (gx && gp)
-            LAUNCH(true, true);
-        else if (gx)
-            LAUNCH(true, false);
-        else
-            LAUNCH(false, true);
-#undef LAUNCH
-        HIP_TRY(hipGetLastError());
-    }
-    const int nleft = int(hp.adj_left.size());
-    if (gp && nleft > 0) {
-        const int nt = (nleft + kVjpTile - 1) / kVjpTile;
-        const int64_t waves = int64_t(nt) * n_kchunks;
-        hipLaunchKernelGGL(k_vjp_branches, dim3(unsigned((waves + 3) / 4)), dim3(256), 0, st,
-                           hp.Bt, nleft, nt, n_kchunks, dp->adj_left, dp->br_f, dp->br_t,
-                           dp->br_on, dp->busx, dp->params, x, W, int(K), gp);
-        HIP_TRY(hipGetLastError());
-    }
-    return PF_OK;
 }
 
 // Coordinate descent over the schedule space: starting from the current
