@@ -163,7 +163,7 @@ def host_cpu():
     return {"usable_cores": len(os.sched_getaffinity(0)), "cpus": os.cpu_count(), "model": model}
 
 
-def cpu_baseline(net, states, seconds=12.0, max_states=200):
+def cpu_baseline(net, states, seconds=12.0, max_states=1000):
     """The CPU oracle (plain C + scipy triplet assembly) on a bounded sample."""
     from oracle import oracle as O
     O.build()
