@@ -663,9 +663,18 @@ def run_c4(args, torch, dev, net70k=None, plain_us=None, **kw):
     ms_f = plain_us * 1e-3
     nb = K * (8 * p.n * 2 + 8 * p.n_params) + 8 * p.n + statics_bytes(p.info) + \
         64 * net.n_branch
+    # the same adjoint with the buses numbered breadth-first at setup: state,
+    # cotangent and gradient rows of neighbouring buses then sit together
+    pl = Plan(net, device=0, bus_order="locality")
+    perm = torch.from_numpy(pl.state_perm().astype(np.int64)).to(dev)
+    xl = x[perm].contiguous()
+    ms_l = time_ms(torch, lambda: pl.vjp(xl, W, gx, gp))
+    pl.close()
     return {"cotangents": K, "vjp_ms": ms, "forward_us": plain_us,
             "vjp_over_forward": ms / ms_f, "vjp_per_cotangent_over_forward": ms / ms_f / K,
-            "gbs": nb / (ms * 1e-3) / 1e9, "hbm_frac": nb / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS}
+            "gbs": nb / (ms * 1e-3) / 1e9, "hbm_frac": nb / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS,
+            "locality_order": {"vjp_ms": ms_l, "gbs": nb / (ms_l * 1e-3) / 1e9,
+                               "hbm_frac": nb / (ms_l * 1e-3) / 1e9 / HBM_PEAK_GBS}}
 
 
 def manufactured_case(torch, dev, net, seed, ang=0.03, sigma=1e-4):

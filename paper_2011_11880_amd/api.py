@@ -366,20 +366,59 @@ class Plan:
 
     def eval_batch(self, X, F=None, J=None, want_F=True, want_J=True):
         """Batched evaluation in the plan's layout: X, F of batch_shape(n),
-        J of batch_shape(nnz), contiguous."""
+        J of batch_shape(nnz), contiguous.  In the row layout X may instead
+        be an instance view, (n_inst, n) with strides (1, ld) (see
+        ``instances``); F and J are then allocated and returned as instance
+        views too, and given ones must be views of the same kind."""
         import math
 
         import torch
         dev = self._dev(X)
+        views = self._is_instance_view(X, self.n)
         sx, sj = self.batch_shape(self.n), self.batch_shape(self.nnz)
         if want_F and F is None:
             F = torch.empty(sx, dtype=torch.float64, device=dev)
+            F = self.instances(F) if views else F
         if want_J and J is None:
             J = torch.empty(sj, dtype=torch.float64, device=dev)
-        check(capi.lib().pf_eval_batch(self._h, _ptr(X, math.prod(sx), "X"),
-                                       _ptr(F, math.prod(sx), "F"),
-                                       _ptr(J, math.prod(sj), "J"), _stream(dev)))
+            J = self.instances(J) if views else J
+        check(capi.lib().pf_eval_batch(self._h, self._batch_ptr(X, self.n, "X", views),
+                                       self._batch_ptr(F, self.n, "F", views),
+                                       self._batch_ptr(J, self.nnz, "J", views), _stream(dev)))
         return F, J
+
+    def instances(self, A):
+        """Zero-copy (n_inst, rows) view of a device array in the row layout
+        (rows, ld): row i is instance i, with stride ld between its entries."""
+        if self.panels:
+            raise ValueError("instance views need the row layout")
+        if tuple(A.shape) != (A.shape[0], self.ld) or not A.is_contiguous():
+            raise ValueError(f"expected a contiguous (rows, {self.ld}) array")
+        return A[:, :self.n_inst].T
+
+    def _is_instance_view(self, A, rows):
+        return (not self.panels and A is not None and A.dim() == 2 and
+                tuple(A.shape) == (self.n_inst, rows) and tuple(A.stride()) == (1, self.ld))
+
+    def _batch_ptr(self, A, rows, name, views):
+        """Device pointer of a batched array: the contiguous layout, or with
+        ``views`` an instance view over a (rows, ld) allocation."""
+        import math
+
+        import torch
+        if A is None:
+            return None
+        if not views:
+            return _ptr(A, math.prod(self.batch_shape(rows)), name)
+        if not self._is_instance_view(A, rows):
+            raise ValueError(f"{name} must be an instance view ({self.n_inst}, {rows}) with "
+                             f"strides (1, {self.ld})")
+        if A.dtype != torch.float64 or not A.is_cuda:
+            raise TypeError(f"{name} must be a float64 CUDA tensor")
+        base = A.untyped_storage()
+        if (A.storage_offset() + rows * self.ld) * 8 > base.nbytes():
+            raise ValueError(f"{name}: the view's storage is smaller than ({rows}, {self.ld})")
+        return ctypes.c_void_p(A.data_ptr())
 
     def to_batch(self, Y):
         """Host array (n_inst, n) of states -> numpy array in the plan's

@@ -289,6 +289,35 @@ def test_padded_instance_stride(cuda):
     assert np.all(F[:, I:] == 7.0) and np.all(J[:, I:] == 7.0)
 
 
+def test_instance_views_are_zero_copy(cuda):
+    """States written through an (n_inst, n) view with strides (1, ld) of a
+    padded (n, ld) allocation evaluate in place: the returned F and J are
+    views of the same kind, equal bit for bit to the contiguous layout's
+    columns, and share storage with the allocation they view."""
+    Plan = _Plan()
+    net = _net()
+    I, LD = 70, 80
+    Y = synth.random_states(net, I, seed=31)
+    pp = Plan(net, batch=dict(n_inst=I, inst_stride=LD))
+    buf = torch.zeros((pp.n, LD), dtype=torch.float64, device=cuda)
+    Xv = pp.instances(buf)
+    assert Xv.shape == (I, pp.n) and Xv.stride() == (1, LD) and Xv.data_ptr() == buf.data_ptr()
+    Xv.copy_(torch.from_numpy(Y).to(cuda))
+    Fv, Jv = pp.eval_batch(Xv)
+    assert Fv.shape == (I, pp.n) and Fv.stride() == (1, LD)
+    assert Jv.shape == (I, pp.nnz) and Jv.stride() == (1, LD)
+    F, J = pp.eval_batch(buf)
+    torch.cuda.synchronize()
+    assert torch.equal(Fv, F[:, :I].T) and torch.equal(Jv, J[:, :I].T)
+    sp = Plan(net)
+    Fs, Js = sp.eval(torch.from_numpy(Y[5]).to(cuda))
+    assert torch.equal(Fv[5], Fs) and torch.equal(Jv[5], Js)
+    with pytest.raises(ValueError):
+        pp.eval_batch(Xv, F=F)           # outputs must follow the input's form
+    with pytest.raises(ValueError):
+        pp.eval_batch(Xv[:, :-1])
+
+
 def test_panel_layout_matches_rows(cuda):
     """Panels of 64 instances hold exactly the values of the row layout;
     padding columns of the last panel stay untouched; every schedule agrees."""
