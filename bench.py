@@ -393,19 +393,20 @@ def run_c1(args, torch, dev):
         n_side = 4
         side = [torch.cuda.Stream() for _ in range(n_side)]
         gc = torch.cuda.CUDAGraph()
+        events = []   # the fork/join events live as long as the graph
         with torch.cuda.stream(st):
             with torch.cuda.graph(gc, stream=st):
-                fork = torch.cuda.Event()
-                fork.record(st)
+                events.append(torch.cuda.Event())
+                events[0].record(st)
                 for q in side:
-                    q.wait_event(fork)
+                    q.wait_event(events[0])
                 for s in range(S):
                     with torch.cuda.stream(side[s % n_side]):
                         pp.eval(Xs[s], Fs[s], Js[s])
                 for q in side:
-                    join = torch.cuda.Event()
-                    join.record(q)
-                    st.wait_event(join)
+                    events.append(torch.cuda.Event())
+                    events[-1].record(q)
+                    st.wait_event(events[-1])
         torch.cuda.synchronize()
         for _ in range(args.warmup):
             gc.replay()
@@ -419,6 +420,7 @@ def run_c1(args, torch, dev):
         res["plain_4_streams"]["hbm_frac"] = res["plain_4_streams"]["gbs"] / HBM_PEAK_GBS
         log("[bench] plain 4 streams", json.dumps(res["plain_4_streams"]))
         del gc
+        del events
         # per-launch floors for context, replayed the same way: an empty
         # launch (64 B fill) and a device copy moving the bytes of one
         # evaluation (half read, half written)
@@ -525,19 +527,20 @@ def time_plain_launches(torch, plan, Xs, Fs, Js, steps, warmup):
             for s in range(S):
                 plan.eval(Xs[s], Fs[s], Js[s])
     g4 = torch.cuda.CUDAGraph()
+    events = []   # the fork/join events live as long as the graph
     with torch.cuda.stream(st):
         with torch.cuda.graph(g4, stream=st):
-            fork = torch.cuda.Event()
-            fork.record(st)
+            events.append(torch.cuda.Event())
+            events[0].record(st)
             for q in side:
-                q.wait_event(fork)
+                q.wait_event(events[0])
             for s in range(S):
                 with torch.cuda.stream(side[s % 4]):
                     plan.eval(Xs[s], Fs[s], Js[s])
             for q in side:
-                join = torch.cuda.Event()
-                join.record(q)
-                st.wait_event(join)
+                events.append(torch.cuda.Event())
+                events[-1].record(q)
+                st.wait_event(events[-1])
     torch.cuda.synchronize()
     out = []
     for g in (g1, g4):
@@ -547,6 +550,9 @@ def time_plain_launches(torch, plan, Xs, Fs, Js, steps, warmup):
             for _ in range(steps):
                 g.replay()
         out.append(t.ms * 1e3 / (steps * S))
+    torch.cuda.synchronize()
+    del g, g1, g4
+    del events
     return out[0], out[1]
 
 
