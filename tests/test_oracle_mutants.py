@@ -3,13 +3,16 @@ pins in test_oracle_pins.py catch every one of them.
 
 Each mutant is a one-site textual change (a dropped term, a flipped sign, a
 wrong index or a transposed operand) to ``oracle/pf_oracle.c`` or
-``oracle/ora_core.inc``, compiled with gcc into a temporary directory.  The
-real oracle is restored after every mutant.  Runs on the CPU only.
+``oracle/ora_core.inc``, compiled with gcc into a temporary directory, or to
+the reactive-limit logic of ``oracle/oracle.py``, executed as a separate
+module.  The real oracle is restored after every mutant.  Runs on the CPU
+only.
 """
 
 import os
 import shutil
 import subprocess
+import types
 
 import pytest
 
@@ -122,4 +125,40 @@ def test_mutant_is_caught(ora, tmp_path, mid, fname, old, new):
     finally:
         ora.use_library(None)
         del prev
+    assert caught, "no pin caught mutant: " + mid
+
+
+# (id, original text, mutated text) in oracle/oracle.py: the switching rule
+# and the Newton loops with limits
+PY_MUTANTS = [
+    ("release at qmax on the wrong side", "(at_max and v > net.pv_v[k] + tol)",
+     "(at_max and v < net.pv_v[k] - tol)"),
+    ("held at the wrong limit", "mode[k], qt[k] = 1, qmax[k]", "mode[k], qt[k] = 1, qmin[k]"),
+    ("lower limit never checked", "elif q < qmin[k] - tol:", "elif q < qmin[k] - tol - 1e9:"),
+    ("in-iteration check never switches", "mode, qt, ns = q_limit_switch(net, y, mode, qt, qmin, qmax, switch_tol)",
+     "ns = 0"),
+]
+
+PY_PINS = [
+    Q.test_switching_rule_cases,
+    Q.test_newton_with_limits_ends_feasible,
+    Q.test_newton_with_limits_checked_in_the_iterations_ends_feasible,
+]
+
+
+@pytest.mark.parametrize("mid,old,new", PY_MUTANTS, ids=[m[0] for m in PY_MUTANTS])
+def test_python_mutant_is_caught(ora, mid, old, new):
+    path = os.path.join(ORA, "oracle.py")
+    with open(path) as fh:
+        src = fh.read()
+    assert src.count(old) == 1, "mutation site must be unique: " + mid
+    mod = types.ModuleType("oracle_mutant")
+    mod.__file__ = path
+    exec(compile(src.replace(old, new), path, "exec"), mod.__dict__)
+    caught = []
+    for pin in PY_PINS:
+        try:
+            pin(mod)
+        except AssertionError:
+            caught.append(pin.__name__)
     assert caught, "no pin caught mutant: " + mid
