@@ -436,7 +436,8 @@ int pf_newton(pf_plan *plan, double *x, const pf_newton_opts *opts,
  *   whose Q_g is outside [q_min - tol, q_max + tol] is held at the violated
  *   limit; a held unit returns to voltage control when its bus voltage
  *   exceeds V_set + tol while held at q_max, or falls below V_set - tol
- *   while held at q_min.  The new modes are applied as by pf_set_gen_modes;
+ *   while held at q_min (a unit held at any other target, set by
+ *   pf_set_gen_modes, counts as held at q_min).  The new modes are applied as by pf_set_gen_modes;
  *   *n_switched (nullable) receives the number of changes.  Copies x to the
  *   host on the given stream (after the work queued there) and synchronises
  *   it.  A Newton solve with limits either repeats solve -> check until
