@@ -372,9 +372,10 @@ int pf_autotune_cached(pf_plan *plan, const double *x, double *F, double *Jval,
  * must be complete before the call.  report (nullable) receives iteration counts, per-iteration
  * norms (up to 64) and times.  Returns PF_ENOCONV if max_iter is reached.
  *
- * Reactive limits inside the iterations (Section II-A: with the extended
- * formulation the same equations serve before and after a PV generator is
- * held, so the limits may be checked at any iterate): with q_min and q_max
+ * Reactive limits inside the iterations (Section II-A: the extended
+ * formulation keeps one set of equations whether a PV unit controls its
+ * voltage or is held at a reactive target, so the limits may be checked at
+ * any iterate): with q_min and q_max
  * set (host [n_pv], read during the call; plan set up with q_limits = 1,
  * not batched), at every iterate x_k whose ||F||_inf is below
  * q_check_below the switching rule of pf_q_limit_check (tolerance
@@ -417,9 +418,10 @@ int pf_newton(pf_plan *plan, double *x, const pf_newton_opts *opts,
               pf_linsolve_fn solve, void *user, pf_newton_report *report);
 
 /*
- * Reactive limits of PV generators (Section II-A: the extended formulation
- * lets the limits be checked during the iterations, and the same equations
- * serve before and after a PV generator becomes a PQ injection).  A held
+ * Reactive limits of PV generators (Section II-A: in the extended
+ * formulation one set of equations covers a PV unit under voltage control
+ * and held at a reactive target, so the limits can be checked during the
+ * iterations).  A held
  * generator keeps its Q_g variable; its control row becomes
  * Q_g - Q_target (slot values 0 at V, 1 at Q_g) instead of V - V_set (1 at
  * V, 0 at Q_g).  Needs a plan set up with q_limits = 1 (else PF_EINVAL).

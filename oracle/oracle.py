@@ -312,9 +312,9 @@ def q_limit_switch(net, y, mode, qt, qmin, qmax, tol=1e-9):
 def newton_qlim_inner(net, y0, qmin, qmax, tol=1e-10, max_iter=20, check_below=1e-3,
                       switch_tol=1e-9):
     """Newton power flow with the reactive limits checked during the
-    iterations (Section II-A: the extended formulation allows it, since the
-    same equations serve before and after a PV generator becomes a PQ
-    injection).  At every iterate whose mismatch is below ``check_below`` the
+    iterations (Section II-A: in the extended formulation one set of equations
+    covers a PV unit both under voltage control and held at a reactive
+    target, so the limits can be checked at any iterate).  At every iterate whose mismatch is below ``check_below`` the
     switching rule (q_limit_switch) is applied; after a switch the residual
     is taken again under the new modes before the step.  Converged when
     ||F||_inf < tol under modes that the check at that iterate left
@@ -344,9 +344,9 @@ def newton_qlim_inner(net, y0, qmin, qmax, tol=1e-10, max_iter=20, check_below=1
 
 
 def newton_qlim(net, y0, qmin, qmax, tol=1e-10, max_iter=10, max_outer=10):
-    """Newton power flow with reactive limits (Section II-A: the extended
-    formulation serves before and after a PV generator becomes a PQ
-    injection): solve, check the limits, switch, and solve again from the
+    """Newton power flow with reactive limits (Section II-A: one set of
+    equations covers a PV unit both under voltage control and held at a
+    reactive target): solve, check the limits, switch, and solve again from the
     last state until no generator switches.  Returns (y, mode, qt, outer
     rounds, converged)."""
     y = np.array(y0, dtype=np.float64)

@@ -1,8 +1,8 @@
 """Pins of the oracle's reactive-limit handling (CPU only).
 
-Section II-A: the extended formulation lets reactive limits be checked
-during the iterations, and the same equations serve before and after a PV
-generator becomes a PQ injection.  A held generator keeps its Q_g variable
+Section II-A: in the extended formulation one set of equations covers a PV
+unit under voltage control and held at a reactive target, so reactive limits
+can be checked during the iterations.  A held generator keeps its Q_g variable
 and its control row becomes Q_g - Q_target.  The pins tie that to the
 classical treatment (the generator replaced by a constant PQ injection), to
 complex-step derivatives, and to the switching rule's plain definition."""
