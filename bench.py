@@ -8,7 +8,8 @@ path); inputs are resident in HBM before timing starts.  Two ways to run a
 step are measured:
 
   batched  one launch over all 1000 states as instances
-           (pf_eval_batch, instance-fastest layout)          -> headline value
+           (pf_eval_batch, instance-fastest layout, buses numbered
+           breadth-first at setup; the input numbering beside it) -> headline value
   plain    1000 single-instance launches (pf_eval), each with its own
            state and output slot, replayed from a captured HIP graph
 
@@ -253,13 +254,17 @@ def run_c1(args, torch, dev):
     res = {}
 
     # ---- batched: all states as instances of one launch; instance rows
-    # padded to a multiple of 16 (128 B) so every 64-instance segment is aligned
+    # padded to a multiple of 16 (128 B) so every 64-instance segment is
+    # aligned.  The plan numbers the buses breadth-first at setup, so the
+    # state rows a work item gathers are neighbours in memory; the states
+    # are written in the plan's order before timing (the same launch on the
+    # input numbering is reported beside it)
     LD = -(-S // 16) * 16
-    bp = Plan(net, batch=dict(n_inst=S, inst_stride=LD), device=0)
+    bp = Plan(net, batch=dict(n_inst=S, inst_stride=LD), device=0, bus_order="locality")
     info = bp.info
     n, nnz = bp.n, bp.nnz
     Xh = np.zeros((n, LD))
-    Xh[:, :S] = Y.T
+    Xh[:, :S] = bp.to_plan(Y).T
     X = torch.from_numpy(Xh).to(dev)
     del Xh
     Fb = torch.empty((n, LD), dtype=torch.float64, device=dev)
@@ -306,6 +311,10 @@ def run_c1(args, torch, dev):
                       "launch": "HIP graph replay", "eager_ms_per_step": ms_e}
     res["batched"]["hbm_frac"] = res["batched"]["gbs"] / HBM_PEAK_GBS
     del gb
+    res["batched"]["bus_order"] = "breadth-first at setup (states and outputs in the plan's order)"
+    if args.headline_only:
+        del Fb, Jb, X
+        return _c1_out(args, torch, dev, net, Y, S, LD, n, nnz, res)
     # equation / Jacobian split of the same launch (Table III reports the two
     # separately): residual-only and Jacobian-only launches, each from its
     # own graph; algorithmic bytes read X once and write F or J
@@ -336,7 +345,26 @@ def run_c1(args, torch, dev):
     res["batched"]["outputs_fill_gbs"] = bytes_w / (ms_w * 1e-3) / 1e9
     res["batched"]["outputs_fill_over_fused"] = ms_w / ms_b
     log("[bench] batched", json.dumps(res["batched"]))
-    del Fb, Jb
+    del Fb, Jb, X
+    # the same batch on the input bus numbering
+    bl = Plan(net, batch=dict(n_inst=S, inst_stride=LD), device=0)
+    Xh = np.zeros((n, LD))
+    Xh[:, :S] = Y.T
+    Xl = torch.from_numpy(Xh).to(dev)
+    del Xh
+    Fl = torch.empty((n, LD), dtype=torch.float64, device=dev)
+    Jl = torch.empty((nnz, LD), dtype=torch.float64, device=dev)
+    best_l = bl.autotune(Xl, Fl, Jl, reps=10, cache=tune_cache(args))
+    gl = captured(lambda: bl.eval_batch(Xl, Fl, Jl))
+    ms_l = timed(gl)
+    del gl
+    res["batched_input_order"] = {
+        "ms_per_step": ms_l, "evals_per_s": S / (ms_l * 1e-3),
+        "gbs": bytes_b / (ms_l * 1e-3) / 1e9,
+        "hbm_frac": bytes_b / (ms_l * 1e-3) / 1e9 / HBM_PEAK_GBS,
+        "schedule": best_l, "schedule_from_tune_cache": bl.tune_hit}
+    log("[bench] batched, input order", json.dumps(res["batched_input_order"]))
+    del Xl, Fl, Jl, bl
 
     # ---- plain: one launch per state, distinct slots, captured graph
     if not args.no_plain:
@@ -465,6 +493,12 @@ def run_c1(args, torch, dev):
         log("[bench] plain, locality order", json.dumps(res["plain_locality_order"]))
         del Xl, Fl, Jl
 
+    return _c1_out(args, torch, dev, net, Y, S, LD, n, nnz, res)
+
+
+def _c1_out(args, torch, dev, net, Y, S, LD, n, nnz, res):
+    """The headline JSON object of the default workload (and the others'
+    summaries unless --no-others)."""
     head = res["batched"]
     # overlay-free batches with an even instance count and pitch run the
     # two-instances-per-lane kernel
@@ -478,6 +512,7 @@ def run_c1(args, torch, dev):
                                f"values at {S} random states per step",
                    "n_bus": net.n_bus, "n_branch": net.n_branch, "n": n, "nnz": nnz,
                    "states": S, "variant": "batched (states as instances of one launch)",
+                   "bus_order": "breadth-first at setup (PF_ORDER_LOCALITY)",
                    "instance_row_pitch": LD, "launch": "one HIP graph replay per step",
                    "schedule": head["schedule"],
                    "schedule_note": "one wavefront per work item (grid_blocks -1): the "
@@ -1071,6 +1106,9 @@ def main():
     ap.add_argument("--retune", action="store_true",
                     help="search every schedule again instead of reading the tune cache")
     ap.add_argument("--no-plain", action="store_true")
+    ap.add_argument("--headline-only", action="store_true",
+                    help="time the headline launch only (no splits, fill, input-order "
+                         "variant or plain launches; for counter runs)")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-others", action="store_true",
                     help="skip the scenario-batch, uneven-grid, adjoint and Newton summaries")

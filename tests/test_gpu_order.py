@@ -124,3 +124,55 @@ def test_adjoint_locality_order(ora, cuda):
             check_close(gp[q * B:(q + 1) * B, k], gpo[name], sc[name], f"{name}[{k}]")
         np.testing.assert_array_equal(gp[5 * B:5 * B + L, k], gpo["load_p"])
         np.testing.assert_array_equal(gp[5 * B + L:, k], gpo["load_q"])
+
+
+def test_70k_x1000_bench_configuration_locality_order(ora, cuda):
+    """The benchmark's headline launch as timed (70,000-bus grid numbered
+    breadth-first at setup, 1000 random states in rows padded to 1008, the
+    schedule from the tune cache): every instance bit-identical to the
+    single-instance kernel on the same plan order, every residual and every
+    eighth Jacobian (plus the chunk edges) against the oracle through the
+    plan's permutation."""
+    import os
+    from paper_2011_11880_amd.api import Plan
+    from parity import check_jacobian_triplets, pattern_keys, triplet_positions
+    net = synth.grid_70k()
+    S = 1000
+    Y = synth.random_states(net, S, seed=1001)
+    bp = Plan(net, batch=dict(n_inst=S, inst_stride=1008), bus_order="locality")
+    perm = bp.state_perm()
+    inv = np.empty_like(perm)
+    inv[perm] = np.arange(perm.size)
+    X = torch.from_numpy(bp.to_batch(bp.to_plan(Y))).to(cuda)
+    F = torch.empty((bp.n, 1008), dtype=torch.float64, device=cuda)
+    J = torch.empty((bp.nnz, 1008), dtype=torch.float64, device=cuda)
+    root = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+    bp.autotune(X, F, J, reps=3,
+                cache=os.path.join(root, "paper_2011_11880_amd", "tune_cache.txt"))
+    bp.eval_batch(X, F, J)
+    sp = Plan(net, bus_order="locality")
+    Xs = torch.from_numpy(bp.to_plan(Y)).to(cuda)
+    Fs = torch.empty(sp.n, dtype=torch.float64, device=cuda)
+    Js = torch.empty(sp.nnz, dtype=torch.float64, device=cuda)
+    for k in range(S):
+        sp.eval(Xs[k], Fs, Js)
+        assert torch.equal(Fs, F[:, k]) and torch.equal(Js, J[:, k]), k
+    Fh = np.ascontiguousarray(F[:, :S].cpu().numpy().T)
+    for k in range(S):
+        Fo, So = ora.residual(net, Y[k])
+        check_close(Fh[k], Fo[perm], So[perm], f"inst {k} F")
+    del Fh
+    rp, ci = bp.pattern()
+    keys = pattern_keys(rp, ci)
+    pos = None
+    ks = sorted(set(range(0, S, 8)) | {63, 64, 127, 128, 511, 959, 960, 999})
+    for g in range(0, len(ks), 64):
+        kk = ks[g:g + 64]
+        Jh = np.ascontiguousarray(J[:, kk].cpu().numpy().T)
+        for q, k in enumerate(kk):
+            r, c, v, m = ora.jacobian_coo(net, Y[k], scales=True)
+            if pos is None:
+                pos = triplet_positions(keys, bp.n, inv[r], inv[c])
+            check_jacobian_triplets(Jh[q], keys, pos, v, m, f"inst {k} J")
+    del F, J, X
+    torch.cuda.empty_cache()
