@@ -643,6 +643,20 @@ def run_c2(args, torch, dev, **kw):
            "plain_us_per_eval": ms_p * 1e3, "plain_evals_per_s": 1e3 / ms_p,
            "batched_over_plain": (I / ms) / (1.0 / ms_p), "schedule": bp.schedule,
            "schedule_from_tune_cache": hit}
+    del g, F, J, X
+    # the same batch with the buses numbered breadth-first at setup (the
+    # overlays address loads, PV units and branches, which keep their order)
+    bl = Plan(net, batch=dict(n_inst=I, load_scale=ls, pv_scale=ps, outage=out), device=0,
+              bus_order="locality")
+    Xl = torch.from_numpy(np.ascontiguousarray(bl.to_plan(Y).T)).to(dev)
+    Fl = torch.empty((bl.n, I), dtype=torch.float64, device=dev)
+    Jl = torch.empty((bl.nnz, I), dtype=torch.float64, device=dev)
+    bl.autotune(Xl, Fl, Jl, reps=10, cache=tune_cache(args))
+    ms_l = time_ms(torch, lambda: bl.eval_batch(Xl, Fl, Jl), reps=20)
+    res["locality_order"] = {"batched_ms": ms_l, "batched_evals_per_s": I / (ms_l * 1e-3),
+                             "batched_hbm_frac": nb / (ms_l * 1e-3) / 1e9 / HBM_PEAK_GBS,
+                             "schedule": bl.schedule, "schedule_from_tune_cache": bl.tune_hit}
+    del Xl, Fl, Jl, bl
     if not getattr(args, "no_cpu", False):
         log("[bench] c2 CPU oracle over instances")
         items = [(ls[k] if k < 512 else None, ps[k] if k < 512 else None, int(out[k]), Y[k])
