@@ -1830,7 +1830,8 @@ static int time_schedule(HostPlan &hp, DevPlan *dp, const double *x, double *F, 
 
 // Coordinate descent over the schedule space: starting from the current
 // schedule, each parameter in turn is set to the fastest of its candidate
-// values while the others stay fixed; two sweeps.  A candidate replaces the
+// values while the others stay fixed; two sweeps, then a joint pass over the
+// axes that interact most (below).  A candidate replaces the
 // best so far only when it is faster by more than kTuneMargin, so that
 // timing noise between near-equal schedules does not decide.  Every candidate gives
 // bit-identical results, so only time decides.
@@ -1869,20 +1870,51 @@ static int autotune_search(HostPlan &hp, DevPlan *dp, const double *x, double *F
     float best_ms = 0.f;
     int rc = apply(best);
     if (!rc) rc = time_schedule(hp, dp, x, F, J, reps, st, best_ms);
+    auto consider = [&](const pf_schedule &cand) -> int {
+        float ms = 0.f;
+        int r = apply(cand);
+        if (!r) r = time_schedule(hp, dp, x, F, J, reps, st, ms);
+        if (!r && ms < best_ms * (1.0f - kTuneMargin)) {
+            best_ms = ms;
+            best = cand;
+        }
+        return r;
+    };
     for (int sweep = 0; sweep < 2 && !rc; ++sweep) {
         for (const Axis &ax : axes) {
             for (int32_t v : ax.values) {
                 if (best.*(ax.field) == v) continue;
                 pf_schedule cand = best;
                 cand.*(ax.field) = v;
-                float ms = 0.f;
-                rc = apply(cand);
-                if (!rc) rc = time_schedule(hp, dp, x, F, J, reps, st, ms);
+                rc = consider(cand);
                 if (rc) break;
-                if (ms < best_ms * (1.0f - kTuneMargin)) {
-                    best_ms = ms;
-                    best = cand;
+            }
+            if (rc) break;
+        }
+    }
+    // Work-item size, waves per block and chunk grouping interact (tile
+    // size and waves per block for single-instance plans), so single-axis
+    // moves can stall short of a better corner: try every combination of
+    // them around the best of the other axes.
+    if (!rc) {
+        const size_t a0 = 0, a1 = batch ? 3 : 1, a2 = 2;
+        const std::vector<int32_t> v2s =
+            batch ? axes[a2].values : std::vector<int32_t>{best.*(axes[a2].field)};
+        for (int32_t v0 : axes[a0].values) {
+            for (int32_t v1 : axes[a1].values) {
+                for (int32_t v2 : v2s) {
+                    pf_schedule cand = best;
+                    cand.*(axes[a0].field) = v0;
+                    cand.*(axes[a1].field) = v1;
+                    cand.*(axes[a2].field) = v2;
+                    if (cand.*(axes[a0].field) == best.*(axes[a0].field) &&
+                        cand.*(axes[a1].field) == best.*(axes[a1].field) &&
+                        cand.*(axes[a2].field) == best.*(axes[a2].field))
+                        continue;
+                    rc = consider(cand);
+                    if (rc) break;
                 }
+                if (rc) break;
             }
             if (rc) break;
         }
