@@ -126,7 +126,7 @@ def test_adjoint_locality_order(ora, cuda):
         np.testing.assert_array_equal(gp[5 * B + L:, k], gpo["load_q"])
 
 
-def test_70k_x1000_bench_configuration_locality_order(ora, cuda):
+def test_70k_x1000_bench_configuration_locality_order(ora, cuda, tmp_path):
     """The benchmark's headline launch as timed (70,000-bus grid numbered
     breadth-first at setup, 1000 random states in rows padded to 1008, the
     schedule from the tune cache): every instance bit-identical to the
@@ -146,9 +146,12 @@ def test_70k_x1000_bench_configuration_locality_order(ora, cuda):
     X = torch.from_numpy(bp.to_batch(bp.to_plan(Y))).to(cuda)
     F = torch.empty((bp.n, 1008), dtype=torch.float64, device=cuda)
     J = torch.empty((bp.nnz, 1008), dtype=torch.float64, device=cuda)
+    # the committed tune cache's schedule (a copy: a miss appends to the file)
+    import shutil
     root = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
-    bp.autotune(X, F, J, reps=3,
-                cache=os.path.join(root, "paper_2011_11880_amd", "tune_cache.txt"))
+    cache = tmp_path / "tune_cache.txt"
+    shutil.copy(os.path.join(root, "paper_2011_11880_amd", "tune_cache.txt"), cache)
+    bp.autotune(X, F, J, reps=3, cache=str(cache))
     bp.eval_batch(X, F, J)
     sp = Plan(net, bus_order="locality")
     Xs = torch.from_numpy(bp.to_plan(Y)).to(cuda)
