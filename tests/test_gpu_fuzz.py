@@ -3,8 +3,10 @@ size from 2 buses up, transformers with taps and shifts, parallel and
 out-of-service branches, shunts, several loads per bus): for each network
 the single-instance kernel against the oracle, a batch of random states
 bit-identical to single evaluations, held PV units against the oracle with
-the same modes, and the adjoint against the oracle; and the networks
-together as one multi-grid launch, bit-identical to their own plans."""
+the same modes, the adjoint against the oracle, and the breadth-first bus
+numbering (single against the oracle, batch bit-identical to single); and
+the networks together as one multi-grid launch, bit-identical to their own
+plans."""
 
 import numpy as np
 import pytest
@@ -74,6 +76,29 @@ def test_random_network(ora, cuda, seed):
     K = int(rng.integers(1, 6))
     Wn = rng.standard_normal((net.n_var, K))
     _check_vjp(ora, p, net, y, Wn, cuda, f"seed {seed} vjp")
+    # buses numbered breadth-first at setup: the single kernel against the
+    # oracle through the plan's permutation, a batch bit-identical to it
+    pl = Plan(net, bus_order="locality")
+    perm = pl.state_perm()
+    Fl, Jl = pl.eval(torch.from_numpy(pl.to_plan(y)).to(cuda))
+    torch.cuda.synchronize()
+    Fo, So = ora.residual(net, y)
+    Jo, Ao = ora.jacobian(net, y)
+    Jp, Ap = Jo[perm][:, perm].tocsr(), Ao[perm][:, perm].tocsr()
+    Jp.sort_indices()
+    Ap.sort_indices()
+    rl, cl = pl.pattern()
+    check_close(Fl.cpu().numpy(), Fo[perm], So[perm], f"seed {seed} locality F")
+    check_jacobian(rl, cl, Jl.cpu().numpy(), Jp, Ap, f"seed {seed} locality J")
+    bl = Plan(net, batch=dict(n_inst=I), bus_order="locality")
+    Fb, Jb = bl.eval_batch(torch.from_numpy(np.ascontiguousarray(bl.to_plan(Y).T)).to(cuda))
+    torch.cuda.synchronize()
+    Fb, Jb = Fb.cpu().numpy(), Jb.cpu().numpy()
+    for k in range(I):
+        Fs, Js = pl.eval(torch.from_numpy(pl.to_plan(Y[k])).to(cuda))
+        torch.cuda.synchronize()
+        assert np.array_equal(Fs.cpu().numpy(), Fb[:, k]), (seed, k)
+        assert np.array_equal(Js.cpu().numpy(), Jb[:, k]), (seed, k)
 
 
 def test_random_networks_as_one_multi_grid_launch(ora, cuda):
