@@ -286,3 +286,44 @@ def test_limit_checks_rejected_where_pivots_are_fixed(cuda):
     rc = L.pf_fdlf_solve(p._fd[0], ctypes.c_void_p(xd.data_ptr()), ctypes.byref(opts),
                          ctypes.byref(rep), None)
     assert rc == capi.PF_EINVAL and b"pf_newton only" in L.pf_last_error()
+
+
+def test_newton_with_limits_in_the_iterations_multi_grid(ora, cuda):
+    """pf_newton with limits checked inside the iterations on a multi-grid
+    plan (two manufactured 200-bus cases, limits binding on both): the run
+    converges, and each grid ends feasible under its own modes -- F = 0 per
+    the oracle, free units inside their limits, held ones at a limit with
+    the voltage on the justifying side -- in the modes the oracle's
+    in-iteration Newton reaches on that grid alone."""
+    from paper_2011_11880_amd.api import Plan
+    cases = [_limits_case(ora, synth.tiny_grid(11), 11, 0.3, (0.02, 0.05), [2, 30],
+                          [1, 4, 9, 20], 0.05),
+             _limits_case(ora, synth.tiny_grid(12), 12, 0.3, (0.02, 0.05), [], [3, 7], 0.05)]
+    nets = [c[0] for c in cases]
+    mp = Plan.multi(nets, q_limits=True)
+    x = torch.from_numpy(np.concatenate([c[1] for c in cases])).to(cuda)
+    qmin = np.concatenate([c[2] for c in cases])
+    qmax = np.concatenate([c[3] for c in cases])
+    rep = mp.newton(x, q_min=qmin, q_max=qmax, max_iter=30)
+    assert rep["converged"] and rep["n_switches"] >= 1
+    m, qt = mp.gen_modes()
+    xh = x.cpu().numpy()
+    k0 = 0
+    for g, (net, y0, lo, hi) in enumerate(cases):
+        NPV, N = net.n_pv, net.n_bus
+        mg, qg_t = m[k0:k0 + NPV], qt[k0:k0 + NPV]
+        y = xh[mp.x_off[g]:mp.x_off[g + 1]]
+        F, _ = ora.residual(net, y, modes=(mg, qg_t))
+        assert np.max(np.abs(F)) < 1e-9, g
+        Qg = y[2 * N:2 * N + NPV]
+        V = y[N + net.pv_bus]
+        free = mg == 0
+        assert np.all(Qg[free] <= hi[free] + 1e-9) and np.all(Qg[free] >= lo[free] - 1e-9)
+        held = ~free
+        assert np.all((qg_t[held] == hi[held]) | (qg_t[held] == lo[held]))
+        up = held & (qg_t == hi)
+        dn = held & (qg_t == lo)
+        assert np.all(V[up] <= net.pv_v[up] + 1e-9) and np.all(V[dn] >= net.pv_v[dn] - 1e-9)
+        _, m_o, qt_o, _, _, ok_o = ora.newton_qlim_inner(net, y0, lo, hi)
+        assert ok_o and np.array_equal(mg, m_o) and np.array_equal(qg_t, qt_o), g
+        k0 += NPV
