@@ -81,20 +81,25 @@ class Timer:
         self.ms = self.a.elapsed_time(self.b)
 
 
-def time_ms(torch, fn, reps=10, warmup=2):
-    """Median time of fn() over reps runs, each bracketed by events on the
-    current stream (libpf launches on torch's current stream)."""
+def time_ms(torch, fn, reps=10, warmup=2, batches=5):
+    """Time of one fn(): the median over ``batches`` batches of the mean of
+    ``reps`` back-to-back runs, each batch bracketed by events on the
+    current stream (libpf launches on torch's current stream).  Running the
+    launches back to back keeps the host's launch latency out of the
+    figure, as a stream of evaluations would."""
     for _ in range(warmup):
         fn()
+    torch.cuda.synchronize()
     ts = []
-    for _ in range(reps):
+    for _ in range(batches):
         a = torch.cuda.Event(enable_timing=True)
         b = torch.cuda.Event(enable_timing=True)
         a.record()
-        fn()
+        for _ in range(reps):
+            fn()
         b.record()
         torch.cuda.synchronize()
-        ts.append(a.elapsed_time(b))
+        ts.append(a.elapsed_time(b) / reps)
     ts.sort()
     return ts[len(ts) // 2]
 
