@@ -881,7 +881,9 @@ def run_newton(args, torch, dev, **kw):
     it, ith = rep["iterations"], reph["iterations"]
     # reactive limits: 20 PV units capped 0.002 below their output at y*,
     # solved with the outer switching loop (a fresh host LU after each switch
-    # on the device path)
+    # on the device paths) and with the limits checked inside the iterations
+    # (host solve; this library's factorisation along pivots that survive a
+    # switch, one host LU for the run)
     q = ystar[2 * N:2 * N + NPV]
     pick = np.random.default_rng(4103).choice(NPV, 20, replace=False)
     qmin, qmax = q - 10.0, q + 10.0
@@ -889,18 +891,22 @@ def run_newton(args, torch, dev, **kw):
     log("[bench] newton: with reactive limits")
     pq = Plan(net, device=0, q_limits=True)
     lim = {}
-    for name, on_dev in (("device", True), ("device_rocsolver", "rocsolver"),
-                         ("host_solve", False)):
+    for name, on_dev, inner in (("device", True, False), ("device_rocsolver", "rocsolver", False),
+                                ("host_solve", False, False), ("device_inner", True, True),
+                                ("host_solve_inner", False, True)):
         pq.set_gen_modes(np.zeros(NPV, np.int32))
         x = torch.from_numpy(y0).to(dev)
         torch.cuda.synchronize()
         t0 = time.perf_counter()
-        r = pq.newton_qlim(x, qmin, qmax, device=on_dev)
+        r = pq.newton_qlim(x, qmin, qmax, device=on_dev, inner=inner,
+                           max_iter=30 if inner else 10)
         t1 = time.perf_counter()
         lim[name] = {"converged": r["converged"], "outer_rounds": r["outer"],
                      "held_units": int(pq.gen_modes()[0].sum()),
                      "iterations": [rr["iterations"] for rr in r["rounds"]],
                      "total_ms": (t1 - t0) * 1e3}
+        if inner:
+            lim[name]["switched_at"] = [k for k, v in enumerate(r["rounds"][0]["switched"]) if v]
     pq.close()
     cpu = None
     if not getattr(args, "no_cpu", False):

@@ -290,6 +290,29 @@ int pf_pattern(const pf_plan *plan, int32_t *rowptr, int32_t *colidx);
 int pf_jacobian_row_order(const pf_plan *plan, int32_t *order);
 
 /*
+ * Row order and pivot pairs for an LU whose pivots stay usable when PV units
+ * switch between voltage control and a held reactive output inside the
+ * Newton iterations (Section II-A: the extended formulation keeps Q_g as a
+ * variable in both modes, so a switch only moves the control row's +1 from
+ * the bus voltage column to the Q_g column; a plan set up with q_limits
+ * carries both slots).  order [n] (host output): as pf_jacobian_row_order
+ * with every PV unit taken under voltage control, whatever its current mode:
+ * the bus's Q row sits on the unit's Q_g column (its -1 there in both modes)
+ * and the unit's control row on the bus voltage column.  qv [2 * n_pv] (host
+ * output, may be NULL): qv[2k] = the Q_g column of PV unit k (also the index
+ * of its control row), qv[2k + 1] = its bus voltage column (also the index
+ * of the bus's Q row).  Under this pairing a held unit's control row takes
+ * its voltage pivot from the bus's Q row, which elimination adds to it once
+ * the Q_g column is gone: an LU that eliminates column qv[2k] before column
+ * qv[2k + 1] has the pivots of a bus without a generator there when the unit
+ * is held and a unit pivot when it is not.  pf_batch_lu_create checks this
+ * for every PV unit, and pf_newton_batch then accepts reactive limits.
+ * Errors: PF_EINVAL (NULL order or plan, plan set up without q_limits).
+ * Works on host-only plans.
+ */
+int pf_jacobian_switch_order(const pf_plan *plan, int32_t *order, int32_t *qv);
+
+/*
  * Residual F(x) (task 1 of the Newton loop, Section I).  x, F: device [n].
  * Errors: PF_EINVAL (NULL buffer, batched plan, host-only plan), PF_EDEVICE.
  */
@@ -384,11 +407,14 @@ int pf_autotune_cached(pf_plan *plan, const double *x, double *F, double *Jval,
  * norm under the modes in force after the check, switched[k] the number of
  * units that changed mode at x_k, and convergence needs ||F||_inf < tol
  * under modes that the check at that iterate left unchanged.  The modes
- * stay on the plan (pf_get_gen_modes).  Only pf_newton checks limits
- * inside its iterations: a switch moves the held row's nonzero from the V
- * column to the Q_g column, which the fixed pivots of pf_newton_device,
- * pf_newton_batch and pf_fdlf_solve cannot follow; they return PF_EINVAL
- * when q_min or q_max is set.
+ * stay on the plan (pf_get_gen_modes).  A switch moves the held row's
+ * nonzero from the V column to the Q_g column.  pf_newton refactorises on
+ * the host each step and follows it; pf_newton_batch follows it on a plan
+ * of one instance when its factorisation was made along
+ * pf_jacobian_switch_order's pivots (limits are per plan, not per
+ * instance).  The fixed pivots of pf_newton_device and of any other
+ * pf_newton_batch factorisation, and the constant B' / B'' of pf_fdlf_solve,
+ * cannot follow it: those return PF_EINVAL when q_min or q_max is set.
  */
 typedef int (*pf_linsolve_fn)(void *user, int64_t n, const int32_t *rowptr,
                               const int32_t *colidx, const double *Jval_host,
@@ -397,7 +423,7 @@ typedef int (*pf_linsolve_fn)(void *user, int64_t n, const int32_t *rowptr,
 typedef struct pf_newton_opts {
     double tol;            /* <= 0: 1e-10 */
     int32_t max_iter;      /* <= 0: 10 */
-    const double *q_min;   /* both NULL: no limit checks (pf_newton only) */
+    const double *q_min;   /* both NULL: no limit checks (pf_newton, pf_newton_batch) */
     const double *q_max;
     double q_check_below;  /* <= 0: 1e-3 */
     double q_switch_tol;   /* < 0: 1e-9; 0 compares exactly */
@@ -628,6 +654,13 @@ void pf_fdlf_destroy(pf_fdlf *fd);
  *   t_eval_s = evaluations, t_solve_s = factorisations + solves + updates
  *   (device time).  PF_ENOCONV if some instance has not converged after
  *   max_iter (<= 64) steps.  Calls on one object must not overlap.
+ *   With q_min / q_max set (plan of one instance set up with q_limits,
+ *   factorisation whose pivots pair and order every PV unit's Q row and
+ *   control row as pf_jacobian_switch_order describes, else PF_EINVAL) the
+ *   limits are checked inside the iterations exactly as pf_newton does
+ *   (same options, same report fields switched / n_switches; the state is
+ *   copied to the host for each check); the factorisation of each step
+ *   then follows the modes in force.
  */
 typedef struct pf_batch_lu pf_batch_lu;
 

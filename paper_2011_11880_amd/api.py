@@ -95,6 +95,24 @@ def host_lu(rowptr, colidx, values, n, permc_spec=None, row_order=None):
     T.sort_indices()
     # the full symbolic pattern of the factors (SuperLU's factors leave out
     # entries whose values vanish for this matrix), SuperLU's values in it
+    trp, tci = lu_pattern(rowptr, colidx, n, pivP, pivQ)
+    rows = np.repeat(np.arange(n, dtype=np.int64), np.diff(trp))
+    keys = rows * n + tci
+    trow = np.repeat(np.arange(n, dtype=np.int64), np.diff(T.indptr))
+    tkeys = trow * n + T.indices
+    pos = np.searchsorted(keys, tkeys)
+    if np.any(pos >= keys.size) or np.any(keys[np.minimum(pos, keys.size - 1)] != tkeys):
+        raise RuntimeError("the numeric LU has entries outside the symbolic pattern")
+    tv = np.zeros(tci.size)
+    tv[pos] = T.data
+    return trp, tci, tv, pivP, pivQ
+
+
+def lu_pattern(rowptr, colidx, n, pivP, pivQ):
+    """(T_rowptr, T_colidx): the filled pattern of the LU of M[pivP][:, pivQ]
+    without pivoting (pf_lu_symbolic), M's pattern being (rowptr, colidx)."""
+    rowptr, colidx = _i32(rowptr), _i32(colidx)
+    pivP, pivQ = _i32(pivP), _i32(pivQ)
     nz = ctypes.c_int64(0)
     L = capi.lib()
     args = (n, rowptr.ctypes.data_as(capi._pi32), colidx.ctypes.data_as(capi._pi32),
@@ -104,16 +122,27 @@ def host_lu(rowptr, colidx, values, n, permc_spec=None, row_order=None):
     tci = np.empty(nz.value, np.int32)
     check(L.pf_lu_symbolic(*args, ctypes.byref(nz), trp.ctypes.data_as(capi._pi32),
                            tci.ctypes.data_as(capi._pi32)))
-    rows = np.repeat(np.arange(n, dtype=np.int64), np.diff(trp))
-    keys = rows * n + tci
-    trow = np.repeat(np.arange(n, dtype=np.int64), np.diff(T.indptr))
-    tkeys = trow * n + T.indices
-    pos = np.searchsorted(keys, tkeys)
-    if np.any(pos >= keys.size) or np.any(keys[np.minimum(pos, keys.size - 1)] != tkeys):
-        raise RuntimeError("the numeric LU has entries outside the symbolic pattern")
-    tv = np.zeros(nz.value)
-    tv[pos] = T.data
-    return trp, tci, tv, pivP, pivQ
+    return trp, tci
+
+
+def switch_safe_pivots(pivQ, order, qv):
+    """Pivots that survive reactive-limit switches, from a column order
+    ``pivQ`` taken with diagonal pivots under the row order ``order`` of
+    pf_jacobian_switch_order (row order[c] pivots on column c): every PV
+    unit's Q_g column qv[2k] is moved to just before its bus voltage column
+    qv[2k + 1] where the order had it later, so that elimination has added
+    the bus's Q row to a held unit's control row before its voltage pivot.
+    Returns (pivP, pivQ)."""
+    pivQ = np.asarray(pivQ, dtype=np.int64)
+    order = np.asarray(order, dtype=np.int64)
+    qv = np.asarray(qv, dtype=np.int64).reshape(-1, 2)
+    at = np.empty(pivQ.size, np.int64)
+    at[pivQ] = np.arange(pivQ.size)
+    key = at.astype(np.float64)
+    late = at[qv[:, 0]] > at[qv[:, 1]]
+    key[qv[late, 0]] = at[qv[late, 1]] - 0.5
+    q = np.argsort(key, kind="stable")
+    return order[q].astype(np.int32), q.astype(np.int32)
 
 
 _ORDERS = {"input": capi.PF_ORDER_INPUT, "locality": capi.PF_ORDER_LOCALITY}
@@ -602,15 +631,27 @@ class Plan:
         row's nonzero moves from the V column to the Q_g column, so a device
         path takes a fresh host LU (new pivots) for the next solve.
         ``inner``: one Newton run that checks the limits inside its
-        iterations instead (host solve only; ``max_iter`` bounds the whole
-        run).  ``x`` is updated in place."""
+        iterations instead (``max_iter`` bounds the whole run): on the host
+        solve, or (device True) on this library's factorisation with pivots
+        that survive a switch, so one host LU serves the whole run.  ``x`` is
+        updated in place."""
         if device not in (False, True, "rocsolver"):
             raise ValueError("device must be False, True or 'rocsolver'")
         if inner:
+            if device == "rocsolver":
+                raise ValueError("rocSOLVER's re-factorisation keeps pivots that a switch breaks")
             if device:
-                raise ValueError("limits are checked inside the iterations with the host solve only")
-            rep = self.newton(x, tol=tol, max_iter=max_iter, q_min=q_min, q_max=q_max,
-                              check_below=check_below, switch_tol=switch_tol)
+                lu = BatchLU(self, x, switchable=True)
+                try:
+                    rep = self.newton_batch(x, lu, tol=tol, max_iter=max_iter, q_min=q_min,
+                                            q_max=q_max, check_below=check_below,
+                                            switch_tol=switch_tol)
+                finally:
+                    lu.close()
+                rep["converged"] = rep["n_converged"] == 1
+            else:
+                rep = self.newton(x, tol=tol, max_iter=max_iter, q_min=q_min, q_max=q_max,
+                                  check_below=check_below, switch_tol=switch_tol)
             return {"converged": rep["converged"], "outer": 1, "rounds": [rep]}
         rounds = []
         lu = None
@@ -699,17 +740,31 @@ class Plan:
     def _lu_shape(self, rows):
         return self.batch_shape(rows) if self.info["kind"] == "batch" else (rows,)
 
-    def newton_batch(self, X, lu=None, tol=1e-10, max_iter=10):
+    def newton_batch(self, X, lu=None, tol=1e-10, max_iter=10, q_min=None, q_max=None,
+                     check_below=1e-3, switch_tol=1e-9):
         """Newton power flow for every instance of this plan at once
         (pf_newton_batch).  X (batch_shape(n), or (n,) for a plan of one
-        instance) is updated in place.  Returns a dict report with
-        per-instance step counts and last norms."""
+        instance) is updated in place.  With ``q_min``/``q_max`` (plan of one
+        instance set up with q_limits) the reactive limits are checked inside
+        the iterations as in ``newton``; ``lu`` must then be a BatchLU made
+        with switchable=True (made so when not given).  Returns a dict report
+        with per-instance step counts and last norms."""
+        if (q_min is None) != (q_max is None):
+            raise ValueError("q_min and q_max go together")
         if lu is None:
-            lu = BatchLU(self, X)
+            lu = BatchLU(self, X, switchable=q_min is not None)
         I = self.n_inst
         its = np.zeros(I, np.int32)
         nrm = np.zeros(I)
         opts = capi.pf_newton_opts(tol=float(tol), max_iter=int(max_iter))
+        if q_min is not None:
+            lo, hi = _f64(q_min), _f64(q_max)
+            if lo.shape != (self.info["n_pv"],) or hi.shape != lo.shape:
+                raise ValueError("q_min and q_max need one entry per PV unit")
+            opts.q_min = lo.ctypes.data_as(capi._pd)
+            opts.q_max = hi.ctypes.data_as(capi._pd)
+            opts.q_check_below = float(check_below)
+            opts.q_switch_tol = float(switch_tol)
         rep = capi.pf_newton_report()
         import math
         rc = capi.lib().pf_newton_batch(self._h, lu._h,
@@ -723,6 +778,8 @@ class Plan:
         return {"iterations": it, "n_converged": int(rep.converged),
                 "inst_iterations": its, "inst_norm": nrm,
                 "norms": [float(v) for v in rep.norm[:min(it + 1, 65)]],
+                "switched": [int(v) for v in rep.switched[:min(it + 1, 65)]],
+                "n_switches": int(rep.n_switches),
                 "t_eval_s": rep.t_eval_s, "t_solve_s": rep.t_solve_s,
                 "t_total_s": rep.t_total_s, "nnz_lu": lu.nnzT}
 
@@ -732,6 +789,17 @@ class Plan:
         order = np.empty(self.n, np.int32)
         check(capi.lib().pf_jacobian_row_order(self._h, order.ctypes.data_as(capi._pi32)))
         return order
+
+    def jacobian_switch_order(self):
+        """pf_jacobian_switch_order: (order [n], qv [n_pv, 2]) -- the row
+        order that pairs every PV unit's bus Q row with its Q_g column and its
+        control row with the bus voltage column, whatever the unit's mode,
+        and each unit's (Q_g column, voltage column)."""
+        order = np.empty(self.n, np.int32)
+        qv = np.empty((self.info["n_pv"], 2), np.int32)
+        check(capi.lib().pf_jacobian_switch_order(self._h, order.ctypes.data_as(capi._pi32),
+                                                  qv.ctypes.data_as(capi._pi32)))
+        return order, qv
 
     def device_lu(self, x, permc_spec=None):
         """A DeviceLU for this plan, its pattern and pivots taken from one host
@@ -854,13 +922,19 @@ class BatchLU:
     along the pattern and pivots of one host LU of one instance's Jacobian
     (a single-instance or multi-grid plan is one instance)."""
 
-    def __init__(self, plan, X, inst=0, permc_spec=None):
+    def __init__(self, plan, X, inst=0, permc_spec=None, switchable=False):
+        """``switchable``: pivots that stay usable when PV units switch mode
+        (pf_jacobian_switch_order; plan of one instance set up with
+        q_limits), which newton_batch needs to check reactive limits inside
+        its iterations."""
         import weakref
         if plan.panels:
             raise ValueError("the batched factorisation needs the row layout")
         self.plan = plan
         self._h = None
         if plan.info["kind"] == "batch":
+            if switchable:
+                raise ValueError("reactive-limit switches need a plan of one instance")
             _, J = plan.eval_batch(X, want_F=False)
             Jh = plan.from_batch(J)[inst]
         else:
@@ -869,8 +943,23 @@ class BatchLU:
             _, J = plan.eval(X, want_F=False)
             Jh = J.cpu().numpy()
         rp, ci = plan.pattern()
-        trp, tci, _, pivP, pivQ = host_lu(rp, ci, Jh, plan.n, permc_spec,
-                                          row_order=plan.jacobian_row_order())
+        if switchable:
+            order, qv = plan.jacobian_switch_order()
+            # SuperLU's diagonal pivots on the values every unit has under
+            # voltage control (+1 on the voltage column of its control row)
+            rows = qv[:, 0].astype(np.int64)
+            if not (np.array_equal(ci[rp[rows]], qv[:, 1]) and np.array_equal(ci[rp[rows] + 1], qv[:, 0])):
+                raise RuntimeError("unexpected control-row pattern")
+            Jh = np.array(Jh, dtype=np.float64)
+            Jh[rp[rows]] = 1.0
+            Jh[rp[rows] + 1] = 0.0
+            _, _, _, _, q0 = host_lu(rp, ci, Jh, plan.n, permc_spec, row_order=order)
+            pivP, pivQ = switch_safe_pivots(q0, order, qv)
+            trp, tci = lu_pattern(rp, ci, plan.n, pivP, pivQ)
+        else:
+            trp, tci, _, pivP, pivQ = host_lu(rp, ci, Jh, plan.n, permc_spec,
+                                              row_order=plan.jacobian_row_order())
+        self.switchable = bool(switchable)
         self.nnzT = int(trp[-1])
         h = capi._vp()
         check(capi.lib().pf_batch_lu_create(

@@ -105,6 +105,7 @@ SIGNATURES = {
     "pf_pattern": (ctypes.c_int, [_P, _pi32, _pi32]),
     "pf_bus_order": (ctypes.c_int, [_P, _pi32]),
     "pf_jacobian_row_order": (ctypes.c_int, [_P, _pi32]),
+    "pf_jacobian_switch_order": (ctypes.c_int, [_P, _pi32, _pi32]),
     "pf_eval_residual": (ctypes.c_int, [_P, _vp, _vp, _vp]),
     "pf_eval_jacobian": (ctypes.c_int, [_P, _vp, _vp, _vp]),
     "pf_eval": (ctypes.c_int, [_P, _vp, _vp, _vp, _vp]),

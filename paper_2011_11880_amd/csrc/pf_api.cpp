@@ -149,6 +149,30 @@ int check_eval(const pf_plan *plan, bool want_batch) {
 
 }  // namespace
 
+// Row order of the Jacobian whose diagonal holds the pivots (see
+// pf_jacobian_row_order).  A control row's first slot is its V (angle)
+// column, whose index equals that of the bus's Q (P) row; the two rows trade
+// places.  A PV unit held at a reactive target keeps its row (its +1 at its
+// own Q_g is then the diagonal) unless every unit is to be taken under
+// voltage control (all_voltage), as for pivots that must survive a switch.
+static void jacobian_row_order(const HostPlan &h, int32_t *order, bool all_voltage) {
+    for (int64_t r = 0; r < h.n; ++r) order[r] = int32_t(r);
+    for (size_t g = 0; g < size_t(h.NGt); ++g) {
+        const int32_t v_row = h.gen4[4 * g];
+        const int32_t th_row = h.gen4[4 * g + 2];
+        if (th_row != kGenHeld || all_voltage) {
+            const int32_t q_row = h.colidx[size_t(h.rowptr[size_t(v_row)])];
+            order[q_row] = v_row;
+            order[v_row] = q_row;
+        }
+        if (th_row >= 0) {
+            const int32_t p_row = h.colidx[size_t(h.rowptr[size_t(th_row)])];
+            order[p_row] = th_row;
+            order[th_row] = p_row;
+        }
+    }
+}
+
 extern "C" {
 
 const char *pf_last_error(void) { return last_error(); }
@@ -286,24 +310,22 @@ int pf_pattern(const pf_plan *plan, int32_t *rowptr, int32_t *colidx) {
 int pf_jacobian_row_order(const pf_plan *plan, int32_t *order) {
     clear_error();
     if (!plan || !order) return fail(PF_EINVAL, "NULL argument");
+    jacobian_row_order(plan->host, order, false);
+    return PF_OK;
+}
+
+int pf_jacobian_switch_order(const pf_plan *plan, int32_t *order, int32_t *qv) {
+    clear_error();
+    if (!plan || !order) return fail(PF_EINVAL, "NULL argument");
     const HostPlan &h = plan->host;
-    for (int64_t r = 0; r < h.n; ++r) order[r] = int32_t(r);
-    // a control row's first slot is its V (angle) column, whose index equals
-    // that of the bus's Q (P) row
-    for (size_t g = 0; g < size_t(h.NGt); ++g) {
-        const int32_t v_row = h.gen4[4 * g];
-        const int32_t th_row = h.gen4[4 * g + 2];
-        // a unit held at a reactive target keeps its row: its +1 sits on
-        // its own Q_g column, the diagonal
-        if (th_row != kGenHeld) {
-            const int32_t q_row = h.colidx[size_t(h.rowptr[size_t(v_row)])];
-            order[q_row] = v_row;
-            order[v_row] = q_row;
-        }
-        if (th_row >= 0) {
-            const int32_t p_row = h.colidx[size_t(h.rowptr[size_t(th_row)])];
-            order[p_row] = th_row;
-            order[th_row] = p_row;
+    if (!h.q_slots)
+        return fail(PF_EINVAL, "the plan was set up without q_limits (no Q_g slot in PV rows)");
+    jacobian_row_order(h, order, true);
+    if (qv) {
+        for (size_t k = 0; k < size_t(h.NPVt); ++k) {
+            const size_t g = size_t(h.pv_gen[k]);
+            qv[2 * k] = h.gen4[4 * g];
+            qv[2 * k + 1] = h.colidx[size_t(h.rowptr[size_t(h.gen4[4 * g])])];
         }
     }
     return PF_OK;

@@ -73,6 +73,10 @@ struct pf_batch_lu {
     double *norm_host = nullptr;              // pinned [ld]
     int part_rows = 0;
     size_t lds_limit = 0;     // dynamic LDS a block may use
+    // every PV unit's Q row pivots on its Q_g column and its control row on
+    // the bus voltage column, Q_g eliminated first: the pivots survive a
+    // switch of any unit's mode (pf_jacobian_switch_order)
+    bool switch_safe = false;
 };
 
 namespace {
@@ -426,6 +430,23 @@ __global__ void __launch_bounds__(256) k_blu_norm_fold(int nb, int n_inst, int S
 // host-side structure
 // ---------------------------------------------------------------------------
 
+// Whether the pivots pair and order every PV unit's rows as a switch needs:
+// row (bus Q) on column Q_g, row (control) on column V, Q_g first.  Plans
+// without Q_g slots, and batched plans (modes are per plan), never qualify.
+bool pivots_switch_safe(const HostPlan &hp, const int32_t *pivP, const int32_t *pivQ) {
+    if (!hp.q_slots || hp.kind == KIND_BATCH) return false;
+    std::vector<int32_t> at(size_t(hp.n));   // position of each column
+    for (int64_t k = 0; k < hp.n; ++k) at[size_t(pivQ[k])] = int32_t(k);
+    for (size_t k = 0; k < size_t(hp.NPVt); ++k) {
+        const size_t g = size_t(hp.pv_gen[k]);
+        const int32_t qg = hp.gen4[4 * g];                                  // Q_g column = control row
+        const int32_t v = hp.colidx[size_t(hp.rowptr[size_t(qg)])];          // V column = bus Q row
+        const int32_t kq = at[size_t(qg)], kv = at[size_t(v)];
+        if (!(kq < kv) || pivP[kq] != v || pivP[kv] != qg) return false;
+    }
+    return true;
+}
+
 int build(pf_batch_lu *b, const HostPlan &hp, int64_t nnzT, const int32_t *trp,
           const int32_t *tci, const int32_t *pivP, const int32_t *pivQ, size_t lds_limit) {
     const int n = int(hp.n);
@@ -697,6 +718,7 @@ int pf_batch_lu_create(pf_plan *plan, int64_t nnzT, const int32_t *T_rowptr,
     b->n_inst = hp.n_inst;
     b->ld = hp.ld;
     b->lds_limit = size_t(lds);
+    b->switch_safe = pivots_switch_safe(hp, pivP, pivQ);
     int rc;
     try {
         rc = build(b, hp, nnzT, T_rowptr, T_colidx, pivP, pivQ, size_t(lds));
@@ -755,10 +777,17 @@ int pf_newton_batch(pf_plan *plan, pf_batch_lu *b, double *X, const pf_newton_op
     if (!plan || !b || !X) return fail(PF_EINVAL, "NULL argument");
     if (b->plan != plan) return fail(PF_EINVAL, "the factorisation belongs to another plan");
     if (opts && opts->max_iter > 64) return fail(PF_EINVAL, "max_iter must be <= 64");
-    if (opts && (opts->q_min || opts->q_max))
-        return fail(PF_EINVAL, "reactive limits are checked inside the iterations by pf_newton only: "
-                    "a switch needs new pivots");
     HostPlan &hp = plan->host;
+    const bool limits = opts && (opts->q_min || opts->q_max);
+    const double check_below = (limits && opts->q_check_below > 0) ? opts->q_check_below : 1e-3;
+    const double switch_tol = (limits && opts->q_switch_tol >= 0) ? opts->q_switch_tol : 1e-9;
+    if (limits) {
+        const int e = q_limits_valid(hp, opts->q_min, opts->q_max, switch_tol);
+        if (e) return e;
+        if (!b->switch_safe)
+            return fail(PF_EINVAL, "reactive limits need a factorisation whose pivots survive a "
+                        "switch (pf_jacobian_switch_order); this one's do not");
+    }
     BGuard g(b->device);
     if (!g.ok) return fail(PF_EDEVICE, "cannot select device %d", b->device);
     hipStream_t st = static_cast<hipStream_t>(stream);
@@ -766,20 +795,32 @@ int pf_newton_batch(pf_plan *plan, pf_batch_lu *b, double *X, const pf_newton_op
     const int max_iter = (opts && opts->max_iter > 0) ? opts->max_iter : 10;
     const int I = b->n_inst, SI = b->ld, n = b->n;
     std::vector<int32_t> act(size_t(SI), 0), iters(size_t(I), 0);
+    // limits are checked on plans of one instance only (switch_safe): X is
+    // then the plain state
+    std::vector<double> xh(limits ? size_t(n) : 0);
     for (int i = 0; i < I; ++i) act[size_t(i)] = 1;
     pf_newton_report r{};
-    hipEvent_t ev[4];
-    for (auto &e : ev) BL_HIP(hipEventCreate(&e));
+    hipEvent_t ev[4] = {nullptr, nullptr, nullptr, nullptr};
+    for (auto &e : ev) {
+        if (hipEventCreate(&e) != hipSuccess) {
+            e = nullptr;
+            for (auto &f : ev)
+                if (f) (void)hipEventDestroy(f);
+            return fail(PF_EDEVICE, "hipEventCreate failed");
+        }
+    }
     float ms = 0.f;
     auto t_start = std::chrono::steady_clock::now();
     int rc = PF_OK;
     int it = 0;
     int n_conv = 0;
-    for (;; ++it) {
+    // F and J at X under the current modes, and every instance's ||F||_inf
+    // on the host (norm_host)
+    auto evaluate = [&]() -> int {
         (void)hipEventRecord(ev[0], st);
-        rc = hp.kind == KIND_BATCH ? dev_eval_batch(hp, plan->dev, X, b->F, b->J, st)
-                                   : dev_eval_single(hp, plan->dev, X, b->F, b->J, st);
-        if (rc) break;
+        const int e = hp.kind == KIND_BATCH ? dev_eval_batch(hp, plan->dev, X, b->F, b->J, st)
+                                            : dev_eval_single(hp, plan->dev, X, b->F, b->J, st);
+        if (e) return e;
         (void)hipEventRecord(ev[1], st);
         hipLaunchKernelGGL(k_blu_norm_part, dim3(unsigned((I + 255) / 256), kNormRowBlocks),
                            dim3(256), 0, st, n, I, SI, b->part_rows, b->F, b->part);
@@ -788,17 +829,37 @@ int pf_newton_batch(pf_plan *plan, pf_batch_lu *b, double *X, const pf_newton_op
         if (hipGetLastError() != hipSuccess ||
             hipMemcpyAsync(b->norm_host, b->norm, size_t(I) * sizeof(double),
                            hipMemcpyDeviceToHost, st) != hipSuccess ||
-            hipStreamSynchronize(st) != hipSuccess) {
-            rc = fail(PF_EDEVICE, "device step failed in iteration %d", it);
-            break;
-        }
+            hipStreamSynchronize(st) != hipSuccess)
+            return fail(PF_EDEVICE, "device step failed in iteration %d", it);
         if (hipEventElapsedTime(&ms, ev[0], ev[1]) == hipSuccess) r.t_eval_s += ms * 1e-3;
-        // an instance stops once its norm is below tol; it is not stepped again
+        return PF_OK;
+    };
+    for (;; ++it) {
+        rc = evaluate();
+        if (rc) break;
+        // the limits at this iterate (as pf_newton): after a switch F and J
+        // are evaluated again under the new modes before the step
+        int32_t ns = 0;
+        if (limits && b->norm_host[0] < check_below) {
+            if (hipMemcpyAsync(xh.data(), X, size_t(n) * sizeof(double), hipMemcpyDeviceToHost,
+                               st) != hipSuccess ||
+                hipStreamSynchronize(st) != hipSuccess) {
+                rc = fail(PF_EDEVICE, "copy of the state failed in iteration %d", it);
+                break;
+            }
+            rc = q_switch(hp, plan->dev, xh.data(), opts->q_min, opts->q_max, switch_tol, &ns);
+            if (!rc && ns) rc = evaluate();
+            if (rc) break;
+        }
+        if (it < 65) r.switched[it] = ns;
+        r.n_switches += ns;
+        // an instance stops once its norm is below tol (under modes that
+        // the check left unchanged); it is not stepped again
         n_conv = 0;
         double worst = 0.0;
         for (int i = 0; i < I; ++i) {
             const double v = b->norm_host[i];
-            if (act[size_t(i)] && v < tol) act[size_t(i)] = 0;
+            if (act[size_t(i)] && v < tol && ns == 0) act[size_t(i)] = 0;
             if (!act[size_t(i)]) ++n_conv;
             else if (v != v || worst != worst) worst = NAN;
             else if (v > worst) worst = v;

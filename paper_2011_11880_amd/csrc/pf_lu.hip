@@ -367,8 +367,8 @@ int pf_newton_device(pf_plan *plan, pf_refact *rf, double *x, const pf_newton_op
     if (!x) return fail(PF_EINVAL, "x is NULL");
     if (opts && opts->max_iter > 64) return fail(PF_EINVAL, "max_iter must be <= 64");
     if (opts && (opts->q_min || opts->q_max))
-        return fail(PF_EINVAL, "reactive limits are checked inside the iterations by pf_newton only: "
-                    "a switch needs new pivots");
+        return fail(PF_EINVAL, "reactive limits are checked inside the iterations by pf_newton and "
+                    "pf_newton_batch only: these fixed pivots cannot follow a switch");
     HostPlan &hp = plan->host;
     Guard g(rf->device);
     if (!g.ok) return fail(PF_EDEVICE, "cannot select device %d", rf->device);
@@ -973,8 +973,8 @@ int pf_fdlf_solve(pf_fdlf *fd, double *x, const pf_newton_opts *opts, pf_newton_
     if (!fd || !x) return fail(PF_EINVAL, "NULL argument");
     if (opts && opts->max_iter > 64) return fail(PF_EINVAL, "max_iter must be <= 64");
     if (opts && (opts->q_min || opts->q_max))
-        return fail(PF_EINVAL, "reactive limits are checked inside the iterations by pf_newton only: "
-                    "a switch needs new pivots");
+        return fail(PF_EINVAL, "reactive limits are checked inside the iterations by pf_newton and "
+                    "pf_newton_batch only: the constant B' and B'' cannot follow a switch");
     HostPlan &hp = fd->plan->host;
     for (int32_t k = 0; k < hp.NPVt; ++k)
         if (!hp.pv_mode.empty() && hp.pv_mode[size_t(k)])

@@ -245,10 +245,46 @@ def test_newton_with_limits_checked_in_the_iterations(ora, cuda, which):
     assert torch.equal(x, x2)
 
 
+@pytest.mark.parametrize("which", ["tiny", "10k"])
+def test_device_newton_with_limits_checked_in_the_iterations(ora, cuda, which):
+    """pf_newton_batch on a plan of one instance, its factorisation along
+    pf_jacobian_switch_order's pivots, with the limits checked inside the
+    iterations: the iterates at which units switch, the final modes and
+    targets, the iteration count and the end state equal the oracle's
+    in-iteration Newton, with one host LU for the whole run; the norms agree
+    wherever they are above rounding.  newton_qlim(device=True, inner=True)
+    gives the same state bit for bit."""
+    from paper_2011_11880_amd.api import Plan, BatchLU
+    net0, seed, ang, pert, lo, hi, margin, atol = _inner_case(which)
+    net, y0, qmin, qmax = _limits_case(ora, net0, seed, ang, pert, lo, hi, margin)
+    y_o, m_o, qt_o, norms_o, sw_o, ok_o = ora.newton_qlim_inner(net, y0, qmin, qmax)
+    assert ok_o and len(sw_o) >= 1
+    p = Plan(net, q_limits=True)
+    x = torch.from_numpy(y0).to(cuda)
+    lu = BatchLU(p, x, switchable=True)
+    rep = p.newton_batch(x, lu, q_min=qmin, q_max=qmax, max_iter=20)
+    lu.close()
+    assert rep["n_converged"] == 1
+    assert [k for k, s in enumerate(rep["switched"]) if s] == sw_o
+    assert rep["n_switches"] == sum(rep["switched"]) == int(m_o.sum())
+    assert rep["iterations"] == len(norms_o) - 1
+    m, qt = p.gen_modes()
+    assert np.array_equal(m, m_o) and np.array_equal(qt, qt_o)
+    np.testing.assert_allclose(x.cpu().numpy(), y_o, rtol=0, atol=atol)
+    big = np.array(norms_o) > 1e-8
+    np.testing.assert_allclose(np.array(rep["norms"])[big], np.array(norms_o)[big], rtol=1e-6)
+    p.set_gen_modes(np.zeros(net.n_pv, np.int32))
+    x2 = torch.from_numpy(y0).to(cuda)
+    r2 = p.newton_qlim(x2, qmin, qmax, device=True, inner=True, max_iter=20)
+    assert r2["converged"] and r2["rounds"][0]["switched"] == rep["switched"]
+    assert torch.equal(x, x2)
+
+
 def test_limit_checks_rejected_where_pivots_are_fixed(cuda):
     """Limit fields are refused by the solvers whose pivots are fixed
-    (device Newton, batched Newton, fast decoupled) and by pf_newton on a
-    plan without Q_g slots or with q_min > q_max."""
+    (device Newton, batched Newton on a factorisation whose pivots a switch
+    breaks, fast decoupled) and by pf_newton on a plan without Q_g slots or
+    with q_min > q_max."""
     import ctypes
     from paper_2011_11880_amd import capi
     from paper_2011_11880_amd.api import Plan, BatchLU
@@ -275,26 +311,39 @@ def test_limit_checks_rejected_where_pivots_are_fixed(cuda):
     lu = BatchLU(p, xd)
     rc = L.pf_newton_batch(p._h, lu._h, ctypes.c_void_p(xd.data_ptr()), ctypes.byref(opts),
                            None, None, ctypes.byref(rep), None)
-    assert rc == capi.PF_EINVAL and b"pf_newton only" in L.pf_last_error()
+    assert rc == capi.PF_EINVAL and b"survive a switch" in L.pf_last_error()
     lu.close()
+    # a batched plan never qualifies: its modes would be every instance's
+    bp = Plan(net, batch=dict(n_inst=2), q_limits=True)
+    X2 = torch.from_numpy(bp.to_batch(np.stack([y, y]))).to(cuda)
+    blu = BatchLU(bp, X2)
+    rc = L.pf_newton_batch(bp._h, blu._h, ctypes.c_void_p(X2.data_ptr()), ctypes.byref(opts),
+                           None, None, ctypes.byref(rep), None)
+    assert rc == capi.PF_EINVAL and b"non-batched" in L.pf_last_error()
+    blu.close()
+    with pytest.raises(ValueError, match="one instance"):
+        BatchLU(bp, X2, switchable=True)
     dl = p.device_lu(xd)
     rc = L.pf_newton_device(p._h, dl._h, ctypes.c_void_p(xd.data_ptr()), ctypes.byref(opts),
                             ctypes.byref(rep), None)
-    assert rc == capi.PF_EINVAL and b"pf_newton only" in L.pf_last_error()
+    assert rc == capi.PF_EINVAL and b"pf_newton and pf_newton_batch only" in L.pf_last_error()
     dl.close()
     p.fdlf(xd, max_iter=1)   # creates the fast decoupled object
     rc = L.pf_fdlf_solve(p._fd[0], ctypes.c_void_p(xd.data_ptr()), ctypes.byref(opts),
                          ctypes.byref(rep), None)
-    assert rc == capi.PF_EINVAL and b"pf_newton only" in L.pf_last_error()
+    assert rc == capi.PF_EINVAL and b"pf_newton and pf_newton_batch only" in L.pf_last_error()
 
 
-def test_newton_with_limits_in_the_iterations_multi_grid(ora, cuda):
-    """pf_newton with limits checked inside the iterations on a multi-grid
-    plan (two manufactured 200-bus cases, limits binding on both): the run
-    converges, and each grid ends feasible under its own modes -- F = 0 per
-    the oracle, free units inside their limits, held ones at a limit with
-    the voltage on the justifying side -- in the modes the oracle's
-    in-iteration Newton reaches on that grid alone."""
+@pytest.mark.parametrize("solver", ["host", "device"])
+def test_newton_with_limits_in_the_iterations_multi_grid(ora, cuda, solver):
+    """pf_newton (host solve) and pf_newton_batch (this library's
+    factorisation, pivots that survive a switch) with limits checked inside
+    the iterations on a multi-grid plan (two manufactured 200-bus cases,
+    limits binding on both): the run converges, and each grid ends feasible
+    under its own modes -- F = 0 per the oracle, free units inside their
+    limits, held ones at a limit with the voltage on the justifying side --
+    in the modes the oracle's in-iteration Newton reaches on that grid
+    alone."""
     from paper_2011_11880_amd.api import Plan
     cases = [_limits_case(ora, synth.tiny_grid(11), 11, 0.3, (0.02, 0.05), [2, 30],
                           [1, 4, 9, 20], 0.05),
@@ -304,7 +353,11 @@ def test_newton_with_limits_in_the_iterations_multi_grid(ora, cuda):
     x = torch.from_numpy(np.concatenate([c[1] for c in cases])).to(cuda)
     qmin = np.concatenate([c[2] for c in cases])
     qmax = np.concatenate([c[3] for c in cases])
-    rep = mp.newton(x, q_min=qmin, q_max=qmax, max_iter=30)
+    if solver == "host":
+        rep = mp.newton(x, q_min=qmin, q_max=qmax, max_iter=30)
+    else:
+        rep = mp.newton_batch(x, q_min=qmin, q_max=qmax, max_iter=30)
+        rep["converged"] = rep["n_converged"] == 1
     assert rep["converged"] and rep["n_switches"] >= 1
     m, qt = mp.gen_modes()
     xh = x.cpu().numpy()

@@ -116,5 +116,94 @@ def test_newton_limit_arguments_checked_before_any_call():
         p.newton(None, q_min=lo)
     with pytest.raises(ValueError, match="one entry per PV unit"):
         p.newton(None, q_min=lo[:-1], q_max=lo[:-1] + 2)
-    with pytest.raises(ValueError, match="host solve only"):
-        p.newton_qlim(None, lo, lo + 2, device=True, inner=True)
+    with pytest.raises(ValueError, match="rocSOLVER"):
+        p.newton_qlim(None, lo, lo + 2, device="rocsolver", inner=True)
+    with pytest.raises(ValueError, match="together"):
+        p.newton_batch(None, lu=object(), q_max=lo)
+
+
+def _lu_no_pivoting(A):
+    """Dense LU of A in its given order (packed L - I + U) and the smallest
+    |pivot| met; (None, 0.0) at an exactly zero pivot."""
+    A = np.array(A, dtype=np.float64)
+    smallest = np.inf
+    for k in range(A.shape[0]):
+        piv = A[k, k]
+        if piv == 0.0:
+            return None, 0.0
+        smallest = min(smallest, abs(piv))
+        A[k + 1:, k] /= piv
+        A[k + 1:, k + 1:] -= np.outer(A[k + 1:, k], A[k, k + 1:])
+    return A, smallest
+
+
+@pytest.mark.parametrize("seed", [1, 3])
+def test_switch_safe_pivots_hold_in_both_modes(ora, seed):
+    """Pivots paired by pf_jacobian_switch_order, each PV unit's Q_g column
+    eliminated ahead of its bus voltage column, factorise the Jacobian
+    without pivoting whatever the units' modes (all under voltage control,
+    all held, mixed): no pivot vanishes, the factors stay inside the filled
+    pattern that pf_lu_symbolic gives for them, and the solve equals a dense
+    solve.  SuperLU's own column order on the same rows, which puts some
+    voltage columns first, meets an exactly zero pivot once every unit is
+    held -- the case the reordering exists for."""
+    import scipy.sparse as sp
+    from parity import oracle_on_pattern
+    from paper_2011_11880_amd.api import host_lu, lu_pattern, switch_safe_pivots
+    net = synth.tiny_grid(seed, n_bus=120, n_branch=170, n_pv=25)
+    N, NPV = net.n_bus, net.n_pv
+    p = Plan(net, host_only=True, q_limits=True)
+    n = p.n
+    rp, ci = p.pattern()
+    order, qv = p.jacobian_switch_order()
+    assert np.array_equal(qv[:, 0], 2 * N + np.arange(NPV))
+    assert np.array_equal(qv[:, 1], N + net.pv_bus)
+    assert np.array_equal(order[qv[:, 0]], qv[:, 1]) and np.array_equal(order[qv[:, 1]], qv[:, 0])
+    assert np.array_equal(np.sort(order), np.arange(n))
+    # the order does not follow the modes
+    held = np.zeros(NPV, np.int32)
+    held[::3] = 1
+    p.set_gen_modes(held, np.zeros(NPV))
+    o2, qv2 = p.jacobian_switch_order()
+    assert np.array_equal(o2, order) and np.array_equal(qv2, qv)
+    assert not np.array_equal(p.jacobian_row_order(), order)
+    y = synth.random_states(net, seed=seed)
+
+    def dense(mode):
+        J, _ = ora.jacobian(net, y, modes=(mode, np.full(NPV, 0.1)))
+        v, _, _ = oracle_on_pattern(rp, ci, J, abs(J))
+        return sp.csr_matrix((v, ci, rp), shape=(n, n)).toarray()
+
+    M0 = dense(np.zeros(NPV, np.int32))
+    v0 = M0[np.repeat(np.arange(n), np.diff(rp)), ci]
+    _, _, _, _, q0 = host_lu(rp, ci, v0, n, None, row_order=order)
+    at0 = np.argsort(q0)
+    assert np.any(at0[qv[:, 0]] > at0[qv[:, 1]])      # some units need the move
+    pivP, pivQ = switch_safe_pivots(q0, order, qv)
+    at = np.argsort(pivQ)
+    assert np.all(at[qv[:, 0]] < at[qv[:, 1]])
+    assert np.array_equal(pivP, order[pivQ])
+    trp, tci = lu_pattern(rp, ci, n, pivP, pivQ)
+    inside = sp.csr_matrix((np.ones(tci.size), tci, trp), shape=(n, n)).toarray() != 0
+    rng = np.random.default_rng(seed)
+    b = rng.normal(size=n)
+    for mode in (np.zeros(NPV, np.int32), np.ones(NPV, np.int32),
+                 (rng.random(NPV) < 0.5).astype(np.int32)):
+        M = dense(mode)
+        LU, smallest = _lu_no_pivoting(M[pivP][:, pivQ])
+        assert LU is not None and smallest > 1e-3, mode
+        assert np.all(inside | (LU == 0.0))
+        L = np.tril(LU, -1) + np.eye(n)
+        z = np.linalg.solve(np.triu(LU), np.linalg.solve(L, b[pivP]))
+        x = np.empty(n)
+        x[pivQ] = z
+        ref = np.linalg.solve(M, b)
+        assert np.max(np.abs(x - ref)) <= 1e-9 * np.max(np.abs(ref))
+    LU, smallest = _lu_no_pivoting(dense(np.ones(NPV, np.int32))[order[q0]][:, q0])
+    assert LU is None and smallest == 0.0
+
+
+def test_switch_order_needs_q_limits():
+    net = synth.tiny_grid(4)
+    with pytest.raises(PFError, match="q_limits"):
+        Plan(net, host_only=True).jacobian_switch_order()
