@@ -77,19 +77,8 @@ def host_lu(rowptr, colidx, values, n, permc_spec=None, row_order=None):
     has more than 9 nonzeros per row (well-meshed grids, where SuperLU's
     minimum degree takes minutes), and COLAMD otherwise."""
     import scipy.sparse as sp
-    import scipy.sparse.linalg as spla
     rowptr, colidx = _i32(rowptr), _i32(colidx)
-    M = sp.csr_matrix((_f64(values), colidx, rowptr), shape=(n, n))
-    R = np.arange(n) if row_order is None else np.asarray(row_order, dtype=np.int64)
-    thresh = 1.0 if row_order is None else 0.0
-    if permc_spec is None:
-        dense = M.nnz > 9 * n
-        permc_spec = "MMD_AT_PLUS_A" if (row_order is not None and not dense) else "COLAMD"
-    lu = spla.splu(M[R].tocsc(), permc_spec=permc_spec, diag_pivot_thresh=thresh)
-    # SuperLU: Pr A Pc = L U with (Pr A)[perm_r[i]] = A[i], (A Pc)[:, perm_c[j]] = A[:, j],
-    # here A = M[R]
-    pivP = R[np.argsort(lu.perm_r)].astype(np.int32)
-    pivQ = np.argsort(lu.perm_c).astype(np.int32)
+    lu, pivP, pivQ = _superlu(rowptr, colidx, values, n, permc_spec, row_order)
     T = (lu.L - sp.identity(n, format="csc") + lu.U).tocsr()
     T.sum_duplicates()
     T.sort_indices()
@@ -106,6 +95,25 @@ def host_lu(rowptr, colidx, values, n, permc_spec=None, row_order=None):
     tv = np.zeros(tci.size)
     tv[pos] = T.data
     return trp, tci, tv, pivP, pivQ
+
+
+def _superlu(rowptr, colidx, values, n, permc_spec, row_order):
+    """SuperLU of M (CSR) as host_lu describes; returns (lu, pivP, pivQ)
+    with M[pivP][:, pivQ] = L U."""
+    import scipy.sparse as sp
+    import scipy.sparse.linalg as spla
+    M = sp.csr_matrix((_f64(values), _i32(colidx), _i32(rowptr)), shape=(n, n))
+    R = np.arange(n) if row_order is None else np.asarray(row_order, dtype=np.int64)
+    thresh = 1.0 if row_order is None else 0.0
+    if permc_spec is None:
+        dense = M.nnz > 9 * n
+        permc_spec = "MMD_AT_PLUS_A" if (row_order is not None and not dense) else "COLAMD"
+    lu = spla.splu(M[R].tocsc(), permc_spec=permc_spec, diag_pivot_thresh=thresh)
+    # SuperLU: Pr A Pc = L U with (Pr A)[perm_r[i]] = A[i], (A Pc)[:, perm_c[j]] = A[:, j],
+    # here A = M[R]
+    pivP = R[np.argsort(lu.perm_r)].astype(np.int32)
+    pivQ = np.argsort(lu.perm_c).astype(np.int32)
+    return lu, pivP, pivQ
 
 
 def lu_pattern(rowptr, colidx, n, pivP, pivQ):
@@ -953,7 +961,8 @@ class BatchLU:
             Jh = np.array(Jh, dtype=np.float64)
             Jh[rp[rows]] = 1.0
             Jh[rp[rows] + 1] = 0.0
-            _, _, _, _, q0 = host_lu(rp, ci, Jh, plan.n, permc_spec, row_order=order)
+            # only SuperLU's column order is kept
+            _, _, q0 = _superlu(rp, ci, Jh, plan.n, permc_spec, order)
             pivP, pivQ = switch_safe_pivots(q0, order, qv)
             trp, tci = lu_pattern(rp, ci, plan.n, pivP, pivQ)
         else:
