@@ -280,6 +280,29 @@ def test_device_newton_with_limits_checked_in_the_iterations(ora, cuda, which):
     assert torch.equal(x, x2)
 
 
+def test_device_newton_with_limits_in_the_iterations_70k(ora, cuda):
+    """The benchmark's shape at full size: the 70k grid, 20 PV units capped
+    0.002 below their output at the manufactured solution, limits checked
+    inside the iterations of the device Newton on switch-proof pivots.  The
+    switches, iteration count, final modes and end state equal the
+    oracle's in-iteration Newton on the same case."""
+    from paper_2011_11880_amd.api import Plan
+    net0 = synth.grid_70k()
+    pick = np.random.default_rng(4103).choice(net0.n_pv, 20, replace=False)
+    net, y0, qmin, qmax = _limits_case(ora, net0, 5, 0.03, (1e-4, 2.5e-4), [], pick, 0.002)
+    y_o, m_o, qt_o, norms_o, sw_o, ok_o = ora.newton_qlim_inner(net, y0, qmin, qmax)
+    assert ok_o and int(m_o.sum()) == 20
+    p = Plan(net, q_limits=True)
+    x = torch.from_numpy(y0).to(cuda)
+    r = p.newton_qlim(x, qmin, qmax, device=True, inner=True, max_iter=30)
+    rep = r["rounds"][0]
+    assert r["converged"] and [k for k, v in enumerate(rep["switched"]) if v] == sw_o
+    assert rep["iterations"] == len(norms_o) - 1
+    m, qt = p.gen_modes()
+    assert np.array_equal(m, m_o) and np.array_equal(qt, qt_o)
+    np.testing.assert_allclose(x.cpu().numpy(), y_o, rtol=0, atol=1e-8)
+
+
 def test_limit_checks_rejected_where_pivots_are_fixed(cuda):
     """Limit fields are refused by the solvers whose pivots are fixed
     (device Newton, batched Newton on a factorisation whose pivots a switch
