@@ -209,6 +209,42 @@ int main() {
         pf_destroy(p);
         CHECK(pf_setup_multi(v.data(), 0, &o, &p) == PF_EINVAL);
     }
+    {   // row orders for diagonal pivots, with and without Q_g slots
+        Net net = ring(40, 5);
+        pf_network v = net.view();
+        pf_setup_opts o = host_only();
+        o.q_limits = 1;
+        pf_plan *p = nullptr;
+        CHECK(pf_setup(&v, &o, &p) == PF_OK);
+        if (p) {
+            int64_t n = 0, nnz = 0;
+            CHECK(pf_info(p, &n, &nnz) == PF_OK);
+            std::vector<int32_t> ord(size_t(n), -1), sw(size_t(n), -1), qv(2 * size_t(v.n_pv), -1);
+            std::vector<char> seen(size_t(n), 0);
+            CHECK(pf_jacobian_row_order(p, ord.data()) == PF_OK);
+            CHECK(pf_jacobian_switch_order(p, sw.data(), qv.data()) == PF_OK);
+            for (int64_t r = 0; r < n; ++r) {
+                CHECK(sw[size_t(r)] >= 0 && sw[size_t(r)] < n);
+                if (sw[size_t(r)] >= 0 && sw[size_t(r)] < n) seen[size_t(sw[size_t(r)])] = 1;
+                CHECK(sw[size_t(r)] == ord[size_t(r)]);   // every unit under voltage control
+            }
+            for (int64_t r = 0; r < n; ++r) CHECK(seen[size_t(r)]);
+            for (int32_t k = 0; k < v.n_pv; ++k) {
+                CHECK(qv[2 * size_t(k)] == 2 * 40 + k);
+                CHECK(qv[2 * size_t(k) + 1] == 40 + net.pvbus[size_t(k)]);
+                CHECK(sw[size_t(qv[2 * size_t(k)])] == qv[2 * size_t(k) + 1]);
+            }
+            CHECK(pf_jacobian_switch_order(p, nullptr, nullptr) == PF_EINVAL);
+        }
+        pf_destroy(p);
+        o.q_limits = 0;
+        CHECK(pf_setup(&v, &o, &p) == PF_OK);
+        if (p) {
+            std::vector<int32_t> sw(size_t(2 * 40 + v.n_pv + 2 * v.n_slack));
+            CHECK(pf_jacobian_switch_order(p, sw.data(), nullptr) == PF_EINVAL);
+        }
+        pf_destroy(p);
+    }
     {   // malformed networks
         Net n = ring(40, 9);
         n.t[3] = n.f[3];
