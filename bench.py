@@ -893,6 +893,7 @@ def run_newton(args, torch, dev, **kw):
     lim = {}
     for name, on_dev, inner in (("device", True, False), ("device_rocsolver", "rocsolver", False),
                                 ("host_solve", False, False), ("device_inner", True, True),
+                                ("device_rocsolver_inner", "rocsolver", True),
                                 ("host_solve_inner", False, True)):
         pq.set_gen_modes(np.zeros(NPV, np.int32))
         x = torch.from_numpy(y0).to(dev)

@@ -409,12 +409,12 @@ int pf_autotune_cached(pf_plan *plan, const double *x, double *F, double *Jval,
  * under modes that the check at that iterate left unchanged.  The modes
  * stay on the plan (pf_get_gen_modes).  A switch moves the held row's
  * nonzero from the V column to the Q_g column.  pf_newton refactorises on
- * the host each step and follows it; pf_newton_batch follows it on a plan
- * of one instance when its factorisation was made along
- * pf_jacobian_switch_order's pivots (limits are per plan, not per
- * instance).  The fixed pivots of pf_newton_device and of any other
- * pf_newton_batch factorisation, and the constant B' / B'' of pf_fdlf_solve,
- * cannot follow it: those return PF_EINVAL when q_min or q_max is set.
+ * the host each step and follows it; pf_newton_batch (on a plan of one
+ * instance: limits are per plan, not per instance) and pf_newton_device
+ * follow it when their factorisation was made along pivots that pair and
+ * order every PV unit's rows as pf_jacobian_switch_order describes.  Other
+ * fixed pivots, and the constant B' / B'' of pf_fdlf_solve, cannot follow
+ * it: those return PF_EINVAL when q_min or q_max is set.
  */
 typedef int (*pf_linsolve_fn)(void *user, int64_t n, const int32_t *rowptr,
                               const int32_t *colidx, const double *Jval_host,
@@ -526,7 +526,10 @@ int pf_refact_solve(pf_refact *rf, const double *Jval, double *b, void *stream);
  * t_solve_s the device time from the end of each evaluation to the end of
  * its step (norm, refactorisation, triangular solves, update).  Runs on the
  * given stream and synchronises it once per iteration.  Returns PF_ENOCONV if
- * max_iter is reached.
+ * max_iter is reached.  Reactive limits (q_min / q_max) are checked inside
+ * the iterations as pf_newton does when rf's pivots survive a switch
+ * (pf_jacobian_switch_order; pf_refact_create records it), else PF_EINVAL;
+ * each check copies x to the host.
  */
 int pf_newton_device(pf_plan *plan, pf_refact *rf, double *x,
                      const pf_newton_opts *opts, pf_newton_report *report,

@@ -76,15 +76,20 @@ def host_lu(rowptr, colidx, values, n, permc_spec=None, row_order=None):
     COLAMD's elimination levels on power-flow Jacobians), unless the matrix
     has more than 9 nonzeros per row (well-meshed grids, where SuperLU's
     minimum degree takes minutes), and COLAMD otherwise."""
-    import scipy.sparse as sp
     rowptr, colidx = _i32(rowptr), _i32(colidx)
     lu, pivP, pivQ = _superlu(rowptr, colidx, values, n, permc_spec, row_order)
+    trp, tci = lu_pattern(rowptr, colidx, n, pivP, pivQ)
+    return trp, tci, _t_values(lu, trp, tci, n), pivP, pivQ
+
+
+def _t_values(lu, trp, tci, n):
+    """SuperLU's L and U as T = (L - I) + U on the full symbolic pattern
+    (trp, tci): SuperLU's factors leave out entries whose values vanish for
+    this matrix, which stay 0."""
+    import scipy.sparse as sp
     T = (lu.L - sp.identity(n, format="csc") + lu.U).tocsr()
     T.sum_duplicates()
     T.sort_indices()
-    # the full symbolic pattern of the factors (SuperLU's factors leave out
-    # entries whose values vanish for this matrix), SuperLU's values in it
-    trp, tci = lu_pattern(rowptr, colidx, n, pivP, pivQ)
     rows = np.repeat(np.arange(n, dtype=np.int64), np.diff(trp))
     keys = rows * n + tci
     trow = np.repeat(np.arange(n, dtype=np.int64), np.diff(T.indptr))
@@ -94,7 +99,35 @@ def host_lu(rowptr, colidx, values, n, permc_spec=None, row_order=None):
         raise RuntimeError("the numeric LU has entries outside the symbolic pattern")
     tv = np.zeros(tci.size)
     tv[pos] = T.data
-    return trp, tci, tv, pivP, pivQ
+    return tv
+
+
+def host_lu_switchable(rowptr, colidx, values, n, order, qv, permc_spec=None):
+    """host_lu with pivots that survive reactive-limit switches: SuperLU's
+    column order under pf_jacobian_switch_order's rows, each Q_g column moved
+    ahead of its voltage column (switch_safe_pivots), then SuperLU again on
+    the matrix so permuted, in that order with diagonal pivots, for the
+    values of T.  ``values`` must have every PV unit under voltage control
+    (+1 on the voltage column of its control row).  Returns (T_rowptr,
+    T_colidx, T_val, pivP, pivQ) as host_lu."""
+    import scipy.sparse as sp
+    import scipy.sparse.linalg as spla
+    rowptr, colidx = _i32(rowptr), _i32(colidx)
+    _, _, q0 = _superlu(rowptr, colidx, values, n, permc_spec, order)
+    P1, Q1 = switch_safe_pivots(q0, order, qv)
+    M = sp.csr_matrix((_f64(values), colidx, rowptr), shape=(n, n))
+    lu = spla.splu(M[P1][:, Q1].tocsc(), permc_spec="NATURAL", diag_pivot_thresh=0.0)
+    if not np.array_equal(lu.perm_r, lu.perm_c):
+        raise RuntimeError("SuperLU pivoted off the diagonal of the switch-proof order")
+    # SuperLU may post-order the columns of its elimination tree
+    pivP = P1[np.argsort(lu.perm_r)].astype(np.int32)
+    pivQ = Q1[np.argsort(lu.perm_c)].astype(np.int32)
+    at = np.argsort(pivQ)
+    qv = np.asarray(qv).reshape(-1, 2)
+    if not np.all(at[qv[:, 0]] < at[qv[:, 1]]):
+        raise RuntimeError("the elimination order lost a Q_g column's place before its voltage column")
+    trp, tci = lu_pattern(rowptr, colidx, n, pivP, pivQ)
+    return trp, tci, _t_values(lu, trp, tci, n), pivP, pivQ
 
 
 def _superlu(rowptr, colidx, values, n, permc_spec, row_order):
@@ -527,6 +560,24 @@ class Plan:
         self._load_info()
         return best.as_dict()
 
+    def _newton_opts(self, tol, max_iter, q_min=None, q_max=None, check_below=1e-3,
+                     switch_tol=1e-9):
+        """pf_newton_opts, with the reactive limits when q_min/q_max are given
+        (one entry per PV unit).  Returns (opts, arrays to keep alive)."""
+        opts = capi.pf_newton_opts(tol=float(tol), max_iter=int(max_iter))
+        if (q_min is None) != (q_max is None):
+            raise ValueError("q_min and q_max go together")
+        if q_min is None:
+            return opts, ()
+        lo, hi = _f64(q_min), _f64(q_max)
+        if lo.shape != (self.info["n_pv"],) or hi.shape != lo.shape:
+            raise ValueError("q_min and q_max need one entry per PV unit")
+        opts.q_min = lo.ctypes.data_as(capi._pd)
+        opts.q_max = hi.ctypes.data_as(capi._pd)
+        opts.q_check_below = float(check_below)
+        opts.q_switch_tol = float(switch_tol)
+        return opts, (lo, hi)
+
     def newton(self, x, solve=None, tol=1e-10, max_iter=10, q_min=None, q_max=None,
                check_below=1e-3, switch_tol=1e-9):
         """Newton power flow with a host sparse solve (scipy SuperLU by default).
@@ -567,17 +618,7 @@ class Plan:
                 errors.append(ex)
                 return 2
 
-        opts = capi.pf_newton_opts(tol=float(tol), max_iter=int(max_iter))
-        if (q_min is None) != (q_max is None):
-            raise ValueError("q_min and q_max go together")
-        if q_min is not None:
-            lo, hi = _f64(q_min), _f64(q_max)
-            if lo.shape != (self.info["n_pv"],) or hi.shape != lo.shape:
-                raise ValueError("q_min and q_max need one entry per PV unit")
-            opts.q_min = lo.ctypes.data_as(capi._pd)
-            opts.q_max = hi.ctypes.data_as(capi._pd)
-            opts.q_check_below = float(check_below)
-            opts.q_switch_tol = float(switch_tol)
+        opts, _keep = self._newton_opts(tol, max_iter, q_min, q_max, check_below, switch_tol)
         rep = capi.pf_newton_report()
         # pf_newton works on the null stream; whatever the caller's stream
         # still has to write into x must land first
@@ -640,15 +681,21 @@ class Plan:
         path takes a fresh host LU (new pivots) for the next solve.
         ``inner``: one Newton run that checks the limits inside its
         iterations instead (``max_iter`` bounds the whole run): on the host
-        solve, or (device True) on this library's factorisation with pivots
-        that survive a switch, so one host LU serves the whole run.  ``x`` is
+        solve, or on the device (either factorisation) with pivots that
+        survive a switch, so one host LU serves the whole run.  ``x`` is
         updated in place."""
         if device not in (False, True, "rocsolver"):
             raise ValueError("device must be False, True or 'rocsolver'")
         if inner:
             if device == "rocsolver":
-                raise ValueError("rocSOLVER's re-factorisation keeps pivots that a switch breaks")
-            if device:
+                lu = DeviceLU(self, x, switchable=True)
+                try:
+                    rep = self.newton_device(x, lu, tol=tol, max_iter=max_iter, q_min=q_min,
+                                             q_max=q_max, check_below=check_below,
+                                             switch_tol=switch_tol)
+                finally:
+                    lu.close()
+            elif device:
                 lu = BatchLU(self, x, switchable=True)
                 try:
                     rep = self.newton_batch(x, lu, tol=tol, max_iter=max_iter, q_min=q_min,
@@ -757,22 +804,12 @@ class Plan:
         the iterations as in ``newton``; ``lu`` must then be a BatchLU made
         with switchable=True (made so when not given).  Returns a dict report
         with per-instance step counts and last norms."""
-        if (q_min is None) != (q_max is None):
-            raise ValueError("q_min and q_max go together")
+        opts, _keep = self._newton_opts(tol, max_iter, q_min, q_max, check_below, switch_tol)
         if lu is None:
             lu = BatchLU(self, X, switchable=q_min is not None)
         I = self.n_inst
         its = np.zeros(I, np.int32)
         nrm = np.zeros(I)
-        opts = capi.pf_newton_opts(tol=float(tol), max_iter=int(max_iter))
-        if q_min is not None:
-            lo, hi = _f64(q_min), _f64(q_max)
-            if lo.shape != (self.info["n_pv"],) or hi.shape != lo.shape:
-                raise ValueError("q_min and q_max need one entry per PV unit")
-            opts.q_min = lo.ctypes.data_as(capi._pd)
-            opts.q_max = hi.ctypes.data_as(capi._pd)
-            opts.q_check_below = float(check_below)
-            opts.q_switch_tol = float(switch_tol)
         rep = capi.pf_newton_report()
         import math
         rc = capi.lib().pf_newton_batch(self._h, lu._h,
@@ -814,18 +851,22 @@ class Plan:
         LU of the Jacobian at ``x`` (device [n])."""
         return DeviceLU(self, x, permc_spec=permc_spec)
 
-    def newton_device(self, x, lu=None, tol=1e-10, max_iter=10):
+    def newton_device(self, x, lu=None, tol=1e-10, max_iter=10, q_min=None, q_max=None,
+                      check_below=1e-3, switch_tol=1e-9):
         """Newton power flow with every step on the device (pf_newton_device).
         ``lu`` (a DeviceLU of this plan) is created at ``x`` when not given.
-        ``x`` is updated in place.  Returns a dict report (as ``newton``, plus
-        the time of the host LU if one was made)."""
+        With ``q_min``/``q_max`` the reactive limits are checked inside the
+        iterations as in ``newton``; ``lu`` must then be a DeviceLU made with
+        switchable=True (made so when not given).  ``x`` is updated in place.
+        Returns a dict report (as ``newton``, plus the time of the host LU if
+        one was made)."""
         import time
+        opts, _keep = self._newton_opts(tol, max_iter, q_min, q_max, check_below, switch_tol)
         t_lu = 0.0
         if lu is None:
             t0 = time.perf_counter()
-            lu = DeviceLU(self, x)
+            lu = DeviceLU(self, x, switchable=q_min is not None)
             t_lu = time.perf_counter() - t0
-        opts = capi.pf_newton_opts(tol=float(tol), max_iter=int(max_iter))
         rep = capi.pf_newton_report()
         rc = capi.lib().pf_newton_device(self._h, lu._h, _ptr(x, self.n, "x"),
                                          ctypes.byref(opts), ctypes.byref(rep),
@@ -835,6 +876,8 @@ class Plan:
         it = int(rep.iterations)
         return {"iterations": it, "converged": bool(rep.converged),
                 "norms": [float(v) for v in rep.norm[:min(it + 1, 65)]],
+                "switched": [int(v) for v in rep.switched[:min(it + 1, 65)]],
+                "n_switches": int(rep.n_switches),
                 "t_eval_s": rep.t_eval_s, "t_solve_s": rep.t_solve_s,
                 "t_total_s": rep.t_total_s, "t_host_lu_s": t_lu, "nnz_lu": lu.nnzT}
 
@@ -844,15 +887,25 @@ class DeviceLU:
     pattern and pivots from one host LU of the plan's Jacobian at ``x``,
     every later factorisation and solve on the GPU (rocSOLVER csrrf)."""
 
-    def __init__(self, plan, x, permc_spec=None):
+    def __init__(self, plan, x, permc_spec=None, switchable=False):
+        """``switchable``: pivots that stay usable when PV units switch mode
+        (pf_jacobian_switch_order; plan set up with q_limits), which
+        newton_device needs to check reactive limits inside its
+        iterations."""
         import weakref
         self.plan = plan
         self._h = None
         J = plan.eval_jacobian(x)
         Jh = J.cpu().numpy()
         rp, ci = plan.pattern()
-        trp, tci, tv, pivP, pivQ = host_lu(rp, ci, Jh, plan.n, permc_spec,
-                                           row_order=plan.jacobian_row_order())
+        if switchable:
+            order, qv, Jh = _voltage_control_values(plan, Jh)
+            trp, tci, tv, pivP, pivQ = host_lu_switchable(rp, ci, Jh, plan.n, order, qv,
+                                                          permc_spec)
+        else:
+            trp, tci, tv, pivP, pivQ = host_lu(rp, ci, Jh, plan.n, permc_spec,
+                                               row_order=plan.jacobian_row_order())
+        self.switchable = bool(switchable)
         self.nnzT = int(trp[-1])
         h = capi._vp()
         check(capi.lib().pf_refact_create(
@@ -925,6 +978,22 @@ class DeviceSparseLU:
             pass
 
 
+def _voltage_control_values(plan, Jh):
+    """(order, qv, values): pf_jacobian_switch_order's row order and pairs,
+    and a copy of the Jacobian values Jh with every PV unit's control row
+    as under voltage control (+1 on the voltage column, 0 on Q_g), on which
+    SuperLU's diagonal pivots in that order are nonzero."""
+    rp, ci = plan.pattern()
+    order, qv = plan.jacobian_switch_order()
+    rows = qv[:, 0].astype(np.int64)
+    if not (np.array_equal(ci[rp[rows]], qv[:, 1]) and np.array_equal(ci[rp[rows] + 1], qv[:, 0])):
+        raise RuntimeError("unexpected control-row pattern")
+    v = np.array(Jh, dtype=np.float64)
+    v[rp[rows]] = 1.0
+    v[rp[rows] + 1] = 0.0
+    return order, qv, v
+
+
 class BatchLU:
     """Batched factorisation (pf_batch_lu_*) of every instance of a plan
     along the pattern and pivots of one host LU of one instance's Jacobian
@@ -952,15 +1021,7 @@ class BatchLU:
             Jh = J.cpu().numpy()
         rp, ci = plan.pattern()
         if switchable:
-            order, qv = plan.jacobian_switch_order()
-            # SuperLU's diagonal pivots on the values every unit has under
-            # voltage control (+1 on the voltage column of its control row)
-            rows = qv[:, 0].astype(np.int64)
-            if not (np.array_equal(ci[rp[rows]], qv[:, 1]) and np.array_equal(ci[rp[rows] + 1], qv[:, 0])):
-                raise RuntimeError("unexpected control-row pattern")
-            Jh = np.array(Jh, dtype=np.float64)
-            Jh[rp[rows]] = 1.0
-            Jh[rp[rows] + 1] = 0.0
+            order, qv, Jh = _voltage_control_values(plan, Jh)
             # only SuperLU's column order is kept
             _, _, q0 = _superlu(rp, ci, Jh, plan.n, permc_spec, order)
             pivP, pivQ = switch_safe_pivots(q0, order, qv)

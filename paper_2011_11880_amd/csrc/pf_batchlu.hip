@@ -430,23 +430,6 @@ __global__ void __launch_bounds__(256) k_blu_norm_fold(int nb, int n_inst, int S
 // host-side structure
 // ---------------------------------------------------------------------------
 
-// Whether the pivots pair and order every PV unit's rows as a switch needs:
-// row (bus Q) on column Q_g, row (control) on column V, Q_g first.  Plans
-// without Q_g slots, and batched plans (modes are per plan), never qualify.
-bool pivots_switch_safe(const HostPlan &hp, const int32_t *pivP, const int32_t *pivQ) {
-    if (!hp.q_slots || hp.kind == KIND_BATCH) return false;
-    std::vector<int32_t> at(size_t(hp.n));   // position of each column
-    for (int64_t k = 0; k < hp.n; ++k) at[size_t(pivQ[k])] = int32_t(k);
-    for (size_t k = 0; k < size_t(hp.NPVt); ++k) {
-        const size_t g = size_t(hp.pv_gen[k]);
-        const int32_t qg = hp.gen4[4 * g];                                  // Q_g column = control row
-        const int32_t v = hp.colidx[size_t(hp.rowptr[size_t(qg)])];          // V column = bus Q row
-        const int32_t kq = at[size_t(qg)], kv = at[size_t(v)];
-        if (!(kq < kv) || pivP[kq] != v || pivP[kv] != qg) return false;
-    }
-    return true;
-}
-
 int build(pf_batch_lu *b, const HostPlan &hp, int64_t nnzT, const int32_t *trp,
           const int32_t *tci, const int32_t *pivP, const int32_t *pivQ, size_t lds_limit) {
     const int n = int(hp.n);

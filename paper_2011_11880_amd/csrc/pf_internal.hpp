@@ -168,6 +168,11 @@ int dev_newton(HostPlan &hp, DevPlan *dp, double *x, const pf_newton_opts *opts,
 int q_limits_valid(const HostPlan &hp, const double *q_min, const double *q_max, double tol);
 int q_switch(HostPlan &hp, DevPlan *dp, const double *xh, const double *q_min,
              const double *q_max, double tol, int32_t *n_switched);
+// Whether an LU's pivots (M[pivP][:, pivQ] = L U) survive any PV unit's
+// switch: each unit's bus Q row on its Q_g column, its control row on the bus
+// voltage column, the Q_g column first.  False for batched plans (modes are
+// per plan) and plans without Q_g slots.
+bool pivots_switch_safe(const HostPlan &hp, const int32_t *pivP, const int32_t *pivQ);
 int dev_autotune(HostPlan &hp, DevPlan *dp, const double *x, double *F,
                  double *J, int32_t reps, void *stream, const char *cache,
                  pf_schedule *best, int32_t *hit);

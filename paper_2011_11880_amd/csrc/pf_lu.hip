@@ -155,6 +155,7 @@ struct pf_refact {
     double *norm_host = nullptr;  // pinned
     rocblas_handle handle = nullptr;
     rocsolver_rfinfo info = nullptr;
+    bool switch_safe = false;     // pivots survive a PV unit's switch (pivots_switch_safe)
 };
 
 namespace {
@@ -344,6 +345,7 @@ int pf_refact_create(pf_plan *plan, const double *Jval_host, int64_t nnzT,
         release(rf);
         return rc;
     }
+    rf->switch_safe = pivots_switch_safe(hp, pivP, pivQ);
     *out = rf;
     return PF_OK;
 }
@@ -366,16 +368,24 @@ int pf_newton_device(pf_plan *plan, pf_refact *rf, double *x, const pf_newton_op
     if (rf->plan != plan) return fail(PF_EINVAL, "the refactorisation belongs to another plan");
     if (!x) return fail(PF_EINVAL, "x is NULL");
     if (opts && opts->max_iter > 64) return fail(PF_EINVAL, "max_iter must be <= 64");
-    if (opts && (opts->q_min || opts->q_max))
-        return fail(PF_EINVAL, "reactive limits are checked inside the iterations by pf_newton and "
-                    "pf_newton_batch only: these fixed pivots cannot follow a switch");
     HostPlan &hp = plan->host;
+    const bool limits = opts && (opts->q_min || opts->q_max);
+    const double check_below = (limits && opts->q_check_below > 0) ? opts->q_check_below : 1e-3;
+    const double switch_tol = (limits && opts->q_switch_tol >= 0) ? opts->q_switch_tol : 1e-9;
+    if (limits) {
+        const int e = q_limits_valid(hp, opts->q_min, opts->q_max, switch_tol);
+        if (e) return e;
+        if (!rf->switch_safe)
+            return fail(PF_EINVAL, "reactive limits need a refactorisation whose pivots survive a "
+                        "switch (pf_jacobian_switch_order); this one's do not");
+    }
     Guard g(rf->device);
     if (!g.ok) return fail(PF_EDEVICE, "cannot select device %d", rf->device);
     hipStream_t st = static_cast<hipStream_t>(stream);
     const double tol = (opts && opts->tol > 0) ? opts->tol : 1e-10;
     const int max_iter = (opts && opts->max_iter > 0) ? opts->max_iter : 10;
     const int64_t n = hp.n;
+    std::vector<double> xh(limits ? size_t(n) : 0);
     pf_newton_report r{};
     // events: per iteration [eval start, eval end, solve end]
     std::vector<hipEvent_t> ev(3 * size_t(max_iter + 1), nullptr);
@@ -396,9 +406,31 @@ int pf_newton_device(pf_plan *plan, pf_refact *rf, double *x, const pf_newton_op
             rc = fail(PF_EDEVICE, "stream synchronisation failed in Newton iteration %d", it);
             break;
         }
-        const double nf = *rf->norm_host;
+        double nf = *rf->norm_host;
+        // the limits at this iterate (as pf_newton): after a switch F and J
+        // are evaluated again under the new modes before the step
+        int32_t ns = 0;
+        if (limits && nf < check_below) {
+            if (hipMemcpyAsync(xh.data(), x, size_t(n) * sizeof(double), hipMemcpyDeviceToHost,
+                               st) != hipSuccess ||
+                hipStreamSynchronize(st) != hipSuccess) {
+                rc = fail(PF_EDEVICE, "copy of the state failed in Newton iteration %d", it);
+                break;
+            }
+            rc = q_switch(hp, plan->dev, xh.data(), opts->q_min, opts->q_max, switch_tol, &ns);
+            if (!rc && ns) {
+                rc = dev_eval_single(hp, plan->dev, x, rf->F, rf->J, st);
+                if (!rc) rc = absmax_on_stream(rf, rf->F, st);
+                if (!rc && hipStreamSynchronize(st) != hipSuccess)
+                    rc = fail(PF_EDEVICE, "stream synchronisation failed in Newton iteration %d", it);
+                nf = *rf->norm_host;
+            }
+            if (rc) break;
+        }
         r.norm[it] = nf;
-        if (nf < tol) {
+        r.switched[it] = ns;
+        r.n_switches += ns;
+        if (nf < tol && ns == 0) {
             r.converged = 1;
             rc = PF_OK;
             break;
@@ -973,8 +1005,8 @@ int pf_fdlf_solve(pf_fdlf *fd, double *x, const pf_newton_opts *opts, pf_newton_
     if (!fd || !x) return fail(PF_EINVAL, "NULL argument");
     if (opts && opts->max_iter > 64) return fail(PF_EINVAL, "max_iter must be <= 64");
     if (opts && (opts->q_min || opts->q_max))
-        return fail(PF_EINVAL, "reactive limits are checked inside the iterations by pf_newton and "
-                    "pf_newton_batch only: the constant B' and B'' cannot follow a switch");
+        return fail(PF_EINVAL, "reactive limits are checked inside the iterations by the Newton "
+                    "solvers only: the constant B' and B'' cannot follow a switch");
     HostPlan &hp = fd->plan->host;
     for (int32_t k = 0; k < hp.NPVt; ++k)
         if (!hp.pv_mode.empty() && hp.pv_mode[size_t(k)])

@@ -88,6 +88,20 @@ int q_switch(HostPlan &hp, DevPlan *dp, const double *xh, const double *q_min,
     return switched ? apply(hp, dp) : PF_OK;
 }
 
+bool pivots_switch_safe(const HostPlan &hp, const int32_t *pivP, const int32_t *pivQ) {
+    if (!hp.q_slots || hp.kind == KIND_BATCH) return false;
+    std::vector<int32_t> at(size_t(hp.n));   // position of each column
+    for (int64_t k = 0; k < hp.n; ++k) at[size_t(pivQ[k])] = int32_t(k);
+    for (size_t k = 0; k < size_t(hp.NPVt); ++k) {
+        const size_t g = size_t(hp.pv_gen[k]);
+        const int32_t qg = hp.gen4[4 * g];                               // Q_g column = control row
+        const int32_t v = hp.colidx[size_t(hp.rowptr[size_t(qg)])];       // V column = bus Q row
+        const int32_t kq = at[size_t(qg)], kv = at[size_t(v)];
+        if (!(kq < kv) || pivP[kq] != v || pivP[kv] != qg) return false;
+    }
+    return true;
+}
+
 }  // namespace pf
 
 extern "C" {

@@ -245,26 +245,33 @@ def test_newton_with_limits_checked_in_the_iterations(ora, cuda, which):
     assert torch.equal(x, x2)
 
 
+@pytest.mark.parametrize("solver", ["library", "rocsolver"])
 @pytest.mark.parametrize("which", ["tiny", "10k"])
-def test_device_newton_with_limits_checked_in_the_iterations(ora, cuda, which):
-    """pf_newton_batch on a plan of one instance, its factorisation along
-    pf_jacobian_switch_order's pivots, with the limits checked inside the
-    iterations: the iterates at which units switch, the final modes and
-    targets, the iteration count and the end state equal the oracle's
-    in-iteration Newton, with one host LU for the whole run; the norms agree
-    wherever they are above rounding.  newton_qlim(device=True, inner=True)
-    gives the same state bit for bit."""
-    from paper_2011_11880_amd.api import Plan, BatchLU
+def test_device_newton_with_limits_checked_in_the_iterations(ora, cuda, which, solver):
+    """Device Newton with the limits checked inside the iterations, on
+    pivots from pf_jacobian_switch_order: pf_newton_batch on a plan of one
+    instance (this library's factorisation) and pf_newton_device
+    (rocSOLVER's re-factorisation).  The iterates at which units switch, the
+    final modes and targets, the iteration count and the end state equal
+    the oracle's in-iteration Newton, with one host LU for the whole run;
+    the norms agree wherever they are above rounding.  newton_qlim(inner=True)
+    on the same device path gives the same state bit for bit."""
+    from paper_2011_11880_amd.api import Plan, BatchLU, DeviceLU
     net0, seed, ang, pert, lo, hi, margin, atol = _inner_case(which)
     net, y0, qmin, qmax = _limits_case(ora, net0, seed, ang, pert, lo, hi, margin)
     y_o, m_o, qt_o, norms_o, sw_o, ok_o = ora.newton_qlim_inner(net, y0, qmin, qmax)
     assert ok_o and len(sw_o) >= 1
     p = Plan(net, q_limits=True)
     x = torch.from_numpy(y0).to(cuda)
-    lu = BatchLU(p, x, switchable=True)
-    rep = p.newton_batch(x, lu, q_min=qmin, q_max=qmax, max_iter=20)
+    if solver == "library":
+        lu = BatchLU(p, x, switchable=True)
+        rep = p.newton_batch(x, lu, q_min=qmin, q_max=qmax, max_iter=20)
+        rep["converged"] = rep["n_converged"] == 1
+    else:
+        lu = DeviceLU(p, x, switchable=True)
+        rep = p.newton_device(x, lu, q_min=qmin, q_max=qmax, max_iter=20)
     lu.close()
-    assert rep["n_converged"] == 1
+    assert rep["converged"]
     assert [k for k, s in enumerate(rep["switched"]) if s] == sw_o
     assert rep["n_switches"] == sum(rep["switched"]) == int(m_o.sum())
     assert rep["iterations"] == len(norms_o) - 1
@@ -275,7 +282,8 @@ def test_device_newton_with_limits_checked_in_the_iterations(ora, cuda, which):
     np.testing.assert_allclose(np.array(rep["norms"])[big], np.array(norms_o)[big], rtol=1e-6)
     p.set_gen_modes(np.zeros(net.n_pv, np.int32))
     x2 = torch.from_numpy(y0).to(cuda)
-    r2 = p.newton_qlim(x2, qmin, qmax, device=True, inner=True, max_iter=20)
+    r2 = p.newton_qlim(x2, qmin, qmax, device=True if solver == "library" else "rocsolver",
+                       inner=True, max_iter=20)
     assert r2["converged"] and r2["rounds"][0]["switched"] == rep["switched"]
     assert torch.equal(x, x2)
 
@@ -304,10 +312,11 @@ def test_device_newton_with_limits_in_the_iterations_70k(ora, cuda):
 
 
 def test_limit_checks_rejected_where_pivots_are_fixed(cuda):
-    """Limit fields are refused by the solvers whose pivots are fixed
-    (device Newton, batched Newton on a factorisation whose pivots a switch
-    breaks, fast decoupled) and by pf_newton on a plan without Q_g slots or
-    with q_min > q_max."""
+    """Limit fields are refused by the device Newtons whose pivots a switch
+    breaks (either factorisation made without pf_jacobian_switch_order's
+    pairing), by the batched Newton on a batched plan, by the fast decoupled
+    method, and by pf_newton on a plan without Q_g slots or with
+    q_min > q_max."""
     import ctypes
     from paper_2011_11880_amd import capi
     from paper_2011_11880_amd.api import Plan, BatchLU
@@ -349,12 +358,12 @@ def test_limit_checks_rejected_where_pivots_are_fixed(cuda):
     dl = p.device_lu(xd)
     rc = L.pf_newton_device(p._h, dl._h, ctypes.c_void_p(xd.data_ptr()), ctypes.byref(opts),
                             ctypes.byref(rep), None)
-    assert rc == capi.PF_EINVAL and b"pf_newton and pf_newton_batch only" in L.pf_last_error()
+    assert rc == capi.PF_EINVAL and b"survive a switch" in L.pf_last_error()
     dl.close()
     p.fdlf(xd, max_iter=1)   # creates the fast decoupled object
     rc = L.pf_fdlf_solve(p._fd[0], ctypes.c_void_p(xd.data_ptr()), ctypes.byref(opts),
                          ctypes.byref(rep), None)
-    assert rc == capi.PF_EINVAL and b"pf_newton and pf_newton_batch only" in L.pf_last_error()
+    assert rc == capi.PF_EINVAL and b"Newton solvers only" in L.pf_last_error()
 
 
 @pytest.mark.parametrize("solver", ["host", "device"])

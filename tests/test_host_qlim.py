@@ -116,10 +116,12 @@ def test_newton_limit_arguments_checked_before_any_call():
         p.newton(None, q_min=lo)
     with pytest.raises(ValueError, match="one entry per PV unit"):
         p.newton(None, q_min=lo[:-1], q_max=lo[:-1] + 2)
-    with pytest.raises(ValueError, match="rocSOLVER"):
-        p.newton_qlim(None, lo, lo + 2, device="rocsolver", inner=True)
     with pytest.raises(ValueError, match="together"):
         p.newton_batch(None, lu=object(), q_max=lo)
+    with pytest.raises(ValueError, match="together"):
+        p.newton_device(None, lu=object(), q_min=lo)
+    with pytest.raises(ValueError, match="one entry per PV unit"):
+        p.newton_device(None, lu=object(), q_min=lo[1:], q_max=lo[1:])
 
 
 def _lu_no_pivoting(A):
@@ -201,6 +203,18 @@ def test_switch_safe_pivots_hold_in_both_modes(ora, seed):
         assert np.max(np.abs(x - ref)) <= 1e-9 * np.max(np.abs(ref))
     LU, smallest = _lu_no_pivoting(dense(np.ones(NPV, np.int32))[order[q0]][:, q0])
     assert LU is None and smallest == 0.0
+    # the same pivots with SuperLU's values of T, for the rocSOLVER path:
+    # T = (L - I) + U on the full pattern, L U = M[pivP][:, pivQ]
+    from paper_2011_11880_amd.api import host_lu_switchable
+    t_rp, t_ci, t_v, sP, sQ = host_lu_switchable(rp, ci, v0, n, order, qv)
+    at = np.argsort(sQ)
+    assert np.all(at[qv[:, 0]] < at[qv[:, 1]]) and np.array_equal(sP, order[sQ])
+    T = sp.csr_matrix((t_v, t_ci, t_rp), shape=(n, n)).toarray()
+    L = np.tril(T, -1) + np.eye(n)
+    A0 = M0[sP][:, sQ]
+    assert np.max(np.abs(L @ np.triu(T) - A0)) <= 1e-12 * np.max(np.abs(A0))
+    LU, _ = _lu_no_pivoting(A0)
+    assert np.max(np.abs(LU - T)) <= 1e-10 * np.max(np.abs(LU))
 
 
 def test_switch_order_needs_q_limits():
