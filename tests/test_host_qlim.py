@@ -221,3 +221,23 @@ def test_switch_order_needs_q_limits():
     net = synth.tiny_grid(4)
     with pytest.raises(PFError, match="q_limits"):
         Plan(net, host_only=True).jacobian_switch_order()
+
+
+def test_switch_order_without_pv_units_and_on_multi_grid():
+    """No PV unit: no pairs, and the order is pf_jacobian_row_order's.  Two
+    grids: the pairs of each grid's units sit at that grid's offsets."""
+    net = synth.tiny_grid(5, n_bus=30, n_branch=40, n_pv=0)
+    p = Plan(net, host_only=True, q_limits=True)
+    order, qv = p.jacobian_switch_order()
+    assert qv.shape == (0, 2) and np.array_equal(order, p.jacobian_row_order())
+    nets = [synth.tiny_grid(1, n_bus=30, n_branch=40, n_pv=4), synth.tiny_grid(2)]
+    mp = Plan.multi(nets, host_only=True, q_limits=True)
+    order, qv = mp.jacobian_switch_order()
+    k = 0
+    for g, n in enumerate(nets):
+        xo = mp.x_off[g]
+        N = n.n_bus
+        assert np.array_equal(qv[k:k + n.n_pv, 0], xo + 2 * N + np.arange(n.n_pv))
+        assert np.array_equal(qv[k:k + n.n_pv, 1], xo + N + n.pv_bus)
+        k += n.n_pv
+    assert np.array_equal(order[qv[:, 0]], qv[:, 1]) and np.array_equal(order[qv[:, 1]], qv[:, 0])
