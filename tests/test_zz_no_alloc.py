@@ -1,7 +1,8 @@
 """pf_lu_solve_noalloc (the constant-factorisation solve with its working
 vector in the library's static device array) against pf_lu_solve, bit for
 bit, on two calls in a row, the second on a smaller system; sizes above the
-array are refused with PF_EINVAL and leave the right-hand side untouched."""
+array are refused with PF_EINVAL and leave the right-hand side untouched; a
+captured solve replays from a HIP graph to the eager result."""
 
 import numpy as np
 import pytest
@@ -55,4 +56,40 @@ def test_noalloc_refuses_more_than_the_array(cuda):
     lu.solve(b)
     torch.cuda.synchronize()
     assert np.allclose(b.cpu().numpy(), 1.0 / d, rtol=1e-15, atol=0)
+    lu.close()
+
+
+def test_noalloc_solve_replays_from_a_graph(cuda):
+    """The callers the no-allocation entry point is for include code under
+    graph capture: a solve captured into a HIP graph replays, three times with
+    eager solves of other right-hand sides between the replays, to the eager
+    result bit for bit each time."""
+    from paper_2011_11880_amd.api import DeviceSparseLU, Plan
+    Bp, _, _, _ = Plan(synth.grid_meshed(2000, 2200), host_only=True).fdlf_matrices()
+    lu = DeviceSparseLU(Bp)
+    rng = np.random.default_rng(3)
+    b0 = torch.from_numpy(rng.normal(size=Bp.shape[0])).to(cuda)
+    ref = b0.clone()
+    lu.solve(ref, noalloc=True)
+    y = b0.clone()
+    st = torch.cuda.Stream()
+    st.wait_stream(torch.cuda.current_stream())
+    with torch.cuda.stream(st):          # warm-up on the capture stream
+        y.copy_(b0)
+        lu.solve(y, noalloc=True)
+    torch.cuda.current_stream().wait_stream(st)
+    torch.cuda.synchronize()
+    g = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(g, stream=st):
+        y.copy_(b0)
+        lu.solve(y, noalloc=True)
+    for k in range(3):
+        other = torch.from_numpy(rng.normal(size=Bp.shape[0])).to(cuda)
+        lu.solve(other, noalloc=True)    # the shared array holds another solve's data
+        torch.cuda.synchronize()
+        y.fill_(7.0)
+        g.replay()
+        torch.cuda.synchronize()
+        assert torch.equal(y, ref), k
+    del g
     lu.close()
