@@ -440,8 +440,6 @@ class Plan:
         be an instance view, (n_inst, n) with strides (1, ld) (see
         ``instances``); F and J are then allocated and returned as instance
         views too, and given ones must be views of the same kind."""
-        import math
-
         import torch
         dev = self._dev(X)
         views = self._is_instance_view(X, self.n)
