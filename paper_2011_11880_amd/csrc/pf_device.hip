@@ -26,6 +26,7 @@
 #include <cstdio>
 #include <cstring>
 #include <string>
+#include <type_traits>
 #include <vector>
 
 #include "pf_internal.hpp"
@@ -316,141 +317,151 @@ k_eval_single(const int4 *__restrict__ tiles, int ntiles, int tiles_per_wave, in
         const int e0 = td.x, e1 = td.y, b0 = td.z;
         const int jP0 = tj.x, nP = tj.y - tj.x, jQ0 = tj.z, nQ = tj.w - tj.z;
         const bool staged = WJ && (nP + nQ <= stage_cap);
-        // Jacobian value of row P_i (slot s) / row Q_i: LDS image or global
-        auto putP = [&](int slot, double v) {
-            if (staged)
-                S[slot - jP0] = v;
-            else
-                stc(&J[slot], v);
-        };
-        auto putQ = [&](int slot, double v) {
-            if (staged)
-                S[nP + slot - jQ0] = v;
-            else
-                stc(&J[slot], v);
-        };
-        const GridDev gd = grids[td.w];
-        const double *xt = x + gd.xoff;
-        const double *xv = xt + gd.N;
-        double cy[6] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
-        int rows_seen = 0;
-        // entry data of the first chunk; later chunks are fetched one chunk
-        // ahead, while the current one computes
-        int raw_n = lane < e1 - e0 ? ycol[e0 + lane] : 0;
-        double G_n = lane < e1 - e0 ? yG[e0 + lane] : 0.0;
-        double B_n = lane < e1 - e0 ? yB[e0 + lane] : 0.0;
-        for (int c0 = e0; c0 < e1; c0 += 64) {
-            const int nvalid = min(64, e1 - c0);
-            const bool valid = lane < nvalid;
-            const int e = c0 + lane;
-            const int raw = raw_n;
-            const double Ge = G_n, Be = B_n;
-            const bool start = raw < 0;
-            const int j = raw & kColMask;
-            const uint64_t smask = __ballot(start);
-            const int r = rows_seen + __popcll(smask & le) - 1;
-            // lanes past the tile end read a valid duplicate (the tile's
-            // first bus) so every per-bus load is issued at once, unmasked
-            const int b = valid ? b0 + r : b0;
-            const int i = b - gd.bus_off;
-            const int4 bi = bus4[b];
-            const int2 b2 = bus2[b];
-            const double2 sp = spec[b];
-            const double thi = xt[i], vi = xv[i];
-            const double thj = xt[j], vj = xv[j];
-            const bool more = c0 + 64 < e1;
-            if (more) {
-                const int en = c0 + 64 + lane;
-                const bool vn = en < e1;
-                raw_n = vn ? ycol[en] : 0;
-                G_n = vn ? yG[en] : 0.0;
-                B_n = vn ? yB[en] : 0.0;
-            }
-            double c[6] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
-            if (valid) {
-                double o[4];
-                const bool diag = (j == i);
-                entry_eval(diag, Ge, Be, thi, vi, thj, vj, c, o);
-                if (WJ && !diag) {
-                    const int p = e - bi.x, Lr = bi.y - bi.x;
-                    putP(bi.z + p, o[0]);
-                    putP(bi.z + Lr + p, o[1]);
-                    putQ(bi.w + p, o[2]);
-                    putQ(bi.w + Lr + p, o[3]);
+        // the tile's walk, compiled once with the Jacobian rows assembled in
+        // LDS and once with values stored straight to their slots, so that
+        // each store has one address space
+        auto walk = [&](auto staged_c) {
+            constexpr bool STG = decltype(staged_c)::value;
+            // Jacobian value of row P_i (slot s) / row Q_i: LDS image or global
+            auto putP = [&](int slot, double v) {
+                if constexpr (STG)
+                    S[slot - jP0] = v;
+                else
+                    stc(&J[slot], v);
+            };
+            auto putQ = [&](int slot, double v) {
+                if constexpr (STG)
+                    S[nP + slot - jQ0] = v;
+                else
+                    stc(&J[slot], v);
+            };
+            const GridDev gd = grids[td.w];
+            const double *xt = x + gd.xoff;
+            const double *xv = xt + gd.N;
+            double cy[6] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
+            int rows_seen = 0;
+            // entry data of the first chunk; later chunks are fetched one chunk
+            // ahead, while the current one computes
+            int raw_n = lane < e1 - e0 ? ycol[e0 + lane] : 0;
+            double G_n = lane < e1 - e0 ? yG[e0 + lane] : 0.0;
+            double B_n = lane < e1 - e0 ? yB[e0 + lane] : 0.0;
+            for (int c0 = e0; c0 < e1; c0 += 64) {
+                const int nvalid = min(64, e1 - c0);
+                const bool valid = lane < nvalid;
+                const int e = c0 + lane;
+                const int raw = raw_n;
+                const double Ge = G_n, Be = B_n;
+                const bool start = raw < 0;
+                const int j = raw & kColMask;
+                const uint64_t smask = __ballot(start);
+                const int r = rows_seen + __popcll(smask & le) - 1;
+                // lanes past the tile end read a valid duplicate (the tile's
+                // first bus) so every per-bus load is issued at once, unmasked
+                const int b = valid ? b0 + r : b0;
+                const int i = b - gd.bus_off;
+                const int4 bi = bus4[b];
+                const int2 b2 = bus2[b];
+                const double2 sp = spec[b];
+                const double thi = xt[i], vi = xv[i];
+                const double thj = xt[j], vj = xv[j];
+                const bool more = c0 + 64 < e1;
+                if (more) {
+                    const int en = c0 + 64 + lane;
+                    const bool vn = en < e1;
+                    raw_n = vn ? ycol[en] : 0;
+                    G_n = vn ? yG[en] : 0.0;
+                    B_n = vn ? yB[en] : 0.0;
                 }
-            }
-#pragma unroll
-            for (int k = 0; k < 6; ++k) L[k * 64 + lane] = c[k];
-            wave_sync();
-            const bool carry_row = !(smask & 1ull);
-            const bool folder = start || (lane == 0 && carry_row);
-            const uint64_t after = smask & ~le;
-            const int next = after ? (__ffsll((unsigned long long)after) - 1) : nvalid;
-            // the entry after this chunk opens a row iff its column carries
-            // the row-start flag (that entry is lane 0 of the prefetch)
-            const bool next_is_start = more ? (__shfl(raw_n, 0) < 0) : true;
-            const bool complete = (next < nvalid) || next_is_start;
-            double a[6];
-#pragma unroll
-            for (int k = 0; k < 6; ++k) a[k] = (lane == 0 && carry_row) ? cy[k] : 0.0;
-            if (folder) {
-                for (int q = lane; q < next; ++q) {
-#pragma unroll
-                    for (int k = 0; k < 6; ++k) a[k] += L[k * 64 + q];
-                }
-            }
-            if (!next_is_start) {
-                const int lastf = smask ? 63 - __clzll((long long)smask) : 0;
-#pragma unroll
-                for (int k = 0; k < 6; ++k) cy[k] = __shfl(a[k], lastf);
-            }
-            if (folder && complete) {
-                const int Lr = bi.y - bi.x;
-                double fp = a[0] + sp.x;
-                double fq = a[1] + sp.y;
-                const int g = b2.y;
-                if (g >= 0) {
-                    const int4 g4 = gen4[g];
-                    const double2 gs = gen2[g];
-                    const double qg = x[g4.x];
-                    const bool held = g4.z == kGenHeld;
-                    fq = fq - qg;
-                    if (WF) stc(&F[g4.x], held ? qg - gs.x : vi - gs.x);
-                    if (WJ) {
-                        putQ(bi.w + 2 * Lr, -1.0);
-                        stc(&J[g4.y], held ? 0.0 : 1.0);
-                        if (g4.z <= kGenVoltageSlot) stc(&J[g4.y + 1], held ? 1.0 : 0.0);
+                double c[6] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
+                if (valid) {
+                    double o[4];
+                    const bool diag = (j == i);
+                    entry_eval(diag, Ge, Be, thi, vi, thj, vj, c, o);
+                    if (WJ && !diag) {
+                        const int p = e - bi.x, Lr = bi.y - bi.x;
+                        putP(bi.z + p, o[0]);
+                        putP(bi.z + Lr + p, o[1]);
+                        putQ(bi.w + p, o[2]);
+                        putQ(bi.w + Lr + p, o[3]);
                     }
-                    if (g4.z >= 0) {
-                        fp = fp - x[g4.z];
-                        if (WF) stc(&F[g4.z], thi - gs.y);
+                }
+    #pragma unroll
+                for (int k = 0; k < 6; ++k) L[k * 64 + lane] = c[k];
+                wave_sync();
+                const bool carry_row = !(smask & 1ull);
+                const bool folder = start || (lane == 0 && carry_row);
+                const uint64_t after = smask & ~le;
+                const int next = after ? (__ffsll((unsigned long long)after) - 1) : nvalid;
+                // the entry after this chunk opens a row iff its column carries
+                // the row-start flag (that entry is lane 0 of the prefetch)
+                const bool next_is_start = more ? (__shfl(raw_n, 0) < 0) : true;
+                const bool complete = (next < nvalid) || next_is_start;
+                double a[6];
+    #pragma unroll
+                for (int k = 0; k < 6; ++k) a[k] = (lane == 0 && carry_row) ? cy[k] : 0.0;
+                if (folder) {
+                    for (int q = lane; q < next; ++q) {
+    #pragma unroll
+                        for (int k = 0; k < 6; ++k) a[k] += L[k * 64 + q];
+                    }
+                }
+                if (!next_is_start) {
+                    const int lastf = smask ? 63 - __clzll((long long)smask) : 0;
+    #pragma unroll
+                    for (int k = 0; k < 6; ++k) cy[k] = __shfl(a[k], lastf);
+                }
+                if (folder && complete) {
+                    const int Lr = bi.y - bi.x;
+                    double fp = a[0] + sp.x;
+                    double fq = a[1] + sp.y;
+                    const int g = b2.y;
+                    if (g >= 0) {
+                        const int4 g4 = gen4[g];
+                        const double2 gs = gen2[g];
+                        const double qg = x[g4.x];
+                        const bool held = g4.z == kGenHeld;
+                        fq = fq - qg;
+                        if (WF) stc(&F[g4.x], held ? qg - gs.x : vi - gs.x);
                         if (WJ) {
-                            putP(bi.z + 2 * Lr, -1.0);
-                            stc(&J[g4.w], 1.0);
+                            putQ(bi.w + 2 * Lr, -1.0);
+                            stc(&J[g4.y], held ? 0.0 : 1.0);
+                            if (g4.z <= kGenVoltageSlot) stc(&J[g4.y + 1], held ? 1.0 : 0.0);
+                        }
+                        if (g4.z >= 0) {
+                            fp = fp - x[g4.z];
+                            if (WF) stc(&F[g4.z], thi - gs.y);
+                            if (WJ) {
+                                putP(bi.z + 2 * Lr, -1.0);
+                                stc(&J[g4.w], 1.0);
+                            }
                         }
                     }
+                    if (WF) {
+                        stc(&F[gd.xoff + i], fp);
+                        stc(&F[gd.xoff + gd.N + i], fq);
+                    }
+                    if (WJ) {
+                        putP(bi.z + b2.x, a[2]);
+                        putP(bi.z + Lr + b2.x, a[3]);
+                        putQ(bi.w + b2.x, a[4]);
+                        putQ(bi.w + Lr + b2.x, a[5]);
+                    }
                 }
-                if (WF) {
-                    stc(&F[gd.xoff + i], fp);
-                    stc(&F[gd.xoff + gd.N + i], fq);
-                }
-                if (WJ) {
-                    putP(bi.z + b2.x, a[2]);
-                    putP(bi.z + Lr + b2.x, a[3]);
-                    putQ(bi.w + b2.x, a[4]);
-                    putQ(bi.w + Lr + b2.x, a[5]);
-                }
+                rows_seen += __popcll(smask);
+                wave_sync();
             }
-            rows_seen += __popcll(smask);
-            wave_sync();
-        }
-        if (staged) {
-            // every slot of both ranges has been written above; stream the
-            // assembled rows out as contiguous runs
-            for (int q = lane; q < nP; q += 64) st(&J[jP0 + q], S[q]);
-            for (int q = lane; q < nQ; q += 64) st(&J[jQ0 + q], S[nP + q]);
-            wave_sync();
-        }
+            if constexpr (STG) {
+                // every slot of both ranges has been written above; stream the
+                // assembled rows out as contiguous runs
+                for (int q = lane; q < nP; q += 64) st(&J[jP0 + q], S[q]);
+                for (int q = lane; q < nQ; q += 64) st(&J[jQ0 + q], S[nP + q]);
+                wave_sync();
+            }
+        };
+        if (staged)
+            walk(std::true_type{});
+        else
+            walk(std::false_type{});
     }
 }
 
