@@ -54,8 +54,9 @@ struct pf_batch_lu {
     // {first level, end level, waves, LDS bytes per wave} (factorisation) and
     // {first level, end level, waves} (forward, backward solves)
     std::vector<int32_t> fchain_factor;
-    TriLevels tri;   // one instance: levels and runs of the solves
+    TriLevels tri;   // one instance: levels, runs and row records of the solves
     int32_t *flev_ptr_d = nullptr, *blev_ptr_d = nullptr;
+    int4 *frec = nullptr, *brec = nullptr;   // one instance: the solves' row records
     // device structure
     int32_t *trp = nullptr;   // n + 1
     int32_t *tci = nullptr;   // nnzT
@@ -126,7 +127,8 @@ void release(pf_batch_lu *b) {
                     (void *)b->item_ptr, (void *)b->item, (void *)b->frows,
                     (void *)b->brows, (void *)b->pivP, (void *)b->pivQ, (void *)b->T,
                     (void *)b->F, (void *)b->J, (void *)b->Y, (void *)b->part, (void *)b->norm,
-                    (void *)b->active, (void *)b->flev_ptr_d, (void *)b->blev_ptr_d})
+                    (void *)b->active, (void *)b->flev_ptr_d, (void *)b->blev_ptr_d,
+                    (void *)b->frec, (void *)b->brec})
         if (p) (void)hipFree(p);
     if (b->norm_host) (void)hipHostFree(b->norm_host);
     if (prev >= 0) (void)hipSetDevice(prev);
@@ -553,6 +555,10 @@ int build(pf_batch_lu *b, const HostPlan &hp, int64_t nnzT, const int32_t *trp,
         b->tri.blev_ptr = b->blev_ptr;
         tri_chains(b->tri.flev_ptr, b->tri.fchain);
         tri_chains(b->tri.blev_ptr, b->tri.bchain);
+        b->tri.tdiag = tdiag;
+        b->tri.frows = frows;
+        b->tri.brows = brows;
+        tri_records(trp, pivP, b->tri);
     }
     int rc = PF_OK;
     if (!rc) rc = balloc(&b->trp, trp, size_t(n) + 1);
@@ -570,6 +576,8 @@ int build(pf_batch_lu *b, const HostPlan &hp, int64_t nnzT, const int32_t *trp,
     if (!rc) rc = balloc(&b->blev_ptr_d, b->blev_ptr.data(), b->blev_ptr.size());
     if (!rc) rc = balloc(&b->pivP, pivP, size_t(n));
     if (!rc) rc = balloc(&b->pivQ, pivQ, size_t(n));
+    if (!rc && !b->tri.frec.empty()) rc = balloc(&b->frec, b->tri.frec.data(), b->tri.frec.size());
+    if (!rc && !b->tri.brec.empty()) rc = balloc(&b->brec, b->tri.brec.data(), b->tri.brec.size());
     return rc;
 }
 
@@ -625,8 +633,7 @@ int solve_levels(pf_batch_lu *b, const double *Fin, double *Y, hipStream_t st) {
     const int I = b->n_inst, SI = b->ld;
     const int nc = (I + 63) / 64;
     if (I == 1 && SI == 1) {   // one instance: lanes over each row's entries
-        const TriDev d{b->flev_ptr_d, b->blev_ptr_d, b->frows, b->brows,
-                       b->trp,        b->tci,        b->tdiag, b->pivP, b->T};
+        const TriDev d{b->flev_ptr_d, b->blev_ptr_d, b->frec, b->brec, b->tci, b->T};
         tri_solve(b->tri, d, Fin, Y, st);
         BL_HIP(hipGetLastError());
         return PF_OK;

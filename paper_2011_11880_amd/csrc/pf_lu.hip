@@ -488,10 +488,11 @@ int pf_newton_device(pf_plan *plan, pf_refact *rf, double *x, const pf_newton_op
 struct pf_lu {
     int device = 0;
     int n = 0, nnzT = 0;
-    int *ptrT = nullptr, *indT = nullptr, *tdiag = nullptr;
+    int *indT = nullptr;
     double *valT = nullptr, *Y = nullptr;
     int *pivP = nullptr, *pivQ = nullptr;
-    int *frows = nullptr, *brows = nullptr, *flev_ptr = nullptr, *blev_ptr = nullptr;
+    int *flev_ptr = nullptr, *blev_ptr = nullptr;
+    int4 *frec = nullptr, *brec = nullptr;   // the rows' records in level order
     TriLevels tri;   // host copy of the level structure
 };
 
@@ -592,9 +593,9 @@ void release_lu(pf_lu *lu) {
     int prev = -1;
     (void)hipGetDevice(&prev);
     (void)hipSetDevice(lu->device);
-    for (void *p : {(void *)lu->ptrT, (void *)lu->indT, (void *)lu->tdiag, (void *)lu->valT,
-                    (void *)lu->Y, (void *)lu->pivP, (void *)lu->pivQ, (void *)lu->frows,
-                    (void *)lu->brows, (void *)lu->flev_ptr, (void *)lu->blev_ptr})
+    for (void *p : {(void *)lu->indT, (void *)lu->valT,
+                    (void *)lu->Y, (void *)lu->pivP, (void *)lu->pivQ, (void *)lu->frec,
+                    (void *)lu->brec, (void *)lu->flev_ptr, (void *)lu->blev_ptr})
         if (p) (void)hipFree(p);
     if (prev >= 0) (void)hipSetDevice(prev);
     delete lu;
@@ -637,19 +638,18 @@ int create_lu(int device, int n, const int32_t *T_rowptr, const int32_t *T_colid
     lu->nnzT = T_rowptr[n];
     try {
         tri_levels(n, T_rowptr, T_colidx, lu->tri);
+        tri_records(T_rowptr, pivP, lu->tri);
     } catch (const std::bad_alloc &) {
         return fail(PF_ENOMEM, "host allocation failed");
     }
     const TriLevels &t = lu->tri;
     int rc = PF_OK;
-    if (!rc) rc = alloc_copy(&lu->ptrT, T_rowptr, size_t(n) + 1);
     if (!rc) rc = alloc_copy(&lu->indT, T_colidx, size_t(lu->nnzT));
     if (!rc) rc = alloc_copy(&lu->valT, T_val, size_t(lu->nnzT));
-    if (!rc) rc = alloc_copy(&lu->tdiag, t.tdiag.data(), t.tdiag.size());
     if (!rc) rc = alloc_copy(&lu->pivP, pivP, size_t(n));
     if (!rc) rc = alloc_copy(&lu->pivQ, pivQ, size_t(n));
-    if (!rc) rc = alloc_copy(&lu->frows, t.frows.data(), t.frows.size());
-    if (!rc) rc = alloc_copy(&lu->brows, t.brows.data(), t.brows.size());
+    if (!rc) rc = alloc_copy(&lu->frec, t.frec.data(), t.frec.size());
+    if (!rc) rc = alloc_copy(&lu->brec, t.brec.data(), t.brec.size());
     if (!rc) rc = alloc_copy(&lu->flev_ptr, t.flev_ptr.data(), t.flev_ptr.size());
     if (!rc) rc = alloc_copy(&lu->blev_ptr, t.blev_ptr.data(), t.blev_ptr.size());
     if (!rc) rc = alloc_copy(&lu->Y, static_cast<const double *>(nullptr), size_t(n));
@@ -667,8 +667,7 @@ __global__ void __launch_bounds__(256) k_lu_unpermute(int n, const int32_t *__re
 // Solve with the permuted working vector Y (n doubles, written in full by
 // the forward solve before anything reads it).
 int lu_solve_in(pf_lu *lu, double *b, double *Y, hipStream_t st) {
-    const TriDev d{lu->flev_ptr, lu->blev_ptr, lu->frows, lu->brows, lu->ptrT,
-                   lu->indT,     lu->tdiag,    lu->pivP,  lu->valT};
+    const TriDev d{lu->flev_ptr, lu->blev_ptr, lu->frec, lu->brec, lu->indT, lu->valT};
     tri_solve(lu->tri, d, b, Y, st);
     hipLaunchKernelGGL(k_lu_unpermute, dim3(unsigned((lu->n + 255) / 256)), dim3(256), 0, st,
                        lu->n, lu->pivQ, Y, b);
