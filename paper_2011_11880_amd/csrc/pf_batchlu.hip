@@ -57,6 +57,8 @@ struct pf_batch_lu {
     TriLevels tri;   // one instance: levels, runs and row records of the solves
     int32_t *flev_ptr_d = nullptr, *blev_ptr_d = nullptr;
     int4 *frec = nullptr, *brec = nullptr;   // one instance: the solves' row records
+    int4 *frec_factor = nullptr;  // factorisation rows in level order: {T start, T end,
+                                  // first item, items end}
     // device structure
     int32_t *trp = nullptr;   // n + 1
     int32_t *tci = nullptr;   // nnzT
@@ -128,7 +130,7 @@ void release(pf_batch_lu *b) {
                     (void *)b->brows, (void *)b->pivP, (void *)b->pivQ, (void *)b->T,
                     (void *)b->F, (void *)b->J, (void *)b->Y, (void *)b->part, (void *)b->norm,
                     (void *)b->active, (void *)b->flev_ptr_d, (void *)b->blev_ptr_d,
-                    (void *)b->frec, (void *)b->brec})
+                    (void *)b->frec, (void *)b->brec, (void *)b->frec_factor})
         if (p) (void)hipFree(p);
     if (b->norm_host) (void)hipHostFree(b->norm_host);
     if (prev >= 0) (void)hipSetDevice(prev);
@@ -221,14 +223,13 @@ __device__ __forceinline__ void wave_sync() {
 // wave-uniform value and its updates over the lanes.  A step's updates change
 // distinct entries of the row, so every result equals that of the one-lane
 // loop of k_blu_factor.
-__device__ __forceinline__ void factor_row1(int r, int lane, const int32_t *__restrict__ trp,
-                                            const int32_t *__restrict__ tsrc,
-                                            const int32_t *__restrict__ item_ptr,
+__device__ __forceinline__ void factor_row1(int4 m, int lane, const int32_t *__restrict__ tsrc,
                                             const int2 *__restrict__ item,
                                             const double *__restrict__ J, double *__restrict__ T,
                                             double *sm, size_t SI = 1, int inst = 0) {
-    const int r0 = trp[r], R = trp[r + 1] - r0;
-    const int i0 = item_ptr[r], NI = item_ptr[r + 1] - i0;
+    // the row's record: {first entry, end, first item, end of its items}
+    const int r0 = m.x, R = m.y - r0;
+    const int i0 = m.z, NI = m.w - i0;
     double *Lrow = sm;
     double *tv = sm + R;
     int *ix = reinterpret_cast<int *>(tv + NI);
@@ -272,21 +273,19 @@ __device__ __forceinline__ void factor_row1(int r, int lane, const int32_t *__re
 // for one instance, instead of one lane per instance walking the row's long
 // chain of items alone.
 __global__ void __launch_bounds__(64) k_blu_factor_inst(
-    const int32_t *__restrict__ rows, int n_inst, int SI, const int32_t *__restrict__ trp,
-    const int32_t *__restrict__ tsrc, const int32_t *__restrict__ item_ptr,
+    const int4 *__restrict__ rec, int n_inst, int SI, const int32_t *__restrict__ tsrc,
     const int2 *__restrict__ item, const double *__restrict__ J, double *__restrict__ T) {
     extern __shared__ double sm[];
-    const int r = rows[blockIdx.x / n_inst];
+    const int4 m = rec[blockIdx.x / n_inst];
     const int inst = blockIdx.x % n_inst;
-    factor_row1(r, threadIdx.x, trp, tsrc, item_ptr, item, J, T, sm, size_t(SI), inst);
+    factor_row1(m, threadIdx.x, tsrc, item, J, T, sm, size_t(SI), inst);
 }
 
 __global__ void __launch_bounds__(64) k_blu_factor1(
-    const int32_t *__restrict__ rows, const int32_t *__restrict__ trp,
-    const int32_t *__restrict__ tsrc, const int32_t *__restrict__ item_ptr,
+    const int4 *__restrict__ rec, const int32_t *__restrict__ tsrc,
     const int2 *__restrict__ item, const double *__restrict__ J, double *__restrict__ T) {
     extern __shared__ double sm[];
-    factor_row1(rows[blockIdx.x], threadIdx.x, trp, tsrc, item_ptr, item, J, T, sm);
+    factor_row1(rec[blockIdx.x], threadIdx.x, tsrc, item, J, T, sm);
 }
 
 // Levels of at most kTriChainRows rows, when consecutive, run in one block:
@@ -295,9 +294,8 @@ __global__ void __launch_bounds__(64) k_blu_factor1(
 // makes visible to the block).  This saves a launch per level where the
 // levels are small.
 __global__ void __launch_bounds__(64 * kTriChainRows) k_blu_factor1_chain(
-    int l0, int l1, const int32_t *__restrict__ lev_ptr, const int32_t *__restrict__ rows,
-    int stride, const int32_t *__restrict__ trp, const int32_t *__restrict__ tsrc,
-    const int32_t *__restrict__ item_ptr, const int2 *__restrict__ item,
+    int l0, int l1, const int32_t *__restrict__ lev_ptr, const int4 *__restrict__ rec,
+    int stride, const int32_t *__restrict__ tsrc, const int2 *__restrict__ item,
     const double *__restrict__ J, double *__restrict__ T) {
     extern __shared__ double sm[];
     const int lane = threadIdx.x & 63;
@@ -305,8 +303,7 @@ __global__ void __launch_bounds__(64 * kTriChainRows) k_blu_factor1_chain(
     for (int l = l0; l < l1; ++l) {
         const int q0 = lev_ptr[l];
         if (wv < lev_ptr[l + 1] - q0)
-            factor_row1(rows[q0 + wv], lane, trp, tsrc, item_ptr, item, J, T,
-                        sm + size_t(wv) * size_t(stride));
+            factor_row1(rec[q0 + wv], lane, tsrc, item, J, T, sm + size_t(wv) * size_t(stride));
         __syncthreads();
     }
 }
@@ -576,6 +573,14 @@ int build(pf_batch_lu *b, const HostPlan &hp, int64_t nnzT, const int32_t *trp,
     if (!rc) rc = balloc(&b->blev_ptr_d, b->blev_ptr.data(), b->blev_ptr.size());
     if (!rc) rc = balloc(&b->pivP, pivP, size_t(n));
     if (!rc) rc = balloc(&b->pivQ, pivQ, size_t(n));
+    {
+        std::vector<int4> fr(frows.size());
+        for (size_t q = 0; q < frows.size(); ++q) {
+            const int r = frows[q];
+            fr[q] = make_int4(trp[r], trp[r + 1], item_ptr[size_t(r)], item_ptr[size_t(r) + 1]);
+        }
+        if (!rc) rc = balloc(&b->frec_factor, fr.data(), fr.size());
+    }
     if (!rc && !b->tri.frec.empty()) rc = balloc(&b->frec, b->tri.frec.data(), b->tri.frec.size());
     if (!rc && !b->tri.brec.empty()) rc = balloc(&b->brec, b->tri.brec.data(), b->tri.brec.size());
     return rc;
@@ -592,8 +597,7 @@ int factor_levels(pf_batch_lu *b, const double *J, hipStream_t st) {
             const int stride = b->fchain_factor[ci + 3];
             hipLaunchKernelGGL(k_blu_factor1_chain, dim3(1), dim3(unsigned(64 * w)),
                                size_t(w) * size_t(stride) * sizeof(double), st, int(l), l1,
-                               b->flev_ptr_d, b->frows, stride, b->trp, b->tsrc, b->item_ptr,
-                               b->item, J, b->T);
+                               b->flev_ptr_d, b->frec_factor, stride, b->tsrc, b->item, J, b->T);
             l = size_t(l1) - 1;
             ci += 4;
             continue;
@@ -603,8 +607,7 @@ int factor_levels(pf_batch_lu *b, const double *J, hipStream_t st) {
                                 size_t(b->flev_maxi[l]) * sizeof(int32_t);
             if (shm1 <= b->lds_limit) {
                 hipLaunchKernelGGL(k_blu_factor1, dim3(unsigned(nr)), dim3(64), shm1, st,
-                                   b->frows + b->flev_ptr[l], b->trp, b->tsrc, b->item_ptr,
-                                   b->item, J, b->T);
+                                   b->frec_factor + b->flev_ptr[l], b->tsrc, b->item, J, b->T);
                 continue;
             }
         }
@@ -613,8 +616,8 @@ int factor_levels(pf_batch_lu *b, const double *J, hipStream_t st) {
                                 size_t(b->flev_maxi[l]) * sizeof(int32_t);
             if (shm1 <= b->lds_limit) {
                 hipLaunchKernelGGL(k_blu_factor_inst, dim3(unsigned(int64_t(nr) * I)), dim3(64), shm1,
-                                   st, b->frows + b->flev_ptr[l], I, SI, b->trp, b->tsrc,
-                                   b->item_ptr, b->item, J, b->T);
+                                   st, b->frec_factor + b->flev_ptr[l], I, SI, b->tsrc, b->item,
+                                   J, b->T);
                 continue;
             }
         }
