@@ -56,19 +56,18 @@ struct pf_batch_lu {
     std::vector<int32_t> fchain_factor;
     TriLevels tri;   // one instance: levels, runs and row records of the solves
     int32_t *flev_ptr_d = nullptr, *blev_ptr_d = nullptr;
-    int4 *frec = nullptr, *brec = nullptr;   // one instance: the solves' row records
+    int4 *frec = nullptr, *brec = nullptr;   // the solves' row records in level order
     int4 *frec_factor = nullptr;  // factorisation rows in level order: {T start, T end,
                                   // first item, items end}
     // device structure
     int32_t *trp = nullptr;   // n + 1
     int32_t *tci = nullptr;   // nnzT
     int32_t *tsrc = nullptr;  // nnzT: Jacobian slot of each T entry, -1 for fill
-    int32_t *tdiag = nullptr; // n
     int32_t *item_ptr = nullptr;  // n + 1: items of each row
     int2 *item = nullptr;     // {-(local index of t_rk) - 1, T position of t_kk} opens a step;
                               // {local index of t_rj, T position of t_kj} is an update
-    int32_t *frows = nullptr, *brows = nullptr;  // rows in level order
-    int32_t *pivP = nullptr, *pivQ = nullptr;
+    int32_t *frows = nullptr;  // factorisation rows in level order
+    int32_t *pivQ = nullptr;
     // device work arrays, instance-fastest with row pitch ld
     double *T = nullptr, *F = nullptr, *J = nullptr, *Y = nullptr;
     double *part = nullptr, *norm = nullptr;  // per-instance norms
@@ -125,9 +124,9 @@ void release(pf_batch_lu *b) {
     int prev = -1;
     (void)hipGetDevice(&prev);
     (void)hipSetDevice(b->device);
-    for (void *p : {(void *)b->trp, (void *)b->tci, (void *)b->tsrc, (void *)b->tdiag,
+    for (void *p : {(void *)b->trp, (void *)b->tci, (void *)b->tsrc,
                     (void *)b->item_ptr, (void *)b->item, (void *)b->frows,
-                    (void *)b->brows, (void *)b->pivP, (void *)b->pivQ, (void *)b->T,
+                    (void *)b->pivQ, (void *)b->T,
                     (void *)b->F, (void *)b->J, (void *)b->Y, (void *)b->part, (void *)b->norm,
                     (void *)b->active, (void *)b->flev_ptr_d, (void *)b->blev_ptr_d,
                     (void *)b->frec, (void *)b->brec, (void *)b->frec_factor})
@@ -309,18 +308,20 @@ __global__ void __launch_bounds__(64 * kTriChainRows) k_blu_factor1_chain(
 }
 
 // forward: Y[r] = F[pivP[r]] - sum_{k < r} t_rk Y[k]
+// (rec: the rows' records in level order, {row, first entry, diagonal,
+// pivP[row]} forward and {row, diagonal, row end, 0} backward)
 __global__ void __launch_bounds__(64) k_blu_fwd(
-    const int32_t *__restrict__ rows, int n_chunks, int W, int n_inst, int SI,
-    const int32_t *__restrict__ trp, const int32_t *__restrict__ tci,
-    const int32_t *__restrict__ tdiag, const int32_t *__restrict__ pivP,
-    const double *__restrict__ T, const double *__restrict__ F, double *__restrict__ Y) {
+    const int4 *__restrict__ rec, int n_chunks, int W, int n_inst, int SI,
+    const int32_t *__restrict__ tci, const double *__restrict__ T, const double *__restrict__ F,
+    double *__restrict__ Y) {
     const int lane = threadIdx.x;
-    const int r = rows[blockIdx.x / n_chunks];
+    const int4 m = rec[blockIdx.x / n_chunks];
+    const int r = m.x;
     const int inst = (blockIdx.x % n_chunks) * W + lane;
     if (lane >= W || inst >= n_inst) return;
-    double s = F[size_t(pivP[r]) * SI + inst];
-    const int e1 = tdiag[r];   // the strictly lower part ends at the diagonal
-    for (int e0 = trp[r]; e0 < e1; e0 += kG) {
+    double s = F[size_t(m.w) * SI + inst];
+    const int e1 = m.z;   // the strictly lower part ends at the diagonal
+    for (int e0 = m.y; e0 < e1; e0 += kG) {
         int c[kG];
         double t[kG], y[kG];
 #pragma unroll
@@ -339,16 +340,16 @@ __global__ void __launch_bounds__(64) k_blu_fwd(
 
 // backward: Y[r] = (Y[r] - sum_{j > r} t_rj Y[j]) / t_rr
 __global__ void __launch_bounds__(64) k_blu_bwd(
-    const int32_t *__restrict__ rows, int n_chunks, int W, int n_inst, int SI,
-    const int32_t *__restrict__ trp, const int32_t *__restrict__ tci,
-    const int32_t *__restrict__ tdiag, const double *__restrict__ T, double *__restrict__ Y) {
+    const int4 *__restrict__ rec, int n_chunks, int W, int n_inst, int SI,
+    const int32_t *__restrict__ tci, const double *__restrict__ T, double *__restrict__ Y) {
     const int lane = threadIdx.x;
-    const int r = rows[blockIdx.x / n_chunks];
+    const int4 m = rec[blockIdx.x / n_chunks];
+    const int r = m.x;
     const int inst = (blockIdx.x % n_chunks) * W + lane;
     if (lane >= W || inst >= n_inst) return;
     double s = Y[size_t(r) * SI + inst];
-    const int e1 = trp[r + 1];
-    for (int e0 = tdiag[r] + 1; e0 < e1; e0 += kG) {
+    const int e1 = m.z;
+    for (int e0 = m.y + 1; e0 < e1; e0 += kG) {
         int c[kG];
         double t[kG], y[kG];
 #pragma unroll
@@ -362,7 +363,7 @@ __global__ void __launch_bounds__(64) k_blu_bwd(
         for (int q = 0; q < kG; ++q)
             if (e0 + q < e1) s = fma(-t[q], y[q], s);
     }
-    Y[size_t(r) * SI + inst] = s / T[size_t(tdiag[r]) * SI + inst];
+    Y[size_t(r) * SI + inst] = s / T[size_t(m.y) * SI + inst];
 }
 
 
@@ -552,11 +553,12 @@ int build(pf_batch_lu *b, const HostPlan &hp, int64_t nnzT, const int32_t *trp,
         b->tri.blev_ptr = b->blev_ptr;
         tri_chains(b->tri.flev_ptr, b->tri.fchain);
         tri_chains(b->tri.blev_ptr, b->tri.bchain);
-        b->tri.tdiag = tdiag;
-        b->tri.frows = frows;
-        b->tri.brows = brows;
-        tri_records(trp, pivP, b->tri);
     }
+    // the solves' row records (every instance count)
+    b->tri.tdiag = tdiag;
+    b->tri.frows = frows;
+    b->tri.brows = brows;
+    tri_records(trp, pivP, b->tri);
     int rc = PF_OK;
     if (!rc) rc = balloc(&b->trp, trp, size_t(n) + 1);
     std::vector<int32_t> tci_pad(tci, tci + nnzT);
@@ -564,14 +566,11 @@ int build(pf_batch_lu *b, const HostPlan &hp, int64_t nnzT, const int32_t *trp,
     item.resize(item.size() + kPad, make_int2(0, 0));
     if (!rc) rc = balloc(&b->tci, tci_pad.data(), tci_pad.size());
     if (!rc) rc = balloc(&b->tsrc, tsrc.data(), tsrc.size());
-    if (!rc) rc = balloc(&b->tdiag, tdiag.data(), tdiag.size());
     if (!rc) rc = balloc(&b->item_ptr, item_ptr.data(), item_ptr.size());
     if (!rc) rc = balloc(&b->item, item.data(), item.size());
     if (!rc) rc = balloc(&b->frows, frows.data(), frows.size());
-    if (!rc) rc = balloc(&b->brows, brows.data(), brows.size());
     if (!rc) rc = balloc(&b->flev_ptr_d, b->flev_ptr.data(), b->flev_ptr.size());
     if (!rc) rc = balloc(&b->blev_ptr_d, b->blev_ptr.data(), b->blev_ptr.size());
-    if (!rc) rc = balloc(&b->pivP, pivP, size_t(n));
     if (!rc) rc = balloc(&b->pivQ, pivQ, size_t(n));
     {
         std::vector<int4> fr(frows.size());
@@ -581,8 +580,8 @@ int build(pf_batch_lu *b, const HostPlan &hp, int64_t nnzT, const int32_t *trp,
         }
         if (!rc) rc = balloc(&b->frec_factor, fr.data(), fr.size());
     }
-    if (!rc && !b->tri.frec.empty()) rc = balloc(&b->frec, b->tri.frec.data(), b->tri.frec.size());
-    if (!rc && !b->tri.brec.empty()) rc = balloc(&b->brec, b->tri.brec.data(), b->tri.brec.size());
+    if (!rc) rc = balloc(&b->frec, b->tri.frec.data(), b->tri.frec.size());
+    if (!rc) rc = balloc(&b->brec, b->tri.brec.data(), b->tri.brec.size());
     return rc;
 }
 
@@ -644,14 +643,12 @@ int solve_levels(pf_batch_lu *b, const double *Fin, double *Y, hipStream_t st) {
     for (size_t l = 0; l + 1 < b->flev_ptr.size(); ++l) {
         const int nr = b->flev_ptr[l + 1] - b->flev_ptr[l];
         hipLaunchKernelGGL(k_blu_fwd, dim3(unsigned(int64_t(nr) * nc)), dim3(64), 0, st,
-                           b->frows + b->flev_ptr[l], nc, 64, I, SI, b->trp, b->tci, b->tdiag,
-                           b->pivP, b->T, Fin, Y);
+                           b->frec + b->flev_ptr[l], nc, 64, I, SI, b->tci, b->T, Fin, Y);
     }
     for (size_t l = 0; l + 1 < b->blev_ptr.size(); ++l) {
         const int nr = b->blev_ptr[l + 1] - b->blev_ptr[l];
         hipLaunchKernelGGL(k_blu_bwd, dim3(unsigned(int64_t(nr) * nc)), dim3(64), 0, st,
-                           b->brows + b->blev_ptr[l], nc, 64, I, SI, b->trp, b->tci, b->tdiag,
-                           b->T, Y);
+                           b->brec + b->blev_ptr[l], nc, 64, I, SI, b->tci, b->T, Y);
     }
     BL_HIP(hipGetLastError());
     return PF_OK;
