@@ -406,9 +406,12 @@ int pf_newton_device(pf_plan *plan, pf_refact *rf, double *x, const pf_newton_op
             rc = fail(PF_EDEVICE, "stream synchronisation failed in Newton iteration %d", it);
             break;
         }
+        float ms = 0.f;
+        if (e[0] && e[1] && hipEventElapsedTime(&ms, e[0], e[1]) == hipSuccess) r.t_eval_s += ms * 1e-3;
         double nf = *rf->norm_host;
         // the limits at this iterate (as pf_newton): after a switch F and J
-        // are evaluated again under the new modes before the step
+        // are evaluated again under the new modes before the step (its time
+        // counts as evaluation; the step's is measured from its end)
         int32_t ns = 0;
         if (limits && nf < check_below) {
             if (hipMemcpyAsync(xh.data(), x, size_t(n) * sizeof(double), hipMemcpyDeviceToHost,
@@ -419,10 +422,14 @@ int pf_newton_device(pf_plan *plan, pf_refact *rf, double *x, const pf_newton_op
             }
             rc = q_switch(hp, plan->dev, xh.data(), opts->q_min, opts->q_max, switch_tol, &ns);
             if (!rc && ns) {
+                if (e[0]) (void)hipEventRecord(e[0], st);
                 rc = dev_eval_single(hp, plan->dev, x, rf->F, rf->J, st);
+                if (!rc && e[1]) (void)hipEventRecord(e[1], st);
                 if (!rc) rc = absmax_on_stream(rf, rf->F, st);
                 if (!rc && hipStreamSynchronize(st) != hipSuccess)
                     rc = fail(PF_EDEVICE, "stream synchronisation failed in Newton iteration %d", it);
+                if (!rc && e[0] && e[1] && hipEventElapsedTime(&ms, e[0], e[1]) == hipSuccess)
+                    r.t_eval_s += ms * 1e-3;
                 nf = *rf->norm_host;
             }
             if (rc) break;
@@ -457,12 +464,10 @@ int pf_newton_device(pf_plan *plan, pf_refact *rf, double *x, const pf_newton_op
     if (hipStreamSynchronize(st) != hipSuccess && rc == PF_OK)
         rc = fail(PF_EDEVICE, "stream synchronisation failed");
     r.t_total_s = std::chrono::duration<double>(std::chrono::steady_clock::now() - t_start).count();
-    for (int k = 0; k <= std::min(it, max_iter); ++k) {
+    for (int k = 0; k < std::min(r.iterations, max_iter + 1); ++k) {
         hipEvent_t *e = &ev[3 * size_t(k)];
         float ms = 0.f;
-        if (e[0] && e[1] && hipEventElapsedTime(&ms, e[0], e[1]) == hipSuccess) r.t_eval_s += ms * 1e-3;
-        if (k < r.iterations && e[1] && e[2] && hipEventElapsedTime(&ms, e[1], e[2]) == hipSuccess)
-            r.t_solve_s += ms * 1e-3;
+        if (e[1] && e[2] && hipEventElapsedTime(&ms, e[1], e[2]) == hipSuccess) r.t_solve_s += ms * 1e-3;
     }
     for (auto &e : ev)
         if (e) (void)hipEventDestroy(e);
