@@ -54,7 +54,7 @@ struct pf_batch_lu {
     // {first level, end level, waves, LDS bytes per wave} (factorisation) and
     // {first level, end level, waves} (forward, backward solves)
     std::vector<int32_t> fchain_factor;
-    TriLevels tri;   // one instance: levels, runs and row records of the solves
+    TriLevels tri;   // the solves: row records (host copies); one instance: levels and runs
     int32_t *flev_ptr_d = nullptr, *blev_ptr_d = nullptr;
     int4 *frec = nullptr, *brec = nullptr;   // the solves' row records in level order
     int4 *frec_factor = nullptr;  // factorisation rows in level order: {T start, T end,
